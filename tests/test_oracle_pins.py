@@ -1,0 +1,358 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Closed forms (direct path, image source, sealed box power), textbook geometry
+(icosahedron, solid angles), brute force on tiny inputs (an independent numpy
+linear solve for ray/triangle hits, all-microphone membership), and invariants
+(energy bookkeeping, mirror symmetry).  A plausible mistake in the oracle (a
+dropped term, a wrong sign or index, a transposed operand) fails one of these.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from scenegen import (block_scene, district_scene, empty_scene, ground_scene, mirror_scene,
+                      sealed_box_scene, tiny_scene)
+
+FOUR_PI = 4.0 * math.pi
+
+
+# ----------------------------------------------------------------------------
+# Icosphere (beam directions)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("level", range(0, 6))
+def test_icosphere_counts_orientation_unit(level):
+    d = O.icosphere(level)
+    assert d.shape == (20 * 4 ** level, 3, 3)
+    norms = np.linalg.norm(d, axis=2)
+    assert np.abs(norms - 1.0).max() < 4e-16
+    det = np.einsum("fi,fi->f", d[:, 0], np.cross(d[:, 1], d[:, 2]))
+    assert (det > 0).all()
+
+
+@pytest.mark.parametrize("level", range(0, 5))
+def test_icosphere_closed_oriented_surface(level):
+    """Every directed edge appears once and its reverse once: a closed, consistently
+    oriented triangulation of the sphere (V - E + F = 2), with shared vertices bit-identical."""
+    d = O.icosphere(level)
+    keys = {}
+    faces = []
+    for f in range(d.shape[0]):
+        ids = []
+        for k in range(3):
+            key = d[f, k].tobytes()
+            ids.append(keys.setdefault(key, len(keys)))
+        faces.append(ids)
+    edges = {}
+    for (a, b, c) in faces:
+        for (u, v) in ((a, b), (b, c), (c, a)):
+            edges[(u, v)] = edges.get((u, v), 0) + 1
+    assert all(n == 1 for n in edges.values())
+    assert all((v, u) in edges for (u, v) in edges)
+    V, E, F = len(keys), len(edges) // 2, len(faces)
+    assert V - E + F == 2
+    assert V == 10 * 4 ** level + 2
+
+
+def test_icosahedron_textbook_geometry():
+    """Level 0 is the regular icosahedron inscribed in the unit sphere: 12 vertices, each
+    of degree 5, edge length 4 / sqrt(10 + 2 sqrt 5)."""
+    d = O.icosphere(0)
+    verts = np.unique(d.reshape(-1, 3), axis=0)
+    assert verts.shape[0] == 12
+    edge = 4.0 / math.sqrt(10.0 + 2.0 * math.sqrt(5.0))
+    for f in range(20):
+        for k in range(3):
+            assert abs(np.linalg.norm(d[f, k] - d[f, (k + 1) % 3]) - edge) < 1e-14
+    deg = [sum(1 for f in range(20) if any((d[f, k] == v).all() for k in range(3))) for v in verts]
+    assert deg == [5] * 12
+
+
+def test_solid_angle_closed_forms():
+    ex, ey, ez = np.eye(3)
+    assert abs(O.solid_angle(ex, ey, ez) - math.pi / 2) < 1e-15  # one octant
+    # a thin cone: area / r^2 of a small flat triangle at unit distance
+    e = 1e-4
+    a, b, c = np.array([0, 0, 1.0]), np.array([e, 0, 1.0]), np.array([0, e, 1.0])
+    a, b, c = (v / np.linalg.norm(v) for v in (a, b, c))
+    assert abs(O.solid_angle(a, b, c) / (0.5 * e * e) - 1) < 1e-3
+
+
+@pytest.mark.parametrize("level", range(0, 6))
+def test_solid_angles_tile_the_sphere(level):
+    d = O.icosphere(level)
+    om = np.array([O.solid_angle(*d[f]) for f in range(d.shape[0])]) if level < 5 else None
+    if om is None:
+        # vectorised Van Oosterom-Strackee for the big level (independent of the oracle's C)
+        num = np.abs(np.einsum("fi,fi->f", d[:, 0], np.cross(d[:, 1], d[:, 2])))
+        den = 1 + np.einsum("fi,fi->f", d[:, 0], d[:, 1]) + np.einsum("fi,fi->f", d[:, 1], d[:, 2]) \
+            + np.einsum("fi,fi->f", d[:, 2], d[:, 0])
+        om = 2 * np.arctan2(num, den)
+    assert abs(om.sum() - FOUR_PI) < 1e-12
+    if level >= 5:
+        ratio = om.max() / om.min()
+        assert 1.25 < ratio < 1.35
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_icosphere_mirror_symmetric(axis):
+    d = O.icosphere(3)
+    c = d.sum(axis=1)
+    c /= np.linalg.norm(c, axis=1, keepdims=True)
+    m = c.copy()
+    m[:, axis] *= -1
+    a = np.round(c, 12)
+    b = np.round(m, 12)
+    a = a[np.lexsort(a.T[::-1])]
+    b = b[np.lexsort(b.T[::-1])]
+    assert np.abs(a - b).max() < 1e-11
+
+
+# ----------------------------------------------------------------------------
+# Closest hit: brute force vs BVH vs an independent linear solve
+# ----------------------------------------------------------------------------
+
+def _random_soup(seed, n_tri=150, span=20.0):
+    rng = np.random.default_rng(seed)
+    cen = rng.uniform(-span, span, size=(n_tri, 3))
+    v = (cen[:, None, :] + rng.normal(scale=2.0, size=(n_tri, 3, 3))).reshape(-1, 3).astype(np.float32)
+    t = np.arange(3 * n_tri, dtype=np.int32).reshape(-1, 3)
+    sc = empty_scene().with_(vertices=v, triangles=t, absorption=np.full(n_tri, 0.1, np.float32))
+    return sc
+
+
+def _solve_hits(scene, o, c, start, t_min):
+    """Independent closest hit: solve o + t c = v0 + u e1 + v e2 with numpy per triangle."""
+    V = scene.vertices.astype(np.float64)
+    T = scene.triangles
+    best_t, best = np.inf, -1
+    for k in range(T.shape[0]):
+        if k == start:
+            continue
+        v0, v1, v2 = V[T[k]]
+        M = np.stack([-c, v1 - v0, v2 - v0], axis=1)
+        if abs(np.linalg.det(M)) < 1e-12:
+            continue
+        t, u, v = np.linalg.solve(M, o - v0)
+        if u >= -1e-9 and v >= -1e-9 and u + v <= 1 + 1e-9 and t > t_min:
+            if t < best_t - 1e-9:
+                best_t, best = t, k
+    return best, best_t
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_closest_hit_bvh_equals_brute_and_linear_solve(seed):
+    sc = _random_soup(seed)
+    rng = np.random.default_rng(100 + seed)
+    n = 400
+    o = rng.uniform(-25, 25, size=(n, 3))
+    # half the rays aim at (jittered) triangle centroids so that many of them hit
+    V = sc.vertices.astype(np.float64)[sc.triangles].mean(axis=1)
+    aim = V[rng.integers(0, sc.n_tri, size=n)] + rng.normal(scale=1.0, size=(n, 3))
+    c = np.where(np.arange(n)[:, None] % 2 == 0, aim - o, rng.normal(size=(n, 3)))
+    c /= np.linalg.norm(c, axis=1, keepdims=True)
+    hb, tb, fb, _, _ = O.closest_hits(sc, o, c, use_bvh=False)
+    hv, tv, fv, nv, tt = O.closest_hits(sc, o, c, use_bvh=True)
+    assert np.array_equal(hb, hv) and np.array_equal(fb, fv)
+    assert np.array_equal(tb[hb >= 0], tv[hv >= 0])
+    assert (hb >= 0).sum() > 80  # the check is not vacuous
+    assert tt.sum() < 0.5 * n * sc.n_tri  # the BVH culls
+    for r in range(n):
+        if fb[r]:
+            continue
+        h, t = _solve_hits(sc, o[r], c[r], -1, O.T_MIN)
+        assert h == hb[r], r
+        if h >= 0:
+            assert abs(t - tb[r]) < 1e-9 * max(1.0, t)
+
+
+def test_tie_and_edge_rules():
+    """Two coplanar triangles sharing a diagonal; a duplicate triangle; start exclusion."""
+    v = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0]], np.float32)
+    t = np.array([[0, 1, 2], [0, 2, 3], [0, 1, 2]], np.int32)  # tri 2 duplicates tri 0
+    sc = empty_scene().with_(vertices=v, triangles=t, absorption=np.full(3, 0.1, np.float32))
+    down = np.array([[0, 0, -1.0]])
+    # interior of tri 0 (x > y): tri 0 and its duplicate tie -> lowest id 0, flagged (tie)
+    h, th, f, _, _ = O.closest_hits(sc, np.array([[0.7, 0.2, 1.0]]), down)
+    assert h[0] == 0 and th[0] == 1.0 and f[0] == 1
+    # interior of tri 1, far from every edge: clean hit, not flagged
+    h, th, f, _, _ = O.closest_hits(sc, np.array([[0.25, 0.7, 1.0]]), down)
+    assert h[0] == 1 and f[0] == 0
+    # exactly on the shared diagonal: both contain the point -> lowest id, flagged
+    h, th, f, _, _ = O.closest_hits(sc, np.array([[0.5, 0.5, 1.0]]), down)
+    assert h[0] == 0 and f[0] == 1
+    # within 1e-6 m of the diagonal (inside tri 1): flagged as near-edge
+    h, th, f, _, _ = O.closest_hits(sc, np.array([[0.4, 0.400001, 1.0]]), down)
+    assert h[0] == 1 and f[0] == 1
+    # near miss just outside the square by 5e-6 m: no hit, flagged
+    h, th, f, _, _ = O.closest_hits(sc, np.array([[1.000005, 0.3, 1.0]]), down)
+    assert h[0] == -1 and f[0] == 1
+    # 1e-3 m outside: clean miss
+    h, th, f, _, _ = O.closest_hits(sc, np.array([[1.001, 0.3, 1.0]]), down)
+    assert h[0] == -1 and f[0] == 0
+    # start triangle excluded: starting on tri 1 the ray sees nothing else
+    h, th, f, _, _ = O.closest_hits(sc, np.array([[0.25, 0.7, 1.0]]), down, start=np.array([1]))
+    assert h[0] == -1
+    # hits at t <= t_min are ignored
+    h, th, f, _, _ = O.closest_hits(sc, np.array([[0.25, 0.7, 0.0005]]), down)
+    assert h[0] == -1
+
+
+# ----------------------------------------------------------------------------
+# Closed forms for microphone energies
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("level", range(0, 6))
+def test_direct_path_free_field(level):
+    """No geometry: each microphone gets W / (4 pi d^2) exactly once, at every level."""
+    sc = empty_scene(level=level, src=(0.3, -0.2, 1.0))
+    r = O.trace(sc, use_bvh=False, mic_mode=0)
+    m = sc.mic_positions()
+    s = sc.sources[0].astype(np.float64)
+    ref = 1.0 / (FOUR_PI * ((m - s) ** 2).sum(1))
+    assert (r.e_flag == 0).all()
+    assert np.abs(r.energy / ref - 1).max() < 1e-13
+    assert r.counters["mic_updates"] == sc.n_mic
+
+
+def test_direct_path_two_sources_and_air_damping():
+    sc = empty_scene(level=3, src=(0.3, -0.2, 1.0))
+    sc = sc.with_(sources=np.array([[0.3, -0.2, 1.0], [-2.1, 3.3, 0.4]], np.float32),
+                  power=np.array([1.0, 2.5], np.float32))
+    m_air = 0.01
+    r = O.trace(sc, m_air=m_air)
+    m = sc.mic_positions()
+    ref = np.zeros(sc.n_mic)
+    for s, w in zip(sc.sources.astype(np.float64), sc.power.astype(np.float64)):
+        d = np.sqrt(((m - s) ** 2).sum(1))
+        ref += w * np.exp(-m_air * d) / (FOUR_PI * d * d)
+    assert np.abs(r.energy / ref - 1).max() < 1e-13
+
+
+def test_tie_rule_on_shared_faces_and_vertex_rays():
+    """Source on the icosphere's symmetry planes: the microphone row y = 0 lies exactly on
+    shared beam faces and the centre microphone on the +z vertex ray.  Every microphone is
+    still owned by exactly one beam (total energy equals the closed form), and the ones on
+    shared faces are reported as ambiguous (flag energy)."""
+    sc = empty_scene(level=2, src=(0.0, 0.0, 1.0), n_mic=9, spacing=3.0, mic_z=2.5)
+    r = O.trace(sc, mic_mode=0)
+    m = sc.mic_positions()
+    ref = 1.0 / (FOUR_PI * ((m - sc.sources[0].astype(np.float64)) ** 2).sum(1))
+    assert np.abs(r.energy / ref - 1).max() < 1e-13
+    amb = (r.e_flag > 0).reshape(9, 9)
+    assert amb[4].all()            # y = 0: on shared faces
+    assert amb.sum() == 9          # nowhere else
+    assert r.counters["mic_updates"] == sc.n_mic
+
+
+@pytest.mark.parametrize("level,alpha", [(3, 0.2), (4, 0.5), (5, 0.05)])
+def test_single_ground_reflection_is_image_source(level, alpha):
+    sc = ground_scene(level=level, alpha=alpha)
+    r = O.trace(sc)
+    m = sc.mic_positions()
+    s = sc.sources[0].astype(np.float64)
+    img = s * np.array([1, 1, -1.0])
+    a32 = float(np.float32(alpha))
+    ref = (1.0 / ((m - s) ** 2).sum(1) + (1 - a32) / ((m - img) ** 2).sum(1)) / FOUR_PI
+    # image direction well below the horizon so its beam's guiding ray hits the ground
+    elev = np.degrees(np.arctan2(m[:, 2] + s[2], np.hypot(m[:, 0] - s[0], m[:, 1] - s[1])))
+    ok = (elev > 15) & (r.e_flag == 0)
+    assert ok.sum() > 60
+    assert np.abs(r.energy[ok] / ref[ok] - 1).max() < 1e-13
+    # depth 0: only the direct path remains
+    r0 = O.trace(sc, depth=0)
+    ref0 = 1.0 / (FOUR_PI * ((m - s) ** 2).sum(1))
+    assert np.abs(r0.energy / ref0 - 1).max() < 1e-13
+
+
+@pytest.mark.parametrize("level,alpha", [(2, 0.25), (3, 0.1), (4, 0.6)])
+def test_sealed_box_counts_and_power(level, alpha):
+    sc = sealed_box_scene(level=level, alpha=alpha, depth=6)
+    r = O.trace(sc)
+    n = 20 * 4 ** level
+    assert (r.flagged == 0).all()
+    assert (r.count == n).all()
+    a32 = float(np.float32(alpha))
+    assert np.abs(r.power - (1 - a32) ** np.arange(7)).max() < 1e-13
+    assert (r.hit >= 0).all()
+
+
+def test_energy_bookkeeping_block():
+    """P_g = sum over beams alive at g of (W / 4 pi) Omega_b prod_k<g (1 - alpha[hit_k]);
+    count_(g+1) = hits at generation g (g < D)."""
+    sc = block_scene(0)
+    r = O.trace(sc)
+    d = O.icosphere(sc.level)
+    num = np.abs(np.einsum("fi,fi->f", d[:, 0], np.cross(d[:, 1], d[:, 2])))
+    den = 1 + np.einsum("fi,fi->f", d[:, 0], d[:, 1]) + np.einsum("fi,fi->f", d[:, 1], d[:, 2]) \
+        + np.einsum("fi,fi->f", d[:, 2], d[:, 0])
+    om = 2 * np.arctan2(num, den)
+    alpha = sc.absorption.astype(np.float64)
+    K = np.full(r.hit.shape[0], 1.0 / FOUR_PI)
+    for g in range(sc.depth + 1):
+        alive = r.hit[:, g] != -2
+        assert alive.sum() == r.count[g]
+        assert abs((K[alive] * om[alive]).sum() - r.power[g]) < 1e-12
+        if g < sc.depth:
+            hit = r.hit[:, g] >= 0
+            assert (r.hit[:, g + 1] != -2).sum() == hit.sum()
+            K = np.where(hit, K * (1 - alpha[np.maximum(r.hit[:, g], 0)]), K)
+    assert (np.diff(r.count) <= 0).all()
+
+
+# ----------------------------------------------------------------------------
+# Microphone enumeration and symmetry
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("maker,kw", [(tiny_scene, {}), (mirror_scene, {}), (block_scene, {"beam_end": 3000})])
+def test_grid_rasterisation_equals_brute_force(maker, kw):
+    sc = maker()
+    a = O.trace(sc, mic_mode=1, n_threads=1, **kw)
+    b = O.trace(sc, mic_mode=0, n_threads=1, **kw)
+    assert np.array_equal(a.e_strict, b.e_strict)
+    assert np.array_equal(a.e_flag, b.e_flag)
+    assert a.counters["mic_updates"] == b.counters["mic_updates"]
+    assert a.counters["mic_updates"] > 0
+    assert a.counters["mic_tests"] < b.counters["mic_tests"]
+
+
+def test_mirror_symmetry():
+    sc = mirror_scene()
+    r = O.trace(sc)
+    E = r.energy.reshape(sc.mic_ny, sc.mic_nx)
+    F = (r.e_flag > 0).reshape(sc.mic_ny, sc.mic_nx)
+    ok = ~(F | F[:, ::-1])
+    assert ok.sum() > 200
+    a, b = E[ok], E[:, ::-1][ok]
+    assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+    assert (E > 0).sum() > 100
+
+
+def test_energy_threshold_stops_reflections():
+    sc = tiny_scene()
+    r = O.trace(sc, e_min=1e9)
+    assert r.count[1:].sum() == 0
+
+
+# ----------------------------------------------------------------------------
+# Scene generator shapes (input recipe)
+# ----------------------------------------------------------------------------
+
+def test_scene_shapes():
+    t = tiny_scene()
+    assert t.n_tri == 42 and t.n_mic == 16 and t.n_beams0 == 1280
+    b = block_scene(0)
+    assert b.n_tri == 1002 and b.n_mic == 10000 and b.n_beams0 == 20480
+    b2 = block_scene(0)
+    assert np.array_equal(b.vertices, b2.vertices)
+    assert not np.array_equal(b.vertices, block_scene(1).vertices)
+
+
+@pytest.mark.slow
+def test_district_shape():
+    d = district_scene(0)
+    assert 300_000 <= d.n_tri <= 360_000
+    assert d.n_src == 64 and d.n_mic == 250_000 and d.n_beams0 == 64 * 81920
+    assert len({tuple(s) for s in d.sources.tolist()}) == 64
