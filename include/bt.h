@@ -1,0 +1,196 @@
+/*
+ * bt.h -- C ABI of the MI355X hybrid beam tracer.
+ *
+ * The library traces triangular-frustum sound beams from point sources through a
+ * triangulated city model and accumulates, at microphones, the energy of every beam
+ * whose frustum contains them (Gbikpi-Benissan & Magoules, "Beam-tracing domain
+ * decomposition method for urban acoustic pollution", Section 2: the hybrid
+ * beam/ray method).  Only a beam's guiding ray is intersected with the model, as in
+ * ray tracing, so beams are never split; each hit spawns one specular child beam
+ * that has lost energy at the surface.
+ *
+ * Conventions
+ *   - Units: metres, watts, W/m^2; levels in dB re i0 = 1e-12 W/m^2.
+ *   - Host input arrays are borrowed for the duration of the call only (copied).
+ *   - Pointers documented as "device" must be device-accessible (hipMalloc or a
+ *     torch CUDA tensor's data_ptr) and stay valid until the stream work finishes.
+ *   - "host or device" output pointers are filled with hipMemcpyDefault.
+ *   - All handles are created and freed by the library; the library never frees
+ *     caller memory.
+ *   - Every call returns a bt_status.  No exception or abort crosses the ABI.  On
+ *     error bt_last_error(ctx) holds a message.
+ *   - A bt_ctx is single-threaded except bt_submit / bt_poll / bt_cancel.
+ *   - Work is enqueued on the context's stream; calls that return results to the
+ *     host (bt_trace with n_next, bt_levels, bt_beams_stats, bt_poll) synchronise it.
+ */
+#ifndef BT_H
+#define BT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BT_OK = 0,
+    BT_PENDING = 1,      /* bt_poll: request not finished yet */
+    BT_EINVAL = -1,      /* invalid argument (nothing was enqueued) */
+    BT_ENOMEM = -2,      /* allocation failed or the context's HBM budget is exceeded */
+    BT_EDEVICE = -3,     /* HIP runtime error; text in bt_last_error */
+    BT_EOVERFLOW = -4,   /* an internal capacity was exceeded (e.g. BVH too deep) */
+    BT_ENOTFOUND = -5,   /* unknown request ticket */
+    BT_ESTATE = -6       /* call out of order (e.g. accumulate before any trace) */
+} bt_status;
+
+#define BT_MAX_LEVEL 9    /* icosphere level: 20 * 4^level beams per source */
+#define BT_MAX_DEPTH 31   /* maximum reflections per beam */
+
+typedef struct bt_ctx bt_ctx;
+typedef struct bt_mesh bt_mesh;
+typedef struct bt_mics bt_mics;
+typedef struct bt_beams bt_beams;
+
+/* Tracing parameters (paper Section 2: reflections lose energy; particle methods
+ * also damp energy in air and delete it below a threshold). */
+typedef struct {
+    int32_t max_depth;    /* D: generations 0..D are traced; only depth < D reflects */
+    double t_min;         /* hits at ray parameter t <= t_min are ignored (1e-3 m) */
+    double edge_delta;    /* flag distance (1e-5 m): a segment whose hit point lies within
+                             it of an edge, or with another triangle within it of the
+                             ray near t*, is flagged; flags are inherited by children */
+    double air_m;         /* air attenuation exp(-air_m * d); 0 = off */
+    double e_min;         /* a child whose power K*Omega is <= e_min is dropped; 0 = off */
+    /* optional per-(initial beam, generation) parity outputs, device pointers,
+       row-major [n_beams0][max_depth + 1]; entries of untraced generations are
+       left untouched (callers pre-fill them, e.g. with -2) */
+    int32_t *hit_out;     /* hit triangle id, -1 = escaped */
+    uint8_t *flag_out;    /* 1 = this segment or an ancestor is flagged */
+    double *t_out;        /* hit parameter (metres along the guiding ray), inf on escape */
+} bt_params;
+
+/* Per-beam-set statistics, filled by bt_beams_stats (synchronises). */
+typedef struct {
+    int32_t generations;                 /* generations traced so far */
+    int64_t count[BT_MAX_DEPTH + 1];     /* beams traced per generation */
+    int64_t flagged[BT_MAX_DEPTH + 1];   /* of which flagged */
+    double power[BT_MAX_DEPTH + 1];      /* sum of K * Omega over traced beams, watts */
+    int64_t segments;                    /* beam segments (traced guiding rays) */
+    int64_t node_visits;                 /* BVH interior nodes fetched */
+    int64_t tri_tests;                   /* ray/triangle tests */
+    int64_t mic_tests;                   /* (segment, microphone) candidates tested */
+    int64_t mic_updates;                 /* (segment, microphone) pairs accumulated */
+} bt_stats;
+
+/* Defaults: max_depth 3, t_min 1e-3, edge_delta 1e-5, air_m 0, e_min 0, no outputs. */
+void bt_params_default(bt_params *p);
+
+const char *bt_status_str(bt_status s);
+const char *bt_last_error(const bt_ctx *ctx);
+
+/* Context on HIP device `device`.  hip_stream: a hipStream_t to enqueue on (e.g. a
+ * torch stream's handle) or NULL for a library-owned stream.  hbm_budget_bytes caps
+ * the device memory the context allocates (0 = unlimited). */
+bt_status bt_create(int device, size_t hbm_budget_bytes, void *hip_stream, bt_ctx **out);
+bt_status bt_destroy(bt_ctx *ctx);
+/* Device bytes currently allocated through the context. */
+bt_status bt_memory_used(const bt_ctx *ctx, size_t *bytes);
+
+/* Triangulated model (paper Section 4: a detailed district model; Section 3: the
+ * model is split once and reused for many simulations).
+ *   xyz        host float[n_vert][3]
+ *   tri        host int32[n_tri][3], vertex indices
+ *   absorption host float[n_tri], energy fraction lost per reflection, in [0, 1]
+ *   tiles_x, tiles_y: on-device partition of the model's xy footprint into
+ *     sub-domains (1..64 each); each has its own hierarchy, and a guiding ray hands
+ *     over from one sub-domain to the next along its path.
+ * Validates indices, finite coordinates, absorption range and non-zero areas
+ * (BT_EINVAL), builds the hierarchy per sub-domain on the host and uploads it.
+ * n_tri may be 0 (free field). */
+bt_status bt_build_mesh(bt_ctx *ctx, const float *xyz, int64_t n_vert, const int32_t *tri,
+                        const float *absorption, int64_t n_tri, int32_t tiles_x, int32_t tiles_y,
+                        bt_mesh **out);
+bt_status bt_mesh_free(bt_mesh *mesh);
+/* Hierarchy facts: nodes, max depth, triangle references after duplication. */
+bt_status bt_mesh_info(const bt_mesh *mesh, int64_t *n_nodes, int32_t *max_depth, int64_t *n_tri_refs);
+
+/* Microphones on a regular planar grid (paper Section 4: microphones regularly
+ * distributed on a grid): positions (x0 + i dx, y0 + j dy, z), i < nx, j < ny,
+ * index j * nx + i.  Energies are owned by the set and start at zero. */
+bt_status bt_mics_grid(bt_ctx *ctx, float x0, float y0, float z, float dx, float dy, int32_t nx, int32_t ny,
+                       bt_mics **out);
+bt_status bt_mics_reset(bt_ctx *ctx, bt_mics *mics);   /* zero the energies (kernel, no memset) */
+bt_status bt_mics_free(bt_mics *mics);
+
+/* Generation-0 beams (paper Section 2: the source energy is split between beams
+ * according to its power in each direction): for each source and each face of the
+ * level-`level` icosphere, one frustum beam with apex at the source and intensity
+ * constant K = W / (4 pi).  src_xyz host float[n_src][3]; src_power host float[n_src].
+ * *inout: NULL to create a beam set, or an existing set to reuse (its capacity grows
+ * if needed).  Resets the set's statistics. */
+bt_status bt_emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_power, int32_t n_src,
+                        int32_t level, bt_beams **inout);
+bt_status bt_beams_free(bt_beams *beams);
+bt_status bt_beams_stats(bt_ctx *ctx, const bt_beams *beams, bt_stats *out);
+
+/* Trace the current generation: closest hit of every guiding ray (paper Section 2:
+ * intersections handled as in ray tracing, guiding ray only), hand-off between
+ * sub-domains, then reflection of hits with depth < max_depth into the next
+ * generation's queue (one child per hit, never split).  The traced segments stay
+ * readable by bt_accumulate_mics until the next bt_trace.  n_next: NULL (no
+ * synchronisation) or host int64 receiving the next generation's size (syncs).
+ * Returns BT_ESTATE once max_depth + 1 generations have been traced. */
+bt_status bt_trace(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *beams, const bt_params *params,
+                   int64_t *n_next);
+
+/* Add the contributions of the last traced segments to the microphones (paper
+ * Section 2: microphones sum the contributions reaching them).  A microphone inside
+ * a segment's frustum (three side planes, the reflecting plane as near cap, the hit
+ * plane as far cap) receives K exp(-air_m d) / d^2, d = distance to the beam's
+ * (image) apex.  Contributions of flagged segments, and memberships decided within
+ * edge_delta of a frustum plane, go to the set's flag energy, the others to its
+ * strict energy; both are FP64. */
+bt_status bt_accumulate_mics(bt_ctx *ctx, const bt_mesh *mesh, const bt_beams *beams,
+                             const bt_params *params, bt_mics *mics);
+
+/* Copy results to caller-owned host or device buffers (any may be NULL), then
+ * synchronise: strict_out / flag_out double[n_mic] energies (W/m^2), level_db_out
+ * double[n_mic] = 10 log10((strict + flag) / 1e-12), -inf where no energy arrived. */
+bt_status bt_levels(bt_ctx *ctx, const bt_mics *mics, double *strict_out, double *flag_out,
+                    double *level_db_out);
+
+/* Convenience: emit, then max_depth + 1 times (trace, accumulate).  Reuses *beams
+ * when non-NULL (created otherwise; caller frees).  Does not synchronise. */
+bt_status bt_run(bt_ctx *ctx, const bt_mesh *mesh, const float *src_xyz, const float *src_power,
+                 int32_t n_src, int32_t level, const bt_params *params, bt_mics *mics, bt_beams **beams);
+
+/* Request interface (paper Section 3: the model is prepared once for multiple
+ * simulations).  A request is a source set, an icosphere level, a depth and the
+ * microphone grid given at submission; its result is the grid's energies. */
+typedef struct {
+    const float *src_xyz;     /* host float[n_src][3] */
+    const float *src_power;   /* host float[n_src] */
+    int32_t n_src;
+    int32_t level;
+    int32_t max_depth;
+    float mic_x0, mic_y0, mic_z, mic_dx, mic_dy;
+    int32_t mic_nx, mic_ny;
+} bt_request;
+
+typedef struct {
+    double *energy;           /* caller-owned host double[mic_nx * mic_ny] (strict + flag) */
+    double *flag_energy;      /* caller-owned host double[...] or NULL */
+    int64_t segments;         /* filled on completion */
+    int64_t mic_updates;
+} bt_result;
+
+bt_status bt_submit(bt_ctx *ctx, const bt_mesh *mesh, const bt_request *req, uint64_t *ticket);
+bt_status bt_poll(bt_ctx *ctx, uint64_t ticket, bt_result *out);
+bt_status bt_cancel(bt_ctx *ctx, uint64_t ticket);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BT_H */

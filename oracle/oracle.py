@@ -26,6 +26,14 @@ DELTA = 1e-5
 T_MIN = 1e-3
 
 
+def default_threads() -> int:
+    """Worker threads: OMP_NUM_THREADS when set, else the CPU count capped at 16."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    return max(1, min(os.cpu_count() or 1, 16))
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C99, no fused multiply-add)."""
     os.makedirs(os.path.dirname(_LIB), exist_ok=True)
@@ -139,7 +147,7 @@ def trace(scene, *, level=None, depth=None, t_min=T_MIN, delta=DELTA, m_air=0.0,
     """Trace the whole scene (or the initial beams [beam_begin, beam_end)) in FP64."""
     level = scene.level if level is None else level
     depth = scene.depth if depth is None else depth
-    n_threads = n_threads or os.cpu_count() or 1
+    n_threads = n_threads or default_threads()
     nb = scene.n_src * 20 * 4 ** level
     keep = []
     sc = _scene_struct(scene, keep)

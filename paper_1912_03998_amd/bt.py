@@ -1,0 +1,254 @@
+"""Thin ctypes binding of libbt.so (include/bt.h), same names as the C ABI.
+
+Argument marshalling only: every step of the tracer runs in the library's kernels.
+PyTorch supplies device buffers (for the optional parity outputs) and the stream.
+The binding fails loudly when the library is missing or no GPU is visible; there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libbt.so")
+
+BT_OK, BT_PENDING = 0, 1
+BT_MAX_LEVEL, BT_MAX_DEPTH = 9, 31
+STATUS = {0: "BT_OK", 1: "BT_PENDING", -1: "BT_EINVAL", -2: "BT_ENOMEM", -3: "BT_EDEVICE",
+          -4: "BT_EOVERFLOW", -5: "BT_ENOTFOUND", -6: "BT_ESTATE"}
+
+EXPORTED = ["bt_params_default", "bt_status_str", "bt_last_error", "bt_create", "bt_destroy", "bt_memory_used",
+            "bt_build_mesh", "bt_mesh_free", "bt_mesh_info", "bt_mics_grid", "bt_mics_reset", "bt_mics_free",
+            "bt_emit_beams", "bt_beams_free", "bt_beams_stats", "bt_trace", "bt_accumulate_mics", "bt_levels",
+            "bt_run", "bt_submit", "bt_poll", "bt_cancel"]
+
+
+class BTError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class bt_params(C.Structure):
+    _fields_ = [("max_depth", C.c_int32), ("t_min", C.c_double), ("edge_delta", C.c_double),
+                ("air_m", C.c_double), ("e_min", C.c_double), ("hit_out", C.c_void_p),
+                ("flag_out", C.c_void_p), ("t_out", C.c_void_p)]
+
+
+class bt_stats(C.Structure):
+    _fields_ = [("generations", C.c_int32), ("count", C.c_int64 * (BT_MAX_DEPTH + 1)),
+                ("flagged", C.c_int64 * (BT_MAX_DEPTH + 1)), ("power", C.c_double * (BT_MAX_DEPTH + 1)),
+                ("segments", C.c_int64), ("node_visits", C.c_int64), ("tri_tests", C.c_int64),
+                ("mic_tests", C.c_int64), ("mic_updates", C.c_int64)]
+
+
+class bt_request(C.Structure):
+    _fields_ = [("src_xyz", C.c_void_p), ("src_power", C.c_void_p), ("n_src", C.c_int32), ("level", C.c_int32),
+                ("max_depth", C.c_int32), ("mic_x0", C.c_float), ("mic_y0", C.c_float), ("mic_z", C.c_float),
+                ("mic_dx", C.c_float), ("mic_dy", C.c_float), ("mic_nx", C.c_int32), ("mic_ny", C.c_int32)]
+
+
+class bt_result(C.Structure):
+    _fields_ = [("energy", C.c_void_p), ("flag_energy", C.c_void_p), ("segments", C.c_int64),
+                ("mic_updates", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libbt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1912_03998_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64, F32, D = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_double
+    sig = {
+        "bt_params_default": (None, [P]),
+        "bt_status_str": (C.c_char_p, [C.c_int]),
+        "bt_last_error": (C.c_char_p, [P]),
+        "bt_create": (C.c_int, [C.c_int, C.c_size_t, P, P]),
+        "bt_destroy": (C.c_int, [P]),
+        "bt_memory_used": (C.c_int, [P, P]),
+        "bt_build_mesh": (C.c_int, [P, P, I64, P, P, I64, I32, I32, P]),
+        "bt_mesh_free": (C.c_int, [P]),
+        "bt_mesh_info": (C.c_int, [P, P, P, P]),
+        "bt_mics_grid": (C.c_int, [P, F32, F32, F32, F32, F32, I32, I32, P]),
+        "bt_mics_reset": (C.c_int, [P, P]),
+        "bt_mics_free": (C.c_int, [P]),
+        "bt_emit_beams": (C.c_int, [P, P, P, I32, I32, P]),
+        "bt_beams_free": (C.c_int, [P]),
+        "bt_beams_stats": (C.c_int, [P, P, P]),
+        "bt_trace": (C.c_int, [P, P, P, P, P]),
+        "bt_accumulate_mics": (C.c_int, [P, P, P, P, P]),
+        "bt_levels": (C.c_int, [P, P, P, P, P]),
+        "bt_run": (C.c_int, [P, P, P, P, I32, I32, P, P, P]),
+        "bt_submit": (C.c_int, [P, P, P, P]),
+        "bt_poll": (C.c_int, [P, C.c_uint64, P]),
+        "bt_cancel": (C.c_int, [P, C.c_uint64]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def _check(ctx, status, what):
+    if status < 0:
+        msg = lib().bt_last_error(ctx).decode() if ctx else ""
+        raise BTError(status, f"{what}: {msg}")
+    return status
+
+
+# ---------------------------------------------------------------------------------------
+# one function per C entry point (ctypes handles are c_void_p values)
+# ---------------------------------------------------------------------------------------
+
+def bt_params_default(**kw) -> bt_params:
+    p = bt_params()
+    lib().bt_params_default(C.byref(p))
+    for k, v in kw.items():
+        if k in ("hit_out", "flag_out", "t_out"):
+            v = _ptr(v)
+        setattr(p, k, v)
+    return p
+
+
+def bt_create(device=0, hbm_budget_bytes=0, stream=None):
+    """stream: a torch.cuda.Stream (its HIP handle is passed), a raw handle, or None."""
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    out = C.c_void_p()
+    _check(None, lib().bt_create(device, hbm_budget_bytes, stream, C.byref(out)), "bt_create")
+    return out
+
+
+def bt_destroy(ctx):
+    _check(ctx, lib().bt_destroy(ctx), "bt_destroy")
+
+
+def bt_memory_used(ctx) -> int:
+    n = C.c_size_t()
+    _check(ctx, lib().bt_memory_used(ctx, C.byref(n)), "bt_memory_used")
+    return n.value
+
+
+def bt_build_mesh(ctx, xyz, tri, absorption, tiles_x=1, tiles_y=1):
+    xyz = np.ascontiguousarray(xyz, np.float32)
+    tri = np.ascontiguousarray(tri, np.int32)
+    absorption = np.ascontiguousarray(absorption, np.float32)
+    out = C.c_void_p()
+    _check(ctx, lib().bt_build_mesh(ctx, _ptr(xyz), xyz.shape[0], _ptr(tri), _ptr(absorption), tri.shape[0],
+                                    tiles_x, tiles_y, C.byref(out)), "bt_build_mesh")
+    return out
+
+
+def bt_mesh_free(mesh):
+    lib().bt_mesh_free(mesh)
+
+
+def bt_mesh_info(mesh):
+    n, d, r = C.c_int64(), C.c_int32(), C.c_int64()
+    _check(None, lib().bt_mesh_info(mesh, C.byref(n), C.byref(d), C.byref(r)), "bt_mesh_info")
+    return {"nodes": n.value, "max_depth": d.value, "tri_refs": r.value}
+
+
+def bt_mics_grid(ctx, x0, y0, z, dx, dy, nx, ny):
+    out = C.c_void_p()
+    _check(ctx, lib().bt_mics_grid(ctx, x0, y0, z, dx, dy, nx, ny, C.byref(out)), "bt_mics_grid")
+    return out
+
+
+def bt_mics_reset(ctx, mics):
+    _check(ctx, lib().bt_mics_reset(ctx, mics), "bt_mics_reset")
+
+
+def bt_mics_free(mics):
+    lib().bt_mics_free(mics)
+
+
+def bt_emit_beams(ctx, src_xyz, src_power, level, beams=None):
+    src_xyz = np.ascontiguousarray(src_xyz, np.float32).reshape(-1, 3)
+    src_power = np.ascontiguousarray(src_power, np.float32)
+    h = C.c_void_p(beams.value if beams is not None else None)
+    _check(ctx, lib().bt_emit_beams(ctx, _ptr(src_xyz), _ptr(src_power), src_xyz.shape[0], level, C.byref(h)),
+           "bt_emit_beams")
+    return h
+
+
+def bt_beams_free(beams):
+    lib().bt_beams_free(beams)
+
+
+def bt_beams_stats(ctx, beams) -> dict:
+    s = bt_stats()
+    _check(ctx, lib().bt_beams_stats(ctx, beams, C.byref(s)), "bt_beams_stats")
+    g = s.generations
+    return {"generations": g, "count": np.array(s.count[:g], np.int64), "flagged": np.array(s.flagged[:g], np.int64),
+            "power": np.array(s.power[:g], np.float64), "segments": s.segments, "node_visits": s.node_visits,
+            "tri_tests": s.tri_tests, "mic_tests": s.mic_tests, "mic_updates": s.mic_updates}
+
+
+def bt_trace(ctx, mesh, beams, params, want_next=False):
+    n = C.c_int64(-1)
+    _check(ctx, lib().bt_trace(ctx, mesh, beams, C.byref(params), C.byref(n) if want_next else None), "bt_trace")
+    return n.value if want_next else None
+
+
+def bt_accumulate_mics(ctx, mesh, beams, params, mics):
+    _check(ctx, lib().bt_accumulate_mics(ctx, mesh, beams, C.byref(params), mics), "bt_accumulate_mics")
+
+
+def bt_levels(ctx, mics, strict_out=None, flag_out=None, level_db_out=None):
+    """Outputs: numpy float64 arrays or torch float64 tensors (host or device)."""
+    _check(ctx, lib().bt_levels(ctx, mics, _ptr(strict_out), _ptr(flag_out), _ptr(level_db_out)), "bt_levels")
+
+
+def bt_run(ctx, mesh, src_xyz, src_power, level, params, mics, beams=None):
+    src_xyz = np.ascontiguousarray(src_xyz, np.float32).reshape(-1, 3)
+    src_power = np.ascontiguousarray(src_power, np.float32)
+    h = C.c_void_p(beams.value if beams is not None else None)
+    _check(ctx, lib().bt_run(ctx, mesh, _ptr(src_xyz), _ptr(src_power), src_xyz.shape[0], level, C.byref(params),
+                             mics, C.byref(h)), "bt_run")
+    return h
+
+
+def bt_submit(ctx, mesh, src_xyz, src_power, level, max_depth, grid):
+    """grid: (x0, y0, z, dx, dy, nx, ny).  Returns the ticket."""
+    src_xyz = np.ascontiguousarray(src_xyz, np.float32).reshape(-1, 3)
+    src_power = np.ascontiguousarray(src_power, np.float32)
+    x0, y0, z, dx, dy, nx, ny = grid
+    req = bt_request(_ptr(src_xyz), _ptr(src_power), src_xyz.shape[0], level, max_depth, x0, y0, z, dx, dy, nx, ny)
+    t = C.c_uint64()
+    _check(ctx, lib().bt_submit(ctx, mesh, C.byref(req), C.byref(t)), "bt_submit")
+    return t.value
+
+
+def bt_poll(ctx, ticket, n_mic):
+    """Returns None while pending, else (energy, flag_energy, segments, mic_updates)."""
+    e = np.empty(n_mic, np.float64)
+    f = np.empty(n_mic, np.float64)
+    r = bt_result(_ptr(e), _ptr(f), 0, 0)
+    s = _check(ctx, lib().bt_poll(ctx, ticket, C.byref(r)), "bt_poll")
+    if s == BT_PENDING:
+        return None
+    return e, f, r.segments, r.mic_updates
+
+
+def bt_cancel(ctx, ticket):
+    _check(ctx, lib().bt_cancel(ctx, ticket), "bt_cancel")

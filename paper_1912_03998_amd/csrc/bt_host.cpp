@@ -1,0 +1,944 @@
+// Host side of the C ABI declared in include/bt.h: contexts, validation, the per-tile
+// BVH build, queue management and kernel sequencing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "bt.h"
+#include "bt_internal.h"
+
+using namespace bt;
+
+struct bt_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t budget = 0;
+    size_t used = 0;
+    int n_cu = 256;
+    double *base20 = nullptr;  // device, 20 base faces x 9 doubles
+    std::string err;
+    std::mutex mtx;            // submit / poll / cancel
+    uint64_t next_ticket = 1;
+    std::map<uint64_t, struct Request *> requests;
+};
+
+struct bt_mesh {
+    bt_ctx *ctx = nullptr;
+    DevMesh dev{};
+    void *bufs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    size_t sizes[6] = {0, 0, 0, 0, 0, 0};
+    int64_t n_nodes = 0, n_refs = 0;
+    int32_t max_depth = 0;
+    double delta_cap = 0.0;   // largest edge_delta the box margins cover
+    double r_eff = 0.0;       // largest |coordinate| of a ray origin the margins cover
+};
+
+struct bt_mics {
+    bt_ctx *ctx = nullptr;
+    DevMics dev{};
+    double *level = nullptr;
+    size_t bytes = 0;
+};
+
+struct bt_beams {
+    bt_ctx *ctx = nullptr;
+    long long cap = 0;
+    DevQueue q[2]{};
+    DevSegs segs{};
+    DevCounters *ctr = nullptr;
+    int *big_list = nullptr;
+    float *src_dev = nullptr, *pow_dev = nullptr;
+    int src_cap = 0;
+    size_t bytes = 0;
+    int gen = 0;              // generations traced
+    int max_depth = -1;       // fixed by the first trace
+    long long n0 = 0;
+    double r_src = 0.0;
+};
+
+struct Request {
+    bt_request req{};
+    std::vector<float> src, pw;
+    bt_mics *mics = nullptr;
+    bt_beams *beams = nullptr;
+    hipEvent_t done = nullptr;
+};
+
+// ---------------------------------------------------------------------------------------
+// errors and memory
+// ---------------------------------------------------------------------------------------
+static bt_status fail(bt_ctx *ctx, bt_status s, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return s;
+}
+
+static bt_status hip_fail(bt_ctx *ctx, hipError_t e, const char *what)
+{
+    return fail(ctx, BT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                                  \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+static bt_status dev_alloc(bt_ctx *ctx, void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (ctx->budget && ctx->used + bytes > ctx->budget)
+        return fail(ctx, BT_ENOMEM, "HBM budget exceeded: %zu + %zu > %zu bytes", ctx->used, bytes, ctx->budget);
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, BT_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    ctx->used += bytes;
+    return BT_OK;
+}
+
+static void dev_free(bt_ctx *ctx, void *p, size_t bytes)
+{
+    if (!p) return;
+    (void)hipFree(p);
+    if (bytes == 0) bytes = 256;
+    if (ctx) ctx->used -= std::min(ctx->used, bytes);
+}
+
+// ---------------------------------------------------------------------------------------
+// misc API
+// ---------------------------------------------------------------------------------------
+extern "C" void bt_params_default(bt_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->max_depth = 3;
+    p->t_min = 1e-3;
+    p->edge_delta = 1e-5;
+    p->air_m = 0.0;
+    p->e_min = 0.0;
+}
+
+extern "C" const char *bt_status_str(bt_status s)
+{
+    switch (s) {
+    case BT_OK: return "ok";
+    case BT_PENDING: return "pending";
+    case BT_EINVAL: return "invalid argument";
+    case BT_ENOMEM: return "out of memory / budget";
+    case BT_EDEVICE: return "device error";
+    case BT_EOVERFLOW: return "internal capacity exceeded";
+    case BT_ENOTFOUND: return "not found";
+    case BT_ESTATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *bt_last_error(const bt_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+// The 20 base faces of the icosahedron used for beam directions: vertices are the cyclic
+// permutations (0,a,b), (a,b,0), (b,0,a) of (0, +-1, +-phi) listed by permutation, then
+// a, then b; faces are the vertex triples at mutual distance 2 in lexicographic order,
+// oriented outward (det > 0) by swapping their last two vertices when needed.
+static void icosahedron_faces(double out[20 * 9])
+{
+    const double phi = (1.0 + std::sqrt(5.0)) / 2.0;
+    double raw[12][3], u[12][3];
+    int nv = 0;
+    for (int perm = 0; perm < 3; ++perm)
+        for (double a : {-1.0, 1.0})
+            for (double b : {-phi, phi}) {
+                double x = perm == 0 ? 0.0 : (perm == 1 ? a : b);
+                double y = perm == 0 ? a : (perm == 1 ? b : 0.0);
+                double z = perm == 0 ? b : (perm == 1 ? 0.0 : a);
+                raw[nv][0] = x; raw[nv][1] = y; raw[nv][2] = z;
+                double n = std::sqrt(x * x + y * y + z * z);
+                u[nv][0] = x / n; u[nv][1] = y / n; u[nv][2] = z / n;
+                nv++;
+            }
+    auto d2 = [&](int i, int j) {
+        double dx = raw[i][0] - raw[j][0], dy = raw[i][1] - raw[j][1], dz = raw[i][2] - raw[j][2];
+        return dx * dx + dy * dy + dz * dz;
+    };
+    int nf = 0;
+    for (int i = 0; i < 12; ++i)
+        for (int j = i + 1; j < 12; ++j)
+            for (int k = j + 1; k < 12; ++k) {
+                if (std::fabs(d2(i, j) - 4.0) > 1e-9 || std::fabs(d2(j, k) - 4.0) > 1e-9 ||
+                    std::fabs(d2(k, i) - 4.0) > 1e-9)
+                    continue;
+                const double *A = u[i], *B = u[j], *C = u[k];
+                double det = A[0] * (B[1] * C[2] - B[2] * C[1]) + A[1] * (B[2] * C[0] - B[0] * C[2]) +
+                             A[2] * (B[0] * C[1] - B[1] * C[0]);
+                const double *f[3] = {A, det < 0.0 ? C : B, det < 0.0 ? B : C};
+                for (int v = 0; v < 3; ++v)
+                    for (int c = 0; c < 3; ++c) out[9 * nf + 3 * v + c] = f[v][c];
+                nf++;
+            }
+}
+
+extern "C" bt_status bt_create(int device, size_t hbm_budget_bytes, void *hip_stream, bt_ctx **out)
+{
+    if (!out) return BT_EINVAL;
+    *out = nullptr;
+    int n_dev = 0;
+    if (hipGetDeviceCount(&n_dev) != hipSuccess || device < 0 || device >= n_dev) {
+        (void)hipGetLastError();
+        return BT_EINVAL;
+    }
+    bt_ctx *ctx = new bt_ctx();
+    ctx->device = device;
+    ctx->budget = hbm_budget_bytes;
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) { delete ctx; return BT_EDEVICE; }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+        ctx->n_cu = ncu;
+    if (hip_stream) {
+        ctx->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) { delete ctx; return BT_EDEVICE; }
+        ctx->own_stream = true;
+    }
+    double base[20 * 9];
+    icosahedron_faces(base);
+    if (dev_alloc(ctx, (void **)&ctx->base20, sizeof base) != BT_OK ||
+        hipMemcpy(ctx->base20, base, sizeof base, hipMemcpyHostToDevice) != hipSuccess) {
+        bt_destroy(ctx);
+        return BT_EDEVICE;
+    }
+    *out = ctx;
+    return BT_OK;
+}
+
+extern "C" bt_status bt_destroy(bt_ctx *ctx)
+{
+    if (!ctx) return BT_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (auto &kv : ctx->requests) {
+        Request *r = kv.second;
+        if (r->done) (void)hipEventDestroy(r->done);
+        bt_mics_free(r->mics);
+        bt_beams_free(r->beams);
+        delete r;
+    }
+    dev_free(ctx, ctx->base20, 20 * 9 * sizeof(double));
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return BT_OK;
+}
+
+extern "C" bt_status bt_memory_used(const bt_ctx *ctx, size_t *bytes)
+{
+    if (!ctx || !bytes) return BT_EINVAL;
+    *bytes = ctx->used;
+    return BT_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// BVH build (host): binned SAH over triangle boxes, 32 bins per axis, leaves of up to 4
+// triangles (7 when forced), flattened so each interior node holds both child boxes.
+// ---------------------------------------------------------------------------------------
+namespace {
+
+struct Box {
+    float lo[3], hi[3];
+    void empty()
+    {
+        for (int k = 0; k < 3; ++k) { lo[k] = INFINITY; hi[k] = -INFINITY; }
+    }
+    void grow(const Box &b)
+    {
+        for (int k = 0; k < 3; ++k) { lo[k] = std::min(lo[k], b.lo[k]); hi[k] = std::max(hi[k], b.hi[k]); }
+    }
+    double area() const
+    {
+        double d[3];
+        for (int k = 0; k < 3; ++k) d[k] = std::max(0.0, (double)hi[k] - (double)lo[k]);
+        return 2.0 * (d[0] * d[1] + d[1] * d[2] + d[2] * d[0]);
+    }
+};
+
+struct Prim {
+    Box box;     // already grown by the margin
+    float cen[3];
+    int id;
+};
+
+struct Builder {
+    std::vector<Prim> &prims;
+    std::vector<float4> &nodes;   // 4 float4 per interior node
+    std::vector<float4> &tris;    // 3 float4 per triangle reference
+    const std::vector<float4> &tri_rec;  // per global triangle, 3 float4
+    int max_depth = 0;
+    bool overflow = false;
+
+    static int leaf_ref(int first, int count) { return ~((first << 3) | count); }
+
+    int make_leaf(int b, int e)
+    {
+        int first = (int)(tris.size() / 3);
+        for (int i = b; i < e; ++i) {
+            const float4 *t = &tri_rec[3 * (size_t)prims[i].id];
+            tris.push_back(t[0]);
+            tris.push_back(t[1]);
+            tris.push_back(t[2]);
+        }
+        return leaf_ref(first, e - b);
+    }
+
+    Box range_box(int b, int e) const
+    {
+        Box bx;
+        bx.empty();
+        for (int i = b; i < e; ++i) bx.grow(prims[i].box);
+        return bx;
+    }
+
+    // Returns the child reference of the subtree over prims[b, e).
+    int build(int b, int e, int depth)
+    {
+        max_depth = std::max(max_depth, depth);
+        int n = e - b;
+        if (n <= 4) return make_leaf(b, e);
+        if (depth >= kStack - 1) {
+            if (n <= 7) return make_leaf(b, e);
+            overflow = true;
+            return make_leaf(b, b + 1);
+        }
+        float clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int i = b; i < e; ++i)
+            for (int k = 0; k < 3; ++k) { clo[k] = std::min(clo[k], prims[i].cen[k]); chi[k] = std::max(chi[k], prims[i].cen[k]); }
+        enum { NB = 32 };
+        double best = INFINITY;
+        int best_axis = -1, best_bin = -1;
+        for (int ax = 0; ax < 3; ++ax) {
+            double ext = (double)chi[ax] - (double)clo[ax];
+            if (!(ext > 0.0)) continue;
+            Box bb[NB];
+            int cnt[NB] = {0};
+            for (int i = 0; i < NB; ++i) bb[i].empty();
+            for (int i = b; i < e; ++i) {
+                int k = (int)(((double)prims[i].cen[ax] - clo[ax]) / ext * NB);
+                k = std::min(std::max(k, 0), NB - 1);
+                cnt[k]++;
+                bb[k].grow(prims[i].box);
+            }
+            double rarea[NB];
+            int rcnt[NB];
+            Box acc;
+            acc.empty();
+            int c = 0;
+            for (int i = NB - 1; i >= 1; --i) {
+                acc.grow(bb[i]);
+                c += cnt[i];
+                rarea[i] = acc.area();
+                rcnt[i] = c;
+            }
+            acc.empty();
+            c = 0;
+            for (int i = 0; i < NB - 1; ++i) {
+                acc.grow(bb[i]);
+                c += cnt[i];
+                if (c == 0 || rcnt[i + 1] == 0) continue;
+                double cost = acc.area() * c + rarea[i + 1] * rcnt[i + 1];
+                if (cost < best) { best = cost; best_axis = ax; best_bin = i + 1; }
+            }
+        }
+        int mid;
+        if (best_axis < 0) {
+            mid = b + n / 2;
+        } else {
+            Box all = range_box(b, e);
+            double leaf_cost = all.area() * n;
+            if (n <= 7 && best >= leaf_cost) return make_leaf(b, e);
+            double ext = (double)chi[best_axis] - (double)clo[best_axis];
+            auto it = std::partition(prims.begin() + b, prims.begin() + e, [&](const Prim &p) {
+                int k = (int)(((double)p.cen[best_axis] - clo[best_axis]) / ext * NB);
+                k = std::min(std::max(k, 0), NB - 1);
+                return k < best_bin;
+            });
+            mid = (int)(it - prims.begin());
+            if (mid == b || mid == e) mid = b + n / 2;
+        }
+        int idx = (int)(nodes.size() / 4);
+        nodes.resize(nodes.size() + 4);
+        Box lb = range_box(b, mid), rb = range_box(mid, e);
+        int l = build(b, mid, depth + 1);
+        int r = build(mid, e, depth + 1);
+        float4 *nd = &nodes[4 * (size_t)idx];
+        nd[0] = make_float4(lb.lo[0], rb.lo[0], lb.hi[0], rb.hi[0]);
+        nd[1] = make_float4(lb.lo[1], rb.lo[1], lb.hi[1], rb.hi[1]);
+        nd[2] = make_float4(lb.lo[2], rb.lo[2], lb.hi[2], rb.hi[2]);
+        float fl, fr;
+        std::memcpy(&fl, &l, 4);
+        std::memcpy(&fr, &r, 4);
+        nd[3] = make_float4(fl, fr, 0.f, 0.f);
+        return idx;
+    }
+};
+
+float round_down_f(double x)
+{
+    float f = (float)x;
+    if ((double)f > x) f = std::nextafter(f, -INFINITY);
+    return f;
+}
+float round_up_f(double x)
+{
+    float f = (float)x;
+    if ((double)f < x) f = std::nextafter(f, INFINITY);
+    return f;
+}
+
+}  // namespace
+
+extern "C" bt_status bt_build_mesh(bt_ctx *ctx, const float *xyz, int64_t n_vert, const int32_t *tri,
+                                   const float *absorption, int64_t n_tri, int32_t tiles_x, int32_t tiles_y,
+                                   bt_mesh **out)
+{
+    if (!ctx) return BT_EINVAL;
+    if (!out) return fail(ctx, BT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_vert < 0 || n_tri < 0 || n_tri > (1ll << 27))
+        return fail(ctx, BT_EINVAL, "bad sizes n_vert=%lld n_tri=%lld", (long long)n_vert, (long long)n_tri);
+    if (n_tri > 0 && (!xyz || !tri || !absorption)) return fail(ctx, BT_EINVAL, "NULL mesh array");
+    if (tiles_x < 1 || tiles_y < 1 || tiles_x > 64 || tiles_y > 64)
+        return fail(ctx, BT_EINVAL, "tiles must be in 1..64 (got %d x %d)", tiles_x, tiles_y);
+    (void)hipSetDevice(ctx->device);
+
+    // validation and per-triangle records
+    const double delta_cap = 1e-3;
+    double r_mesh = 0.0;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t t = 0; t < n_tri; ++t) {
+        for (int k = 0; k < 3; ++k) {
+            int32_t v = tri[3 * t + k];
+            if (v < 0 || v >= n_vert) return fail(ctx, BT_EINVAL, "triangle %lld has vertex index %d out of range", (long long)t, v);
+            for (int c = 0; c < 3; ++c) {
+                float x = xyz[3 * (int64_t)v + c];
+                if (!std::isfinite(x)) return fail(ctx, BT_EINVAL, "vertex %d is not finite", v);
+                r_mesh = std::max(r_mesh, (double)std::fabs(x));
+                lo[c] = std::min(lo[c], (double)x);
+                hi[c] = std::max(hi[c], (double)x);
+            }
+        }
+        float a = absorption[t];
+        if (!(a >= 0.0f && a <= 1.0f)) return fail(ctx, BT_EINVAL, "absorption of triangle %lld not in [0, 1]", (long long)t);
+    }
+    const double r_eff = 2.0 * r_mesh + 10.0;
+    const double margin = delta_cap + 12.0 * r_eff * std::ldexp(1.0, -24);
+
+    std::vector<float> tri_g((size_t)n_tri * 9);
+    std::vector<float4> tri_rec((size_t)n_tri * 3);
+    std::vector<Prim> all((size_t)n_tri);
+    for (int64_t t = 0; t < n_tri; ++t) {
+        double v[3][3];
+        for (int k = 0; k < 3; ++k)
+            for (int c = 0; c < 3; ++c) {
+                float x = xyz[3 * (int64_t)tri[3 * t + k] + c];
+                tri_g[9 * t + 3 * k + c] = x;
+                v[k][c] = x;
+            }
+        double e1[3], e2[3], e3[3], N[3];
+        for (int c = 0; c < 3; ++c) { e1[c] = v[1][c] - v[0][c]; e2[c] = v[2][c] - v[0][c]; e3[c] = v[2][c] - v[1][c]; }
+        N[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        N[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        N[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        double a2 = std::sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+        if (!(a2 > 0.0)) return fail(ctx, BT_EINVAL, "triangle %lld has zero area", (long long)t);
+        double l1 = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+        double l2 = std::sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+        double l3 = std::sqrt(e3[0] * e3[0] + e3[1] * e3[1] + e3[2] * e3[2]);
+        double hmin = a2 / std::max(l1, std::max(l2, l3)) * (1.0 - 1e-12);
+        float idf;
+        int idi = (int)t;
+        std::memcpy(&idf, &idi, 4);
+        tri_rec[3 * t + 0] = make_float4((float)v[0][0], (float)v[0][1], (float)v[0][2], (float)v[1][0]);
+        tri_rec[3 * t + 1] = make_float4((float)v[1][1], (float)v[1][2], (float)v[2][0], (float)v[2][1]);
+        tri_rec[3 * t + 2] = make_float4((float)v[2][2], idf, round_down_f(hmin), 0.f);
+        Prim &p = all[t];
+        p.id = (int)t;
+        for (int c = 0; c < 3; ++c) {
+            double mn = std::min(v[0][c], std::min(v[1][c], v[2][c]));
+            double mx = std::max(v[0][c], std::max(v[1][c], v[2][c]));
+            p.box.lo[c] = round_down_f(mn - margin);
+            p.box.hi[c] = round_up_f(mx + margin);
+            p.cen[c] = (float)(0.5 * (mn + mx));
+        }
+    }
+
+    // tile grid over the (grown) xy footprint
+    DevMesh dm{};
+    dm.tiles_x = tiles_x;
+    dm.tiles_y = tiles_y;
+    dm.n_tri = (int)n_tri;
+    if (n_tri > 0) {
+        dm.gx0 = lo[0] - margin; dm.gx1 = hi[0] + margin;
+        dm.gy0 = lo[1] - margin; dm.gy1 = hi[1] + margin;
+        dm.zmin = lo[2] - margin; dm.zmax = hi[2] + margin;
+    } else {
+        dm.gx0 = 0.0; dm.gx1 = 1.0; dm.gy0 = 0.0; dm.gy1 = 1.0; dm.zmin = 1.0; dm.zmax = -1.0;
+    }
+    dm.tw = (dm.gx1 - dm.gx0) / tiles_x;
+    dm.th = (dm.gy1 - dm.gy0) / tiles_y;
+
+    std::vector<float4> nodes, trefs;
+    std::vector<int> roots((size_t)tiles_x * tiles_y, kEmptyRoot);
+    std::vector<float> tboxes((size_t)tiles_x * tiles_y * 6, 0.f);
+    int max_depth = 0;
+    bool overflow = false;
+    for (int ty = 0; ty < tiles_y; ++ty)
+        for (int tx = 0; tx < tiles_x; ++tx) {
+            double x0 = dm.gx0 + tx * dm.tw, x1 = dm.gx0 + (tx + 1) * dm.tw;
+            double y0 = dm.gy0 + ty * dm.th, y1 = dm.gy0 + (ty + 1) * dm.th;
+            if (tx == tiles_x - 1) x1 = dm.gx1;
+            if (ty == tiles_y - 1) y1 = dm.gy1;
+            std::vector<Prim> prims;
+            for (const Prim &p : all)
+                if ((double)p.box.lo[0] <= x1 + margin && (double)p.box.hi[0] >= x0 - margin &&
+                    (double)p.box.lo[1] <= y1 + margin && (double)p.box.hi[1] >= y0 - margin)
+                    prims.push_back(p);
+            int tile = ty * tiles_x + tx;
+            if (prims.empty()) continue;
+            Builder b{prims, nodes, trefs, tri_rec};
+            roots[tile] = b.build(0, (int)prims.size(), 0);
+            max_depth = std::max(max_depth, b.max_depth);
+            overflow = overflow || b.overflow;
+            Box rb;
+            rb.empty();
+            for (const Prim &p : prims) rb.grow(p.box);
+            for (int c = 0; c < 3; ++c) { tboxes[6 * tile + c] = rb.lo[c]; tboxes[6 * tile + 3 + c] = rb.hi[c]; }
+        }
+    if (overflow) return fail(ctx, BT_EOVERFLOW, "BVH deeper than the %d-entry traversal stack", kStack);
+    if (trefs.size() / 3 >= (1u << 28)) return fail(ctx, BT_EOVERFLOW, "too many triangle references");
+
+    bt_mesh *m = new bt_mesh();
+    m->ctx = ctx;
+    m->n_nodes = (int64_t)(nodes.size() / 4);
+    m->n_refs = (int64_t)(trefs.size() / 3);
+    m->max_depth = max_depth;
+    m->delta_cap = delta_cap;
+    m->r_eff = r_eff;
+    const void *src[6] = {nodes.data(), trefs.data(), tri_g.data(), absorption, roots.data(), tboxes.data()};
+    size_t sz[6] = {nodes.size() * sizeof(float4), trefs.size() * sizeof(float4), tri_g.size() * sizeof(float),
+                    (size_t)n_tri * sizeof(float), roots.size() * sizeof(int), tboxes.size() * sizeof(float)};
+    for (int i = 0; i < 6; ++i) {
+        bt_status s = dev_alloc(ctx, &m->bufs[i], sz[i]);
+        if (s != BT_OK) { bt_mesh_free(m); return s; }
+        m->sizes[i] = sz[i];
+        if (sz[i] && hipMemcpy(m->bufs[i], src[i], sz[i], hipMemcpyHostToDevice) != hipSuccess) {
+            bt_mesh_free(m);
+            return fail(ctx, BT_EDEVICE, "mesh upload failed");
+        }
+    }
+    dm.nodes = (const float4 *)m->bufs[0];
+    dm.tris = (const float4 *)m->bufs[1];
+    dm.tri_g = (const float *)m->bufs[2];
+    dm.alpha = (const float *)m->bufs[3];
+    dm.tile_root = (const int *)m->bufs[4];
+    dm.tile_box = (const float *)m->bufs[5];
+    m->dev = dm;
+    *out = m;
+    return BT_OK;
+}
+
+extern "C" bt_status bt_mesh_free(bt_mesh *m)
+{
+    if (!m) return BT_EINVAL;
+    for (int i = 0; i < 6; ++i) dev_free(m->ctx, m->bufs[i], m->sizes[i]);
+    delete m;
+    return BT_OK;
+}
+
+extern "C" bt_status bt_mesh_info(const bt_mesh *m, int64_t *n_nodes, int32_t *max_depth, int64_t *n_tri_refs)
+{
+    if (!m) return BT_EINVAL;
+    if (n_nodes) *n_nodes = m->n_nodes;
+    if (max_depth) *max_depth = m->max_depth;
+    if (n_tri_refs) *n_tri_refs = m->n_refs;
+    return BT_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// microphones
+// ---------------------------------------------------------------------------------------
+extern "C" bt_status bt_mics_grid(bt_ctx *ctx, float x0, float y0, float z, float dx, float dy, int32_t nx, int32_t ny,
+                                  bt_mics **out)
+{
+    if (!ctx) return BT_EINVAL;
+    if (!out) return fail(ctx, BT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || (int64_t)nx * ny > (1ll << 31))
+        return fail(ctx, BT_EINVAL, "bad microphone grid %d x %d", nx, ny);
+    if (!std::isfinite(x0) || !std::isfinite(y0) || !std::isfinite(z) || !(dx > 0.f) || !(dy > 0.f) ||
+        !std::isfinite(dx) || !std::isfinite(dy))
+        return fail(ctx, BT_EINVAL, "bad microphone grid geometry");
+    (void)hipSetDevice(ctx->device);
+    bt_mics *m = new bt_mics();
+    m->ctx = ctx;
+    long long n = (long long)nx * ny;
+    m->bytes = (size_t)n * sizeof(double) * 3;
+    void *p = nullptr;
+    bt_status s = dev_alloc(ctx, &p, m->bytes);
+    if (s != BT_OK) { delete m; return s; }
+    m->dev.x0 = x0; m->dev.y0 = y0; m->dev.z = z; m->dev.dx = dx; m->dev.dy = dy;
+    m->dev.nx = nx; m->dev.ny = ny;
+    m->dev.e_strict = (double *)p;
+    m->dev.e_flag = m->dev.e_strict + n;
+    m->level = m->dev.e_flag + n;
+    s = bt_mics_reset(ctx, m);
+    if (s != BT_OK) { bt_mics_free(m); return s; }
+    *out = m;
+    return BT_OK;
+}
+
+extern "C" bt_status bt_mics_reset(bt_ctx *ctx, bt_mics *m)
+{
+    if (!ctx || !m) return BT_EINVAL;
+    long long n = (long long)m->dev.nx * m->dev.ny;
+    HIP_TRY(ctx, launch_fill(m->dev.e_strict, 2 * n, 0.0, ctx->stream));
+    return BT_OK;
+}
+
+extern "C" bt_status bt_mics_free(bt_mics *m)
+{
+    if (!m) return BT_EINVAL;
+    dev_free(m->ctx, m->dev.e_strict, m->bytes);
+    delete m;
+    return BT_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// beams
+// ---------------------------------------------------------------------------------------
+static void beams_release(bt_beams *b)
+{
+    bt_ctx *ctx = b->ctx;
+    for (int k = 0; k < 2; ++k) {
+        dev_free(ctx, b->q[k].dbl, (size_t)b->cap * D_N * sizeof(double));
+        dev_free(ctx, b->q[k].flt, (size_t)b->cap * F_N * sizeof(float));
+        dev_free(ctx, b->q[k].ints, (size_t)b->cap * I_N * sizeof(int));
+        b->q[k] = DevQueue{};
+    }
+    dev_free(ctx, b->segs.hit, (size_t)b->cap * sizeof(int));
+    dev_free(ctx, b->segs.t, (size_t)b->cap * sizeof(double));
+    dev_free(ctx, b->segs.flag, (size_t)b->cap * sizeof(int));
+    b->segs = DevSegs{};
+    dev_free(ctx, b->big_list, (size_t)b->cap * sizeof(int));
+    b->big_list = nullptr;
+    b->cap = 0;
+}
+
+static bt_status beams_reserve(bt_ctx *ctx, bt_beams *b, long long n)
+{
+    if (n <= b->cap) return BT_OK;
+    beams_release(b);
+    bt_status s;
+    for (int k = 0; k < 2; ++k) {
+        if ((s = dev_alloc(ctx, (void **)&b->q[k].dbl, (size_t)n * D_N * sizeof(double))) != BT_OK) return s;
+        if ((s = dev_alloc(ctx, (void **)&b->q[k].flt, (size_t)n * F_N * sizeof(float))) != BT_OK) return s;
+        if ((s = dev_alloc(ctx, (void **)&b->q[k].ints, (size_t)n * I_N * sizeof(int))) != BT_OK) return s;
+        b->q[k].cap = n;
+    }
+    if ((s = dev_alloc(ctx, (void **)&b->segs.hit, (size_t)n * sizeof(int))) != BT_OK) return s;
+    if ((s = dev_alloc(ctx, (void **)&b->segs.t, (size_t)n * sizeof(double))) != BT_OK) return s;
+    if ((s = dev_alloc(ctx, (void **)&b->segs.flag, (size_t)n * sizeof(int))) != BT_OK) return s;
+    if ((s = dev_alloc(ctx, (void **)&b->big_list, (size_t)n * sizeof(int))) != BT_OK) return s;
+    b->cap = n;
+    return BT_OK;
+}
+
+extern "C" bt_status bt_emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_power, int32_t n_src,
+                                   int32_t level, bt_beams **inout)
+{
+    if (!ctx) return BT_EINVAL;
+    if (!inout) return fail(ctx, BT_EINVAL, "inout is NULL");
+    if (n_src < 0 || (n_src > 0 && (!src_xyz || !src_power))) return fail(ctx, BT_EINVAL, "bad sources");
+    if (level < 0 || level > BT_MAX_LEVEL) return fail(ctx, BT_EINVAL, "level %d not in 0..%d", level, BT_MAX_LEVEL);
+    long long nf = 20ll << (2 * level);
+    long long n0 = nf * n_src;
+    if (n0 > (1ll << 31) - 1) return fail(ctx, BT_EINVAL, "too many beams (%lld)", n0);
+    double r_src = 0.0;
+    for (int i = 0; i < n_src; ++i) {
+        for (int c = 0; c < 3; ++c) {
+            if (!std::isfinite(src_xyz[3 * i + c])) return fail(ctx, BT_EINVAL, "source %d not finite", i);
+            r_src = std::max(r_src, (double)std::fabs(src_xyz[3 * i + c]));
+        }
+        if (!(src_power[i] >= 0.f) || !std::isfinite(src_power[i])) return fail(ctx, BT_EINVAL, "source %d power invalid", i);
+    }
+    (void)hipSetDevice(ctx->device);
+    bt_beams *b = *inout;
+    bool fresh = false;
+    if (!b) {
+        b = new bt_beams();
+        b->ctx = ctx;
+        fresh = true;
+        bt_status s = dev_alloc(ctx, (void **)&b->ctr, sizeof(DevCounters));
+        if (s != BT_OK) { delete b; return s; }
+    }
+    bt_status s = beams_reserve(ctx, b, std::max(n0, 1ll));
+    if (s == BT_OK && n_src > b->src_cap) {
+        dev_free(ctx, b->src_dev, (size_t)b->src_cap * 3 * sizeof(float));
+        dev_free(ctx, b->pow_dev, (size_t)b->src_cap * sizeof(float));
+        b->src_dev = b->pow_dev = nullptr;
+        b->src_cap = 0;
+        s = dev_alloc(ctx, (void **)&b->src_dev, (size_t)n_src * 3 * sizeof(float));
+        if (s == BT_OK) s = dev_alloc(ctx, (void **)&b->pow_dev, (size_t)n_src * sizeof(float));
+        if (s == BT_OK) b->src_cap = n_src;
+    }
+    if (s != BT_OK) {
+        if (fresh) bt_beams_free(b);
+        return s;
+    }
+    if (n_src > 0) {
+        HIP_TRY(ctx, hipMemcpyAsync(b->src_dev, src_xyz, (size_t)n_src * 3 * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(b->pow_dev, src_power, (size_t)n_src * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+    }
+    HIP_TRY(ctx, launch_init_counters(b->ctr, n0, ctx->stream));
+    HIP_TRY(ctx, launch_emit(ctx->base20, b->src_dev, b->pow_dev, n_src, level, b->q[0], ctx->stream));
+    // host inputs are borrowed for the call only
+    if (n_src > 0) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    b->gen = 0;
+    b->max_depth = -1;
+    b->n0 = n0;
+    b->r_src = r_src;
+    *inout = b;
+    return BT_OK;
+}
+
+extern "C" bt_status bt_beams_free(bt_beams *b)
+{
+    if (!b) return BT_EINVAL;
+    beams_release(b);
+    dev_free(b->ctx, b->ctr, sizeof(DevCounters));
+    dev_free(b->ctx, b->src_dev, (size_t)b->src_cap * 3 * sizeof(float));
+    dev_free(b->ctx, b->pow_dev, (size_t)b->src_cap * sizeof(float));
+    delete b;
+    return BT_OK;
+}
+
+extern "C" bt_status bt_beams_stats(bt_ctx *ctx, const bt_beams *b, bt_stats *out)
+{
+    if (!ctx || !b || !out) return BT_EINVAL;
+    DevCounters h;
+    HIP_TRY(ctx, hipMemcpyAsync(&h, b->ctr, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    std::memset(out, 0, sizeof *out);
+    out->generations = b->gen;
+    for (int g = 0; g <= BT_MAX_DEPTH; ++g) {
+        if (g < b->gen) {
+            out->count[g] = (int64_t)h.count[g];
+            out->flagged[g] = (int64_t)h.flagged[g];
+            out->power[g] = h.power[g];
+            out->segments += (int64_t)h.count[g];
+        }
+    }
+    out->node_visits = (int64_t)h.node_visits;
+    out->tri_tests = (int64_t)h.tri_tests;
+    out->mic_tests = (int64_t)h.mic_tests;
+    out->mic_updates = (int64_t)h.mic_updates;
+    return BT_OK;
+}
+
+static bt_status check_params(bt_ctx *ctx, const bt_mesh *mesh, const bt_params *p)
+{
+    if (!p) return fail(ctx, BT_EINVAL, "params is NULL");
+    if (p->max_depth < 0 || p->max_depth > BT_MAX_DEPTH) return fail(ctx, BT_EINVAL, "max_depth %d not in 0..%d", p->max_depth, BT_MAX_DEPTH);
+    if (!(p->t_min >= 0.0) || !std::isfinite(p->t_min)) return fail(ctx, BT_EINVAL, "t_min invalid");
+    if (!(p->edge_delta >= 0.0) || !(p->edge_delta <= mesh->delta_cap))
+        return fail(ctx, BT_EINVAL, "edge_delta must be in [0, %g]", mesh->delta_cap);
+    if (!(p->air_m >= 0.0) || !std::isfinite(p->air_m)) return fail(ctx, BT_EINVAL, "air_m invalid");
+    if (!(p->e_min >= 0.0)) return fail(ctx, BT_EINVAL, "e_min invalid");
+    return BT_OK;
+}
+
+static TraceArgs make_args(const bt_params *p, int gen)
+{
+    TraceArgs a{};
+    a.gen = gen;
+    a.max_depth = p->max_depth;
+    a.t_min = p->t_min;
+    a.delta = p->edge_delta;
+    a.air_m = p->air_m;
+    a.e_min = p->e_min;
+    a.hit_out = p->hit_out;
+    a.flag_out = p->flag_out;
+    a.t_out = p->t_out;
+    return a;
+}
+
+extern "C" bt_status bt_trace(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *b, const bt_params *p, int64_t *n_next)
+{
+    if (!ctx) return BT_EINVAL;
+    if (!mesh || !b) return fail(ctx, BT_EINVAL, "NULL mesh or beams");
+    bt_status s = check_params(ctx, mesh, p);
+    if (s != BT_OK) return s;
+    if (b->max_depth >= 0 && b->max_depth != p->max_depth)
+        return fail(ctx, BT_EINVAL, "max_depth changed between generations (%d -> %d)", b->max_depth, p->max_depth);
+    if (b->gen > p->max_depth) return fail(ctx, BT_ESTATE, "all %d generations already traced", p->max_depth + 1);
+    if (b->r_src > mesh->r_eff) return fail(ctx, BT_EINVAL, "a source lies outside the region the mesh margins cover (|x| <= %g)", mesh->r_eff);
+    (void)hipSetDevice(ctx->device);
+    b->max_depth = p->max_depth;
+    int g = b->gen;
+    TraceArgs a = make_args(p, g);
+    HIP_TRY(ctx, launch_trace(mesh->dev, b->q[g & 1], b->q[(g + 1) & 1], b->segs, b->ctr, a, ctx->n_cu, ctx->stream));
+    b->gen = g + 1;
+    if (n_next) {
+        unsigned long long c = 0;
+        HIP_TRY(ctx, hipMemcpyAsync(&c, &b->ctr->count[g + 1], sizeof c, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        *n_next = (int64_t)c;
+    }
+    return BT_OK;
+}
+
+extern "C" bt_status bt_accumulate_mics(bt_ctx *ctx, const bt_mesh *mesh, const bt_beams *b, const bt_params *p,
+                                        bt_mics *mics)
+{
+    if (!ctx) return BT_EINVAL;
+    if (!mesh || !b || !mics) return fail(ctx, BT_EINVAL, "NULL mesh, beams or mics");
+    bt_status s = check_params(ctx, mesh, p);
+    if (s != BT_OK) return s;
+    if (b->gen == 0) return fail(ctx, BT_ESTATE, "no generation traced yet");
+    (void)hipSetDevice(ctx->device);
+    int g = b->gen - 1;
+    TraceArgs a = make_args(p, g);
+    HIP_TRY(ctx, launch_mics(mesh->dev, b->q[g & 1], b->segs, b->ctr, mics->dev, a, b->big_list, ctx->n_cu, ctx->stream));
+    return BT_OK;
+}
+
+extern "C" bt_status bt_levels(bt_ctx *ctx, const bt_mics *m, double *strict_out, double *flag_out, double *level_db_out)
+{
+    if (!ctx || !m) return BT_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    long long n = (long long)m->dev.nx * m->dev.ny;
+    size_t bytes = (size_t)n * sizeof(double);
+    if (level_db_out) {
+        HIP_TRY(ctx, launch_levels(m->dev.e_strict, m->dev.e_flag, m->level, n, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(level_db_out, m->level, bytes, hipMemcpyDefault, ctx->stream));
+    }
+    if (strict_out) HIP_TRY(ctx, hipMemcpyAsync(strict_out, m->dev.e_strict, bytes, hipMemcpyDefault, ctx->stream));
+    if (flag_out) HIP_TRY(ctx, hipMemcpyAsync(flag_out, m->dev.e_flag, bytes, hipMemcpyDefault, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return BT_OK;
+}
+
+extern "C" bt_status bt_run(bt_ctx *ctx, const bt_mesh *mesh, const float *src_xyz, const float *src_power,
+                            int32_t n_src, int32_t level, const bt_params *p, bt_mics *mics, bt_beams **beams)
+{
+    if (!ctx) return BT_EINVAL;
+    if (!mesh || !mics || !beams) return fail(ctx, BT_EINVAL, "NULL mesh, mics or beams");
+    bt_status s = check_params(ctx, mesh, p);
+    if (s != BT_OK) return s;
+    s = bt_emit_beams(ctx, src_xyz, src_power, n_src, level, beams);
+    if (s != BT_OK) return s;
+    for (int g = 0; g <= p->max_depth; ++g) {
+        if ((s = bt_trace(ctx, mesh, *beams, p, nullptr)) != BT_OK) return s;
+        if ((s = bt_accumulate_mics(ctx, mesh, *beams, p, mics)) != BT_OK) return s;
+    }
+    return BT_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// request interface: each submission is enqueued on the context stream at once (one
+// request per launch sequence); bt_poll reports completion through an event.
+// ---------------------------------------------------------------------------------------
+extern "C" bt_status bt_submit(bt_ctx *ctx, const bt_mesh *mesh, const bt_request *req, uint64_t *ticket)
+{
+    if (!ctx) return BT_EINVAL;
+    if (!mesh || !req || !ticket) return fail(ctx, BT_EINVAL, "NULL mesh, request or ticket");
+    std::lock_guard<std::mutex> lk(ctx->mtx);
+    if (req->n_src < 0 || (req->n_src > 0 && (!req->src_xyz || !req->src_power)))
+        return fail(ctx, BT_EINVAL, "bad request sources");
+    bt_params p;
+    bt_params_default(&p);
+    p.max_depth = req->max_depth;
+    bt_status s = check_params(ctx, mesh, &p);
+    if (s != BT_OK) return s;
+    Request *r = new Request();
+    r->req = *req;
+    r->src.assign(req->src_xyz, req->src_xyz + 3 * (size_t)req->n_src);
+    r->pw.assign(req->src_power, req->src_power + (size_t)req->n_src);
+    s = bt_mics_grid(ctx, req->mic_x0, req->mic_y0, req->mic_z, req->mic_dx, req->mic_dy, req->mic_nx, req->mic_ny,
+                     &r->mics);
+    if (s == BT_OK) s = bt_run(ctx, mesh, r->src.data(), r->pw.data(), req->n_src, req->level, &p, r->mics, &r->beams);
+    if (s == BT_OK && hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess) s = BT_EDEVICE;
+    if (s == BT_OK && hipEventRecord(r->done, ctx->stream) != hipSuccess) s = BT_EDEVICE;
+    if (s != BT_OK) {
+        if (r->done) (void)hipEventDestroy(r->done);
+        if (r->mics) bt_mics_free(r->mics);
+        if (r->beams) bt_beams_free(r->beams);
+        delete r;
+        return s;
+    }
+    *ticket = ctx->next_ticket++;
+    ctx->requests[*ticket] = r;
+    return BT_OK;
+}
+
+extern "C" bt_status bt_poll(bt_ctx *ctx, uint64_t ticket, bt_result *out)
+{
+    if (!ctx) return BT_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mtx);
+    auto it = ctx->requests.find(ticket);
+    if (it == ctx->requests.end()) return fail(ctx, BT_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    Request *r = it->second;
+    hipError_t q = hipEventQuery(r->done);
+    if (q == hipErrorNotReady) return BT_PENDING;
+    if (q != hipSuccess) return hip_fail(ctx, q, "hipEventQuery");
+    if (!out) return fail(ctx, BT_EINVAL, "out is NULL");
+    long long n = (long long)r->req.mic_nx * r->req.mic_ny;
+    std::vector<double> es((size_t)n), ef((size_t)n);
+    bt_status s = bt_levels(ctx, r->mics, es.data(), ef.data(), nullptr);
+    if (s != BT_OK) return s;
+    bt_stats st;
+    if ((s = bt_beams_stats(ctx, r->beams, &st)) != BT_OK) return s;
+    if (out->energy)
+        for (long long i = 0; i < n; ++i) out->energy[i] = es[i] + ef[i];
+    if (out->flag_energy) std::memcpy(out->flag_energy, ef.data(), (size_t)n * sizeof(double));
+    out->segments = st.segments;
+    out->mic_updates = st.mic_updates;
+    (void)hipEventDestroy(r->done);
+    bt_mics_free(r->mics);
+    bt_beams_free(r->beams);
+    delete r;
+    ctx->requests.erase(it);
+    return BT_OK;
+}
+
+extern "C" bt_status bt_cancel(bt_ctx *ctx, uint64_t ticket)
+{
+    if (!ctx) return BT_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mtx);
+    auto it = ctx->requests.find(ticket);
+    if (it == ctx->requests.end()) return fail(ctx, BT_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    Request *r = it->second;
+    (void)hipEventSynchronize(r->done);  // device work cannot be withdrawn once enqueued
+    (void)hipEventDestroy(r->done);
+    bt_mics_free(r->mics);
+    bt_beams_free(r->beams);
+    delete r;
+    ctx->requests.erase(it);
+    return BT_OK;
+}
