@@ -1,0 +1,186 @@
+#!/usr/bin/env python
+"""Throughput of the hybrid beam tracer on one MI355X: beam segments/s and microphone
+updates/s on the synthetic 2 x 2 km district (331,815 triangles, 64 sources x 81,920
+beams, depth 8, 250,000 microphones, 4 x 4 on-device tiles).
+
+A step is one pass of the whole hot path over the workload: emission, then for every
+generation the trace (closest hit, tile hand-off, reflection + compaction) and the
+microphone accumulation, then the levels.  The mesh and its hierarchy are built once
+before timing (reported separately as setup).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1912_03998_amd", "csrc", "bt_kernels.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "trace_pmc_district.txt")
+REF_WORK = os.path.join(ROOT, "oracle", "reference_work.json")
+
+# algorithmic bytes (canonical record sizes): a beam record 80 B read, a child record
+# 80 B written, an 8 B hit record, 64 B per hierarchy node fetched, 36 B per triangle
+# tested, 16 B (FP64 read + write) per microphone update
+B_BEAM, B_CHILD, B_HIT, B_NODE, B_TRI, B_MIC = 80, 80, 8, 64, 36, 16
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def pmc_traffic(n_launch_units):
+    """HBM bytes per trace launch from the committed rocprofv3 --pmc summary, or None
+    when the summary is missing or the kernel source changed since it was taken."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    text = open(PMC_SUMMARY).read()
+    m = re.search(r"kernel_sha256_16:\s*([0-9a-f]+)", text)
+    b = re.search(r"hbm_bytes_per_step:\s*([0-9.eE+]+)", text)
+    if not m or not b or m.group(1) != kernel_hash():
+        return None
+    return float(b.group(1)) / n_launch_units
+
+
+def cpu_baseline(scene):
+    """The FP64 oracle on the host cores over the whole workload (it finishes in seconds)."""
+    from oracle import oracle as O
+
+    threads = O.default_threads()
+    t0 = time.perf_counter()
+    r = O.trace(scene, keep_paths=False, n_threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": r.counters["segments"] / dt, "unit": "beam-segments/s", "cores": threads, "kind": "oracle",
+            "sample": f"whole workload ({r.counters['segments']} segments, {r.counters['mic_updates']} mic updates) "
+                      f"in {dt:.2f} s", "mic_updates_per_s": r.counters["mic_updates"] / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2, help="0 tiny, 1 block, 2 district (default)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the tracer runs on one device)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1912_03998_amd import bt
+    from paper_1912_03998_amd.tracer import Session, scene_grid
+    from scenegen import config_scene
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    scene = config_scene(args.config)
+    print(f"[bench] {scene.name}: {scene.n_tri} triangles, {scene.n_beams0} beams, depth {scene.depth}, "
+          f"{scene.n_mic} mics, tiles {scene.tiles_x}x{scene.tiles_y}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    sess = Session.from_scene(scene)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    ctx, mesh, stream = sess.ctx, sess.mesh, sess.stream
+    grid = scene_grid(scene)
+    mics = sess._mics(grid)
+    params = sess.params(scene.depth)
+    D = scene.depth
+    with torch.cuda.stream(stream):
+        level_out = torch.empty(scene.n_mic, dtype=torch.float64, device="cuda")
+    src = np.ascontiguousarray(scene.sources, np.float32)
+    pw = np.ascontiguousarray(scene.power, np.float32)
+
+    def step(ev=None):
+        sess.beams = bt.bt_emit_beams(ctx, src, pw, scene.level, sess.beams)
+        bt.bt_mics_reset(ctx, mics)
+        for g in range(D + 1):
+            if ev is not None:
+                ev[g][0].record(stream)
+            bt.bt_trace(ctx, mesh, sess.beams, params)
+            if ev is not None:
+                ev[g][1].record(stream)
+            bt.bt_accumulate_mics(ctx, mesh, sess.beams, params, mics)
+            if ev is not None:
+                ev[g][2].record(stream)
+        bt.bt_levels(ctx, mics, None, None, level_out)
+
+    for _ in range(args.warmup):
+        step()
+    events = [[[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(D + 1)]
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = bt.bt_beams_stats(ctx, sess.beams)
+    trace_ms = sum(events[k][g][0].elapsed_time(events[k][g][1]) for k in range(args.steps) for g in range(D + 1))
+    mic_ms = sum(events[k][g][1].elapsed_time(events[k][g][2]) for k in range(args.steps) for g in range(D + 1))
+    trace_ms /= args.steps
+    mic_ms /= args.steps
+    ms_per_step = elapsed * 1000.0 / args.steps
+    segs, upd = st["segments"], st["mic_updates"]
+
+    # algorithmic bytes of the trace kernel, fixed by the oracle's reference traversal
+    ref = json.load(open(REF_WORK)).get(scene.name) if os.path.exists(REF_WORK) else None
+    roofline = None
+    if ref is not None:
+        trace_bytes = (B_BEAM + B_HIT) * ref["segments"] + B_CHILD * ref["children"] + \
+            B_NODE * ref["node_visits"] + B_TRI * ref["tri_tests"]
+        mic_bytes = B_MIC * ref["mic_updates"]
+        dominant = "k_trace" if trace_ms >= mic_ms else "k_mics"
+        t_dom = trace_ms if dominant == "k_trace" else mic_ms
+        b_dom = trace_bytes if dominant == "k_trace" else mic_bytes
+        achieved = b_dom / (t_dom * 1e-3) / 1e9
+        traffic = pmc_traffic(D + 1) if dominant == "k_trace" else None
+        roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "algorithmic_bytes_per_step": b_dom, "launches_per_step": D + 1,
+                    "kernel_ms_per_step": round(t_dom, 3)}
+    gpu_bytes = (B_BEAM + B_HIT) * segs + B_NODE * st["node_visits"] + B_TRI * st["tri_tests"]
+
+    out = {
+        "metric": "beam-segments/s + mic updates/s on district mesh",
+        "value": segs * args.steps / elapsed,
+        "unit": "beam-segments/s",
+        "mic_updates_per_s": upd * args.steps / elapsed,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 rays / f32 geometry",
+        "data": "synthetic",
+        "config": {"workload": f"{scene.name}: {scene.n_tri} triangles, {scene.n_src} sources x "
+                               f"{20 * 4 ** scene.level} beams (icosphere level {scene.level}), depth {scene.depth}, "
+                               f"{scene.n_mic} microphones, {scene.tiles_x}x{scene.tiles_y} tiles",
+                   "segments_per_step": segs, "mic_updates_per_step": upd,
+                   "generation_counts": st["count"].tolist(),
+                   "flagged_per_generation": st["flagged"].tolist()},
+        "roofline": roofline,
+        "kernel_ms_per_step": {"trace": round(trace_ms, 3), "mics": round(mic_ms, 3)},
+        "gpu_hierarchy_bytes_per_s": gpu_bytes / (trace_ms * 1e-3) if trace_ms > 0 else None,
+        "gpu_node_visits_per_segment": st["node_visits"] / max(segs, 1),
+        "gpu_tri_tests_per_segment": st["tri_tests"] / max(segs, 1),
+        "setup_s": round(setup_s, 3),
+        "end_to_end_segments_per_s": segs / (setup_s + ms_per_step * 1e-3),
+        "kernel_sha256_16": kernel_hash(),
+    }
+    sess.close()
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(scene)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

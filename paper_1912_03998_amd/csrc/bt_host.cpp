@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -56,6 +57,8 @@ struct bt_beams {
     DevSegs segs{};
     DevCounters *ctr = nullptr;
     int *big_list = nullptr;
+    int2 *rows = nullptr;
+    long long rows_cap = 0;
     float *src_dev = nullptr, *pow_dev = nullptr;
     int src_cap = 0;
     size_t bytes = 0;
@@ -647,6 +650,9 @@ static void beams_release(bt_beams *b)
     b->segs = DevSegs{};
     dev_free(ctx, b->big_list, (size_t)b->cap * sizeof(int));
     b->big_list = nullptr;
+    dev_free(ctx, b->rows, (size_t)b->rows_cap * sizeof(int2));
+    b->rows = nullptr;
+    b->rows_cap = 0;
     b->cap = 0;
 }
 
@@ -665,6 +671,15 @@ static bt_status beams_reserve(bt_ctx *ctx, bt_beams *b, long long n)
     if ((s = dev_alloc(ctx, (void **)&b->segs.t, (size_t)n * sizeof(double))) != BT_OK) return s;
     if ((s = dev_alloc(ctx, (void **)&b->segs.flag, (size_t)n * sizeof(int))) != BT_OK) return s;
     if ((s = dev_alloc(ctx, (void **)&b->big_list, (size_t)n * sizeof(int))) != BT_OK) return s;
+    // row work items of wide microphone footprints: 2 per beam covers the district workload
+    // with room to spare; overflow falls back to one wave per segment
+    long long rows_cap = std::max(2 * n, 1ll << 20);
+    if (const char *env = std::getenv("BT_MIC_ROW_CAPACITY")) {  // testing the overflow path
+        long long v = std::atoll(env);
+        if (v > 0) rows_cap = v;
+    }
+    if ((s = dev_alloc(ctx, (void **)&b->rows, (size_t)rows_cap * sizeof(int2))) != BT_OK) return s;
+    b->rows_cap = rows_cap;
     b->cap = n;
     return BT_OK;
 }
@@ -824,7 +839,8 @@ extern "C" bt_status bt_accumulate_mics(bt_ctx *ctx, const bt_mesh *mesh, const 
     (void)hipSetDevice(ctx->device);
     int g = b->gen - 1;
     TraceArgs a = make_args(p, g);
-    HIP_TRY(ctx, launch_mics(mesh->dev, b->q[g & 1], b->segs, b->ctr, mics->dev, a, b->big_list, ctx->n_cu, ctx->stream));
+    MicWork w{b->rows, b->rows_cap, b->big_list};
+    HIP_TRY(ctx, launch_mics(mesh->dev, b->q[g & 1], b->segs, b->ctr, mics->dev, a, w, ctx->n_cu, ctx->stream));
     return BT_OK;
 }
 

@@ -78,7 +78,9 @@ struct DevCounters {
     unsigned long long work_trace[BT_MAX_DEPTH + 2]; // wave work-grab cursors
     unsigned long long work_mic[BT_MAX_DEPTH + 2];
     unsigned long long work_big[BT_MAX_DEPTH + 2];
-    unsigned long long n_big[BT_MAX_DEPTH + 2];      // segments deferred to the wide path
+    unsigned long long n_big[BT_MAX_DEPTH + 2];      // segments for the wave-per-segment fallback
+    unsigned long long n_rows[BT_MAX_DEPTH + 2];     // (segment, row) work items requested
+    unsigned long long work_rows[BT_MAX_DEPTH + 2];
     unsigned long long node_visits, tri_tests, mic_tests, mic_updates;
 };
 
@@ -87,6 +89,14 @@ struct DevMics {
     int nx, ny;
     double *e_strict;          // [nx*ny]
     double *e_flag;            // [nx*ny]
+};
+
+// Work buffers of the microphone stage: (segment, row) items of wide footprints and the
+// overflow list of segments handled one wave each.
+struct MicWork {
+    int2 *rows;
+    long long rows_cap;
+    int *big_list;     // capacity: the queue capacity
 };
 
 struct TraceArgs {
@@ -105,7 +115,7 @@ hipError_t launch_emit(const double *base20, const float *src, const float *powe
 hipError_t launch_trace(const DevMesh &m, DevQueue in, DevQueue out, DevSegs segs, DevCounters *ctr,
                         const TraceArgs &a, int n_cu, hipStream_t s);
 hipError_t launch_mics(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mics,
-                       const TraceArgs &a, int *big_list, int n_cu, hipStream_t s);
+                       const TraceArgs &a, MicWork w, int n_cu, hipStream_t s);
 hipError_t launch_fill(double *p, long long n, double v, hipStream_t s);
 hipError_t launch_levels(const double *es, const double *ef, double *level, long long n, hipStream_t s);
 

@@ -540,16 +540,27 @@ hipError_t launch_trace(const DevMesh &m, DevQueue in, DevQueue out, DevSegs seg
 
 // ---------------------------------------------------------------------------------------
 // Microphones
+//
+// A segment's frustum meets the microphone plane z = zm in a convex polygon: three side
+// half-planes through the (image) apex, the reflecting plane (outgoing side, strict) and
+// the hit plane (incoming side, closed).  The kernels first bound the polygon's rows,
+// then enumerate candidate microphones row by row (one column of slack on each side)
+// and decide membership with the exact plane tests.
+//   k_mics:      one lane per segment; footprints of <= kInlineRows rows are finished
+//                in place, wider ones are split into (segment, row) work items
+//   k_mic_rows:  one lane per (segment, row) work item
+//   k_mics_big:  one wave per segment, for segments whose rows did not fit the item
+//                buffer (overflow fallback)
 // ---------------------------------------------------------------------------------------
 struct Frustum {
     V3 A;
     V3 n[3];
-    double inv_len[3];
+    double amb2[3];     // delta^2 |n_k|^2: |s| < delta |n| <=> s^2 < amb2
     bool has_near, has_far;
     V3 Nn, Pn;
-    double near_sign, inv_near;
+    double near_sign, amb2_near;
     V3 Nf, Pf;
-    double far_sign, inv_far;
+    double far_sign, amb2_far;
     float K;
     int flag;
 };
@@ -565,23 +576,27 @@ __device__ __forceinline__ bool lex_positive(V3 n)
     return n.z > 0.0;
 }
 
+// Keep-side half-plane g . (p - P) >= 0 on z = zm, relaxed by eps * |g|_1 (>= eps |g|).
 __device__ __forceinline__ HalfPlane make_hp(V3 g, V3 P, double z, double eps)
 {
     HalfPlane h;
     h.a = g.x;
     h.b = g.y;
-    h.k = g.z * (z - P.z) - g.x * P.x - g.y * P.y + eps * sqrt(dot(g, g));
+    h.k = g.z * (z - P.z) - g.x * P.x - g.y * P.y + eps * (fabs(g.x) + fabs(g.y) + fabs(g.z));
     return h;
 }
 
-__device__ void load_frustum(const DevMesh &M, const DevQueue &q, const DevSegs &segs, long long i, Frustum &f)
+__device__ void load_frustum(const DevMesh &M, const DevQueue &q, const DevSegs &segs, long long i, double delta,
+                             Frustum &f)
 {
     const long long cap = q.cap;
+    const double d2 = delta * delta;
     f.A = ld3(q.dbl + D_A * cap, cap, i);
     V3 d[3] = {ld3(q.dbl + D_D0 * cap, cap, i), ld3(q.dbl + D_D1 * cap, cap, i), ld3(q.dbl + D_D2 * cap, cap, i)};
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
         f.n[k] = cross(d[k], d[(k + 1) % 3]);
-        f.inv_len[k] = 1.0 / sqrt(dot(f.n[k], f.n[k]));
+        f.amb2[k] = d2 * dot(f.n[k], f.n[k]);
     }
     int meta = q.ints[I_META * cap + i];
     int start = q.ints[I_START * cap + i];
@@ -595,7 +610,7 @@ __device__ void load_frustum(const DevMesh &M, const DevQueue &q, const DevSegs 
         f.Nn = cross(v1 - v0, v2 - v0);
         f.Pn = v0;
         f.near_sign = (meta & kMetaNegNear) ? -1.0 : 1.0;
-        f.inv_near = 1.0 / sqrt(dot(f.Nn, f.Nn));
+        f.amb2_near = d2 * dot(f.Nn, f.Nn);
     }
     f.has_far = hit >= 0;
     if (f.has_far) {
@@ -605,222 +620,278 @@ __device__ void load_frustum(const DevMesh &M, const DevQueue &q, const DevSegs 
         f.Pf = v0;
         V3 c = ld3(q.dbl + D_C * cap, cap, i);
         f.far_sign = dot(c, f.Nf) > 0.0 ? 1.0 : -1.0;
-        f.inv_far = 1.0 / sqrt(dot(f.Nf, f.Nf));
+        f.amb2_far = d2 * dot(f.Nf, f.Nf);
     }
 }
 
-// Half-planes of the frustum on the microphone plane, relaxed by eps metres.
-__device__ int frustum_halfplanes(const Frustum &f, double z, HalfPlane *hp)
+// The frustum's half-planes plus the grid rectangle (grown by half a cell) as 9 lines;
+// unused slots are the always-true constraint 0 x + 0 y + 1 >= 0.
+__device__ __forceinline__ void footprint_lines(const Frustum &f, const DevMics &mc, HalfPlane *L)
 {
     const double eps = 1e-6;
-    int nh = 0;
-    for (int k = 0; k < 3; ++k) hp[nh++] = make_hp(f.n[k], f.A, z, eps);
-    if (f.has_near) hp[nh++] = make_hp(f.near_sign * f.Nn, f.Pn, z, eps);
-    if (f.has_far) hp[nh++] = make_hp((-f.far_sign) * f.Nf, f.Pf, z, eps);
-    return nh;
-}
-
-// Row range of the clipped footprint polygon (Sutherland-Hodgman on the grid rectangle).
-__device__ bool footprint_rows(const HalfPlane *hp, int nh, const DevMics &mc, int &j0, int &j1)
-{
-    double px[12], py[12], qx[12], qy[12];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) L[k] = make_hp(f.n[k], f.A, mc.z, eps);
+    L[3] = f.has_near ? make_hp(f.near_sign * f.Nn, f.Pn, mc.z, eps) : HalfPlane{0.0, 0.0, 1.0};
+    L[4] = f.has_far ? make_hp((-f.far_sign) * f.Nf, f.Pf, mc.z, eps) : HalfPlane{0.0, 0.0, 1.0};
     double xlo = mc.x0 - 0.5 * mc.dx, xhi = mc.x0 + ((double)mc.nx - 0.5) * mc.dx;
     double ylo = mc.y0 - 0.5 * mc.dy, yhi = mc.y0 + ((double)mc.ny - 0.5) * mc.dy;
-    px[0] = xlo; py[0] = ylo;
-    px[1] = xhi; py[1] = ylo;
-    px[2] = xhi; py[2] = yhi;
-    px[3] = xlo; py[3] = yhi;
-    int n = 4;
-    for (int h = 0; h < nh && n > 0; ++h) {
-        int m = 0;
-        for (int i = 0; i < n; ++i) {
-            int j = i + 1 == n ? 0 : i + 1;
-            double fi = hp[h].a * px[i] + hp[h].b * py[i] + hp[h].k;
-            double fj = hp[h].a * px[j] + hp[h].b * py[j] + hp[h].k;
-            if (fi >= 0.0 && m < 12) { qx[m] = px[i]; qy[m] = py[i]; m++; }
-            if ((fi >= 0.0) != (fj >= 0.0) && m < 12) {
-                double u = fi / (fi - fj);
-                qx[m] = px[i] + u * (px[j] - px[i]);
-                qy[m] = py[i] + u * (py[j] - py[i]);
-                m++;
+    L[5] = HalfPlane{1.0, 0.0, -xlo};
+    L[6] = HalfPlane{-1.0, 0.0, xhi};
+    L[7] = HalfPlane{0.0, 1.0, -ylo};
+    L[8] = HalfPlane{0.0, -1.0, yhi};
+}
+
+// Row range of the footprint polygon: every constraint line is clipped by all the
+// others (parametrically, comparing fractions without dividing); the endpoints of the
+// surviving edges bound the polygon's y-extent.  One row of slack on each side.
+__device__ bool footprint_rows(const HalfPlane *L, const DevMics &mc, int &j0, int &j1)
+{
+    double ymn = INFINITY, ymx = -INFINITY;
+#pragma unroll
+    for (int h = 0; h < 9; ++h) {
+        const double a = L[h].a, b = L[h].b, k = L[h].k;
+        const double nn = a * a + b * b;
+        if (nn == 0.0) continue;
+        const double px = -k * a / nn, py = -k * b / nn;  // point on the line
+        const double dx = -b, dy = a;                     // direction along it
+        // t >= lo_n / lo_d and t <= hi_n / hi_d with positive denominators
+        double lo_n = -1.0, lo_d = 0.0, hi_n = 1.0, hi_d = 0.0;  // -inf, +inf
+        bool empty = false;
+#pragma unroll
+        for (int g = 0; g < 9; ++g) {
+            if (g == h) continue;
+            const double den = L[g].a * dx + L[g].b * dy;
+            const double num = -(L[g].a * px + L[g].b * py + L[g].k);  // need den * t >= num
+            if (den > 0.0) {
+                if (lo_d == 0.0 || num * lo_d > lo_n * den) { lo_n = num; lo_d = den; }
+            } else if (den < 0.0) {
+                if (hi_d == 0.0 || (-num) * hi_d < hi_n * (-den)) { hi_n = -num; hi_d = -den; }
+            } else if (num > 0.0) {
+                empty = true;
             }
         }
-        n = m;
-        for (int i = 0; i < n; ++i) { px[i] = qx[i]; py[i] = qy[i]; }
+        if (empty || lo_d == 0.0 || hi_d == 0.0) continue;  // (bounded by the rectangle otherwise)
+        const double tlo = lo_n / lo_d, thi = hi_n / hi_d;
+        if (!(tlo <= thi)) continue;
+        const double y0 = py + tlo * dy, y1 = py + thi * dy;
+        ymn = fmin(ymn, fmin(y0, y1));
+        ymx = fmax(ymx, fmax(y0, y1));
     }
-    if (n == 0) return false;
-    double ymn = py[0], ymx = py[0];
-    for (int i = 1; i < n; ++i) { ymn = fmin(ymn, py[i]); ymx = fmax(ymx, py[i]); }
+    if (!(ymn <= ymx)) return false;
     double fj0 = ceil((ymn - mc.y0) / mc.dy) - 1.0, fj1 = floor((ymx - mc.y0) / mc.dy) + 1.0;
     fj0 = fmax(fj0, 0.0);
     fj1 = fmin(fj1, (double)(mc.ny - 1));
-    if (fj0 > fj1) return false;
+    if (!(fj0 <= fj1)) return false;
     j0 = (int)fj0;
     j1 = (int)fj1;
     return true;
 }
 
-// Column range of row j inside the relaxed half-planes (with one column of slack).
-__device__ __forceinline__ bool row_cols(const HalfPlane *hp, int nh, const DevMics &mc, int j, int &i0, int &i1)
+// Column range of row j inside the relaxed frustum half-planes (one column of slack).
+__device__ __forceinline__ bool row_cols(const HalfPlane *L, const DevMics &mc, int j, int &i0, int &i1)
 {
-    double y = mc.y0 + (double)j * mc.dy;
+    const double y = mc.y0 + (double)j * mc.dy;
     double lo = -INFINITY, hi = INFINITY;
-    for (int h = 0; h < nh; ++h) {
-        double rest = hp[h].b * y + hp[h].k;
-        if (hp[h].a > 0.0) lo = fmax(lo, -rest / hp[h].a);
-        else if (hp[h].a < 0.0) hi = fmin(hi, -rest / hp[h].a);
+#pragma unroll
+    for (int h = 0; h < 5; ++h) {
+        const double rest = L[h].b * y + L[h].k;
+        if (L[h].a > 0.0) lo = fmax(lo, -rest / L[h].a);
+        else if (L[h].a < 0.0) hi = fmin(hi, -rest / L[h].a);
         else if (rest < 0.0) return false;
     }
-    if (lo > hi) return false;
-    double flo = (lo - mc.x0) / mc.dx, fhi = (hi - mc.x0) / mc.dx;
+    if (!(lo <= hi)) return false;
+    const double flo = (lo - mc.x0) / mc.dx, fhi = (hi - mc.x0) / mc.dx;
     if (flo > (double)mc.nx || fhi < -1.0) return false;
-    double a0 = fmax(ceil(flo) - 1.0, 0.0), a1 = fmin(floor(fhi) + 1.0, (double)(mc.nx - 1));
-    if (a0 > a1) return false;
+    const double a0 = fmax(ceil(flo) - 1.0, 0.0), a1 = fmin(floor(fhi) + 1.0, (double)(mc.nx - 1));
+    if (!(a0 <= a1)) return false;
     i0 = (int)a0;
     i1 = (int)a1;
     return true;
 }
 
 // Membership of grid microphone (i, j) and its contribution; returns 1 if accumulated.
-__device__ __forceinline__ int mic_apply(const Frustum &f, const DevMics &mc, int i, int j, double delta,
-                                         double air_m)
+// Ambiguous: every active test passes within -delta and one is within delta of its plane.
+__device__ __forceinline__ int mic_apply(const Frustum &f, const DevMics &mc, int i, int j, double air_m)
 {
-    V3 m = {mc.x0 + (double)i * mc.dx, mc.y0 + (double)j * mc.dy, mc.z};
-    V3 r = m - f.A;
+    const V3 m = {mc.x0 + (double)i * mc.dx, mc.y0 + (double)j * mc.dy, mc.z};
+    const V3 r = m - f.A;
     bool inside = true, far_out = false, near_any = false;
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-        double s = dot(f.n[k], r);
-        bool in = s > 0.0 || (s == 0.0 && lex_positive(f.n[k]));
-        inside = inside && in;
-        double dist = s * f.inv_len[k];
-        far_out = far_out || dist <= -delta;
-        near_any = near_any || fabs(dist) < delta;
+        const double s = dot(f.n[k], r);
+        inside = inside && (s > 0.0 || (s == 0.0 && lex_positive(f.n[k])));
+        const double s2 = s * s;
+        far_out = far_out || (s < 0.0 && s2 >= f.amb2[k]);
+        near_any = near_any || s2 < f.amb2[k];
     }
     if (f.has_near) {
-        double sn = f.near_sign * dot(f.Nn, m - f.Pn);
-        inside = inside && sn > 0.0;
-        double dist = sn * f.inv_near;
-        far_out = far_out || dist <= -delta;
-        near_any = near_any || fabs(dist) < delta;
+        const double s = f.near_sign * dot(f.Nn, m - f.Pn);
+        inside = inside && s > 0.0;
+        const double s2 = s * s;
+        far_out = far_out || (s < 0.0 && s2 >= f.amb2_near);
+        near_any = near_any || s2 < f.amb2_near;
     }
     if (f.has_far) {
-        double sf = -f.far_sign * dot(f.Nf, m - f.Pf);
-        inside = inside && sf >= 0.0;
-        double dist = sf * f.inv_far;
-        far_out = far_out || dist <= -delta;
-        near_any = near_any || fabs(dist) < delta;
+        const double s = -f.far_sign * dot(f.Nf, m - f.Pf);
+        inside = inside && s >= 0.0;
+        const double s2 = s * s;
+        far_out = far_out || (s < 0.0 && s2 >= f.amb2_far);
+        near_any = near_any || s2 < f.amb2_far;
     }
     if (!inside) return 0;
-    double d2 = dot(r, r);
+    const double d2 = dot(r, r);
     float e = f.K / (float)d2;
     if (air_m > 0.0) e *= expf(-(float)(air_m * sqrt(d2)));
-    bool amb = !far_out && near_any;
-    long long idx = (long long)j * mc.nx + i;
+    const bool amb = !far_out && near_any;
+    const long long idx = (long long)j * mc.nx + i;
     atomicAdd((f.flag || amb) ? &mc.e_flag[idx] : &mc.e_strict[idx], (double)e);
     return 1;
 }
 
 constexpr int kInlineRows = 4;
-constexpr int kInlineCells = 64;
+
+__device__ __forceinline__ void flush_mic_counters(DevCounters *ctr, unsigned tests, unsigned updates)
+{
+    unsigned long long st = wave_sum_u64(tests), su = wave_sum_u64(updates);
+    if (lane_id() == 0) {
+        if (st) atomicAdd(&ctr->mic_tests, st);
+        if (su) atomicAdd(&ctr->mic_updates, su);
+    }
+}
 
 __global__ void __launch_bounds__(256) k_mics(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mc,
-                                              TraceArgs a, int *big_list)
+                                              TraceArgs a, MicWork w)
 {
     const unsigned long long n = ctr->count[a.gen];
     const int lane = lane_id();
     while (true) {
-        unsigned long long base = wave_grab(&ctr->work_mic[a.gen]);
+        const unsigned long long base = wave_grab(&ctr->work_mic[a.gen]);
         if (base >= n) break;
-        long long i = (long long)base + lane;
+        const long long i = (long long)base + lane;
         unsigned tests = 0, updates = 0;
-        int big = 0;
+        int nrows = 0, j0 = 0, j1 = -1;
+        bool wide = false;
         if (i < (long long)n) {
             Frustum f;
-            load_frustum(M, q, segs, i, f);
-            HalfPlane hp[5];
-            int nh = frustum_halfplanes(f, mc.z, hp);
-            int j0, j1;
-            if (footprint_rows(hp, nh, mc, j0, j1)) {
-                int cells = 0;
-                int ra[kInlineRows], rb[kInlineRows];
-                if (j1 - j0 + 1 <= kInlineRows) {
+            load_frustum(M, q, segs, i, a.delta, f);
+            HalfPlane L[9];
+            footprint_lines(f, mc, L);
+            if (footprint_rows(L, mc, j0, j1)) {
+                nrows = j1 - j0 + 1;
+                if (nrows <= kInlineRows) {
                     for (int j = j0; j <= j1; ++j) {
-                        int i0 = 0, i1 = -1;
-                        if (!row_cols(hp, nh, mc, j, i0, i1)) { i0 = 0; i1 = -1; }
-                        ra[j - j0] = i0;
-                        rb[j - j0] = i1;
-                        cells += i1 - i0 + 1;
-                    }
-                } else {
-                    cells = kInlineCells + 1;
-                }
-                if (cells <= kInlineCells) {
-                    for (int j = j0; j <= j1; ++j) {
-                        for (int c = ra[j - j0]; c <= rb[j - j0]; ++c) {
+                        int c0, c1;
+                        if (!row_cols(L, mc, j, c0, c1)) continue;
+                        for (int c = c0; c <= c1; ++c) {
                             tests++;
-                            updates += mic_apply(f, mc, c, j, a.delta, a.air_m);
+                            updates += mic_apply(f, mc, c, j, a.air_m);
                         }
                     }
                 } else {
-                    big = 1;
+                    wide = true;
                 }
             }
         }
-        unsigned long long bm = __ballot(big);
-        unsigned long long bbase = 0;
-        unsigned long long st = wave_sum_u64(tests), su = wave_sum_u64(updates);
-        if (lane == 0) {
-            if (bm) bbase = atomicAdd(&ctr->n_big[a.gen], (unsigned long long)__popcll(bm));
-            if (st) atomicAdd(&ctr->mic_tests, st);
-            if (su) atomicAdd(&ctr->mic_updates, su);
+        // wide footprints: reserve one work item per row (wave-aggregated)
+        const int want = wide ? nrows : 0;
+        int incl = want;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            int v = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += v;
         }
+        const int total = __shfl(incl, 63, 64);
+        unsigned long long rbase = 0;
+        if (lane == 0 && total > 0) rbase = atomicAdd(&ctr->n_rows[a.gen], (unsigned long long)total);
+        rbase = __shfl(rbase, 0, 64);
+        bool to_big = false;
+        if (wide) {
+            const unsigned long long first = rbase + (unsigned long long)(incl - want);
+            if (first + (unsigned long long)want <= (unsigned long long)w.rows_cap) {
+                for (int r = 0; r < want; ++r) w.rows[first + r] = make_int2((int)i, j0 + r);
+            } else {
+                // does not fit: the whole segment goes to the wave path; slots of its
+                // reservation that lie inside the buffer are marked empty
+                for (unsigned long long r = first; r < (unsigned long long)w.rows_cap; ++r)
+                    w.rows[r] = make_int2(-1, 0);
+                to_big = true;
+            }
+        }
+        const unsigned long long bm = __ballot(to_big);
+        unsigned long long bbase = 0;
+        if (lane == 0 && bm) bbase = atomicAdd(&ctr->n_big[a.gen], (unsigned long long)__popcll(bm));
         bbase = __shfl(bbase, 0, 64);
-        if (big) big_list[bbase + __popcll(bm & ((1ull << lane) - 1ull))] = (int)i;
+        if (to_big) w.big_list[bbase + __popcll(bm & ((1ull << lane) - 1ull))] = (int)i;
+        flush_mic_counters(ctr, tests, updates);
     }
 }
 
-// Wide footprints: one wave per segment; the wave walks the rows and its lanes split
-// each row's columns.
+__global__ void __launch_bounds__(256) k_mic_rows(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mc,
+                                                  TraceArgs a, MicWork w)
+{
+    unsigned long long n = ctr->n_rows[a.gen];
+    if (n > (unsigned long long)w.rows_cap) n = (unsigned long long)w.rows_cap;
+    while (true) {
+        const unsigned long long base = wave_grab(&ctr->work_rows[a.gen]);
+        if (base >= n) break;
+        const unsigned long long r = base + (unsigned long long)lane_id();
+        unsigned tests = 0, updates = 0;
+        const int2 it = r < n ? w.rows[r] : make_int2(-1, 0);
+        if (it.x >= 0) {
+            Frustum f;
+            load_frustum(M, q, segs, it.x, a.delta, f);
+            HalfPlane L[9];
+            footprint_lines(f, mc, L);
+            int c0, c1;
+            if (row_cols(L, mc, it.y, c0, c1)) {
+                for (int c = c0; c <= c1; ++c) {
+                    tests++;
+                    updates += mic_apply(f, mc, c, it.y, a.air_m);
+                }
+            }
+        }
+        flush_mic_counters(ctr, tests, updates);
+    }
+}
+
 __global__ void __launch_bounds__(256) k_mics_big(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
-                                                  DevMics mc, TraceArgs a, const int *big_list)
+                                                  DevMics mc, TraceArgs a, MicWork w)
 {
     const unsigned long long n = ctr->n_big[a.gen];
     const int lane = lane_id();
     const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const int n_waves = (int)((gridDim.x * blockDim.x) >> 6);
-    for (unsigned long long w = (unsigned long long)wave; w < n; w += (unsigned long long)n_waves) {
-        long long i = big_list[w];
+    for (unsigned long long s = (unsigned long long)wave; s < n; s += (unsigned long long)n_waves) {
+        const long long i = w.big_list[s];
         Frustum f;
-        load_frustum(M, q, segs, i, f);
-        HalfPlane hp[5];
-        int nh = frustum_halfplanes(f, mc.z, hp);
+        load_frustum(M, q, segs, i, a.delta, f);
+        HalfPlane L[9];
+        footprint_lines(f, mc, L);
         int j0, j1;
         unsigned tests = 0, updates = 0;
-        if (footprint_rows(hp, nh, mc, j0, j1)) {
-            for (int j = j0; j <= j1; ++j) {
-                int i0, i1;
-                if (!row_cols(hp, nh, mc, j, i0, i1)) continue;
-                for (int c = i0 + lane; c <= i1; c += 64) {
+        if (footprint_rows(L, mc, j0, j1)) {
+            for (int j = j0 + lane; j <= j1; j += 64) {
+                int c0, c1;
+                if (!row_cols(L, mc, j, c0, c1)) continue;
+                for (int c = c0; c <= c1; ++c) {
                     tests++;
-                    updates += mic_apply(f, mc, c, j, a.delta, a.air_m);
+                    updates += mic_apply(f, mc, c, j, a.air_m);
                 }
             }
         }
-        unsigned long long st = wave_sum_u64(tests), su = wave_sum_u64(updates);
-        if (lane == 0) {
-            if (st) atomicAdd(&ctr->mic_tests, st);
-            if (su) atomicAdd(&ctr->mic_updates, su);
-        }
+        flush_mic_counters(ctr, tests, updates);
     }
 }
 
 hipError_t launch_mics(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mics,
-                       const TraceArgs &a, int *big_list, int n_cu, hipStream_t s)
+                       const TraceArgs &a, MicWork w, int n_cu, hipStream_t s)
 {
-    k_mics<<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, big_list);
+    k_mics<<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_mics_big<<<n_cu * 4, 256, 0, s>>>(m, q, segs, ctr, mics, a, big_list);
+    k_mic_rows<<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_mics_big<<<n_cu * 4, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
     return hipGetLastError();
 }
 

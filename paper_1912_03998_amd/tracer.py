@@ -37,7 +37,9 @@ class Session:
             raise RuntimeError("no GPU visible: the tracer has no CPU path")
         self.torch = torch
         self.device = device
-        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        # a dedicated stream (torch's default stream has the null handle, which the C ABI
+        # reads as "library-owned stream"); torch work for the session goes on it too
+        self.stream = stream if stream is not None else torch.cuda.Stream(device)
         self.ctx = bt.bt_create(device, hbm_budget, self.stream)
         self.mesh = bt.bt_build_mesh(self.ctx, xyz, tri, absorption, tiles_x, tiles_y)
         self.beams = None
@@ -81,9 +83,10 @@ class Session:
         outs = {}
         if parity:
             dev = torch.device("cuda", self.device)
-            outs["hit_out"] = torch.full((n0, depth + 1), -2, dtype=torch.int32, device=dev)
-            outs["flag_out"] = torch.zeros((n0, depth + 1), dtype=torch.uint8, device=dev)
-            outs["t_out"] = torch.full((n0, depth + 1), float("nan"), dtype=torch.float64, device=dev)
+            with torch.cuda.stream(self.stream):
+                outs["hit_out"] = torch.full((n0, depth + 1), -2, dtype=torch.int32, device=dev)
+                outs["flag_out"] = torch.zeros((n0, depth + 1), dtype=torch.uint8, device=dev)
+                outs["t_out"] = torch.full((n0, depth + 1), float("nan"), dtype=torch.float64, device=dev)
         p = self.params(depth, **kw, **outs)
         mics = self.enqueue(sources, power, level, depth, grid, p)
         n_mic = grid[5] * grid[6]
@@ -94,6 +97,7 @@ class Session:
         st = bt.bt_beams_stats(self.ctx, self.beams) if stats else {}
         res = RunResult(es, ef, lv, st)
         if parity:
+            self.stream.synchronize()
             res.hit = outs["hit_out"].cpu().numpy()
             res.flag = outs["flag_out"].cpu().numpy()
             res.t_hit = outs["t_out"].cpu().numpy()
