@@ -22,7 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_1912_03998_amd", "csrc", "bt_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1912_03998_amd", "csrc")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "trace_pmc_district.txt")
 REF_WORK = os.path.join(ROOT, "oracle", "reference_work.json")
 
@@ -33,7 +33,13 @@ B_BEAM, B_CHILD, B_HIT, B_NODE, B_TRI, B_MIC = 80, 80, 8, 64, 36, 16
 
 
 def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the device sources (kernels and the headers they include)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def pmc_traffic(n_launch_units):
@@ -69,6 +75,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2, help="0 tiny, 1 block, 2 district (default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tiles", type=int, default=0, help="override the tile partition (n x n)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the tracer runs on one device)",
@@ -77,6 +86,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = 1 << 30
+        a = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}), flush=True)
+        return
 
     from paper_1912_03998_amd import bt
     from paper_1912_03998_amd.tracer import Session, scene_grid
@@ -87,7 +106,7 @@ def main():
     print(f"[bench] {scene.name}: {scene.n_tri} triangles, {scene.n_beams0} beams, depth {scene.depth}, "
           f"{scene.n_mic} mics, tiles {scene.tiles_x}x{scene.tiles_y}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    sess = Session.from_scene(scene)
+    sess = Session.from_scene(scene, tiles=(args.tiles, args.tiles) if args.tiles > 0 else None)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     ctx, mesh, stream = sess.ctx, sess.mesh, sess.stream
@@ -101,23 +120,23 @@ def main():
     pw = np.ascontiguousarray(scene.power, np.float32)
 
     def step(ev=None):
+        # the sequence of bt_run, with events between the stages
         sess.beams = bt.bt_emit_beams(ctx, src, pw, scene.level, sess.beams)
         bt.bt_mics_reset(ctx, mics)
+        if ev is not None:
+            ev[0].record(stream)
         for g in range(D + 1):
-            if ev is not None:
-                ev[g][0].record(stream)
             bt.bt_trace(ctx, mesh, sess.beams, params)
-            if ev is not None:
-                ev[g][1].record(stream)
-            bt.bt_accumulate_mics(ctx, mesh, sess.beams, params, mics)
-            if ev is not None:
-                ev[g][2].record(stream)
+        if ev is not None:
+            ev[1].record(stream)
+        bt.bt_accumulate_mics(ctx, mesh, sess.beams, params, mics)
+        if ev is not None:
+            ev[2].record(stream)
         bt.bt_levels(ctx, mics, None, None, level_out)
 
     for _ in range(args.warmup):
         step()
-    events = [[[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(D + 1)]
-              for _ in range(args.steps)]
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -125,8 +144,8 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st = bt.bt_beams_stats(ctx, sess.beams)
-    trace_ms = sum(events[k][g][0].elapsed_time(events[k][g][1]) for k in range(args.steps) for g in range(D + 1))
-    mic_ms = sum(events[k][g][1].elapsed_time(events[k][g][2]) for k in range(args.steps) for g in range(D + 1))
+    trace_ms = sum(events[k][0].elapsed_time(events[k][1]) for k in range(args.steps))
+    mic_ms = sum(events[k][1].elapsed_time(events[k][2]) for k in range(args.steps))
     trace_ms /= args.steps
     mic_ms /= args.steps
     ms_per_step = elapsed * 1000.0 / args.steps
@@ -139,14 +158,16 @@ def main():
         trace_bytes = (B_BEAM + B_HIT) * ref["segments"] + B_CHILD * ref["children"] + \
             B_NODE * ref["node_visits"] + B_TRI * ref["tri_tests"]
         mic_bytes = B_MIC * ref["mic_updates"]
-        dominant = "k_trace" if trace_ms >= mic_ms else "k_mics"
-        t_dom = trace_ms if dominant == "k_trace" else mic_ms
-        b_dom = trace_bytes if dominant == "k_trace" else mic_bytes
+        # the trace stage is k_trace + k_reflect (both launched by each bt_trace call)
+        dominant = "k_trace+k_reflect" if trace_ms >= mic_ms else "k_mics+k_mic_rows+k_mic_spans"
+        t_dom = trace_ms if trace_ms >= mic_ms else mic_ms
+        b_dom = trace_bytes if trace_ms >= mic_ms else mic_bytes
+        launches = 2 * (D + 1) if trace_ms >= mic_ms else 4
         achieved = b_dom / (t_dom * 1e-3) / 1e9
-        traffic = pmc_traffic(D + 1) if dominant == "k_trace" else None
+        traffic = pmc_traffic(launches) if trace_ms >= mic_ms else None
         roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "algorithmic_bytes_per_step": b_dom, "launches_per_step": D + 1,
+                    "algorithmic_bytes_per_step": b_dom, "launches_per_step": launches,
                     "kernel_ms_per_step": round(t_dom, 3)}
     gpu_bytes = (B_BEAM + B_HIT) * segs + B_NODE * st["node_visits"] + B_TRI * st["tri_tests"]
 
@@ -162,7 +183,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{scene.name}: {scene.n_tri} triangles, {scene.n_src} sources x "
                                f"{20 * 4 ** scene.level} beams (icosphere level {scene.level}), depth {scene.depth}, "
-                               f"{scene.n_mic} microphones, {scene.tiles_x}x{scene.tiles_y} tiles",
+                               f"{scene.n_mic} microphones, "
+                               f"{args.tiles or scene.tiles_x}x{args.tiles or scene.tiles_y} tiles",
                    "segments_per_step": segs, "mic_updates_per_step": upd,
                    "generation_counts": st["count"].tolist(),
                    "flagged_per_generation": st["flagged"].tolist()},

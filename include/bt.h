@@ -137,22 +137,25 @@ bt_status bt_beams_stats(bt_ctx *ctx, const bt_beams *beams, bt_stats *out);
 /* Trace the current generation: closest hit of every guiding ray (paper Section 2:
  * intersections handled as in ray tracing, guiding ray only), hand-off between
  * sub-domains, then reflection of hits with depth < max_depth into the next
- * generation's queue (one child per hit, never split).  The traced segments stay
- * readable by bt_accumulate_mics until the next bt_trace.  n_next: NULL (no
- * synchronisation) or host int64 receiving the next generation's size (syncs).
- * Returns BT_ESTATE once max_depth + 1 generations have been traced. */
+ * generation's queue (one child per hit, never split).  Every generation's segments
+ * stay resident in device memory (n_beams0 * (max_depth + 1) records at most) until the
+ * next emission.  n_next: NULL (no synchronisation) or host int64 receiving the next
+ * generation's size (syncs).  Returns BT_ESTATE once max_depth + 1 generations have been
+ * traced, BT_EINVAL if n_beams0 * (max_depth + 1) exceeds 2^31 - 1. */
 bt_status bt_trace(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *beams, const bt_params *params,
                    int64_t *n_next);
 
-/* Add the contributions of the last traced segments to the microphones (paper
- * Section 2: microphones sum the contributions reaching them).  A microphone inside
+/* Add the contributions of every segment traced since the previous call (all of them
+ * after a first call) to the microphones, in one pass (paper Section 2: microphones sum
+ * the contributions reaching them); a call with nothing new traced does nothing.
+ * Returns BT_ESTATE before the first bt_trace.  A microphone inside
  * a segment's frustum (three side planes, the reflecting plane as near cap, the hit
  * plane as far cap) receives K exp(-air_m d) / d^2, d = distance to the beam's
  * (image) apex.  Contributions of flagged segments, and memberships decided within
  * edge_delta of a frustum plane, go to the set's flag energy, the others to its
  * strict energy; both are FP64. */
-bt_status bt_accumulate_mics(bt_ctx *ctx, const bt_mesh *mesh, const bt_beams *beams,
-                             const bt_params *params, bt_mics *mics);
+bt_status bt_accumulate_mics(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *beams, const bt_params *params,
+                             bt_mics *mics);
 
 /* Copy results to caller-owned host or device buffers (any may be NULL), then
  * synchronise: strict_out / flag_out double[n_mic] energies (W/m^2), level_db_out

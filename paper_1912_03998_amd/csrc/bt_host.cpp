@@ -53,12 +53,17 @@ struct bt_mics {
 struct bt_beams {
     bt_ctx *ctx = nullptr;
     long long cap = 0;
-    DevQueue q[2]{};
+    DevQueue q{};             // every generation, contiguous (see DevQueue)
     DevSegs segs{};
     DevCounters *ctr = nullptr;
     int *big_list = nullptr;
     int2 *rows = nullptr;
     long long rows_cap = 0;
+    int4 *spans = nullptr;
+    long long spans_cap = 0;
+    long long work_n0 = 0;    // generation-0 size the work buffers were sized for
+    int acc_gen = 0;          // first generation not yet accumulated at the microphones
+    int depth_hint = 0;       // max_depth of the previous run, to size the queue at emission
     float *src_dev = nullptr, *pow_dev = nullptr;
     int src_cap = 0;
     size_t bytes = 0;
@@ -635,52 +640,106 @@ extern "C" bt_status bt_mics_free(bt_mics *m)
 // ---------------------------------------------------------------------------------------
 // beams
 // ---------------------------------------------------------------------------------------
+static void queue_free(bt_ctx *ctx, DevQueue &q)
+{
+    dev_free(ctx, q.dbl, (size_t)q.cap * D_N * sizeof(double));
+    dev_free(ctx, q.flt, (size_t)q.cap * F_N * sizeof(float));
+    dev_free(ctx, q.ints, (size_t)q.cap * I_N * sizeof(int));
+    q = DevQueue{};
+}
+
 static void beams_release(bt_beams *b)
 {
     bt_ctx *ctx = b->ctx;
-    for (int k = 0; k < 2; ++k) {
-        dev_free(ctx, b->q[k].dbl, (size_t)b->cap * D_N * sizeof(double));
-        dev_free(ctx, b->q[k].flt, (size_t)b->cap * F_N * sizeof(float));
-        dev_free(ctx, b->q[k].ints, (size_t)b->cap * I_N * sizeof(int));
-        b->q[k] = DevQueue{};
-    }
+    queue_free(ctx, b->q);
     dev_free(ctx, b->segs.hit, (size_t)b->cap * sizeof(int));
     dev_free(ctx, b->segs.t, (size_t)b->cap * sizeof(double));
     dev_free(ctx, b->segs.flag, (size_t)b->cap * sizeof(int));
     b->segs = DevSegs{};
     dev_free(ctx, b->big_list, (size_t)b->cap * sizeof(int));
     b->big_list = nullptr;
+    b->cap = 0;
     dev_free(ctx, b->rows, (size_t)b->rows_cap * sizeof(int2));
     b->rows = nullptr;
     b->rows_cap = 0;
-    b->cap = 0;
+    dev_free(ctx, b->spans, (size_t)b->spans_cap * sizeof(int4));
+    b->spans = nullptr;
+    b->spans_cap = 0;
+    b->work_n0 = 0;
 }
 
-static bt_status beams_reserve(bt_ctx *ctx, bt_beams *b, long long n)
+// Queue, segment and overflow-list capacity of at least n records.  When the arrays
+// move, the first `keep` queue records (every field) are carried over on the stream.
+static bt_status reserve_queue(bt_ctx *ctx, bt_beams *b, long long n, long long keep)
 {
     if (n <= b->cap) return BT_OK;
-    beams_release(b);
+    DevQueue nq{};
     bt_status s;
-    for (int k = 0; k < 2; ++k) {
-        if ((s = dev_alloc(ctx, (void **)&b->q[k].dbl, (size_t)n * D_N * sizeof(double))) != BT_OK) return s;
-        if ((s = dev_alloc(ctx, (void **)&b->q[k].flt, (size_t)n * F_N * sizeof(float))) != BT_OK) return s;
-        if ((s = dev_alloc(ctx, (void **)&b->q[k].ints, (size_t)n * I_N * sizeof(int))) != BT_OK) return s;
-        b->q[k].cap = n;
+    if ((s = dev_alloc(ctx, (void **)&nq.dbl, (size_t)n * D_N * sizeof(double))) != BT_OK ||
+        (s = dev_alloc(ctx, (void **)&nq.flt, (size_t)n * F_N * sizeof(float))) != BT_OK ||
+        (s = dev_alloc(ctx, (void **)&nq.ints, (size_t)n * I_N * sizeof(int))) != BT_OK) {
+        nq.cap = n;
+        queue_free(ctx, nq);
+        return s;
     }
+    nq.cap = n;
+    if (keep > 0) {
+        for (int k = 0; k < D_N; ++k)
+            HIP_TRY(ctx, hipMemcpyAsync(nq.dbl + k * n, b->q.dbl + k * b->q.cap, (size_t)keep * sizeof(double),
+                                        hipMemcpyDeviceToDevice, ctx->stream));
+        for (int k = 0; k < F_N; ++k)
+            HIP_TRY(ctx, hipMemcpyAsync(nq.flt + k * n, b->q.flt + k * b->q.cap, (size_t)keep * sizeof(float),
+                                        hipMemcpyDeviceToDevice, ctx->stream));
+        for (int k = 0; k < I_N; ++k)
+            HIP_TRY(ctx, hipMemcpyAsync(nq.ints + k * n, b->q.ints + k * b->q.cap, (size_t)keep * sizeof(int),
+                                        hipMemcpyDeviceToDevice, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the old arrays are freed next
+    }
+    queue_free(ctx, b->q);
+    b->q = nq;
+    dev_free(ctx, b->segs.hit, (size_t)b->cap * sizeof(int));
+    dev_free(ctx, b->segs.t, (size_t)b->cap * sizeof(double));
+    dev_free(ctx, b->segs.flag, (size_t)b->cap * sizeof(int));
+    dev_free(ctx, b->big_list, (size_t)b->cap * sizeof(int));
+    b->segs = DevSegs{};
+    b->big_list = nullptr;
+    b->cap = 0;
     if ((s = dev_alloc(ctx, (void **)&b->segs.hit, (size_t)n * sizeof(int))) != BT_OK) return s;
     if ((s = dev_alloc(ctx, (void **)&b->segs.t, (size_t)n * sizeof(double))) != BT_OK) return s;
     if ((s = dev_alloc(ctx, (void **)&b->segs.flag, (size_t)n * sizeof(int))) != BT_OK) return s;
     if ((s = dev_alloc(ctx, (void **)&b->big_list, (size_t)n * sizeof(int))) != BT_OK) return s;
-    // row work items of wide microphone footprints: 2 per beam covers the district workload
-    // with room to spare; overflow falls back to one wave per segment
-    long long rows_cap = std::max(2 * n, 1ll << 20);
+    b->cap = n;
+    return BT_OK;
+}
+
+// Work-item buffers of the microphone stage, sized from the generation-0 count.
+static bt_status reserve_work(bt_ctx *ctx, bt_beams *b, long long n0)
+{
+    if (n0 <= b->work_n0) return BT_OK;
+    dev_free(ctx, b->rows, (size_t)b->rows_cap * sizeof(int2));
+    dev_free(ctx, b->spans, (size_t)b->spans_cap * sizeof(int4));
+    b->rows = nullptr;
+    b->spans = nullptr;
+    b->rows_cap = b->spans_cap = 0;
+    bt_status s;
+    // row work items of wide footprints over all generations: 2 per initial beam covers the
+    // district workload (1.3 per beam) with room; overflow falls back to one wave per segment
+    long long rows_cap = std::max(2 * n0, 1ll << 20);
     if (const char *env = std::getenv("BT_MIC_ROW_CAPACITY")) {  // testing the overflow path
         long long v = std::atoll(env);
         if (v > 0) rows_cap = v;
     }
     if ((s = dev_alloc(ctx, (void **)&b->rows, (size_t)rows_cap * sizeof(int2))) != BT_OK) return s;
     b->rows_cap = rows_cap;
-    b->cap = n;
+    // column spans of long rows; a full buffer makes the row's lane process it in place
+    long long spans_cap = std::max(n0, 1ll << 20);
+    if (const char *env = std::getenv("BT_MIC_SPAN_CAPACITY")) {  // testing the full-buffer path
+        long long v = std::atoll(env);
+        if (v > 0) spans_cap = v;
+    }
+    if ((s = dev_alloc(ctx, (void **)&b->spans, (size_t)spans_cap * sizeof(int4))) != BT_OK) return s;
+    b->spans_cap = spans_cap;
+    b->work_n0 = n0;
     return BT_OK;
 }
 
@@ -712,7 +771,11 @@ extern "C" bt_status bt_emit_beams(bt_ctx *ctx, const float *src_xyz, const floa
         bt_status s = dev_alloc(ctx, (void **)&b->ctr, sizeof(DevCounters));
         if (s != BT_OK) { delete b; return s; }
     }
-    bt_status s = beams_reserve(ctx, b, std::max(n0, 1ll));
+    // room for every generation of the previous run's depth (grown at the first trace if
+    // the depth is larger)
+    const long long want = std::max(n0, 1ll) * (long long)(b->depth_hint + 1);
+    bt_status s = reserve_queue(ctx, b, want <= (1ll << 31) - 1 ? want : std::max(n0, 1ll), 0);
+    if (s == BT_OK) s = reserve_work(ctx, b, std::max(n0, 1ll));
     if (s == BT_OK && n_src > b->src_cap) {
         dev_free(ctx, b->src_dev, (size_t)b->src_cap * 3 * sizeof(float));
         dev_free(ctx, b->pow_dev, (size_t)b->src_cap * sizeof(float));
@@ -731,10 +794,11 @@ extern "C" bt_status bt_emit_beams(bt_ctx *ctx, const float *src_xyz, const floa
         HIP_TRY(ctx, hipMemcpyAsync(b->pow_dev, src_power, (size_t)n_src * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
     }
     HIP_TRY(ctx, launch_init_counters(b->ctr, n0, ctx->stream));
-    HIP_TRY(ctx, launch_emit(ctx->base20, b->src_dev, b->pow_dev, n_src, level, b->q[0], ctx->stream));
+    HIP_TRY(ctx, launch_emit(ctx->base20, b->src_dev, b->pow_dev, n_src, level, b->q, ctx->stream));
     // host inputs are borrowed for the call only
     if (n_src > 0) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     b->gen = 0;
+    b->acc_gen = 0;
     b->max_depth = -1;
     b->n0 = n0;
     b->r_src = r_src;
@@ -814,10 +878,18 @@ extern "C" bt_status bt_trace(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *b, con
     if (b->gen > p->max_depth) return fail(ctx, BT_ESTATE, "all %d generations already traced", p->max_depth + 1);
     if (b->r_src > mesh->r_eff) return fail(ctx, BT_EINVAL, "a source lies outside the region the mesh margins cover (|x| <= %g)", mesh->r_eff);
     (void)hipSetDevice(ctx->device);
-    b->max_depth = p->max_depth;
     int g = b->gen;
+    if (g == 0) {
+        // every generation stays resident: at most n0 records each
+        const long long total = std::max(b->n0, 1ll) * (long long)(p->max_depth + 1);
+        if (total > (1ll << 31) - 1)
+            return fail(ctx, BT_EINVAL, "n_beams0 * (max_depth + 1) = %lld exceeds 2^31 - 1", total);
+        if ((s = reserve_queue(ctx, b, total, b->n0)) != BT_OK) return s;
+        b->depth_hint = p->max_depth;
+    }
+    b->max_depth = p->max_depth;
     TraceArgs a = make_args(p, g);
-    HIP_TRY(ctx, launch_trace(mesh->dev, b->q[g & 1], b->q[(g + 1) & 1], b->segs, b->ctr, a, ctx->n_cu, ctx->stream));
+    HIP_TRY(ctx, launch_trace(mesh->dev, b->q, b->segs, b->ctr, a, ctx->n_cu, ctx->stream));
     b->gen = g + 1;
     if (n_next) {
         unsigned long long c = 0;
@@ -828,7 +900,7 @@ extern "C" bt_status bt_trace(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *b, con
     return BT_OK;
 }
 
-extern "C" bt_status bt_accumulate_mics(bt_ctx *ctx, const bt_mesh *mesh, const bt_beams *b, const bt_params *p,
+extern "C" bt_status bt_accumulate_mics(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *b, const bt_params *p,
                                         bt_mics *mics)
 {
     if (!ctx) return BT_EINVAL;
@@ -836,11 +908,14 @@ extern "C" bt_status bt_accumulate_mics(bt_ctx *ctx, const bt_mesh *mesh, const 
     bt_status s = check_params(ctx, mesh, p);
     if (s != BT_OK) return s;
     if (b->gen == 0) return fail(ctx, BT_ESTATE, "no generation traced yet");
+    if (b->acc_gen == b->gen) return BT_OK;  // nothing traced since the last call
     (void)hipSetDevice(ctx->device);
-    int g = b->gen - 1;
-    TraceArgs a = make_args(p, g);
-    MicWork w{b->rows, b->rows_cap, b->big_list};
-    HIP_TRY(ctx, launch_mics(mesh->dev, b->q[g & 1], b->segs, b->ctr, mics->dev, a, w, ctx->n_cu, ctx->stream));
+    // all generations traced since the previous call, in one pass
+    TraceArgs a = make_args(p, b->acc_gen);
+    a.gen_end = b->gen;
+    MicWork w{b->rows, b->rows_cap, b->spans, b->spans_cap, b->big_list};
+    HIP_TRY(ctx, launch_mics(mesh->dev, b->q, b->segs, b->ctr, mics->dev, a, w, ctx->n_cu, ctx->stream));
+    b->acc_gen = b->gen;
     return BT_OK;
 }
 
@@ -869,11 +944,10 @@ extern "C" bt_status bt_run(bt_ctx *ctx, const bt_mesh *mesh, const float *src_x
     if (s != BT_OK) return s;
     s = bt_emit_beams(ctx, src_xyz, src_power, n_src, level, beams);
     if (s != BT_OK) return s;
-    for (int g = 0; g <= p->max_depth; ++g) {
+    for (int g = 0; g <= p->max_depth; ++g)
         if ((s = bt_trace(ctx, mesh, *beams, p, nullptr)) != BT_OK) return s;
-        if ((s = bt_accumulate_mics(ctx, mesh, *beams, p, mics)) != BT_OK) return s;
-    }
-    return BT_OK;
+    // one microphone pass over the segments of every generation (all stay resident)
+    return bt_accumulate_mics(ctx, mesh, *beams, p, mics);
 }
 
 // ---------------------------------------------------------------------------------------

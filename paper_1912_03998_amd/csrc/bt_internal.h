@@ -45,7 +45,9 @@ struct DevMesh {
     int n_tri;
 };
 
-// Beam queue, structure of arrays with capacity `cap`:
+// Beam queue, structure of arrays with capacity `cap`.  All generations of a beam set
+// stay resident: generation g occupies [start_g, start_g + count_g) with
+// start_g = count_0 + ... + count_(g-1), so the capacity is n0 * (max_depth + 1) records.
 //   dbl[k * cap + i], k = 0..17: A.xyz, d0.xyz, d1.xyz, d2.xyz, o.xyz, c.xyz
 //   flt[k * cap + i], k = 0..1: K (W/sr), Omega (sr)
 //   ints[k * cap + i], k = 0..2: initial beam id, start triangle, meta
@@ -63,7 +65,7 @@ struct DevQueue {
     long long cap;
 };
 
-// Segments of the last traced generation (indexed like the queue that was traced).
+// Traced segments, indexed like the queue.
 struct DevSegs {
     int *hit;        // hit triangle id or -1
     double *t;       // hit parameter or +inf
@@ -75,12 +77,9 @@ struct DevCounters {
     unsigned long long count[BT_MAX_DEPTH + 2];      // beams per generation
     unsigned long long flagged[BT_MAX_DEPTH + 2];
     double power[BT_MAX_DEPTH + 2];
-    unsigned long long work_trace[BT_MAX_DEPTH + 2]; // wave work-grab cursors
-    unsigned long long work_mic[BT_MAX_DEPTH + 2];
-    unsigned long long work_big[BT_MAX_DEPTH + 2];
     unsigned long long n_big[BT_MAX_DEPTH + 2];      // segments for the wave-per-segment fallback
     unsigned long long n_rows[BT_MAX_DEPTH + 2];     // (segment, row) work items requested
-    unsigned long long work_rows[BT_MAX_DEPTH + 2];
+    unsigned long long n_spans[BT_MAX_DEPTH + 2];    // (segment, row, columns) work items
     unsigned long long node_visits, tri_tests, mic_tests, mic_updates;
 };
 
@@ -91,16 +90,20 @@ struct DevMics {
     double *e_flag;            // [nx*ny]
 };
 
-// Work buffers of the microphone stage: (segment, row) items of wide footprints and the
-// overflow list of segments handled one wave each.
+// Work buffers of the microphone stage: (segment, row) items of wide footprints,
+// (segment, row, first column, last column) spans of long rows, and the overflow list
+// of segments handled one wave each.
 struct MicWork {
     int2 *rows;
     long long rows_cap;
+    int4 *spans;
+    long long spans_cap;
     int *big_list;     // capacity: the queue capacity
 };
 
 struct TraceArgs {
-    int gen;
+    int gen;         // trace: the generation traced; microphones: first generation
+    int gen_end;     // microphones: one past the last generation accumulated
     int max_depth;
     double t_min, delta, air_m, e_min;
     int *hit_out;
@@ -112,8 +115,8 @@ struct TraceArgs {
 hipError_t launch_init_counters(DevCounters *ctr, long long n0, hipStream_t s);
 hipError_t launch_emit(const double *base20, const float *src, const float *power, int n_src, int level,
                        DevQueue q, hipStream_t s);
-hipError_t launch_trace(const DevMesh &m, DevQueue in, DevQueue out, DevSegs segs, DevCounters *ctr,
-                        const TraceArgs &a, int n_cu, hipStream_t s);
+hipError_t launch_trace(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, const TraceArgs &a, int n_cu,
+                        hipStream_t s);
 hipError_t launch_mics(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mics,
                        const TraceArgs &a, MicWork w, int n_cu, hipStream_t s);
 hipError_t launch_fill(double *p, long long n, double v, hipStream_t s);

@@ -1,0 +1,443 @@
+// Microphone accumulation: frustum footprints on the microphone plane, exact membership
+// and FP64 accumulation.  Built with -ffp-contract=off: the tie rule on shared beam faces
+// relies on exactly antisymmetric cross products.
+#include "bt_device.h"
+
+namespace bt {
+
+// ---------------------------------------------------------------------------------------
+// Microphones
+//
+// A segment's frustum meets the microphone plane z = zm in a convex polygon: three side
+// half-planes through the (image) apex, the reflecting plane (outgoing side, strict) and
+// the hit plane (incoming side, closed).  The kernels first bound the polygon's rows,
+// then enumerate candidate microphones row by row (one column of slack on each side)
+// and decide membership with the exact plane tests.
+//   k_mics:      one lane per segment; footprints of <= kInlineRows rows are finished
+//                in place, wider ones are split into (segment, row) work items
+//   k_mic_rows:  one lane per (segment, row) work item
+//   k_mics_big:  one wave per segment, for segments whose rows did not fit the item
+//                buffer (overflow fallback)
+// ---------------------------------------------------------------------------------------
+struct Frustum {
+    V3 A;
+    V3 n[3];
+    double amb2[3];     // delta^2 |n_k|^2: |s| < delta |n| <=> s^2 < amb2
+    bool has_near, has_far;
+    V3 Nn, Pn;
+    double near_sign, amb2_near;
+    V3 Nf, Pf;
+    double far_sign, amb2_far;
+    float K;
+    int flag;
+};
+
+struct HalfPlane {
+    double a, b, k;  // a x + b y + k >= 0 on the microphone plane
+};
+
+__device__ __forceinline__ bool lex_positive(V3 n)
+{
+    if (n.x != 0.0) return n.x > 0.0;
+    if (n.y != 0.0) return n.y > 0.0;
+    return n.z > 0.0;
+}
+
+// Keep-side half-plane g . (p - P) >= 0 on z = zm, relaxed by eps * |g|_1 (>= eps |g|).
+__device__ __forceinline__ HalfPlane make_hp(V3 g, V3 P, double z, double eps)
+{
+    HalfPlane h;
+    h.a = g.x;
+    h.b = g.y;
+    h.k = g.z * (z - P.z) - g.x * P.x - g.y * P.y + eps * (fabs(g.x) + fabs(g.y) + fabs(g.z));
+    return h;
+}
+
+__device__ void load_frustum(const DevMesh &M, const DevQueue &q, const DevSegs &segs, long long i, double delta,
+                             Frustum &f)
+{
+    const long long cap = q.cap;
+    const double d2 = delta * delta;
+    f.A = ld3(q.dbl + D_A * cap, cap, i);
+    V3 d[3] = {ld3(q.dbl + D_D0 * cap, cap, i), ld3(q.dbl + D_D1 * cap, cap, i), ld3(q.dbl + D_D2 * cap, cap, i)};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        f.n[k] = cross(d[k], d[(k + 1) % 3]);
+        f.amb2[k] = d2 * dot(f.n[k], f.n[k]);
+    }
+    int meta = q.ints[I_META * cap + i];
+    int start = q.ints[I_START * cap + i];
+    int hit = segs.hit[i];
+    f.K = q.flt[F_K * cap + i];
+    f.flag = segs.flag[i];
+    f.has_near = (meta & 0xff) > 0;
+    if (f.has_near) {
+        V3 v0, v1, v2;
+        tri_vertices(M.tri_g, start, v0, v1, v2);
+        f.Nn = cross(v1 - v0, v2 - v0);
+        f.Pn = v0;
+        f.near_sign = (meta & kMetaNegNear) ? -1.0 : 1.0;
+        f.amb2_near = d2 * dot(f.Nn, f.Nn);
+    }
+    f.has_far = hit >= 0;
+    if (f.has_far) {
+        V3 v0, v1, v2;
+        tri_vertices(M.tri_g, hit, v0, v1, v2);
+        f.Nf = cross(v1 - v0, v2 - v0);
+        f.Pf = v0;
+        V3 c = ld3(q.dbl + D_C * cap, cap, i);
+        f.far_sign = dot(c, f.Nf) > 0.0 ? 1.0 : -1.0;
+        f.amb2_far = d2 * dot(f.Nf, f.Nf);
+    }
+}
+
+// The frustum's half-planes plus the grid rectangle (grown by half a cell) as 9 lines;
+// unused slots are the always-true constraint 0 x + 0 y + 1 >= 0.
+__device__ __forceinline__ void footprint_lines(const Frustum &f, const DevMics &mc, HalfPlane *L)
+{
+    const double eps = 1e-6;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) L[k] = make_hp(f.n[k], f.A, mc.z, eps);
+    L[3] = f.has_near ? make_hp(f.near_sign * f.Nn, f.Pn, mc.z, eps) : HalfPlane{0.0, 0.0, 1.0};
+    L[4] = f.has_far ? make_hp((-f.far_sign) * f.Nf, f.Pf, mc.z, eps) : HalfPlane{0.0, 0.0, 1.0};
+    double xlo = mc.x0 - 0.5 * mc.dx, xhi = mc.x0 + ((double)mc.nx - 0.5) * mc.dx;
+    double ylo = mc.y0 - 0.5 * mc.dy, yhi = mc.y0 + ((double)mc.ny - 0.5) * mc.dy;
+    L[5] = HalfPlane{1.0, 0.0, -xlo};
+    L[6] = HalfPlane{-1.0, 0.0, xhi};
+    L[7] = HalfPlane{0.0, 1.0, -ylo};
+    L[8] = HalfPlane{0.0, -1.0, yhi};
+}
+
+// Row range of the footprint polygon: every constraint line is clipped by all the
+// others (parametrically, comparing fractions without dividing); the endpoints of the
+// surviving edges bound the polygon's y-extent.  One row of slack on each side.
+__device__ bool footprint_rows(const HalfPlane *L, const DevMics &mc, int &j0, int &j1)
+{
+    double ymn = INFINITY, ymx = -INFINITY;
+#pragma unroll
+    for (int h = 0; h < 9; ++h) {
+        const double a = L[h].a, b = L[h].b, k = L[h].k;
+        const double nn = a * a + b * b;
+        if (nn == 0.0) continue;
+        const double px = -k * a / nn, py = -k * b / nn;  // point on the line
+        const double dx = -b, dy = a;                     // direction along it
+        // t >= lo_n / lo_d and t <= hi_n / hi_d with positive denominators
+        double lo_n = -1.0, lo_d = 0.0, hi_n = 1.0, hi_d = 0.0;  // -inf, +inf
+        bool empty = false;
+#pragma unroll
+        for (int g = 0; g < 9; ++g) {
+            if (g == h) continue;
+            const double den = L[g].a * dx + L[g].b * dy;
+            const double num = -(L[g].a * px + L[g].b * py + L[g].k);  // need den * t >= num
+            if (den > 0.0) {
+                if (lo_d == 0.0 || num * lo_d > lo_n * den) { lo_n = num; lo_d = den; }
+            } else if (den < 0.0) {
+                if (hi_d == 0.0 || (-num) * hi_d < hi_n * (-den)) { hi_n = -num; hi_d = -den; }
+            } else if (num > 0.0) {
+                empty = true;
+            }
+        }
+        if (empty || lo_d == 0.0 || hi_d == 0.0) continue;  // (bounded by the rectangle otherwise)
+        const double tlo = lo_n / lo_d, thi = hi_n / hi_d;
+        if (!(tlo <= thi)) continue;
+        const double y0 = py + tlo * dy, y1 = py + thi * dy;
+        ymn = fmin(ymn, fmin(y0, y1));
+        ymx = fmax(ymx, fmax(y0, y1));
+    }
+    if (!(ymn <= ymx)) return false;
+    double fj0 = ceil((ymn - mc.y0) / mc.dy) - 1.0, fj1 = floor((ymx - mc.y0) / mc.dy) + 1.0;
+    fj0 = fmax(fj0, 0.0);
+    fj1 = fmin(fj1, (double)(mc.ny - 1));
+    if (!(fj0 <= fj1)) return false;
+    j0 = (int)fj0;
+    j1 = (int)fj1;
+    return true;
+}
+
+// Column range of row j inside the relaxed frustum half-planes (one column of slack).
+__device__ __forceinline__ bool row_cols(const HalfPlane *L, const DevMics &mc, int j, int &i0, int &i1)
+{
+    const double y = mc.y0 + (double)j * mc.dy;
+    double lo = -INFINITY, hi = INFINITY;
+#pragma unroll
+    for (int h = 0; h < 5; ++h) {
+        const double rest = L[h].b * y + L[h].k;
+        if (L[h].a > 0.0) lo = fmax(lo, -rest / L[h].a);
+        else if (L[h].a < 0.0) hi = fmin(hi, -rest / L[h].a);
+        else if (rest < 0.0) return false;
+    }
+    if (!(lo <= hi)) return false;
+    const double flo = (lo - mc.x0) / mc.dx, fhi = (hi - mc.x0) / mc.dx;
+    if (flo > (double)mc.nx || fhi < -1.0) return false;
+    const double a0 = fmax(ceil(flo) - 1.0, 0.0), a1 = fmin(floor(fhi) + 1.0, (double)(mc.nx - 1));
+    if (!(a0 <= a1)) return false;
+    i0 = (int)a0;
+    i1 = (int)a1;
+    return true;
+}
+
+// Membership of grid microphone (i, j) and its contribution; returns 1 if accumulated.
+// Ambiguous: every active test passes within -delta and one is within delta of its plane.
+__device__ __forceinline__ int mic_apply(const Frustum &f, const DevMics &mc, int i, int j, double air_m)
+{
+    const V3 m = {mc.x0 + (double)i * mc.dx, mc.y0 + (double)j * mc.dy, mc.z};
+    const V3 r = m - f.A;
+    bool inside = true, far_out = false, near_any = false;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double s = dot(f.n[k], r);
+        inside = inside && (s > 0.0 || (s == 0.0 && lex_positive(f.n[k])));
+        const double s2 = s * s;
+        far_out = far_out || (s < 0.0 && s2 >= f.amb2[k]);
+        near_any = near_any || s2 < f.amb2[k];
+    }
+    if (f.has_near) {
+        const double s = f.near_sign * dot(f.Nn, m - f.Pn);
+        inside = inside && s > 0.0;
+        const double s2 = s * s;
+        far_out = far_out || (s < 0.0 && s2 >= f.amb2_near);
+        near_any = near_any || s2 < f.amb2_near;
+    }
+    if (f.has_far) {
+        const double s = -f.far_sign * dot(f.Nf, m - f.Pf);
+        inside = inside && s >= 0.0;
+        const double s2 = s * s;
+        far_out = far_out || (s < 0.0 && s2 >= f.amb2_far);
+        near_any = near_any || s2 < f.amb2_far;
+    }
+    if (!inside) return 0;
+    const double d2 = dot(r, r);
+    float e = f.K / (float)d2;
+    if (air_m > 0.0) e *= expf(-(float)(air_m * sqrt(d2)));
+    const bool amb = !far_out && near_any;
+    const long long idx = (long long)j * mc.nx + i;
+    atomicAdd((f.flag || amb) ? &mc.e_flag[idx] : &mc.e_strict[idx], (double)e);
+    return 1;
+}
+
+constexpr int kInlineRows = 4;
+constexpr int kSpan = 32;   // longest column run one lane processes in place
+
+// Columns [c0, c1] of row j: processed here when short, else split into kSpan-column
+// span items (processed here anyway if the span buffer is full).
+__device__ __forceinline__ void process_row(const Frustum &f, const DevMics &mc, const MicWork &w, DevCounters *ctr,
+                                            int gen, long long seg, int j, int c0, int c1, double air_m,
+                                            unsigned &tests, unsigned &updates)
+{
+    const int ncol = c1 - c0 + 1;
+    if (ncol > kSpan) {
+        const int nsp = (ncol + kSpan - 1) / kSpan;
+        const unsigned long long b = atomicAdd(&ctr->n_spans[gen], (unsigned long long)nsp);
+        if (b + (unsigned long long)nsp <= (unsigned long long)w.spans_cap) {
+            for (int k = 0; k < nsp; ++k) {
+                const int a0 = c0 + k * kSpan;
+                w.spans[b + k] = make_int4((int)seg, j, a0, min(a0 + kSpan - 1, c1));
+            }
+            return;
+        }
+        for (unsigned long long r = b; r < (unsigned long long)w.spans_cap; ++r) w.spans[r] = make_int4(-1, 0, 0, -1);
+    }
+    for (int c = c0; c <= c1; ++c) {
+        tests++;
+        updates += mic_apply(f, mc, c, j, air_m);
+    }
+}
+
+__device__ __forceinline__ void flush_mic_counters(DevCounters *ctr, unsigned tests, unsigned updates)
+{
+    unsigned long long st = wave_sum_u64(tests), su = wave_sum_u64(updates);
+    if (lane_id() == 0) {
+        if (st) atomicAdd(&ctr->mic_tests, st);
+        if (su) atomicAdd(&ctr->mic_updates, su);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_mics(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mc,
+                                              TraceArgs a, MicWork w)
+{
+    // the segments of generations [gen, gen_end), contiguous in the queue
+    const unsigned long long s0 = gen_start(ctr, a.gen);
+    const unsigned long long n = gen_start(ctr, a.gen_end) - s0;
+    const int lane = lane_id();
+    for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
+        const long long i = (long long)(s0 + base) + lane;
+        unsigned tests = 0, updates = 0;
+        int nrows = 0, j0 = 0, j1 = -1;
+        bool wide = false;
+        bool general = false;
+        Frustum f;
+        if ((long long)base + lane < (long long)n) {
+            // Fast path: when all three edge rays cross the microphone plane ahead of the
+            // apex, the frustum meets the plane inside the triangle of the three crossing
+            // points (the caps only cut it down), so the lattice points of that triangle's
+            // bounding box are the only candidates.  Most segments have none, and are
+            // dismissed before the rest of the frustum is loaded.
+            const long long cap = q.cap;
+            const V3 A = ld3(q.dbl + D_A * cap, cap, i);
+            const double zr = mc.z - A.z;
+            double xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
+            bool proper = zr != 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const V3 d = ld3(q.dbl + (D_D0 + 3 * k) * cap, cap, i);
+                const double s = zr / d.z;
+                proper = proper && s > 0.0 && isfinite(s);
+                const double px = A.x + s * d.x, py = A.y + s * d.y;
+                xmn = fmin(xmn, px); xmx = fmax(xmx, px);
+                ymn = fmin(ymn, py); ymx = fmax(ymx, py);
+            }
+            general = true;
+            if (proper) {
+                const double relax = 1e-6;
+                const double fi0 = fmax(ceil((xmn - relax - mc.x0) / mc.dx), 0.0);
+                const double fi1 = fmin(floor((xmx + relax - mc.x0) / mc.dx), (double)(mc.nx - 1));
+                const double fj0 = fmax(ceil((ymn - relax - mc.y0) / mc.dy), 0.0);
+                const double fj1 = fmin(floor((ymx + relax - mc.y0) / mc.dy), (double)(mc.ny - 1));
+                if (!(fi0 <= fi1 && fj0 <= fj1)) {
+                    general = false;  // no lattice point under the footprint
+                } else if ((fi1 - fi0 + 1.0) * (fj1 - fj0 + 1.0) <= (double)kSpan) {
+                    general = false;
+                    load_frustum(M, q, segs, i, a.delta, f);
+                    for (int j = (int)fj0; j <= (int)fj1; ++j)
+                        for (int c = (int)fi0; c <= (int)fi1; ++c) {
+                            tests++;
+                            updates += mic_apply(f, mc, c, j, a.air_m);
+                        }
+                }
+            }
+            if (general) load_frustum(M, q, segs, i, a.delta, f);
+        }
+        if (general) {
+            HalfPlane L[9];
+            footprint_lines(f, mc, L);
+            if (footprint_rows(L, mc, j0, j1)) {
+                nrows = j1 - j0 + 1;
+                if (nrows <= kInlineRows) {
+                    for (int j = j0; j <= j1; ++j) {
+                        int c0, c1;
+                        if (!row_cols(L, mc, j, c0, c1)) continue;
+                        process_row(f, mc, w, ctr, a.gen, i, j, c0, c1, a.air_m, tests, updates);
+                    }
+                } else {
+                    wide = true;
+                }
+            }
+        }
+        // wide footprints: reserve one work item per row (wave-aggregated)
+        const int want = wide ? nrows : 0;
+        int incl = want;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            int v = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += v;
+        }
+        const int total = __shfl(incl, 63, 64);
+        unsigned long long rbase = 0;
+        if (lane == 0 && total > 0) rbase = atomicAdd(&ctr->n_rows[a.gen], (unsigned long long)total);
+        rbase = __shfl(rbase, 0, 64);
+        bool to_big = false;
+        if (wide) {
+            const unsigned long long first = rbase + (unsigned long long)(incl - want);
+            if (first + (unsigned long long)want <= (unsigned long long)w.rows_cap) {
+                for (int r = 0; r < want; ++r) w.rows[first + r] = make_int2((int)i, j0 + r);
+            } else {
+                // does not fit: the whole segment goes to the wave path; slots of its
+                // reservation that lie inside the buffer are marked empty
+                for (unsigned long long r = first; r < (unsigned long long)w.rows_cap; ++r)
+                    w.rows[r] = make_int2(-1, 0);
+                to_big = true;
+            }
+        }
+        const unsigned long long bm = __ballot(to_big);
+        unsigned long long bbase = 0;
+        if (lane == 0 && bm) bbase = atomicAdd(&ctr->n_big[a.gen], (unsigned long long)__popcll(bm));
+        bbase = __shfl(bbase, 0, 64);
+        if (to_big) w.big_list[bbase + __popcll(bm & ((1ull << lane) - 1ull))] = (int)i;
+        flush_mic_counters(ctr, tests, updates);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_mic_rows(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mc,
+                                                  TraceArgs a, MicWork w)
+{
+    unsigned long long n = ctr->n_rows[a.gen];
+    if (n > (unsigned long long)w.rows_cap) n = (unsigned long long)w.rows_cap;
+    for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
+        const unsigned long long r = base + (unsigned long long)lane_id();
+        unsigned tests = 0, updates = 0;
+        const int2 it = r < n ? w.rows[r] : make_int2(-1, 0);
+        if (it.x >= 0) {
+            Frustum f;
+            load_frustum(M, q, segs, it.x, a.delta, f);
+            HalfPlane L[9];
+            footprint_lines(f, mc, L);
+            int c0, c1;
+            if (row_cols(L, mc, it.y, c0, c1))
+                process_row(f, mc, w, ctr, a.gen, it.x, it.y, c0, c1, a.air_m, tests, updates);
+        }
+        flush_mic_counters(ctr, tests, updates);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_mic_spans(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
+                                                   DevMics mc, TraceArgs a, MicWork w)
+{
+    unsigned long long n = ctr->n_spans[a.gen];
+    if (n > (unsigned long long)w.spans_cap) n = (unsigned long long)w.spans_cap;
+    for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
+        const unsigned long long r = base + (unsigned long long)lane_id();
+        unsigned tests = 0, updates = 0;
+        const int4 sp = r < n ? w.spans[r] : make_int4(-1, 0, 0, -1);
+        if (sp.x >= 0) {
+            Frustum f;
+            load_frustum(M, q, segs, sp.x, a.delta, f);
+            for (int c = sp.z; c <= sp.w; ++c) {
+                tests++;
+                updates += mic_apply(f, mc, c, sp.y, a.air_m);
+            }
+        }
+        flush_mic_counters(ctr, tests, updates);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_mics_big(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
+                                                  DevMics mc, TraceArgs a, MicWork w)
+{
+    const unsigned long long n = ctr->n_big[a.gen];
+    const int lane = lane_id();
+    const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int n_waves = (int)((gridDim.x * blockDim.x) >> 6);
+    for (unsigned long long s = (unsigned long long)wave; s < n; s += (unsigned long long)n_waves) {
+        const long long i = w.big_list[s];
+        Frustum f;
+        load_frustum(M, q, segs, i, a.delta, f);
+        HalfPlane L[9];
+        footprint_lines(f, mc, L);
+        int j0, j1;
+        unsigned tests = 0, updates = 0;
+        if (footprint_rows(L, mc, j0, j1)) {
+            for (int j = j0 + lane; j <= j1; j += 64) {
+                int c0, c1;
+                if (!row_cols(L, mc, j, c0, c1)) continue;
+                process_row(f, mc, w, ctr, a.gen, i, j, c0, c1, a.air_m, tests, updates);
+            }
+        }
+        flush_mic_counters(ctr, tests, updates);
+    }
+}
+
+hipError_t launch_mics(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mics,
+                       const TraceArgs &a, MicWork w, int n_cu, hipStream_t s)
+{
+    k_mics<<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_mic_rows<<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_mics_big<<<n_cu * 4, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_mic_spans<<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
+    return hipGetLastError();
+}
+
+}  // namespace bt

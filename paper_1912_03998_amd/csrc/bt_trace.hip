@@ -1,0 +1,464 @@
+// Guiding-ray trace: closest hit through the per-tile hierarchies with hand-off along the
+// ray's tile path, edge/tie flags, and the fused specular reflection + compaction of the
+// children into the next generation's queue.
+//
+// Precision: boxes are tested in FP32 against boxes grown by a margin that covers the
+// rounding of the ray; every triangle first goes through a conservative FP32
+// Moller-Trumbore filter, and only triangles that may be a hit or a flag candidate are
+// decided by the exact FP64 test (FP32 vertices widened exactly, FP64 ray).  The FP64 ray
+// is read from the queue where it is needed rather than held in registers, which keeps
+// the traversal loop small enough for more waves per SIMD.
+#include "bt_device.h"
+
+namespace bt {
+
+__device__ __forceinline__ float f32_down(double x)
+{
+    float f = (float)x;
+    if ((double)f > x) f = nextafterf(f, -INFINITY);
+    return f;
+}
+__device__ __forceinline__ float f32_up(double x)
+{
+    float f = (float)x;
+    if ((double)f < x) f = nextafterf(f, INFINITY);
+    return f;
+}
+
+// Where the ray's FP64 origin and direction live (the input queue), so that the rare
+// exact tests reload them instead of keeping 12 registers busy during traversal.
+struct RaySrc {
+    const double *o;   // queue + D_O * cap
+    const double *c;   // queue + D_C * cap
+    long long cap, i;
+};
+
+__device__ __forceinline__ void load_ray64(RaySrc src, V3 &o, V3 &c)
+{
+    // launder the index so the loads are not hoisted out of the traversal loop
+    long long i = src.i;
+    asm volatile("" : "+v"(i));
+    o = {src.o[i], src.o[src.cap + i], src.o[2 * src.cap + i]};
+    c = {src.c[i], src.c[src.cap + i], src.c[2 * src.cap + i]};
+}
+
+struct RayState {
+    float ox, oy, oz;     // FP32 rounded origin
+    float cx, cy, cz;     // FP32 rounded direction
+    float ix, iy, iz;     // FP32 reciprocal direction (|c| clamped away from 0)
+    float o_l1;           // |ox| + |oy| + |oz|, bounds the origin's rounding
+    int start;
+    double best_t;
+    int best_id;
+    int best_near;        // hit point within delta of an edge, or t* - t_min < delta
+    double c1_t, c2_t;    // two smallest flag-candidate parameters
+    int c1_id;
+    unsigned node_visits, tri_tests;
+};
+
+// Distance from P to segment [a, b].
+__device__ double seg_dist(V3 p, V3 a, V3 b)
+{
+    const V3 ab = b - a, ap = p - a;
+    const double l2 = dot(ab, ab);
+    double u = l2 > 0.0 ? dot(ap, ab) / l2 : 0.0;
+    u = fmin(fmax(u, 0.0), 1.0);
+    const V3 r = p - (a + u * ab);
+    return sqrt(dot(r, r));
+}
+
+// Signed in-plane distance of the plane point to the triangle boundary (>= 0 inside:
+// distance to the nearest edge; < 0 outside: minus the distance to the triangle).
+__device__ double exact_signed_dist(V3 P, double u, double v, double w, V3 v0, V3 v1, V3 v2)
+{
+    const V3 e1 = v1 - v0, e2 = v2 - v0, e12 = v2 - v1;
+    const V3 N = cross(e1, e2);
+    const double a2 = sqrt(dot(N, N));
+    const double s0 = w * a2 / sqrt(dot(e12, e12));
+    const double s1 = u * a2 / sqrt(dot(e2, e2));
+    const double s2 = v * a2 / sqrt(dot(e1, e1));
+    const double m = fmin(s0, fmin(s1, s2));
+    if (m >= 0.0) return m;
+    return -fmin(seg_dist(P, v0, v1), fmin(seg_dist(P, v1, v2), seg_dist(P, v2, v0)));
+}
+
+// Conservative FP32 filter.  Each FP32 quantity (det, the barycentric numerators, the
+// parameter numerator) deviates from its exact value by far less than
+// B = 2^-18 x (product of the L1 magnitudes of its operands), including the rounding of
+// the ray origin and direction.  The triangle is skipped only when, under those bounds,
+// its plane point is surely more than delta outside an edge or surely outside the
+// parameter window (lo, hi).
+__device__ __forceinline__ bool maybe_candidate(const float4 &a, const float4 &b, const float4 &cc,
+                                                const RayState &r, float lo, float hi, float dh_num)
+{
+    const float e1x = a.w - a.x, e1y = b.x - a.y, e1z = b.y - a.z;
+    const float e2x = b.z - a.x, e2y = b.w - a.y, e2z = cc.x - a.z;
+    const float tx = r.ox - a.x, ty = r.oy - a.y, tz = r.oz - a.z;
+    const float px = r.cy * e2z - r.cz * e2y, py = r.cz * e2x - r.cx * e2z, pz = r.cx * e2y - r.cy * e2x;
+    const float qx = ty * e1z - tz * e1y, qy = tz * e1x - tx * e1z, qz = tx * e1y - ty * e1x;
+    float det = e1x * px + e1y * py + e1z * pz;
+    float un = tx * px + ty * py + tz * pz;
+    float vn = r.cx * qx + r.cy * qy + r.cz * qz;
+    float tn = e2x * qx + e2y * qy + e2z * qz;
+    const float k = 0x1p-18f;
+    const float l1 = fabsf(e1x) + fabsf(e1y) + fabsf(e1z), l2 = fabsf(e2x) + fabsf(e2y) + fabsf(e2z);
+    const float lt = fabsf(tx) + fabsf(ty) + fabsf(tz) + r.o_l1;
+    const float bd = k * l1 * l2, bu = k * lt * l2, bv = k * lt * l1, bt = k * lt * l1 * l2;
+    if (!(fabsf(det) > bd)) return true;  // grazing or sign uncertain: decide exactly
+    if (det < 0.0f) {
+        det = -det;
+        un = -un;
+        vn = -vn;
+        tn = -tn;
+    }
+    const float wn = det - un - vn, bw = bd + bu + bv;
+    const float slack = (dh_num / cc.z) * (det + bd);  // (delta / h_min) * max |det|
+    if (un + bu < -slack || vn + bv < -slack || wn + bw < -slack) return false;
+    if (lo > -INFINITY && tn + bt <= lo * (lo >= 0.0f ? det - bd : det + bd)) return false;
+    if (hi < INFINITY && hi >= 0.0f && tn - bt >= hi * (det + bd)) return false;
+    return true;
+}
+
+// Test the triangle references [first, first + count) over the tile window.
+//   valid hit:   t in (hit_lo, t_hi], inside, better than the current best
+//   candidate:   t in (cand_lo, t_hi], t < best_t + delta, within delta of the triangle
+__device__ __forceinline__ void test_leaf(const float4 *__restrict__ tris, int first, int count, RayState &r,
+                                          RaySrc src, double hit_lo, double cand_lo, double t_hi, double t_min,
+                                          double delta)
+{
+    for (int k = first; k < first + count; ++k) {
+        const float4 a = tris[3 * k], b = tris[3 * k + 1], cc = tris[3 * k + 2];
+        const int id = __float_as_int(cc.y);
+        if (id == r.start) continue;
+        r.tri_tests++;
+        const double upper = fmin(t_hi, r.best_t + delta);
+        if (!maybe_candidate(a, b, cc, r, f32_down(cand_lo), f32_up(upper), (float)delta)) continue;
+        V3 o, c;
+        load_ray64(src, o, c);
+        const V3 v0 = {a.x, a.y, a.z}, v1 = {a.w, b.x, b.y}, v2 = {b.z, b.w, cc.x};
+        const V3 e1 = v1 - v0, e2 = v2 - v0;
+        const V3 p = cross(c, e2);
+        const double det = dot(e1, p);
+        if (det == 0.0) continue;
+        const double inv = 1.0 / det;
+        const V3 T = o - v0;
+        const V3 q = cross(T, e1);
+        const double t = dot(e2, q) * inv;
+        if (!(t > cand_lo && t <= t_hi && t < r.best_t + delta)) continue;
+        const double u = dot(T, p) * inv;
+        const double v = dot(c, q) * inv;
+        const double w = (1.0 - u) - v;
+        const double wmin = fmin(u, fmin(v, w));
+        const double hmin = (double)cc.z;
+        double sd;
+        if (wmin >= 0.0 && wmin * hmin >= delta) {
+            sd = delta;  // inside and at least delta from every edge
+        } else if (wmin < 0.0 && -wmin * hmin >= delta) {
+            continue;    // outside by at least delta
+        } else {
+            sd = exact_signed_dist(o + t * c, u, v, w, v0, v1, v2);
+            if (sd <= -delta) continue;
+        }
+        // flag candidate: keep the two smallest parameters (ties by id for the first)
+        if (t < r.c1_t || (t == r.c1_t && id < r.c1_id)) {
+            r.c2_t = r.c1_t;
+            r.c1_t = t;
+            r.c1_id = id;
+        } else if (t < r.c2_t) {
+            r.c2_t = t;
+        }
+        if (sd >= 0.0 && t > hit_lo && (t < r.best_t || (t == r.best_t && id < r.best_id))) {
+            r.best_t = t;
+            r.best_id = id;
+            r.best_near = (sd < delta) || (t - t_min < delta);
+        }
+    }
+}
+
+__device__ __forceinline__ void box2(const float4 &nx, const float4 &ny, const float4 &nz, const RayState &r,
+                                     float tlo, float thi, float &t0, float &t1, bool &h0, bool &h1)
+{
+    const float ax0 = (nx.x - r.ox) * r.ix, bx0 = (nx.z - r.ox) * r.ix;
+    const float ay0 = (ny.x - r.oy) * r.iy, by0 = (ny.z - r.oy) * r.iy;
+    const float az0 = (nz.x - r.oz) * r.iz, bz0 = (nz.z - r.oz) * r.iz;
+    const float mn0 = fmaxf(fmaxf(fminf(ax0, bx0), fminf(ay0, by0)), fmaxf(fminf(az0, bz0), tlo));
+    const float mx0 = fminf(fminf(fmaxf(ax0, bx0), fmaxf(ay0, by0)), fminf(fmaxf(az0, bz0), thi));
+    const float ax1 = (nx.y - r.ox) * r.ix, bx1 = (nx.w - r.ox) * r.ix;
+    const float ay1 = (ny.y - r.oy) * r.iy, by1 = (ny.w - r.oy) * r.iy;
+    const float az1 = (nz.y - r.oz) * r.iz, bz1 = (nz.w - r.oz) * r.iz;
+    const float mn1 = fmaxf(fmaxf(fminf(ax1, bx1), fminf(ay1, by1)), fmaxf(fminf(az1, bz1), tlo));
+    const float mx1 = fminf(fminf(fmaxf(ax1, bx1), fmaxf(ay1, by1)), fminf(fmaxf(az1, bz1), thi));
+    h0 = mn0 <= mx0;
+    h1 = mn1 <= mx1;
+    t0 = mn0;
+    t1 = mn1;
+}
+
+__device__ __forceinline__ bool box1(const float *bx, const RayState &r, float tlo, float thi)
+{
+    const float ax = (bx[0] - r.ox) * r.ix, bxx = (bx[3] - r.ox) * r.ix;
+    const float ay = (bx[1] - r.oy) * r.iy, by = (bx[4] - r.oy) * r.iy;
+    const float az = (bx[2] - r.oz) * r.iz, bz = (bx[5] - r.oz) * r.iz;
+    const float mn = fmaxf(fmaxf(fminf(ax, bxx), fminf(ay, by)), fmaxf(fminf(az, bz), tlo));
+    const float mx = fminf(fminf(fmaxf(ax, bxx), fmaxf(ay, by)), fminf(fmaxf(az, bz), thi));
+    return mn <= mx;
+}
+
+// Traverse one tile's hierarchy over the ray window (t_lo, t_hi].
+__device__ void traverse_tile(const DevMesh &M, int tile, RayState &r, RaySrc src, double t_lo, double t_hi,
+                              double t_min, double delta, int *stk)
+{
+    const int root = M.tile_root[tile];
+    if (root == kEmptyRoot) return;
+    const double hit_lo = fmax(t_lo, t_min);
+    const double cand_lo = fmax(t_lo, t_min - delta);
+    const float flo = f32_down(cand_lo);
+    if (!box1(M.tile_box + 6 * tile, r, flo, f32_up(fmin(t_hi, r.best_t + delta)))) return;
+    const int bdim = blockDim.x;
+    const int tid = threadIdx.x;
+    int sp = 0;
+    int ref = root;
+    while (true) {
+        if (ref >= 0) {
+            const float4 *nd = M.nodes + 4 * (long long)ref;
+            const float4 nx = nd[0], ny = nd[1], nz = nd[2], nr = nd[3];
+            r.node_visits++;
+            float t0, t1;
+            bool h0, h1;
+            box2(nx, ny, nz, r, flo, f32_up(fmin(t_hi, r.best_t + delta)), t0, t1, h0, h1);
+            const int c0 = __float_as_int(nr.x), c1 = __float_as_int(nr.y);
+            if (h0 && h1) {
+                const bool first0 = t0 <= t1;
+                stk[sp * bdim + tid] = first0 ? c1 : c0;
+                sp++;
+                ref = first0 ? c0 : c1;
+                continue;
+            } else if (h0) {
+                ref = c0;
+                continue;
+            } else if (h1) {
+                ref = c1;
+                continue;
+            }
+        } else {
+            const int v = ~ref;
+            test_leaf(M.tris, v >> 3, v & 7, r, src, hit_lo, cand_lo, t_hi, t_min, delta);
+        }
+        if (sp == 0) break;
+        sp--;
+        ref = stk[sp * bdim + tid];
+    }
+}
+
+// Walk the tiles crossed by the ray in order (half-open parameter windows (t_lo, t_hi]
+// shared by consecutive tiles) and traverse each over its window.
+__device__ void trace_ray(const DevMesh &M, RayState &r, RaySrc src, double t_min, double delta, int *stk)
+{
+    double te = -INFINITY, tx = INFINITY;
+    bool ok = true;
+    double tnx = INFINITY, tny = INFINITY, dtx = INFINITY, dty = INFINITY;
+    int ix, iy, sx, sy;
+    {
+        V3 o, c;
+        load_ray64(src, o, c);
+        const double o3[3] = {o.x, o.y, o.z}, c3[3] = {c.x, c.y, c.z};
+        const double lo3[3] = {M.gx0, M.gy0, M.zmin}, hi3[3] = {M.gx1, M.gy1, M.zmax};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (c3[k] != 0.0) {
+                const double ta = (lo3[k] - o3[k]) / c3[k], tb = (hi3[k] - o3[k]) / c3[k];
+                te = fmax(te, fmin(ta, tb));
+                tx = fmin(tx, fmax(ta, tb));
+            } else if (o3[k] < lo3[k] || o3[k] > hi3[k]) {
+                ok = false;
+            }
+        }
+        const double t_start = fmax(te, t_min - delta);
+        if (!ok || !(t_start <= tx)) return;
+        te = t_start;
+        const double px = o.x + t_start * c.x, py = o.y + t_start * c.y;
+        ix = (int)floor((px - M.gx0) / M.tw);
+        iy = (int)floor((py - M.gy0) / M.th);
+        ix = ix < 0 ? 0 : (ix >= M.tiles_x ? M.tiles_x - 1 : ix);
+        iy = iy < 0 ? 0 : (iy >= M.tiles_y ? M.tiles_y - 1 : iy);
+        sx = c.x > 0.0 ? 1 : (c.x < 0.0 ? -1 : 0);
+        sy = c.y > 0.0 ? 1 : (c.y < 0.0 ? -1 : 0);
+        // parameter of the next interior tile boundary in x and y, and the step between
+        // boundaries; the outermost boundary is left to the exit parameter tx
+        if ((sx > 0 && ix < M.tiles_x - 1) || (sx < 0 && ix > 0)) {
+            tnx = (M.gx0 + (double)(sx > 0 ? ix + 1 : ix) * M.tw - o.x) / c.x;
+            dtx = M.tw / fabs(c.x);
+        }
+        if ((sy > 0 && iy < M.tiles_y - 1) || (sy < 0 && iy > 0)) {
+            tny = (M.gy0 + (double)(sy > 0 ? iy + 1 : iy) * M.th - o.y) / c.y;
+            dty = M.th / fabs(c.y);
+        }
+    }
+    double t_lo = te;
+    for (int guard = 0; guard < 2 * (M.tiles_x + M.tiles_y) + 2; ++guard) {
+        const double t_hi = fmin(fmin(tnx, tny), tx);
+        if (t_hi > t_lo) traverse_tile(M, iy * M.tiles_x + ix, r, src, t_lo, t_hi, t_min, delta, stk);
+        if (t_hi >= tx || t_hi >= r.best_t + delta) break;
+        const bool stepx = tnx <= tny, stepy = tny <= tnx;
+        if (stepx) {
+            ix += sx;
+            const bool more = (sx > 0 && ix < M.tiles_x - 1) || (sx < 0 && ix > 0);
+            tnx = more ? tnx + dtx : INFINITY;
+        }
+        if (stepy) {
+            iy += sy;
+            const bool more = (sy > 0 && iy < M.tiles_y - 1) || (sy < 0 && iy > 0);
+            tny = more ? tny + dty : INFINITY;
+        }
+        if (ix < 0 || ix >= M.tiles_x || iy < 0 || iy >= M.tiles_y) break;
+        t_lo = t_hi;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_trace(DevMesh M, DevQueue in, DevSegs segs, DevCounters *ctr, TraceArgs a)
+{
+    __shared__ int stk[kStack * 256];
+    const unsigned long long n = ctr->count[a.gen];
+    const long long s0 = (long long)gen_start(ctr, a.gen);
+    const int lane = lane_id();
+    const long long icap = in.cap;
+    const int D1 = a.max_depth + 1;
+    for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
+        const bool active = (long long)base + lane < (long long)n;
+        const long long i = s0 + (long long)base + lane;
+        int flag_total = 0;
+        double power_term = 0.0;
+        unsigned nv = 0, tt = 0;
+        const RaySrc src{in.dbl + D_O * icap, in.dbl + D_C * icap, icap, active ? i : 0};
+        if (active) {
+            RayState r;
+            {
+                V3 o, c;
+                load_ray64(src, o, c);
+                r.ox = (float)o.x;
+                r.oy = (float)o.y;
+                r.oz = (float)o.z;
+                r.cx = (float)c.x;
+                r.cy = (float)c.y;
+                r.cz = (float)c.z;
+                r.o_l1 = fabsf(r.ox) + fabsf(r.oy) + fabsf(r.oz);
+                const double tiny = 1e-20;
+                r.ix = (float)(1.0 / (fabs(c.x) < tiny ? copysign(tiny, c.x) : c.x));
+                r.iy = (float)(1.0 / (fabs(c.y) < tiny ? copysign(tiny, c.y) : c.y));
+                r.iz = (float)(1.0 / (fabs(c.z) < tiny ? copysign(tiny, c.z) : c.z));
+            }
+            r.start = in.ints[I_START * icap + i];
+            r.best_t = INFINITY;
+            r.best_id = -1;
+            r.best_near = 0;
+            r.c1_t = INFINITY;
+            r.c2_t = INFINITY;
+            r.c1_id = -1;
+            r.node_visits = 0;
+            r.tri_tests = 0;
+            trace_ray(M, r, src, a.t_min, a.delta, stk);
+            const int meta = in.ints[I_META * icap + i];
+            const int id = in.ints[I_ID * icap + i];
+            const float K = in.flt[F_K * icap + i];
+            const float om = in.flt[F_OMEGA * icap + i];
+            const int hit = r.best_id;
+            int own_flag;
+            if (hit >= 0) own_flag = r.best_near || (r.c1_id != hit) || (r.c2_t < r.best_t + a.delta);
+            else own_flag = r.c1_t < INFINITY;
+            flag_total = ((meta & kMetaFlag) != 0) || own_flag;
+            segs.hit[i] = hit;
+            segs.t[i] = r.best_t;
+            segs.flag[i] = flag_total;
+            const long long oidx = (long long)id * D1 + a.gen;
+            if (a.hit_out) a.hit_out[oidx] = hit;
+            if (a.flag_out) a.flag_out[oidx] = (uint8_t)flag_total;
+            if (a.t_out) a.t_out[oidx] = r.best_t;
+            power_term = (double)K * (double)om;
+            nv = r.node_visits;
+            tt = r.tri_tests;
+        }
+        // wave-aggregated counters (fire-and-forget atomics)
+        const unsigned long long fl = wave_sum_u64((unsigned long long)(active && flag_total));
+        const double pw = wave_sum_f64(power_term);
+        const unsigned long long snv = wave_sum_u64(nv), stt = wave_sum_u64(tt);
+        if (lane == 0) {
+            if (fl) atomicAdd(&ctr->flagged[a.gen], fl);
+            atomicAdd(&ctr->power[a.gen], pw);
+            atomicAdd(&ctr->node_visits, snv);
+            atomicAdd(&ctr->tri_tests, stt);
+        }
+    }
+}
+
+// Specular reflection without splitting: every hit with depth < max_depth (and, when set,
+// power above e_min) spawns one child mirrored in the hit triangle's plane (apex, edge and
+// guiding directions; d1 and d2 swapped to keep det > 0), starting at the hit point with
+// K (1 - alpha).  Children are compacted into the next queue with a wave ballot, a
+// popcount prefix and one atomic per wave.
+__global__ void __launch_bounds__(256) k_reflect(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, TraceArgs a)
+{
+    const unsigned long long n = ctr->count[a.gen];
+    const long long s0 = (long long)gen_start(ctr, a.gen);
+    const long long s1 = s0 + (long long)n;  // the children's generation starts here
+    const int lane = lane_id();
+    const DevQueue &in = q, &out = q;
+    const long long icap = q.cap, ocap = q.cap;
+    for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
+        const long long i = s0 + (long long)base + lane;
+        int child = 0, hit = -1, meta = 0;
+        float K = 0.f, Kc = 0.f;
+        if ((long long)base + lane < (long long)n) {
+            hit = segs.hit[i];
+            meta = in.ints[I_META * icap + i];
+            if (hit >= 0 && (meta & 0xff) < a.max_depth) {
+                K = in.flt[F_K * icap + i];
+                Kc = K * (1.0f - M.alpha[hit]);
+                child = !(a.e_min > 0.0) || ((double)Kc * (double)in.flt[F_OMEGA * icap + i] > a.e_min);
+            }
+        }
+        const unsigned long long mask = __ballot(child);
+        if (mask == 0) continue;
+        unsigned long long obase = 0;
+        if (lane == 0) obase = atomicAdd(&ctr->count[a.gen + 1], (unsigned long long)__popcll(mask));
+        obase = __shfl(obase, 0, 64);
+        if (child) {
+            V3 v0, v1, v2;
+            tri_vertices(M.tri_g, hit, v0, v1, v2);
+            const V3 N = cross(v1 - v0, v2 - v0);
+            const V3 nn = unit(N);
+            const V3 A = ld3(in.dbl + D_A * icap, icap, i);
+            const V3 o = ld3(in.dbl + D_O * icap, icap, i), c = ld3(in.dbl + D_C * icap, icap, i);
+            const double t = segs.t[i];
+            const V3 A2 = A - (2.0 * dot(A - v0, nn)) * nn;
+            const V3 o2 = o + t * c;
+            const V3 c2 = mirror(c, nn);
+            // the child lives on the side the parent came from
+            const int meta2 = ((meta & 0xff) + 1) | (dot(c, N) > 0.0 ? kMetaNegNear : 0) |
+                              (segs.flag[i] ? kMetaFlag : 0);
+            const long long j = s1 + (long long)obase + __popcll(mask & ((1ull << lane) - 1ull));
+            st3(out.dbl + D_A * ocap, ocap, j, A2);
+            st3(out.dbl + D_D0 * ocap, ocap, j, mirror(ld3(in.dbl + D_D0 * icap, icap, i), nn));
+            st3(out.dbl + D_D1 * ocap, ocap, j, mirror(ld3(in.dbl + D_D2 * icap, icap, i), nn));
+            st3(out.dbl + D_D2 * ocap, ocap, j, mirror(ld3(in.dbl + D_D1 * icap, icap, i), nn));
+            st3(out.dbl + D_O * ocap, ocap, j, o2);
+            st3(out.dbl + D_C * ocap, ocap, j, c2);
+            out.flt[F_K * ocap + j] = Kc;
+            out.flt[F_OMEGA * ocap + j] = in.flt[F_OMEGA * icap + i];
+            out.ints[I_ID * ocap + j] = in.ints[I_ID * icap + i];
+            out.ints[I_START * ocap + j] = hit;
+            out.ints[I_META * ocap + j] = meta2;
+        }
+    }
+}
+
+hipError_t launch_trace(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, const TraceArgs &a, int n_cu,
+                        hipStream_t s)
+{
+    k_trace<<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_reflect<<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, a);
+    return hipGetLastError();
+}
+
+}  // namespace bt

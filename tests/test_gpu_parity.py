@@ -342,13 +342,14 @@ def test_submit_poll_matches_plain_run(torch_cuda):
             bt.bt_poll(s.ctx, tk, sc.n_mic)
 
 
-def test_mic_row_overflow_fallback(torch_cuda, monkeypatch):
-    """A tiny (segment, row) item buffer forces wide footprints onto the one-wave-per-
-    segment path; results must not change."""
+@pytest.mark.parametrize("env", ["BT_MIC_ROW_CAPACITY", "BT_MIC_SPAN_CAPACITY"])
+def test_mic_work_buffer_overflow(torch_cuda, monkeypatch, env):
+    """Tiny work-item buffers force wide footprints onto the one-wave-per-segment path and
+    long rows onto in-place processing; results must not change."""
     sc = block_scene(0)
-    say("mic row-item overflow fallback")
+    say("mic work buffer overflow", env)
     o = O.trace(sc)
-    monkeypatch.setenv("BT_MIC_ROW_CAPACITY", "1000")
+    monkeypatch.setenv(env, "1000")
     with session(sc) as s:
         g = gpu_run(s, sc)
     full_verdict(sc, g, o)
