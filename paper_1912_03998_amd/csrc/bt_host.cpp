@@ -56,7 +56,10 @@ struct bt_beams {
     DevQueue q{};             // every generation, contiguous (see DevQueue)
     DevSegs segs{};
     DevCounters *ctr = nullptr;
-    int *big_list = nullptr;
+    WaveScratch ws{};         // per-wave records of the statically partitioned kernels
+    void *ws_buf = nullptr;
+    size_t ws_bytes = 0;
+    int *big_list = nullptr;  // 2 * cap: wave-path overflow list, then the general-path list
     int2 *rows = nullptr;
     long long rows_cap = 0;
     int4 *spans = nullptr;
@@ -640,6 +643,33 @@ extern "C" bt_status bt_mics_free(bt_mics *m)
 // ---------------------------------------------------------------------------------------
 // beams
 // ---------------------------------------------------------------------------------------
+// Integers in the segment-list buffer of a queue of capacity n: the wave-path overflow
+// list (n), then the general-path list, whose per-wave regions hold 64 items per batch
+// (at most n + 64 (W + 1)).
+static size_t list_ints(long long n, int n_waves)
+{
+    return (size_t)(2 * n + 64 * ((long long)n_waves + 1));
+}
+
+// Per-wave scratch of a beam set for a grid of W = n_cu * kBlocksPerCU * kWavesPerBlock
+// waves: children, offsets, 3 stats, power (8 B each) and general counts (4 B).
+static bt_status alloc_wave_scratch(bt_ctx *ctx, bt_beams *b)
+{
+    const int W = ctx->n_cu * kBlocksPerCU * kWavesPerBlock;
+    const size_t bytes = (size_t)W * (6 * 8 + 4);
+    bt_status s = dev_alloc(ctx, &b->ws_buf, bytes);
+    if (s != BT_OK) return s;
+    b->ws_bytes = bytes;
+    char *p = (char *)b->ws_buf;
+    b->ws.children = (unsigned long long *)p;
+    b->ws.offset = b->ws.children + W;
+    b->ws.stats = b->ws.offset + W;
+    b->ws.power = (double *)(b->ws.stats + 3 * (size_t)W);
+    b->ws.general = (unsigned int *)(b->ws.power + W);
+    b->ws.n_waves = W;
+    return BT_OK;
+}
+
 static void queue_free(bt_ctx *ctx, DevQueue &q)
 {
     dev_free(ctx, q.dbl, (size_t)q.cap * D_N * sizeof(double));
@@ -656,7 +686,7 @@ static void beams_release(bt_beams *b)
     dev_free(ctx, b->segs.t, (size_t)b->cap * sizeof(double));
     dev_free(ctx, b->segs.flag, (size_t)b->cap * sizeof(int));
     b->segs = DevSegs{};
-    dev_free(ctx, b->big_list, (size_t)b->cap * sizeof(int));
+    dev_free(ctx, b->big_list, list_ints(b->cap, b->ws.n_waves) * sizeof(int));
     b->big_list = nullptr;
     b->cap = 0;
     dev_free(ctx, b->rows, (size_t)b->rows_cap * sizeof(int2));
@@ -700,14 +730,14 @@ static bt_status reserve_queue(bt_ctx *ctx, bt_beams *b, long long n, long long 
     dev_free(ctx, b->segs.hit, (size_t)b->cap * sizeof(int));
     dev_free(ctx, b->segs.t, (size_t)b->cap * sizeof(double));
     dev_free(ctx, b->segs.flag, (size_t)b->cap * sizeof(int));
-    dev_free(ctx, b->big_list, (size_t)b->cap * sizeof(int));
+    dev_free(ctx, b->big_list, list_ints(b->cap, b->ws.n_waves) * sizeof(int));
     b->segs = DevSegs{};
     b->big_list = nullptr;
     b->cap = 0;
     if ((s = dev_alloc(ctx, (void **)&b->segs.hit, (size_t)n * sizeof(int))) != BT_OK) return s;
     if ((s = dev_alloc(ctx, (void **)&b->segs.t, (size_t)n * sizeof(double))) != BT_OK) return s;
     if ((s = dev_alloc(ctx, (void **)&b->segs.flag, (size_t)n * sizeof(int))) != BT_OK) return s;
-    if ((s = dev_alloc(ctx, (void **)&b->big_list, (size_t)n * sizeof(int))) != BT_OK) return s;
+    if ((s = dev_alloc(ctx, (void **)&b->big_list, list_ints(n, b->ws.n_waves) * sizeof(int))) != BT_OK) return s;
     b->cap = n;
     return BT_OK;
 }
@@ -769,7 +799,11 @@ extern "C" bt_status bt_emit_beams(bt_ctx *ctx, const float *src_xyz, const floa
         b->ctx = ctx;
         fresh = true;
         bt_status s = dev_alloc(ctx, (void **)&b->ctr, sizeof(DevCounters));
-        if (s != BT_OK) { delete b; return s; }
+        if (s == BT_OK) s = alloc_wave_scratch(ctx, b);
+        if (s != BT_OK) {
+            bt_beams_free(b);
+            return s;
+        }
     }
     // room for every generation of the previous run's depth (grown at the first trace if
     // the depth is larger)
@@ -811,6 +845,7 @@ extern "C" bt_status bt_beams_free(bt_beams *b)
     if (!b) return BT_EINVAL;
     beams_release(b);
     dev_free(b->ctx, b->ctr, sizeof(DevCounters));
+    dev_free(b->ctx, b->ws_buf, b->ws_bytes);
     dev_free(b->ctx, b->src_dev, (size_t)b->src_cap * 3 * sizeof(float));
     dev_free(b->ctx, b->pow_dev, (size_t)b->src_cap * sizeof(float));
     delete b;
@@ -889,7 +924,7 @@ extern "C" bt_status bt_trace(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *b, con
     }
     b->max_depth = p->max_depth;
     TraceArgs a = make_args(p, g);
-    HIP_TRY(ctx, launch_trace(mesh->dev, b->q, b->segs, b->ctr, a, ctx->n_cu, ctx->stream));
+    HIP_TRY(ctx, launch_trace(mesh->dev, b->q, b->segs, b->ctr, a, b->ws, ctx->n_cu, ctx->stream));
     b->gen = g + 1;
     if (n_next) {
         unsigned long long c = 0;
@@ -913,8 +948,8 @@ extern "C" bt_status bt_accumulate_mics(bt_ctx *ctx, const bt_mesh *mesh, bt_bea
     // all generations traced since the previous call, in one pass
     TraceArgs a = make_args(p, b->acc_gen);
     a.gen_end = b->gen;
-    MicWork w{b->rows, b->rows_cap, b->spans, b->spans_cap, b->big_list};
-    HIP_TRY(ctx, launch_mics(mesh->dev, b->q, b->segs, b->ctr, mics->dev, a, w, ctx->n_cu, ctx->stream));
+    MicWork w{b->rows, b->rows_cap, b->spans, b->spans_cap, b->big_list + b->cap, b->big_list};
+    HIP_TRY(ctx, launch_mics(mesh->dev, b->q, b->segs, b->ctr, mics->dev, a, w, b->ws, ctx->n_cu, ctx->stream));
     b->acc_gen = b->gen;
     return BT_OK;
 }

@@ -98,7 +98,24 @@ struct MicWork {
     long long rows_cap;
     int4 *spans;
     long long spans_cap;
+    int *general;      // segments for the general footprint path; capacity: the queue's
     int *big_list;     // capacity: the queue capacity
+};
+
+// Per-wave records of the statically partitioned kernels (wave w of a grid of W waves
+// takes the batches w, w + W, ...), so that counts and offsets need no shared atomic:
+//   trace:  children[w], stats (flagged, node visits, triangle tests) and power per wave,
+//           turned into child offsets and per-generation totals by a one-block scan;
+//   microphones: general[w] items found by wave w, stored in its own region.
+constexpr int kBlocksPerCU = 8;
+constexpr int kWavesPerBlock = 4;
+struct WaveScratch {
+    unsigned long long *children;  // [W]
+    unsigned long long *offset;    // [W] exclusive scan of children
+    unsigned long long *stats;     // [W][3] flagged, node visits, triangle tests
+    double *power;                 // [W]
+    unsigned int *general;         // [W] general-path items per wave (microphones)
+    int n_waves;                   // W
 };
 
 struct TraceArgs {
@@ -115,10 +132,10 @@ struct TraceArgs {
 hipError_t launch_init_counters(DevCounters *ctr, long long n0, hipStream_t s);
 hipError_t launch_emit(const double *base20, const float *src, const float *power, int n_src, int level,
                        DevQueue q, hipStream_t s);
-hipError_t launch_trace(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, const TraceArgs &a, int n_cu,
-                        hipStream_t s);
+hipError_t launch_trace(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, const TraceArgs &a,
+                        WaveScratch ws, int n_cu, hipStream_t s);
 hipError_t launch_mics(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mics,
-                       const TraceArgs &a, MicWork w, int n_cu, hipStream_t s);
+                       const TraceArgs &a, MicWork w, WaveScratch ws, int n_cu, hipStream_t s);
 hipError_t launch_fill(double *p, long long n, double v, hipStream_t s);
 hipError_t launch_levels(const double *es, const double *ef, double *level, long long n, hipStream_t s);
 

@@ -252,21 +252,32 @@ __device__ __forceinline__ void flush_mic_counters(DevCounters *ctr, unsigned te
     }
 }
 
-__global__ void __launch_bounds__(256) k_mics(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mc,
-                                              TraceArgs a, MicWork w)
+// Fast path over all segments of generations [gen, gen_end) (contiguous in the queue):
+// footprints that are a proper triangle on the microphone plane with at most kSpan
+// lattice points in their bounding box are finished here (most have none); the others
+// are appended to the general list.
+// Wave w's region of the general list: room for 64 items per batch it processes.
+__device__ __forceinline__ unsigned long long general_region(unsigned long long n, int n_waves)
 {
-    // the segments of generations [gen, gen_end), contiguous in the queue
+    const unsigned long long batches = (n + 63) / 64;
+    return ((batches + (unsigned long long)n_waves - 1) / (unsigned long long)n_waves) * 64;
+}
+
+__global__ void __launch_bounds__(256) k_mics(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mc,
+                                              TraceArgs a, MicWork w, WaveScratch ws)
+{
     const unsigned long long s0 = gen_start(ctr, a.gen);
     const unsigned long long n = gen_start(ctr, a.gen_end) - s0;
     const int lane = lane_id();
+    const unsigned long long wave = wave_first_batch() >> 6;
+    const unsigned long long region = wave * general_region(n, ws.n_waves);
+    unsigned gcount = 0;
+    unsigned tests = 0, updates = 0;
     for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
         const long long i = (long long)(s0 + base) + lane;
-        unsigned tests = 0, updates = 0;
-        int nrows = 0, j0 = 0, j1 = -1;
-        bool wide = false;
         bool general = false;
-        Frustum f;
         if ((long long)base + lane < (long long)n) {
+            Frustum f;
             // Fast path: when all three edge rays cross the microphone plane ahead of the
             // apex, the frustum meets the plane inside the triangle of the three crossing
             // points (the caps only cut it down), so the lattice points of that triangle's
@@ -305,9 +316,38 @@ __global__ void __launch_bounds__(256) k_mics(DevMesh M, DevQueue q, DevSegs seg
                         }
                 }
             }
-            if (general) load_frustum(M, q, segs, i, a.delta, f);
         }
-        if (general) {
+        // general-path segments go to this wave's own region of the list (no atomics)
+        const unsigned long long gm = __ballot(general);
+        if (general) w.general[region + gcount + __popcll(gm & ((1ull << lane) - 1ull))] = (int)i;
+        gcount += (unsigned)__popcll(gm);
+    }
+    if (lane == 0) ws.general[wave] = gcount;
+    flush_mic_counters(ctr, tests, updates);
+}
+
+// General path, one lane per listed segment: the footprint's row range from the clipped
+// polygon; up to kInlineRows rows are finished here, wider footprints become (segment,
+// row) work items.
+__global__ void __launch_bounds__(256) k_mics_general(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
+                                                      DevMics mc, TraceArgs a, MicWork w, WaveScratch ws)
+{
+    // wave w takes the items k_mics wave w put in its region (same grid)
+    const unsigned long long s0 = gen_start(ctr, a.gen);
+    const unsigned long long n_seg = gen_start(ctr, a.gen_end) - s0;
+    const int lane = lane_id();
+    const unsigned long long wave = wave_first_batch() >> 6;
+    const unsigned long long region = wave * general_region(n_seg, ws.n_waves);
+    const unsigned long long n = ws.general[wave];
+    unsigned tests = 0, updates = 0;
+    for (unsigned long long base = 0; base < n; base += 64) {
+        const bool active = base + lane < n;
+        const long long i = active ? w.general[region + base + lane] : 0;
+        int nrows = 0, j0 = 0, j1 = -1;
+        bool wide = false;
+        if (active) {
+            Frustum f;
+            load_frustum(M, q, segs, i, a.delta, f);
             HalfPlane L[9];
             footprint_lines(f, mc, L);
             if (footprint_rows(L, mc, j0, j1)) {
@@ -353,8 +393,8 @@ __global__ void __launch_bounds__(256) k_mics(DevMesh M, DevQueue q, DevSegs seg
         if (lane == 0 && bm) bbase = atomicAdd(&ctr->n_big[a.gen], (unsigned long long)__popcll(bm));
         bbase = __shfl(bbase, 0, 64);
         if (to_big) w.big_list[bbase + __popcll(bm & ((1ull << lane) - 1ull))] = (int)i;
-        flush_mic_counters(ctr, tests, updates);
     }
+    flush_mic_counters(ctr, tests, updates);
 }
 
 __global__ void __launch_bounds__(256) k_mic_rows(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mc,
@@ -362,9 +402,9 @@ __global__ void __launch_bounds__(256) k_mic_rows(DevMesh M, DevQueue q, DevSegs
 {
     unsigned long long n = ctr->n_rows[a.gen];
     if (n > (unsigned long long)w.rows_cap) n = (unsigned long long)w.rows_cap;
+    unsigned tests = 0, updates = 0;
     for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
         const unsigned long long r = base + (unsigned long long)lane_id();
-        unsigned tests = 0, updates = 0;
         const int2 it = r < n ? w.rows[r] : make_int2(-1, 0);
         if (it.x >= 0) {
             Frustum f;
@@ -375,8 +415,8 @@ __global__ void __launch_bounds__(256) k_mic_rows(DevMesh M, DevQueue q, DevSegs
             if (row_cols(L, mc, it.y, c0, c1))
                 process_row(f, mc, w, ctr, a.gen, it.x, it.y, c0, c1, a.air_m, tests, updates);
         }
-        flush_mic_counters(ctr, tests, updates);
     }
+    flush_mic_counters(ctr, tests, updates);
 }
 
 __global__ void __launch_bounds__(256) k_mic_spans(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
@@ -384,9 +424,9 @@ __global__ void __launch_bounds__(256) k_mic_spans(DevMesh M, DevQueue q, DevSeg
 {
     unsigned long long n = ctr->n_spans[a.gen];
     if (n > (unsigned long long)w.spans_cap) n = (unsigned long long)w.spans_cap;
+    unsigned tests = 0, updates = 0;
     for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
         const unsigned long long r = base + (unsigned long long)lane_id();
-        unsigned tests = 0, updates = 0;
         const int4 sp = r < n ? w.spans[r] : make_int4(-1, 0, 0, -1);
         if (sp.x >= 0) {
             Frustum f;
@@ -396,8 +436,8 @@ __global__ void __launch_bounds__(256) k_mic_spans(DevMesh M, DevQueue q, DevSeg
                 updates += mic_apply(f, mc, c, sp.y, a.air_m);
             }
         }
-        flush_mic_counters(ctr, tests, updates);
     }
+    flush_mic_counters(ctr, tests, updates);
 }
 
 __global__ void __launch_bounds__(256) k_mics_big(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
@@ -407,6 +447,7 @@ __global__ void __launch_bounds__(256) k_mics_big(DevMesh M, DevQueue q, DevSegs
     const int lane = lane_id();
     const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const int n_waves = (int)((gridDim.x * blockDim.x) >> 6);
+    unsigned tests = 0, updates = 0;
     for (unsigned long long s = (unsigned long long)wave; s < n; s += (unsigned long long)n_waves) {
         const long long i = w.big_list[s];
         Frustum f;
@@ -414,7 +455,6 @@ __global__ void __launch_bounds__(256) k_mics_big(DevMesh M, DevQueue q, DevSegs
         HalfPlane L[9];
         footprint_lines(f, mc, L);
         int j0, j1;
-        unsigned tests = 0, updates = 0;
         if (footprint_rows(L, mc, j0, j1)) {
             for (int j = j0 + lane; j <= j1; j += 64) {
                 int c0, c1;
@@ -422,16 +462,21 @@ __global__ void __launch_bounds__(256) k_mics_big(DevMesh M, DevQueue q, DevSegs
                 process_row(f, mc, w, ctr, a.gen, i, j, c0, c1, a.air_m, tests, updates);
             }
         }
-        flush_mic_counters(ctr, tests, updates);
     }
+    flush_mic_counters(ctr, tests, updates);
 }
 
 hipError_t launch_mics(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mics,
-                       const TraceArgs &a, MicWork w, int n_cu, hipStream_t s)
+                       const TraceArgs &a, MicWork w, WaveScratch ws, int n_cu, hipStream_t s)
 {
-    k_mics<<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
+    // k_mics and k_mics_general must use the same grid: wave w hands its region to wave w
+    const int blocks = n_cu * kBlocksPerCU;
+    if (blocks * kWavesPerBlock != ws.n_waves) return hipErrorInvalidValue;
+    k_mics<<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, mics, a, w, ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    k_mics_general<<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, mics, a, w, ws);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     k_mic_rows<<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_mics_big<<<n_cu * 4, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);

@@ -315,7 +315,18 @@ __device__ void trace_ray(const DevMesh &M, RayState &r, RaySrc src, double t_mi
     }
 }
 
-__global__ void __launch_bounds__(256) k_trace(DevMesh M, DevQueue in, DevSegs segs, DevCounters *ctr, TraceArgs a)
+// A child is spawned by a hit with depth < max_depth whose power after absorption exceeds
+// e_min (when set).  k_trace counts children with this rule and k_reflect writes them.
+__device__ __forceinline__ bool spawns_child(const DevMesh &M, const TraceArgs &a, int hit, int meta, float K,
+                                             float om)
+{
+    if (hit < 0 || (meta & 0xff) >= a.max_depth) return false;
+    const float Kc = K * (1.0f - M.alpha[hit]);
+    return !(a.e_min > 0.0) || ((double)Kc * (double)om > a.e_min);
+}
+
+__global__ void __launch_bounds__(256) k_trace(DevMesh M, DevQueue in, DevSegs segs, DevCounters *ctr, TraceArgs a,
+                                               WaveScratch ws)
 {
     __shared__ int stk[kStack * 256];
     const unsigned long long n = ctr->count[a.gen];
@@ -323,12 +334,12 @@ __global__ void __launch_bounds__(256) k_trace(DevMesh M, DevQueue in, DevSegs s
     const int lane = lane_id();
     const long long icap = in.cap;
     const int D1 = a.max_depth + 1;
+    // per-lane totals over all of this wave's batches, reduced once at the end
+    unsigned children = 0, flagged = 0, nv = 0, tt = 0;
+    double power = 0.0;
     for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
         const bool active = (long long)base + lane < (long long)n;
         const long long i = s0 + (long long)base + lane;
-        int flag_total = 0;
-        double power_term = 0.0;
-        unsigned nv = 0, tt = 0;
         const RaySrc src{in.dbl + D_O * icap, in.dbl + D_C * icap, icap, active ? i : 0};
         if (active) {
             RayState r;
@@ -365,7 +376,7 @@ __global__ void __launch_bounds__(256) k_trace(DevMesh M, DevQueue in, DevSegs s
             int own_flag;
             if (hit >= 0) own_flag = r.best_near || (r.c1_id != hit) || (r.c2_t < r.best_t + a.delta);
             else own_flag = r.c1_t < INFINITY;
-            flag_total = ((meta & kMetaFlag) != 0) || own_flag;
+            const int flag_total = ((meta & kMetaFlag) != 0) || own_flag;
             segs.hit[i] = hit;
             segs.t[i] = r.best_t;
             segs.flag[i] = flag_total;
@@ -373,20 +384,82 @@ __global__ void __launch_bounds__(256) k_trace(DevMesh M, DevQueue in, DevSegs s
             if (a.hit_out) a.hit_out[oidx] = hit;
             if (a.flag_out) a.flag_out[oidx] = (uint8_t)flag_total;
             if (a.t_out) a.t_out[oidx] = r.best_t;
-            power_term = (double)K * (double)om;
-            nv = r.node_visits;
-            tt = r.tri_tests;
+            children += spawns_child(M, a, hit, meta, K, om);
+            flagged += flag_total;
+            power += (double)K * (double)om;
+            nv += r.node_visits;
+            tt += r.tri_tests;
         }
-        // wave-aggregated counters (fire-and-forget atomics)
-        const unsigned long long fl = wave_sum_u64((unsigned long long)(active && flag_total));
-        const double pw = wave_sum_f64(power_term);
-        const unsigned long long snv = wave_sum_u64(nv), stt = wave_sum_u64(tt);
-        if (lane == 0) {
-            if (fl) atomicAdd(&ctr->flagged[a.gen], fl);
-            atomicAdd(&ctr->power[a.gen], pw);
-            atomicAdd(&ctr->node_visits, snv);
-            atomicAdd(&ctr->tri_tests, stt);
+    }
+    // one record per wave (no shared atomics); reduced by k_gen_scan
+    const unsigned long long sc = wave_sum_u64(children), sf = wave_sum_u64(flagged);
+    const unsigned long long snv = wave_sum_u64(nv), stt = wave_sum_u64(tt);
+    const double sp = wave_sum_f64(power);
+    if (lane == 0) {
+        const unsigned long long w = wave_first_batch() >> 6;
+        ws.children[w] = sc;
+        ws.stats[3 * w] = sf;
+        ws.stats[3 * w + 1] = snv;
+        ws.stats[3 * w + 2] = stt;
+        ws.power[w] = sp;
+    }
+}
+
+// One block: exclusive scan of the per-wave child counts (the children's queue offsets,
+// in wave order, so the next generation's order is deterministic) and the generation's
+// totals, summed in a fixed order.
+__global__ void __launch_bounds__(1024) k_gen_scan(DevCounters *ctr, TraceArgs a, WaveScratch ws)
+{
+    __shared__ unsigned long long part[1024];
+    __shared__ unsigned long long sred[3][1024];
+    __shared__ double pred[1024];
+    const int t = threadIdx.x;
+    const int W = ws.n_waves;
+    const int per = (W + 1023) / 1024;
+    const int b0 = t * per, b1 = min(b0 + per, W);
+    unsigned long long c = 0, f = 0, nv = 0, tt = 0;
+    double p = 0.0;
+    for (int w = b0; w < b1; ++w) {
+        c += ws.children[w];
+        f += ws.stats[3 * w];
+        nv += ws.stats[3 * w + 1];
+        tt += ws.stats[3 * w + 2];
+        p += ws.power[w];
+    }
+    part[t] = c;
+    sred[0][t] = f;
+    sred[1][t] = nv;
+    sred[2][t] = tt;
+    pred[t] = p;
+    __syncthreads();
+    // inclusive scan of part[] (Hillis-Steele)
+    for (int off = 1; off < 1024; off <<= 1) {
+        const unsigned long long v = t >= off ? part[t - off] : 0ull;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    unsigned long long run = t > 0 ? part[t - 1] : 0ull;
+    for (int w = b0; w < b1; ++w) {
+        ws.offset[w] = run;
+        run += ws.children[w];
+    }
+    // tree reductions of the totals
+    for (int off = 512; off > 0; off >>= 1) {
+        if (t < off) {
+            sred[0][t] += sred[0][t + off];
+            sred[1][t] += sred[1][t + off];
+            sred[2][t] += sred[2][t + off];
+            pred[t] += pred[t + off];
         }
+        __syncthreads();
+    }
+    if (t == 0) {
+        ctr->count[a.gen + 1] = part[1023];
+        ctr->flagged[a.gen] = sred[0][0];
+        ctr->power[a.gen] = pred[0];
+        ctr->node_visits += sred[1][0];
+        ctr->tri_tests += sred[2][0];
     }
 }
 
@@ -395,7 +468,8 @@ __global__ void __launch_bounds__(256) k_trace(DevMesh M, DevQueue in, DevSegs s
 // guiding directions; d1 and d2 swapped to keep det > 0), starting at the hit point with
 // K (1 - alpha).  Children are compacted into the next queue with a wave ballot, a
 // popcount prefix and one atomic per wave.
-__global__ void __launch_bounds__(256) k_reflect(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, TraceArgs a)
+__global__ void __launch_bounds__(256) k_reflect(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, TraceArgs a,
+                                                 WaveScratch ws)
 {
     const unsigned long long n = ctr->count[a.gen];
     const long long s0 = (long long)gen_start(ctr, a.gen);
@@ -403,6 +477,9 @@ __global__ void __launch_bounds__(256) k_reflect(DevMesh M, DevQueue q, DevSegs 
     const int lane = lane_id();
     const DevQueue &in = q, &out = q;
     const long long icap = q.cap, ocap = q.cap;
+    // this wave's children go to [offset, offset + children) of the next generation, in
+    // batch order (the same static partition as k_trace, which counted them)
+    unsigned long long obase = ws.offset[wave_first_batch() >> 6];
     for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
         const long long i = s0 + (long long)base + lane;
         int child = 0, hit = -1, meta = 0;
@@ -410,17 +487,15 @@ __global__ void __launch_bounds__(256) k_reflect(DevMesh M, DevQueue q, DevSegs 
         if ((long long)base + lane < (long long)n) {
             hit = segs.hit[i];
             meta = in.ints[I_META * icap + i];
-            if (hit >= 0 && (meta & 0xff) < a.max_depth) {
-                K = in.flt[F_K * icap + i];
-                Kc = K * (1.0f - M.alpha[hit]);
-                child = !(a.e_min > 0.0) || ((double)Kc * (double)in.flt[F_OMEGA * icap + i] > a.e_min);
-            }
+            K = in.flt[F_K * icap + i];
+            child = spawns_child(M, a, hit, meta, K, in.flt[F_OMEGA * icap + i]);
+            if (child) Kc = K * (1.0f - M.alpha[hit]);
         }
         const unsigned long long mask = __ballot(child);
         if (mask == 0) continue;
-        unsigned long long obase = 0;
-        if (lane == 0) obase = atomicAdd(&ctr->count[a.gen + 1], (unsigned long long)__popcll(mask));
-        obase = __shfl(obase, 0, 64);
+        V3 A2, o2, c2, m0, m1, m2;
+        int meta2 = 0, id = 0;
+        float om = 0.f;
         if (child) {
             V3 v0, v1, v2;
             tri_vertices(M.tri_g, hit, v0, v1, v2);
@@ -429,35 +504,48 @@ __global__ void __launch_bounds__(256) k_reflect(DevMesh M, DevQueue q, DevSegs 
             const V3 A = ld3(in.dbl + D_A * icap, icap, i);
             const V3 o = ld3(in.dbl + D_O * icap, icap, i), c = ld3(in.dbl + D_C * icap, icap, i);
             const double t = segs.t[i];
-            const V3 A2 = A - (2.0 * dot(A - v0, nn)) * nn;
-            const V3 o2 = o + t * c;
-            const V3 c2 = mirror(c, nn);
+            A2 = A - (2.0 * dot(A - v0, nn)) * nn;
+            o2 = o + t * c;
+            c2 = mirror(c, nn);
+            m0 = mirror(ld3(in.dbl + D_D0 * icap, icap, i), nn);
+            m1 = mirror(ld3(in.dbl + D_D2 * icap, icap, i), nn);  // d1 and d2 swap: det stays > 0
+            m2 = mirror(ld3(in.dbl + D_D1 * icap, icap, i), nn);
             // the child lives on the side the parent came from
-            const int meta2 = ((meta & 0xff) + 1) | (dot(c, N) > 0.0 ? kMetaNegNear : 0) |
-                              (segs.flag[i] ? kMetaFlag : 0);
-            const long long j = s1 + (long long)obase + __popcll(mask & ((1ull << lane) - 1ull));
+            meta2 = ((meta & 0xff) + 1) | (dot(c, N) > 0.0 ? kMetaNegNear : 0) | (segs.flag[i] ? kMetaFlag : 0);
+            om = in.flt[F_OMEGA * icap + i];
+            id = in.ints[I_ID * icap + i];
+        }
+        const unsigned long long my_base = obase;
+        obase += (unsigned long long)__popcll(mask);
+        if (child) {
+            const long long j = s1 + (long long)my_base + __popcll(mask & ((1ull << lane) - 1ull));
             st3(out.dbl + D_A * ocap, ocap, j, A2);
-            st3(out.dbl + D_D0 * ocap, ocap, j, mirror(ld3(in.dbl + D_D0 * icap, icap, i), nn));
-            st3(out.dbl + D_D1 * ocap, ocap, j, mirror(ld3(in.dbl + D_D2 * icap, icap, i), nn));
-            st3(out.dbl + D_D2 * ocap, ocap, j, mirror(ld3(in.dbl + D_D1 * icap, icap, i), nn));
+            st3(out.dbl + D_D0 * ocap, ocap, j, m0);
+            st3(out.dbl + D_D1 * ocap, ocap, j, m1);
+            st3(out.dbl + D_D2 * ocap, ocap, j, m2);
             st3(out.dbl + D_O * ocap, ocap, j, o2);
             st3(out.dbl + D_C * ocap, ocap, j, c2);
             out.flt[F_K * ocap + j] = Kc;
-            out.flt[F_OMEGA * ocap + j] = in.flt[F_OMEGA * icap + i];
-            out.ints[I_ID * ocap + j] = in.ints[I_ID * icap + i];
+            out.flt[F_OMEGA * ocap + j] = om;
+            out.ints[I_ID * ocap + j] = id;
             out.ints[I_START * ocap + j] = hit;
             out.ints[I_META * ocap + j] = meta2;
         }
     }
 }
 
-hipError_t launch_trace(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, const TraceArgs &a, int n_cu,
-                        hipStream_t s)
+hipError_t launch_trace(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, const TraceArgs &a,
+                        WaveScratch ws, int n_cu, hipStream_t s)
 {
-    k_trace<<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, a);
+    // k_trace and k_reflect must use the same grid: wave w owns the same batches in both
+    const int blocks = n_cu * kBlocksPerCU;
+    if (blocks * kWavesPerBlock != ws.n_waves) return hipErrorInvalidValue;
+    k_trace<<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, a, ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_reflect<<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, a);
+    k_gen_scan<<<1, 1024, 0, s>>>(ctr, a, ws);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_reflect<<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, a, ws);
     return hipGetLastError();
 }
 
