@@ -158,15 +158,19 @@ def main():
         trace_bytes = (B_BEAM + B_HIT) * ref["segments"] + B_CHILD * ref["children"] + \
             B_NODE * ref["node_visits"] + B_TRI * ref["tri_tests"]
         mic_bytes = B_MIC * ref["mic_updates"]
-        # the trace stage is k_trace + k_reflect (both launched by each bt_trace call)
-        dominant = "k_trace+k_reflect" if trace_ms >= mic_ms else "k_mics+k_mic_rows+k_mic_spans"
-        t_dom = trace_ms if trace_ms >= mic_ms else mic_ms
-        b_dom = trace_bytes if trace_ms >= mic_ms else mic_bytes
-        launches = 2 * (D + 1) if trace_ms >= mic_ms else 4
+        # the trace stage is k_trace + k_gen_scan + k_reflect, launched by each bt_trace call;
+        # the microphone stage is the five kernels of one bt_accumulate_mics call
+        trace_dominant = trace_ms >= mic_ms
+        dominant = "k_trace+k_gen_scan+k_reflect" if trace_dominant else \
+            "k_mics+k_mics_general+k_mic_rows+k_mics_big+k_mic_spans"
+        t_dom = trace_ms if trace_dominant else mic_ms
+        b_dom = trace_bytes if trace_dominant else mic_bytes
+        launches = 3 * (D + 1) if trace_dominant else 5
         achieved = b_dom / (t_dom * 1e-3) / 1e9
         traffic = pmc_traffic(launches) if trace_ms >= mic_ms else None
         roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "traffic_unit": "HBM bytes per launch (stage total / launches)",
                     "algorithmic_bytes_per_step": b_dom, "launches_per_step": launches,
                     "kernel_ms_per_step": round(t_dom, 3)}
     gpu_bytes = (B_BEAM + B_HIT) * segs + B_NODE * st["node_visits"] + B_TRI * st["tri_tests"]
