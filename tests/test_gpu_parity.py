@@ -342,6 +342,36 @@ def test_submit_poll_matches_plain_run(torch_cuda):
             bt.bt_poll(s.ctx, tk, sc.n_mic)
 
 
+@pytest.mark.parametrize("every", [1, 3])
+def test_microphone_passes_between_generations(torch_cuda, every):
+    """However the generations are grouped into microphone passes (each pass reuses the
+    work buffers of the previous one), the energies equal one pass at the end (up to
+    FP64 atomic ordering) and the oracle's."""
+    from paper_1912_03998_amd import bt
+    sc = block_scene(0)
+    say("microphone passes every", every, "generations")
+    o = O.trace(sc)
+    with session(sc) as s:
+        ref = gpu_run(s, sc, parity=False)
+        mics = s._mics(grid(sc))
+        p = s.params(sc.depth)
+        s.beams = bt.bt_emit_beams(s.ctx, sc.sources, sc.power, sc.level, s.beams)
+        bt.bt_mics_reset(s.ctx, mics)
+        for g in range(sc.depth + 1):
+            bt.bt_trace(s.ctx, s.mesh, s.beams, p)
+            if (g + 1) % every == 0:
+                bt.bt_accumulate_mics(s.ctx, s.mesh, s.beams, p, mics)
+        bt.bt_accumulate_mics(s.ctx, s.mesh, s.beams, p, mics)
+        n = sc.n_mic
+        es, ef = np.zeros(n), np.zeros(n)
+        bt.bt_levels(s.ctx, mics, es, ef, None)
+        st = bt.bt_beams_stats(s.ctx, s.beams)
+    assert st["mic_updates"] == ref.stats["mic_updates"]
+    assert np.abs(es - ref.e_strict).max() <= 1e-12 * ref.e_strict.max()
+    assert np.abs(ef - ref.e_flag).max() <= 1e-12 * max(ref.e_flag.max(), 1e-300)
+    check_mics(o.e_strict, o.e_flag, es, ef)
+
+
 @pytest.mark.parametrize("env", ["BT_MIC_ROW_CAPACITY", "BT_MIC_SPAN_CAPACITY"])
 def test_mic_work_buffer_overflow(torch_cuda, monkeypatch, env):
     """Tiny work-item buffers force wide footprints onto the one-wave-per-segment path and
