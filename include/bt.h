@@ -192,6 +192,68 @@ bt_status bt_submit(bt_ctx *ctx, const bt_mesh *mesh, const bt_request *req, uin
 bt_status bt_poll(bt_ctx *ctx, uint64_t ticket, bt_result *out);
 bt_status bt_cancel(bt_ctx *ctx, uint64_t ticket);
 
+/* ------------------------------------------------------------------------------------
+ * Batches of independent scenarios (paper Section 3: one model, many simulations; the
+ * work of all of them is shared out over the same processors).  The beams of many
+ * scenarios are traced together: each generation of every scenario in a chunk is one
+ * set of kernel launches over a shared queue whose beams carry their scenario's slot and
+ * depth limit, and each segment's contributions go to its own scenario's microphones.
+ * Every scenario's result equals the one it has when run alone with bt_run (up to the
+ * order of FP64 additions).
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+    const float *src_xyz;       /* host float[n_src][3] */
+    const float *src_power;     /* host float[n_src] */
+    int32_t n_src;              /* >= 0 */
+    int32_t level;              /* icosphere level of the scenario's sources, 0..BT_MAX_LEVEL */
+    int32_t max_depth;          /* 0..BT_MAX_DEPTH */
+    float mic_x0, mic_y0, mic_z, mic_dx, mic_dy;   /* microphone grid, as bt_mics_grid */
+    int32_t mic_nx, mic_ny;
+    const int32_t *mic_subset;  /* host int32[n_subset]: grid indices j * nx + i, in output
+                                   order (repeats allowed); NULL = the whole grid */
+    int64_t n_subset;
+    double *energy_out;         /* caller-owned host double[n_out] (strict + flag), n_out =
+                                   n_subset, or nx * ny without a subset */
+    double *flag_out;           /* caller-owned host double[n_out] (flag part) or NULL */
+} bt_scenario;
+
+typedef struct {
+    int64_t chunk_beams;        /* generation-0 beams traced together at most (a larger
+                                   scenario forms a chunk of its own); 0 = 16 Mi */
+    int32_t blocks_per_cu;      /* workgroups per compute unit of the statically partitioned
+                                   trace and microphone kernels, 1..16; 0 = 8 */
+    int32_t use_graph;          /* 1: a chunk's launches are captured once in a hipGraph and
+                                   replayed for every chunk */
+} bt_batch_opts;
+
+typedef struct {
+    int32_t chunks;
+    int64_t beams0;             /* generation-0 beams */
+    int64_t segments;           /* beam segments traced */
+    int64_t mic_updates;
+    double seconds;             /* wall time of the call after validation */
+} bt_batch_stats;
+
+/* Run n scenarios and write each one's microphone energies to its buffers; synchronises.
+ * params: physics (t_min, edge_delta, air_m, e_min; NULL = defaults); its max_depth and
+ * parity outputs are not used (each scenario has its own depth).  opts: NULL = defaults.
+ * stats: NULL or filled.  Scenarios are taken in order into chunks.  BT_EINVAL on a bad
+ * scenario (nothing is run), BT_ENOMEM when a chunk does not fit the budget. */
+bt_status bt_batch_run(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *scenarios, int32_t n,
+                       const bt_params *params, const bt_batch_opts *opts, bt_batch_stats *stats);
+
+#define BT_TUNE_MAX_CANDIDATES 32
+
+/* Choose bt_batch_opts for a workload by running a leading sample of it (about a quarter
+ * of the generation-0 beams, at most 32 Mi) under each candidate chunk size and
+ * workgroup count, with and without graphs, and keeping the fastest.  The sample's
+ * scenarios have their output buffers written.  out receives the choice; seconds_out
+ * (NULL or double[n_candidates]) the measured time of each candidate, n_candidates_out
+ * (NULL or filled) their number. */
+bt_status bt_batch_autotune(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *scenarios, int32_t n,
+                            const bt_params *params, bt_batch_opts *out, double *seconds_out,
+                            int32_t *n_candidates_out);
+
 #ifdef __cplusplus
 }
 #endif

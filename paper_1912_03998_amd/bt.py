@@ -23,7 +23,7 @@ STATUS = {0: "BT_OK", 1: "BT_PENDING", -1: "BT_EINVAL", -2: "BT_ENOMEM", -3: "BT
 EXPORTED = ["bt_params_default", "bt_status_str", "bt_last_error", "bt_create", "bt_destroy", "bt_memory_used",
             "bt_build_mesh", "bt_mesh_free", "bt_mesh_info", "bt_mics_grid", "bt_mics_reset", "bt_mics_free",
             "bt_emit_beams", "bt_beams_free", "bt_beams_stats", "bt_trace", "bt_accumulate_mics", "bt_levels",
-            "bt_run", "bt_submit", "bt_poll", "bt_cancel"]
+            "bt_run", "bt_submit", "bt_poll", "bt_cancel", "bt_batch_run", "bt_batch_autotune"]
 
 
 class BTError(RuntimeError):
@@ -91,6 +91,8 @@ def lib():
         "bt_submit": (C.c_int, [P, P, P, P]),
         "bt_poll": (C.c_int, [P, C.c_uint64, P]),
         "bt_cancel": (C.c_int, [P, C.c_uint64]),
+        "bt_batch_run": (C.c_int, [P, P, P, I32, P, P, P]),
+        "bt_batch_autotune": (C.c_int, [P, P, P, I32, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -252,3 +254,75 @@ def bt_poll(ctx, ticket, n_mic):
 
 def bt_cancel(ctx, ticket):
     _check(ctx, lib().bt_cancel(ctx, ticket), "bt_cancel")
+
+
+class bt_scenario(C.Structure):
+    _fields_ = [("src_xyz", C.c_void_p), ("src_power", C.c_void_p), ("n_src", C.c_int32), ("level", C.c_int32),
+                ("max_depth", C.c_int32), ("mic_x0", C.c_float), ("mic_y0", C.c_float), ("mic_z", C.c_float),
+                ("mic_dx", C.c_float), ("mic_dy", C.c_float), ("mic_nx", C.c_int32), ("mic_ny", C.c_int32),
+                ("mic_subset", C.c_void_p), ("n_subset", C.c_int64), ("energy_out", C.c_void_p),
+                ("flag_out", C.c_void_p)]
+
+
+class bt_batch_opts(C.Structure):
+    _fields_ = [("chunk_beams", C.c_int64), ("blocks_per_cu", C.c_int32), ("use_graph", C.c_int32)]
+
+
+class bt_batch_stats(C.Structure):
+    _fields_ = [("chunks", C.c_int32), ("beams0", C.c_int64), ("segments", C.c_int64), ("mic_updates", C.c_int64),
+                ("seconds", C.c_double)]
+
+
+BT_TUNE_MAX_CANDIDATES = 32
+
+
+class Scenario:
+    """One scenario of a batch: sources, level, depth, microphone grid (x0, y0, z, dx, dy,
+    nx, ny) and an optional subset of grid indices.  After the batch runs, `energy` and
+    `flag` hold its outputs."""
+
+    def __init__(self, src_xyz, src_power, level, max_depth, grid, subset=None):
+        self.src = np.ascontiguousarray(src_xyz, np.float32).reshape(-1, 3)
+        self.power = np.ascontiguousarray(src_power, np.float32)
+        self.level, self.max_depth, self.grid = int(level), int(max_depth), tuple(grid)
+        self.subset = None if subset is None else np.ascontiguousarray(subset, np.int32)
+        nx, ny = int(grid[5]), int(grid[6])
+        n_out = len(self.subset) if self.subset is not None else nx * ny
+        self.energy = np.zeros(n_out, np.float64)
+        self.flag = np.zeros(n_out, np.float64)
+
+    def struct(self) -> bt_scenario:
+        x0, y0, z, dx, dy, nx, ny = self.grid
+        return bt_scenario(_ptr(self.src), _ptr(self.power), self.src.shape[0], self.level, self.max_depth, x0, y0, z,
+                           dx, dy, nx, ny, _ptr(self.subset), 0 if self.subset is None else len(self.subset),
+                           _ptr(self.energy), _ptr(self.flag))
+
+
+def _scenario_array(scenarios):
+    arr = (bt_scenario * max(len(scenarios), 1))()
+    for k, s in enumerate(scenarios):
+        arr[k] = s.struct()
+    return arr
+
+
+def bt_batch_run(ctx, mesh, scenarios, params=None, opts=None) -> dict:
+    """Runs the Scenario objects (their energy / flag arrays are filled); returns the stats."""
+    arr = _scenario_array(scenarios)
+    st = bt_batch_stats()
+    o = None if opts is None else (opts if isinstance(opts, bt_batch_opts) else bt_batch_opts(**opts))
+    _check(ctx, lib().bt_batch_run(ctx, mesh, arr, len(scenarios), None if params is None else C.byref(params),
+                                   None if o is None else C.byref(o), C.byref(st)), "bt_batch_run")
+    return {"chunks": st.chunks, "beams0": st.beams0, "segments": st.segments, "mic_updates": st.mic_updates,
+            "seconds": st.seconds}
+
+
+def bt_batch_autotune(ctx, mesh, scenarios, params=None):
+    """Returns (chosen options as a dict, per-candidate seconds)."""
+    arr = _scenario_array(scenarios)
+    out = bt_batch_opts()
+    secs = (C.c_double * BT_TUNE_MAX_CANDIDATES)()
+    nc = C.c_int32()
+    _check(ctx, lib().bt_batch_autotune(ctx, mesh, arr, len(scenarios), None if params is None else C.byref(params),
+                                        C.byref(out), secs, C.byref(nc)), "bt_batch_autotune")
+    return ({"chunk_beams": out.chunk_beams, "blocks_per_cu": out.blocks_per_cu, "use_graph": out.use_graph},
+            list(secs[:nc.value]))

@@ -12,8 +12,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libbt.so")
 
-SOURCES = ["bt_emit.hip", "bt_trace.hip", "bt_mics.hip", "bt_host.cpp"]
-HEADERS = ["bt_internal.h", "bt_device.h"]
+SOURCES = ["bt_emit.hip", "bt_trace.hip", "bt_mics.hip", "bt_host.cpp", "bt_batch.cpp"]
+HEADERS = ["bt_internal.h", "bt_device.h", "bt_host.h"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

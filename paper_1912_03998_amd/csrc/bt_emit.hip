@@ -42,6 +42,40 @@ hipError_t launch_fill(double *p, long long n, double v, hipStream_t s)
 // edge midpoints are normalize(x + y) and the child at position j of (a, b, c) is
 // (a, ab, ca), (ab, b, bc), (ca, bc, c) or (ab, bc, ca).
 // ---------------------------------------------------------------------------------------
+// Beam `f` (face index) of a level-`level` source at S with power W, written at queue
+// index j.
+__device__ void emit_one(const double *__restrict__ base20, int level, long long f, V3 S, float W, int meta, int id,
+                         DevQueue q, long long j)
+{
+    int bf = (int)(f >> (2 * level));
+    const double *bp = base20 + 9 * bf;
+    V3 a = {bp[0], bp[1], bp[2]}, bb = {bp[3], bp[4], bp[5]}, c = {bp[6], bp[7], bp[8]};
+    for (int l = level - 1; l >= 0; --l) {
+        int k = (int)((f >> (2 * l)) & 3);
+        V3 ab = unit(a + bb), bc = unit(bb + c), ca = unit(c + a);
+        if (k == 0) { bb = ab; c = ca; }
+        else if (k == 1) { a = ab; c = bc; }
+        else if (k == 2) { a = ca; bb = bc; }
+        else { a = ab; bb = bc; c = ca; }
+    }
+    V3 cc = unit((a + bb) + c);
+    double num = fabs(dot(a, cross(bb, c)));
+    double den = 1.0 + dot(a, bb) + dot(bb, c) + dot(c, a);
+    double omega = 2.0 * atan2(num, den);
+    const long long cap = q.cap;
+    st3(q.dbl + D_A * cap, cap, j, S);
+    st3(q.dbl + D_D0 * cap, cap, j, a);
+    st3(q.dbl + D_D1 * cap, cap, j, bb);
+    st3(q.dbl + D_D2 * cap, cap, j, c);
+    st3(q.dbl + D_O * cap, cap, j, S);
+    st3(q.dbl + D_C * cap, cap, j, cc);
+    q.flt[F_K * cap + j] = (float)((double)W / (4.0 * M_PI));
+    q.flt[F_OMEGA * cap + j] = (float)omega;
+    q.ints[I_ID * cap + j] = id;
+    q.ints[I_START * cap + j] = -1;
+    q.ints[I_META * cap + j] = meta;
+}
+
 __global__ void k_emit(const double *__restrict__ base20, const float *__restrict__ src,
                        const float *__restrict__ power, int n_src, int level, long long nf, DevQueue q)
 {
@@ -49,34 +83,8 @@ __global__ void k_emit(const double *__restrict__ base20, const float *__restric
     long long total = nf * n_src;
     if (b >= total) return;
     long long s = b / nf, f = b - s * nf;
-    int bf = (int)(f >> (2 * level));
-    const double *bp = base20 + 9 * bf;
-    V3 a = {bp[0], bp[1], bp[2]}, bb = {bp[3], bp[4], bp[5]}, c = {bp[6], bp[7], bp[8]};
-    for (int l = level - 1; l >= 0; --l) {
-        int j = (int)((f >> (2 * l)) & 3);
-        V3 ab = unit(a + bb), bc = unit(bb + c), ca = unit(c + a);
-        if (j == 0) { bb = ab; c = ca; }
-        else if (j == 1) { a = ab; c = bc; }
-        else if (j == 2) { a = ca; bb = bc; }
-        else { a = ab; bb = bc; c = ca; }
-    }
-    V3 cc = unit((a + bb) + c);
-    double num = fabs(dot(a, cross(bb, c)));
-    double den = 1.0 + dot(a, bb) + dot(bb, c) + dot(c, a);
-    double omega = 2.0 * atan2(num, den);
-    V3 S = {src[3 * s], src[3 * s + 1], src[3 * s + 2]};
-    const long long cap = q.cap;
-    st3(q.dbl + D_A * cap, cap, b, S);
-    st3(q.dbl + D_D0 * cap, cap, b, a);
-    st3(q.dbl + D_D1 * cap, cap, b, bb);
-    st3(q.dbl + D_D2 * cap, cap, b, c);
-    st3(q.dbl + D_O * cap, cap, b, S);
-    st3(q.dbl + D_C * cap, cap, b, cc);
-    q.flt[F_K * cap + b] = (float)((double)power[s] / (4.0 * M_PI));
-    q.flt[F_OMEGA * cap + b] = (float)omega;
-    q.ints[I_ID * cap + b] = (int)b;
-    q.ints[I_START * cap + b] = -1;
-    q.ints[I_META * cap + b] = 0;
+    const V3 S = {src[3 * s], src[3 * s + 1], src[3 * s + 2]};
+    emit_one(base20, level, f, S, power[s], 0, (int)b, q, b);
 }
 
 hipError_t launch_emit(const double *base20, const float *src, const float *power, int n_src, int level,
@@ -88,6 +96,92 @@ hipError_t launch_emit(const double *base20, const float *src, const float *powe
     k_emit<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(base20, src, power, n_src, level, nf, q);
     return hipGetLastError();
 }
+
+// Beams of an emission table appended to generation `gen` after its current count[gen]
+// beams; the grid strides over the table's beams.
+__global__ void k_emit_table(const double *__restrict__ base20, EmitTable t, DevQueue q, const DevCounters *ctr,
+                             int gen)
+{
+    const long long total = t.dims[0];
+    const int n = (int)t.dims[1];
+    if (n <= 0) return;
+    const long long base = (long long)(gen_start(ctr, gen) + ctr->count[gen]);
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < total; b += stride) {
+        // the source whose beam range holds b: first[lo] <= b < first[hi + 1]
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (t.first[mid] <= b) lo = mid;
+            else hi = mid - 1;
+        }
+        const long long f = b - t.first[lo];
+        const V3 S = {t.src[3 * lo], t.src[3 * lo + 1], t.src[3 * lo + 2]};
+        emit_one(base20, t.level[lo], f, S, t.power[lo], t.meta[lo], t.id0[lo] + (int)f, q, base + b);
+    }
+}
+
+__global__ void k_count_add(DevCounters *ctr, int gen, const long long *n)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->count[gen] += (unsigned long long)n[0];
+}
+
+hipError_t launch_emit_table(const double *base20, const EmitTable &t, long long max_total, DevQueue q,
+                             DevCounters *ctr, int gen, hipStream_t s)
+{
+    long long blocks = (max_total + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    k_emit_table<<<(unsigned)blocks, 256, 0, s>>>(base20, t, q, ctr, gen);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_count_add<<<1, 64, 0, s>>>(ctr, gen, t.dims);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Batch chunks: zero the energies, and gather each scenario's outputs (strict + flag,
+// and flag) from its grid arrays; sizes come from the chunk descriptor.
+// ---------------------------------------------------------------------------------------
+__global__ void k_fill_desc(double *p, const BatchDesc *d)
+{
+    const long long n = d->n_fill;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0.0;
+}
+
+__global__ void k_gather(const double *__restrict__ e, const long long *__restrict__ idx, const BatchDesc *d,
+                         double *__restrict__ out_e, double *__restrict__ out_f)
+{
+    const long long n = d->n_out, es = d->e_stride;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += stride) {
+        const long long i = idx[k];
+        const double f = e[es + i];
+        out_e[k] = e[i] + f;
+        out_f[k] = f;
+    }
+}
+
+hipError_t launch_fill_desc(double *p, const BatchDesc *d, long long max_n, hipStream_t s)
+{
+    long long blocks = (max_n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    k_fill_desc<<<(unsigned)blocks, 256, 0, s>>>(p, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const double *e, const long long *idx, const BatchDesc *d, long long max_n, double *out_e,
+                         double *out_f, hipStream_t s)
+{
+    long long blocks = (max_n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    k_gather<<<(unsigned)blocks, 256, 0, s>>>(e, idx, d, out_e, out_f);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------------------
 // Levels: L = 10 log10((strict + flag) / 1e-12)
 // ---------------------------------------------------------------------------------------

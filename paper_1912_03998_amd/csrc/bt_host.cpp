@@ -14,80 +14,14 @@
 #include <vector>
 
 #include "bt.h"
-#include "bt_internal.h"
+#include "bt_host.h"
 
 using namespace bt;
-
-struct bt_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    size_t budget = 0;
-    size_t used = 0;
-    int n_cu = 256;
-    double *base20 = nullptr;  // device, 20 base faces x 9 doubles
-    std::string err;
-    std::mutex mtx;            // submit / poll / cancel
-    uint64_t next_ticket = 1;
-    std::map<uint64_t, struct Request *> requests;
-};
-
-struct bt_mesh {
-    bt_ctx *ctx = nullptr;
-    DevMesh dev{};
-    void *bufs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    size_t sizes[6] = {0, 0, 0, 0, 0, 0};
-    int64_t n_nodes = 0, n_refs = 0;
-    int32_t max_depth = 0;
-    double delta_cap = 0.0;   // largest edge_delta the box margins cover
-    double r_eff = 0.0;       // largest |coordinate| of a ray origin the margins cover
-};
-
-struct bt_mics {
-    bt_ctx *ctx = nullptr;
-    DevMics dev{};
-    double *level = nullptr;
-    size_t bytes = 0;
-};
-
-struct bt_beams {
-    bt_ctx *ctx = nullptr;
-    long long cap = 0;
-    DevQueue q{};             // every generation, contiguous (see DevQueue)
-    DevSegs segs{};
-    DevCounters *ctr = nullptr;
-    WaveScratch ws{};         // per-wave records of the statically partitioned kernels
-    void *ws_buf = nullptr;
-    size_t ws_bytes = 0;
-    int *big_list = nullptr;  // 2 * cap: wave-path overflow list, then the general-path list
-    int2 *rows = nullptr;
-    long long rows_cap = 0;
-    int4 *spans = nullptr;
-    long long spans_cap = 0;
-    long long work_n0 = 0;    // generation-0 size the work buffers were sized for
-    int acc_gen = 0;          // first generation not yet accumulated at the microphones
-    int depth_hint = 0;       // max_depth of the previous run, to size the queue at emission
-    float *src_dev = nullptr, *pow_dev = nullptr;
-    int src_cap = 0;
-    size_t bytes = 0;
-    int gen = 0;              // generations traced
-    int max_depth = -1;       // fixed by the first trace
-    long long n0 = 0;
-    double r_src = 0.0;
-};
-
-struct Request {
-    bt_request req{};
-    std::vector<float> src, pw;
-    bt_mics *mics = nullptr;
-    bt_beams *beams = nullptr;
-    hipEvent_t done = nullptr;
-};
 
 // ---------------------------------------------------------------------------------------
 // errors and memory
 // ---------------------------------------------------------------------------------------
-static bt_status fail(bt_ctx *ctx, bt_status s, const char *fmt, ...)
+bt_status fail(bt_ctx *ctx, bt_status s, const char *fmt, ...)
 {
     if (ctx) {
         char buf[512];
@@ -100,18 +34,12 @@ static bt_status fail(bt_ctx *ctx, bt_status s, const char *fmt, ...)
     return s;
 }
 
-static bt_status hip_fail(bt_ctx *ctx, hipError_t e, const char *what)
+bt_status hip_fail(bt_ctx *ctx, hipError_t e, const char *what)
 {
     return fail(ctx, BT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIP_TRY(ctx, expr)                                  \
-    do {                                                    \
-        hipError_t e_ = (expr);                             \
-        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
-    } while (0)
-
-static bt_status dev_alloc(bt_ctx *ctx, void **p, size_t bytes)
+bt_status dev_alloc(bt_ctx *ctx, void **p, size_t bytes)
 {
     *p = nullptr;
     if (bytes == 0) bytes = 256;
@@ -127,7 +55,7 @@ static bt_status dev_alloc(bt_ctx *ctx, void **p, size_t bytes)
     return BT_OK;
 }
 
-static void dev_free(bt_ctx *ctx, void *p, size_t bytes)
+void dev_free(bt_ctx *ctx, void *p, size_t bytes)
 {
     if (!p) return;
     (void)hipFree(p);
@@ -646,16 +574,16 @@ extern "C" bt_status bt_mics_free(bt_mics *m)
 // Integers in the segment-list buffer of a queue of capacity n: the wave-path overflow
 // list (n), then the general-path list, whose per-wave regions hold 64 items per batch
 // (at most n + 64 (W + 1)).
-static size_t list_ints(long long n, int n_waves)
+size_t list_ints(long long n, int n_waves)
 {
     return (size_t)(2 * n + 64 * ((long long)n_waves + 1));
 }
 
-// Per-wave scratch of a beam set for a grid of W = n_cu * kBlocksPerCU * kWavesPerBlock
+// Per-wave scratch of a beam set for a grid of W = n_cu * blocks_per_cu * kWavesPerBlock
 // waves: children, offsets, 3 stats, power (8 B each) and general counts (4 B).
-static bt_status alloc_wave_scratch(bt_ctx *ctx, bt_beams *b)
+bt_status alloc_wave_scratch(bt_ctx *ctx, bt_beams *b, int blocks_per_cu)
 {
-    const int W = ctx->n_cu * kBlocksPerCU * kWavesPerBlock;
+    const int W = ctx->n_cu * blocks_per_cu * kWavesPerBlock;
     const size_t bytes = (size_t)W * (6 * 8 + 4);
     bt_status s = dev_alloc(ctx, &b->ws_buf, bytes);
     if (s != BT_OK) return s;
@@ -670,7 +598,7 @@ static bt_status alloc_wave_scratch(bt_ctx *ctx, bt_beams *b)
     return BT_OK;
 }
 
-static void queue_free(bt_ctx *ctx, DevQueue &q)
+void queue_free(bt_ctx *ctx, DevQueue &q)
 {
     dev_free(ctx, q.dbl, (size_t)q.cap * D_N * sizeof(double));
     dev_free(ctx, q.flt, (size_t)q.cap * F_N * sizeof(float));
@@ -678,7 +606,7 @@ static void queue_free(bt_ctx *ctx, DevQueue &q)
     q = DevQueue{};
 }
 
-static void beams_release(bt_beams *b)
+void beams_release(bt_beams *b)
 {
     bt_ctx *ctx = b->ctx;
     queue_free(ctx, b->q);
@@ -700,7 +628,7 @@ static void beams_release(bt_beams *b)
 
 // Queue, segment and overflow-list capacity of at least n records.  When the arrays
 // move, the first `keep` queue records (every field) are carried over on the stream.
-static bt_status reserve_queue(bt_ctx *ctx, bt_beams *b, long long n, long long keep)
+bt_status reserve_queue(bt_ctx *ctx, bt_beams *b, long long n, long long keep)
 {
     if (n <= b->cap) return BT_OK;
     DevQueue nq{};
@@ -743,7 +671,7 @@ static bt_status reserve_queue(bt_ctx *ctx, bt_beams *b, long long n, long long 
 }
 
 // Work-item buffers of the microphone stage, sized from the generation-0 count.
-static bt_status reserve_work(bt_ctx *ctx, bt_beams *b, long long n0)
+bt_status reserve_work(bt_ctx *ctx, bt_beams *b, long long n0)
 {
     if (n0 <= b->work_n0) return BT_OK;
     dev_free(ctx, b->rows, (size_t)b->rows_cap * sizeof(int2));
@@ -799,7 +727,7 @@ extern "C" bt_status bt_emit_beams(bt_ctx *ctx, const float *src_xyz, const floa
         b->ctx = ctx;
         fresh = true;
         bt_status s = dev_alloc(ctx, (void **)&b->ctr, sizeof(DevCounters));
-        if (s == BT_OK) s = alloc_wave_scratch(ctx, b);
+        if (s == BT_OK) s = alloc_wave_scratch(ctx, b, kBlocksPerCU);
         if (s != BT_OK) {
             bt_beams_free(b);
             return s;
@@ -875,7 +803,7 @@ extern "C" bt_status bt_beams_stats(bt_ctx *ctx, const bt_beams *b, bt_stats *ou
     return BT_OK;
 }
 
-static bt_status check_params(bt_ctx *ctx, const bt_mesh *mesh, const bt_params *p)
+bt_status check_params(bt_ctx *ctx, const bt_mesh *mesh, const bt_params *p)
 {
     if (!p) return fail(ctx, BT_EINVAL, "params is NULL");
     if (p->max_depth < 0 || p->max_depth > BT_MAX_DEPTH) return fail(ctx, BT_EINVAL, "max_depth %d not in 0..%d", p->max_depth, BT_MAX_DEPTH);
@@ -887,7 +815,7 @@ static bt_status check_params(bt_ctx *ctx, const bt_mesh *mesh, const bt_params 
     return BT_OK;
 }
 
-static TraceArgs make_args(const bt_params *p, int gen)
+TraceArgs make_args(const bt_params *p, int gen)
 {
     TraceArgs a{};
     a.gen = gen;

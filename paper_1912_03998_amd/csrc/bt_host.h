@@ -1,0 +1,109 @@
+// Host-side state of the C ABI handles and the helpers shared by the host sources
+// (bt_host.cpp: contexts, meshes, single beam sets; bt_batch.cpp: scenario batches).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "bt.h"
+#include "bt_internal.h"
+
+using namespace bt;
+
+struct bt_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t budget = 0;
+    size_t used = 0;
+    int n_cu = 256;
+    double *base20 = nullptr;  // device, 20 base faces x 9 doubles
+    std::string err;
+    std::mutex mtx;            // submit / poll / cancel
+    uint64_t next_ticket = 1;
+    std::map<uint64_t, struct Request *> requests;
+};
+
+struct bt_mesh {
+    bt_ctx *ctx = nullptr;
+    DevMesh dev{};
+    void *bufs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    size_t sizes[6] = {0, 0, 0, 0, 0, 0};
+    int64_t n_nodes = 0, n_refs = 0;
+    int32_t max_depth = 0;
+    double delta_cap = 0.0;   // largest edge_delta the box margins cover
+    double r_eff = 0.0;       // largest |coordinate| of a ray origin the margins cover
+};
+
+struct bt_mics {
+    bt_ctx *ctx = nullptr;
+    DevMics dev{};
+    double *level = nullptr;
+    size_t bytes = 0;
+};
+
+struct bt_beams {
+    bt_ctx *ctx = nullptr;
+    long long cap = 0;
+    DevQueue q{};             // every generation, contiguous (see DevQueue)
+    DevSegs segs{};
+    DevCounters *ctr = nullptr;
+    WaveScratch ws{};         // per-wave records of the statically partitioned kernels
+    void *ws_buf = nullptr;
+    size_t ws_bytes = 0;
+    int *big_list = nullptr;  // 2 * cap: wave-path overflow list, then the general-path list
+    int2 *rows = nullptr;
+    long long rows_cap = 0;
+    int4 *spans = nullptr;
+    long long spans_cap = 0;
+    long long work_n0 = 0;    // generation-0 size the work buffers were sized for
+    int acc_gen = 0;          // first generation not yet accumulated at the microphones
+    int depth_hint = 0;       // max_depth of the previous run, to size the queue at emission
+    float *src_dev = nullptr, *pow_dev = nullptr;
+    int src_cap = 0;
+    size_t bytes = 0;
+    int gen = 0;              // generations traced
+    int max_depth = -1;       // fixed by the first trace
+    long long n0 = 0;
+    double r_src = 0.0;
+};
+
+struct Request {
+    bt_request req{};
+    std::vector<float> src, pw;
+    bt_mics *mics = nullptr;
+    bt_beams *beams = nullptr;
+    hipEvent_t done = nullptr;
+};
+
+// ---------------------------------------------------------------------------------------
+// errors and memory
+// ---------------------------------------------------------------------------------------
+bt_status fail(bt_ctx *ctx, bt_status s, const char *fmt, ...);
+bt_status hip_fail(bt_ctx *ctx, hipError_t e, const char *what);
+
+#define HIP_TRY(ctx, expr)                                  \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+// Device allocation counted against the context's budget, and its release.
+bt_status dev_alloc(bt_ctx *ctx, void **p, size_t bytes);
+void dev_free(bt_ctx *ctx, void *p, size_t bytes);
+
+// Beam-set buffers: per-wave scratch for blocks_per_cu workgroups per CU, queue / segment
+// / list capacity of n records (keeping the first `keep` records), microphone work items
+// for n0 generation-0 beams, and their release.
+size_t list_ints(long long n, int n_waves);
+bt_status alloc_wave_scratch(bt_ctx *ctx, bt_beams *b, int blocks_per_cu);
+void queue_free(bt_ctx *ctx, DevQueue &q);
+void beams_release(bt_beams *b);
+bt_status reserve_queue(bt_ctx *ctx, bt_beams *b, long long n, long long keep);
+bt_status reserve_work(bt_ctx *ctx, bt_beams *b, long long n0);
+
+bt_status check_params(bt_ctx *ctx, const bt_mesh *mesh, const bt_params *p);
+TraceArgs make_args(const bt_params *p, int gen);

@@ -1,4 +1,4 @@
-// Internal layouts shared by the host code (bt_host.cpp) and the kernels (bt_kernels.hip).
+// Internal layouts shared by the host code (bt_host.cpp) and the kernels (*.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -51,12 +51,25 @@ struct DevMesh {
 //   dbl[k * cap + i], k = 0..17: A.xyz, d0.xyz, d1.xyz, d2.xyz, o.xyz, c.xyz
 //   flt[k * cap + i], k = 0..1: K (W/sr), Omega (sr)
 //   ints[k * cap + i], k = 0..2: initial beam id, start triangle, meta
-// meta: bits 0-7 depth, bit 8 near side is negative, bit 9 flagged (inherited)
+// meta: bits 0-7 depth, bit 8 near side is negative, bit 9 flagged (inherited); for beams
+// of a multi-scenario set (batches, served requests) also bits 10-14 the scenario's
+// max_depth and bits 16-31 its slot, inherited unchanged by children (zero otherwise)
 enum { D_A = 0, D_D0 = 3, D_D1 = 6, D_D2 = 9, D_O = 12, D_C = 15, D_N = 18 };
 enum { F_K = 0, F_OMEGA = 1, F_N = 2 };
 enum { I_ID = 0, I_START = 1, I_META = 2, I_N = 3 };
 constexpr int kMetaNegNear = 1 << 8;
 constexpr int kMetaFlag = 1 << 9;
+constexpr int kMetaMaxDepthShift = 10;
+constexpr int kMetaSlotShift = 16;
+constexpr int kMetaInherited = ~0x3ff;   // the scenario bits
+constexpr int kMaxSlots = 1 << 16;
+
+__host__ __device__ inline int scenario_meta(int slot, int max_depth)
+{
+    return (int)(((unsigned)slot << kMetaSlotShift) | ((unsigned)max_depth << kMetaMaxDepthShift));
+}
+__host__ __device__ inline int meta_slot(int meta) { return (int)((unsigned)meta >> kMetaSlotShift); }
+__host__ __device__ inline int meta_max_depth(int meta) { return (meta >> kMetaMaxDepthShift) & 31; }
 
 struct DevQueue {
     double *dbl;
@@ -88,6 +101,8 @@ struct DevMics {
     int nx, ny;
     double *e_strict;          // [nx*ny]
     double *e_flag;            // [nx*ny]
+    const unsigned *mask;      // scenario sets only: bit (j nx + i) set for the microphones of
+                               // the set's subset; NULL = every grid point
 };
 
 // Work buffers of the microphone stage: (segment, row) items of wide footprints,
@@ -121,17 +136,50 @@ struct WaveScratch {
 struct TraceArgs {
     int gen;         // trace: the generation traced; microphones: first generation
     int gen_end;     // microphones: one past the last generation accumulated
-    int max_depth;
+    int max_depth;   // single-scenario sets; a scenario set reads each beam's from its meta
+    int scenarios;   // 1: a multi-scenario set (per-beam max_depth and slot in meta)
+    const DevMics *slot_mics;  // scenario sets: microphone set of each slot
     double t_min, delta, air_m, e_min;
     int *hit_out;
     uint8_t *flag_out;
     double *t_out;
 };
 
-// Kernel launchers (bt_kernels.hip); all enqueue on `s` and return hipGetLastError().
+// Generation-0 beams of many scenarios, appended in one launch: source s emits the
+// 20 4^level[s] beams [first[s], first[s + 1]) (relative to the append position) with
+// the given meta and beam ids id0[s] + face.  The sizes are read from device memory so
+// that a captured launch serves tables of any size up to the buffers' capacity.
+struct EmitTable {
+    const float *src;          // [n][3]
+    const float *power;        // [n]
+    const int *level;          // [n]
+    const int *meta;           // [n]
+    const int *id0;            // [n]
+    const long long *first;    // [n + 1], first[n] = total beams
+    const long long *dims;     // [0] total beams, [1] n (sources)
+};
+
+// Sizes of one batch chunk, read by its kernels from device memory.
+struct BatchDesc {
+    long long n_fill;          // energies to zero (strict then flag arrays)
+    long long n_out;           // gathered outputs
+    long long e_stride;        // offset of the flag energies from the strict ones
+};
+
+// Kernel launchers; all enqueue on `s` and return hipGetLastError().  The statically
+// partitioned kernels run ws.n_waves waves (blocks of kWavesPerBlock waves).
 hipError_t launch_init_counters(DevCounters *ctr, long long n0, hipStream_t s);
 hipError_t launch_emit(const double *base20, const float *src, const float *power, int n_src, int level,
                        DevQueue q, hipStream_t s);
+// Appends the table's beams to generation `gen` (after its current beams) and adds their
+// number to count[gen].
+hipError_t launch_emit_table(const double *base20, const EmitTable &t, long long max_total, DevQueue q,
+                             DevCounters *ctr, int gen, hipStream_t s);
+// Zero d->n_fill doubles at p; gather d->n_out outputs (e[i] + e[stride + i] and
+// e[stride + i] for i = idx[k]).  max_n bounds the sizes (grid size).
+hipError_t launch_fill_desc(double *p, const BatchDesc *d, long long max_n, hipStream_t s);
+hipError_t launch_gather(const double *e, const long long *idx, const BatchDesc *d, long long max_n, double *out_e,
+                         double *out_f, hipStream_t s);
 hipError_t launch_trace(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, const TraceArgs &a,
                         WaveScratch ws, int n_cu, hipStream_t s);
 hipError_t launch_mics(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mics,

@@ -178,6 +178,7 @@ __device__ __forceinline__ bool row_cols(const HalfPlane *L, const DevMics &mc, 
 
 // Membership of grid microphone (i, j) and its contribution; returns 1 if accumulated.
 // Ambiguous: every active test passes within -delta and one is within delta of its plane.
+template <bool kSlots>
 __device__ __forceinline__ int mic_apply(const Frustum &f, const DevMics &mc, int i, int j, double air_m)
 {
     const V3 m = {mc.x0 + (double)i * mc.dx, mc.y0 + (double)j * mc.dy, mc.z};
@@ -206,11 +207,12 @@ __device__ __forceinline__ int mic_apply(const Frustum &f, const DevMics &mc, in
         near_any = near_any || s2 < f.amb2_far;
     }
     if (!inside) return 0;
+    const long long idx = (long long)j * mc.nx + i;
+    if (kSlots && mc.mask && !((mc.mask[idx >> 5] >> (idx & 31)) & 1u)) return 0;
     const double d2 = dot(r, r);
     float e = f.K / (float)d2;
     if (air_m > 0.0) e *= expf(-(float)(air_m * sqrt(d2)));
     const bool amb = !far_out && near_any;
-    const long long idx = (long long)j * mc.nx + i;
     atomicAdd((f.flag || amb) ? &mc.e_flag[idx] : &mc.e_strict[idx], (double)e);
     return 1;
 }
@@ -220,6 +222,7 @@ constexpr int kSpan = 32;   // longest column run one lane processes in place
 
 // Columns [c0, c1] of row j: processed here when short, else split into kSpan-column
 // span items (processed here anyway if the span buffer is full).
+template <bool kSlots>
 __device__ __forceinline__ void process_row(const Frustum &f, const DevMics &mc, const MicWork &w, DevCounters *ctr,
                                             int gen, long long seg, int j, int c0, int c1, double air_m,
                                             unsigned &tests, unsigned &updates)
@@ -239,8 +242,17 @@ __device__ __forceinline__ void process_row(const Frustum &f, const DevMics &mc,
     }
     for (int c = c0; c <= c1; ++c) {
         tests++;
-        updates += mic_apply(f, mc, c, j, air_m);
+        updates += mic_apply<kSlots>(f, mc, c, j, air_m);
     }
+}
+
+// The microphone set a segment contributes to: the set's own, or in a multi-scenario set
+// the one of the segment's slot.
+template <bool kSlots>
+__device__ __forceinline__ DevMics seg_mics(const DevMics &mc, const TraceArgs &a, const DevQueue &q, long long i)
+{
+    if (!kSlots) return mc;
+    return a.slot_mics[meta_slot(q.ints[I_META * q.cap + i])];
 }
 
 __device__ __forceinline__ void flush_mic_counters(DevCounters *ctr, unsigned tests, unsigned updates)
@@ -263,7 +275,8 @@ __device__ __forceinline__ unsigned long long general_region(unsigned long long 
     return ((batches + (unsigned long long)n_waves - 1) / (unsigned long long)n_waves) * 64;
 }
 
-__global__ void __launch_bounds__(256) k_mics(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mc,
+template <bool kSlots>
+__global__ void __launch_bounds__(256) k_mics(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mc0,
                                               TraceArgs a, MicWork w, WaveScratch ws)
 {
     const unsigned long long s0 = gen_start(ctr, a.gen);
@@ -284,6 +297,7 @@ __global__ void __launch_bounds__(256) k_mics(DevMesh M, DevQueue q, DevSegs seg
             // bounding box are the only candidates.  Most segments have none, and are
             // dismissed before the rest of the frustum is loaded.
             const long long cap = q.cap;
+            const DevMics mc = seg_mics<kSlots>(mc0, a, q, i);
             const V3 A = ld3(q.dbl + D_A * cap, cap, i);
             const double zr = mc.z - A.z;
             double xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
@@ -312,7 +326,7 @@ __global__ void __launch_bounds__(256) k_mics(DevMesh M, DevQueue q, DevSegs seg
                     for (int j = (int)fj0; j <= (int)fj1; ++j)
                         for (int c = (int)fi0; c <= (int)fi1; ++c) {
                             tests++;
-                            updates += mic_apply(f, mc, c, j, a.air_m);
+                            updates += mic_apply<kSlots>(f, mc, c, j, a.air_m);
                         }
                 }
             }
@@ -329,8 +343,9 @@ __global__ void __launch_bounds__(256) k_mics(DevMesh M, DevQueue q, DevSegs seg
 // General path, one lane per listed segment: the footprint's row range from the clipped
 // polygon; up to kInlineRows rows are finished here, wider footprints become (segment,
 // row) work items.
+template <bool kSlots>
 __global__ void __launch_bounds__(256) k_mics_general(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
-                                                      DevMics mc, TraceArgs a, MicWork w, WaveScratch ws)
+                                                      DevMics mc0, TraceArgs a, MicWork w, WaveScratch ws)
 {
     // wave w takes the items k_mics wave w put in its region (same grid)
     const unsigned long long s0 = gen_start(ctr, a.gen);
@@ -346,6 +361,7 @@ __global__ void __launch_bounds__(256) k_mics_general(DevMesh M, DevQueue q, Dev
         int nrows = 0, j0 = 0, j1 = -1;
         bool wide = false;
         if (active) {
+            const DevMics mc = seg_mics<kSlots>(mc0, a, q, i);
             Frustum f;
             load_frustum(M, q, segs, i, a.delta, f);
             HalfPlane L[9];
@@ -356,7 +372,7 @@ __global__ void __launch_bounds__(256) k_mics_general(DevMesh M, DevQueue q, Dev
                     for (int j = j0; j <= j1; ++j) {
                         int c0, c1;
                         if (!row_cols(L, mc, j, c0, c1)) continue;
-                        process_row(f, mc, w, ctr, a.gen, i, j, c0, c1, a.air_m, tests, updates);
+                        process_row<kSlots>(f, mc, w, ctr, a.gen, i, j, c0, c1, a.air_m, tests, updates);
                     }
                 } else {
                     wide = true;
@@ -397,7 +413,8 @@ __global__ void __launch_bounds__(256) k_mics_general(DevMesh M, DevQueue q, Dev
     flush_mic_counters(ctr, tests, updates);
 }
 
-__global__ void __launch_bounds__(256) k_mic_rows(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mc,
+template <bool kSlots>
+__global__ void __launch_bounds__(256) k_mic_rows(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mc0,
                                                   TraceArgs a, MicWork w)
 {
     unsigned long long n = ctr->n_rows[a.gen];
@@ -407,20 +424,22 @@ __global__ void __launch_bounds__(256) k_mic_rows(DevMesh M, DevQueue q, DevSegs
         const unsigned long long r = base + (unsigned long long)lane_id();
         const int2 it = r < n ? w.rows[r] : make_int2(-1, 0);
         if (it.x >= 0) {
+            const DevMics mc = seg_mics<kSlots>(mc0, a, q, it.x);
             Frustum f;
             load_frustum(M, q, segs, it.x, a.delta, f);
             HalfPlane L[9];
             footprint_lines(f, mc, L);
             int c0, c1;
             if (row_cols(L, mc, it.y, c0, c1))
-                process_row(f, mc, w, ctr, a.gen, it.x, it.y, c0, c1, a.air_m, tests, updates);
+                process_row<kSlots>(f, mc, w, ctr, a.gen, it.x, it.y, c0, c1, a.air_m, tests, updates);
         }
     }
     flush_mic_counters(ctr, tests, updates);
 }
 
+template <bool kSlots>
 __global__ void __launch_bounds__(256) k_mic_spans(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
-                                                   DevMics mc, TraceArgs a, MicWork w)
+                                                   DevMics mc0, TraceArgs a, MicWork w)
 {
     unsigned long long n = ctr->n_spans[a.gen];
     if (n > (unsigned long long)w.spans_cap) n = (unsigned long long)w.spans_cap;
@@ -429,19 +448,21 @@ __global__ void __launch_bounds__(256) k_mic_spans(DevMesh M, DevQueue q, DevSeg
         const unsigned long long r = base + (unsigned long long)lane_id();
         const int4 sp = r < n ? w.spans[r] : make_int4(-1, 0, 0, -1);
         if (sp.x >= 0) {
+            const DevMics mc = seg_mics<kSlots>(mc0, a, q, sp.x);
             Frustum f;
             load_frustum(M, q, segs, sp.x, a.delta, f);
             for (int c = sp.z; c <= sp.w; ++c) {
                 tests++;
-                updates += mic_apply(f, mc, c, sp.y, a.air_m);
+                updates += mic_apply<kSlots>(f, mc, c, sp.y, a.air_m);
             }
         }
     }
     flush_mic_counters(ctr, tests, updates);
 }
 
+template <bool kSlots>
 __global__ void __launch_bounds__(256) k_mics_big(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
-                                                  DevMics mc, TraceArgs a, MicWork w)
+                                                  DevMics mc0, TraceArgs a, MicWork w)
 {
     const unsigned long long n = ctr->n_big[a.gen];
     const int lane = lane_id();
@@ -450,6 +471,7 @@ __global__ void __launch_bounds__(256) k_mics_big(DevMesh M, DevQueue q, DevSegs
     unsigned tests = 0, updates = 0;
     for (unsigned long long s = (unsigned long long)wave; s < n; s += (unsigned long long)n_waves) {
         const long long i = w.big_list[s];
+        const DevMics mc = seg_mics<kSlots>(mc0, a, q, i);
         Frustum f;
         load_frustum(M, q, segs, i, a.delta, f);
         HalfPlane L[9];
@@ -459,30 +481,41 @@ __global__ void __launch_bounds__(256) k_mics_big(DevMesh M, DevQueue q, DevSegs
             for (int j = j0 + lane; j <= j1; j += 64) {
                 int c0, c1;
                 if (!row_cols(L, mc, j, c0, c1)) continue;
-                process_row(f, mc, w, ctr, a.gen, i, j, c0, c1, a.air_m, tests, updates);
+                process_row<kSlots>(f, mc, w, ctr, a.gen, i, j, c0, c1, a.air_m, tests, updates);
             }
         }
     }
     flush_mic_counters(ctr, tests, updates);
 }
 
+template <bool kSlots>
+static hipError_t launch_mics_t(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mics,
+                                const TraceArgs &a, MicWork w, WaveScratch ws, int n_cu, hipStream_t s)
+{
+    // k_mics and k_mics_general must use the same grid: wave w hands its region to wave w
+    const int blocks = ws.n_waves / kWavesPerBlock;
+    if (blocks <= 0 || blocks * kWavesPerBlock != ws.n_waves) return hipErrorInvalidValue;
+    k_mics<kSlots><<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, mics, a, w, ws);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_mics_general<kSlots><<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, mics, a, w, ws);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_mic_rows<kSlots><<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_mics_big<kSlots><<<n_cu * 4, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_mic_spans<kSlots><<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
+    return hipGetLastError();
+}
+
 hipError_t launch_mics(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mics,
                        const TraceArgs &a, MicWork w, WaveScratch ws, int n_cu, hipStream_t s)
 {
-    // k_mics and k_mics_general must use the same grid: wave w hands its region to wave w
-    const int blocks = n_cu * kBlocksPerCU;
-    if (blocks * kWavesPerBlock != ws.n_waves) return hipErrorInvalidValue;
-    k_mics<<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, mics, a, w, ws);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_mics_general<<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, mics, a, w, ws);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_mic_rows<<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_mics_big<<<n_cu * 4, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_mic_spans<<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
-    return hipGetLastError();
+    if (a.scenarios) {
+        if (!a.slot_mics) return hipErrorInvalidValue;
+        return launch_mics_t<true>(m, q, segs, ctr, mics, a, w, ws, n_cu, s);
+    }
+    return launch_mics_t<false>(m, q, segs, ctr, mics, a, w, ws, n_cu, s);
 }
 
 }  // namespace bt

@@ -320,7 +320,8 @@ __device__ void trace_ray(const DevMesh &M, RayState &r, RaySrc src, double t_mi
 __device__ __forceinline__ bool spawns_child(const DevMesh &M, const TraceArgs &a, int hit, int meta, float K,
                                              float om)
 {
-    if (hit < 0 || (meta & 0xff) >= a.max_depth) return false;
+    const int max_depth = a.scenarios ? meta_max_depth(meta) : a.max_depth;
+    if (hit < 0 || (meta & 0xff) >= max_depth) return false;
     const float Kc = K * (1.0f - M.alpha[hit]);
     return !(a.e_min > 0.0) || ((double)Kc * (double)om > a.e_min);
 }
@@ -511,7 +512,8 @@ __global__ void __launch_bounds__(256) k_reflect(DevMesh M, DevQueue q, DevSegs 
             m1 = mirror(ld3(in.dbl + D_D2 * icap, icap, i), nn);  // d1 and d2 swap: det stays > 0
             m2 = mirror(ld3(in.dbl + D_D1 * icap, icap, i), nn);
             // the child lives on the side the parent came from
-            meta2 = ((meta & 0xff) + 1) | (dot(c, N) > 0.0 ? kMetaNegNear : 0) | (segs.flag[i] ? kMetaFlag : 0);
+            meta2 = (meta & kMetaInherited) | ((meta & 0xff) + 1) | (dot(c, N) > 0.0 ? kMetaNegNear : 0) |
+                    (segs.flag[i] ? kMetaFlag : 0);
             om = in.flt[F_OMEGA * icap + i];
             id = in.ints[I_ID * icap + i];
         }
@@ -538,8 +540,9 @@ hipError_t launch_trace(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters 
                         WaveScratch ws, int n_cu, hipStream_t s)
 {
     // k_trace and k_reflect must use the same grid: wave w owns the same batches in both
-    const int blocks = n_cu * kBlocksPerCU;
-    if (blocks * kWavesPerBlock != ws.n_waves) return hipErrorInvalidValue;
+    (void)n_cu;
+    const int blocks = ws.n_waves / kWavesPerBlock;
+    if (blocks <= 0 || blocks * kWavesPerBlock != ws.n_waves) return hipErrorInvalidValue;
     k_trace<<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, a, ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

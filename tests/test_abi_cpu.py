@@ -58,7 +58,8 @@ def _c_layout(struct, fields, tmp_path):
     return [int(x) for x in out]
 
 
-@pytest.mark.parametrize("name", ["bt_params", "bt_stats", "bt_request", "bt_result"])
+@pytest.mark.parametrize("name", ["bt_params", "bt_stats", "bt_request", "bt_result", "bt_scenario",
+                                  "bt_batch_opts", "bt_batch_stats"])
 def test_struct_layouts_match_header(name, tmp_path):
     cls = getattr(bt, name)
     fields = [f[0] for f in cls._fields_]
