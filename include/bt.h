@@ -242,6 +242,51 @@ typedef struct {
 bt_status bt_batch_run(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *scenarios, int32_t n,
                        const bt_params *params, const bt_batch_opts *opts, bt_batch_stats *stats);
 
+/* ------------------------------------------------------------------------------------
+ * Serving (paper Section 3: the model is built once and serves many simulations).  A
+ * server owns a thread that admits requests as they arrive.  In the batched mode it runs
+ * continuous batching: at every generation step, requests that fit the free queue
+ * records and microphone memory join the shared multi-scenario beam set (their
+ * generation-0 beams are appended to the generation being traced), every live request
+ * advances by one generation in the same launches, and a request is finished once its
+ * max_depth + 1 generations have been traced and accumulated.  In the plain mode it runs
+ * one request at a time through bt_run (the baseline).  A request's result equals the
+ * result of bt_run on it alone (up to the order of FP64 additions).
+ * ------------------------------------------------------------------------------------ */
+typedef struct bt_server bt_server;
+
+#define BT_SERVE_BATCHED 0
+#define BT_SERVE_PLAIN 1
+
+typedef struct {
+    int32_t mode;               /* BT_SERVE_BATCHED or BT_SERVE_PLAIN */
+    int64_t max_records;        /* queue records of a batch session (sum over its requests of
+                                   n_beams0 (max_depth + 1)); 0 = 32 Mi */
+    int64_t arena_bytes;        /* device bytes per session for microphone energies and
+                                   outputs; 0 = 1 GiB */
+    int32_t blocks_per_cu;      /* 0 = 8 */
+} bt_server_opts;
+
+typedef struct {
+    double t_submit;            /* seconds since the server started */
+    double t_admit;             /* when its beams were first enqueued */
+    double t_done;              /* when its outputs were written */
+} bt_serve_result;
+
+/* Start a server on (ctx, mesh); params as for bt_batch_run.  The server uses the
+ * context's stream; other work on the same context must not run while it lives. */
+bt_status bt_server_create(bt_ctx *ctx, const bt_mesh *mesh, const bt_params *params, const bt_server_opts *opts,
+                           bt_server **out);
+/* Queue a request (a scenario; its host inputs are copied).  Its output buffers must stay
+ * valid until bt_server_poll reports it finished.  BT_EINVAL for a bad request, BT_ENOMEM
+ * for one that can never fit a session. */
+bt_status bt_server_submit(bt_server *s, const bt_scenario *req, uint64_t *ticket);
+/* BT_PENDING while the request runs; BT_OK once its outputs are written (the ticket is
+ * then released and out, if not NULL, filled); BT_ENOTFOUND for an unknown ticket. */
+bt_status bt_server_poll(bt_server *s, uint64_t ticket, bt_serve_result *out);
+/* Finish every queued request, stop the thread and free the server. */
+bt_status bt_server_destroy(bt_server *s);
+
 #define BT_TUNE_MAX_CANDIDATES 32
 
 /* Choose bt_batch_opts for a workload by running a leading sample of it (about a quarter

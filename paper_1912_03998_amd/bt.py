@@ -23,7 +23,8 @@ STATUS = {0: "BT_OK", 1: "BT_PENDING", -1: "BT_EINVAL", -2: "BT_ENOMEM", -3: "BT
 EXPORTED = ["bt_params_default", "bt_status_str", "bt_last_error", "bt_create", "bt_destroy", "bt_memory_used",
             "bt_build_mesh", "bt_mesh_free", "bt_mesh_info", "bt_mics_grid", "bt_mics_reset", "bt_mics_free",
             "bt_emit_beams", "bt_beams_free", "bt_beams_stats", "bt_trace", "bt_accumulate_mics", "bt_levels",
-            "bt_run", "bt_submit", "bt_poll", "bt_cancel", "bt_batch_run", "bt_batch_autotune"]
+            "bt_run", "bt_submit", "bt_poll", "bt_cancel", "bt_batch_run", "bt_batch_autotune",
+            "bt_server_create", "bt_server_submit", "bt_server_poll", "bt_server_destroy"]
 
 
 class BTError(RuntimeError):
@@ -93,6 +94,10 @@ def lib():
         "bt_cancel": (C.c_int, [P, C.c_uint64]),
         "bt_batch_run": (C.c_int, [P, P, P, I32, P, P, P]),
         "bt_batch_autotune": (C.c_int, [P, P, P, I32, P, P, P, P]),
+        "bt_server_create": (C.c_int, [P, P, P, P, P]),
+        "bt_server_submit": (C.c_int, [P, P, P]),
+        "bt_server_poll": (C.c_int, [P, C.c_uint64, P]),
+        "bt_server_destroy": (C.c_int, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -326,3 +331,77 @@ def bt_batch_autotune(ctx, mesh, scenarios, params=None):
                                         C.byref(out), secs, C.byref(nc)), "bt_batch_autotune")
     return ({"chunk_beams": out.chunk_beams, "blocks_per_cu": out.blocks_per_cu, "use_graph": out.use_graph},
             list(secs[:nc.value]))
+
+
+BT_SERVE_BATCHED, BT_SERVE_PLAIN = 0, 1
+
+
+class bt_server_opts(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("max_records", C.c_int64), ("arena_bytes", C.c_int64),
+                ("blocks_per_cu", C.c_int32)]
+
+
+class bt_serve_result(C.Structure):
+    _fields_ = [("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+def bt_server_create(ctx, mesh, params=None, mode=BT_SERVE_BATCHED, max_records=0, arena_bytes=0, blocks_per_cu=0):
+    o = bt_server_opts(mode, max_records, arena_bytes, blocks_per_cu)
+    out = C.c_void_p()
+    _check(ctx, lib().bt_server_create(ctx, mesh, None if params is None else C.byref(params), C.byref(o),
+                                       C.byref(out)), "bt_server_create")
+    return out
+
+
+def bt_server_submit(ctx, server, scenario) -> int:
+    """scenario: a Scenario; its energy / flag arrays receive the outputs."""
+    t = C.c_uint64()
+    sc = scenario.struct()
+    _check(ctx, lib().bt_server_submit(server, C.byref(sc), C.byref(t)), "bt_server_submit")
+    return t.value
+
+
+def bt_server_poll(ctx, server, ticket):
+    """None while pending, else (t_submit, t_admit, t_done) in seconds since the server started."""
+    r = bt_serve_result()
+    s = _check(ctx, lib().bt_server_poll(server, ticket, C.byref(r)), "bt_server_poll")
+    if s == BT_PENDING:
+        return None
+    return r.t_submit, r.t_admit, r.t_done
+
+
+def bt_server_destroy(ctx, server):
+    _check(ctx, lib().bt_server_destroy(server), "bt_server_destroy")
+
+
+class Server:
+    """A request server on (ctx, mesh): submit Scenario objects, poll their tickets.  The
+    submitted Scenario objects are kept alive here until their outputs are written."""
+
+    def __init__(self, ctx, mesh, params=None, mode=BT_SERVE_BATCHED, **opts):
+        self.ctx = ctx
+        self.h = bt_server_create(ctx, mesh, params, mode, **opts)
+        self.live = {}
+
+    def submit(self, scenario) -> int:
+        t = bt_server_submit(self.ctx, self.h, scenario)
+        self.live[t] = scenario
+        return t
+
+    def poll(self, ticket):
+        r = bt_server_poll(self.ctx, self.h, ticket)
+        if r is not None:
+            self.live.pop(ticket, None)
+        return r
+
+    def close(self):
+        if self.h is not None:
+            bt_server_destroy(self.ctx, self.h)
+            self.h = None
+            self.live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libbt.so")
 
-SOURCES = ["bt_emit.hip", "bt_trace.hip", "bt_mics.hip", "bt_host.cpp", "bt_batch.cpp"]
+SOURCES = ["bt_emit.hip", "bt_trace.hip", "bt_mics.hip", "bt_host.cpp", "bt_batch.cpp", "bt_serve.cpp"]
 HEADERS = ["bt_internal.h", "bt_device.h", "bt_host.h"]
 
 FLAGS = [

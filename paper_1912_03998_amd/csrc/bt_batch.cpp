@@ -22,14 +22,6 @@ constexpr long long kDefaultChunkBeams = 16ll << 20;
 constexpr long long kMaxChunkEnergies = 1ll << 28;   // strict doubles per chunk (2 GiB of both)
 constexpr long long kIndexLimit = (1ll << 31) - 1;    // queue records and work items are int32
 
-struct ScenarioSize {
-    long long n0;         // generation-0 beams
-    long long records;    // n0 (max_depth + 1): queue records at most
-    long long grid;       // grid microphones
-    long long n_out;      // outputs
-    long long mask_words; // subset bitmap words (0 without a subset)
-};
-
 struct Chunk {
     int first = 0, end = 0;
     long long n0 = 0, records = 0, sources = 0, energy = 0, mask_words = 0, n_out = 0;
@@ -95,45 +87,6 @@ struct BatchWork {
     }
 };
 
-bt_status validate(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario &sc, int k, ScenarioSize &z)
-{
-    if (sc.n_src < 0 || (sc.n_src > 0 && (!sc.src_xyz || !sc.src_power)))
-        return fail(ctx, BT_EINVAL, "scenario %d: bad sources", k);
-    if (sc.level < 0 || sc.level > BT_MAX_LEVEL) return fail(ctx, BT_EINVAL, "scenario %d: level %d", k, sc.level);
-    if (sc.max_depth < 0 || sc.max_depth > BT_MAX_DEPTH)
-        return fail(ctx, BT_EINVAL, "scenario %d: max_depth %d", k, sc.max_depth);
-    for (int i = 0; i < sc.n_src; ++i) {
-        for (int c = 0; c < 3; ++c) {
-            const float v = sc.src_xyz[3 * i + c];
-            if (!std::isfinite(v) || std::fabs((double)v) > mesh->r_eff)
-                return fail(ctx, BT_EINVAL, "scenario %d: source %d outside the region the mesh margins cover", k, i);
-        }
-        if (!(sc.src_power[i] >= 0.f) || !std::isfinite(sc.src_power[i]))
-            return fail(ctx, BT_EINVAL, "scenario %d: source %d power invalid", k, i);
-    }
-    if (sc.mic_nx < 1 || sc.mic_ny < 1 || (long long)sc.mic_nx * sc.mic_ny > kIndexLimit)
-        return fail(ctx, BT_EINVAL, "scenario %d: bad microphone grid %d x %d", k, sc.mic_nx, sc.mic_ny);
-    if (!std::isfinite(sc.mic_x0) || !std::isfinite(sc.mic_y0) || !std::isfinite(sc.mic_z) || !(sc.mic_dx > 0.f) ||
-        !(sc.mic_dy > 0.f) || !std::isfinite(sc.mic_dx) || !std::isfinite(sc.mic_dy))
-        return fail(ctx, BT_EINVAL, "scenario %d: bad microphone grid geometry", k);
-    if (!sc.energy_out) return fail(ctx, BT_EINVAL, "scenario %d: energy_out is NULL", k);
-    z.grid = (long long)sc.mic_nx * sc.mic_ny;
-    if (sc.mic_subset) {
-        if (sc.n_subset < 1 || sc.n_subset > kIndexLimit) return fail(ctx, BT_EINVAL, "scenario %d: n_subset", k);
-        for (long long i = 0; i < sc.n_subset; ++i)
-            if (sc.mic_subset[i] < 0 || (long long)sc.mic_subset[i] >= z.grid)
-                return fail(ctx, BT_EINVAL, "scenario %d: subset index %lld out of the grid", k, i);
-        z.n_out = sc.n_subset;
-        z.mask_words = (z.grid + 31) / 32;
-    } else {
-        z.n_out = z.grid;
-        z.mask_words = 0;
-    }
-    z.n0 = (long long)sc.n_src * (20ll << (2 * sc.level));
-    z.records = z.n0 * (sc.max_depth + 1);
-    if (z.records > kIndexLimit) return fail(ctx, BT_EINVAL, "scenario %d: too many beams", k);
-    return BT_OK;
-}
 
 // The chunk's launches: counters, emission, zeroed energies, every generation's trace,
 // one microphone pass over all of them, the gather.
@@ -174,7 +127,7 @@ bt_status run_batch(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *sc, int
     std::vector<ScenarioSize> z((size_t)n);
     int depth = 0;
     for (int k = 0; k < n; ++k) {
-        if ((st = validate(ctx, mesh, sc[k], k, z[k])) != BT_OK) return st;
+        if ((st = validate_scenario(ctx, mesh, sc[k], k, z[k])) != BT_OK) return st;
         depth = std::max(depth, sc[k].max_depth);
     }
     // chunks, in scenario order
@@ -368,6 +321,46 @@ bt_status resolve_opts(bt_ctx *ctx, const bt_batch_opts *opts, bt_batch_opts &o)
 }
 
 }  // namespace
+
+bt_status validate_scenario(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario &sc, int k, ScenarioSize &z)
+{
+    if (sc.n_src < 0 || (sc.n_src > 0 && (!sc.src_xyz || !sc.src_power)))
+        return fail(ctx, BT_EINVAL, "scenario %d: bad sources", k);
+    if (sc.level < 0 || sc.level > BT_MAX_LEVEL) return fail(ctx, BT_EINVAL, "scenario %d: level %d", k, sc.level);
+    if (sc.max_depth < 0 || sc.max_depth > BT_MAX_DEPTH)
+        return fail(ctx, BT_EINVAL, "scenario %d: max_depth %d", k, sc.max_depth);
+    for (int i = 0; i < sc.n_src; ++i) {
+        for (int c = 0; c < 3; ++c) {
+            const float v = sc.src_xyz[3 * i + c];
+            if (!std::isfinite(v) || std::fabs((double)v) > mesh->r_eff)
+                return fail(ctx, BT_EINVAL, "scenario %d: source %d outside the region the mesh margins cover", k, i);
+        }
+        if (!(sc.src_power[i] >= 0.f) || !std::isfinite(sc.src_power[i]))
+            return fail(ctx, BT_EINVAL, "scenario %d: source %d power invalid", k, i);
+    }
+    if (sc.mic_nx < 1 || sc.mic_ny < 1 || (long long)sc.mic_nx * sc.mic_ny > kIndexLimit)
+        return fail(ctx, BT_EINVAL, "scenario %d: bad microphone grid %d x %d", k, sc.mic_nx, sc.mic_ny);
+    if (!std::isfinite(sc.mic_x0) || !std::isfinite(sc.mic_y0) || !std::isfinite(sc.mic_z) || !(sc.mic_dx > 0.f) ||
+        !(sc.mic_dy > 0.f) || !std::isfinite(sc.mic_dx) || !std::isfinite(sc.mic_dy))
+        return fail(ctx, BT_EINVAL, "scenario %d: bad microphone grid geometry", k);
+    if (!sc.energy_out) return fail(ctx, BT_EINVAL, "scenario %d: energy_out is NULL", k);
+    z.grid = (long long)sc.mic_nx * sc.mic_ny;
+    if (sc.mic_subset) {
+        if (sc.n_subset < 1 || sc.n_subset > kIndexLimit) return fail(ctx, BT_EINVAL, "scenario %d: n_subset", k);
+        for (long long i = 0; i < sc.n_subset; ++i)
+            if (sc.mic_subset[i] < 0 || (long long)sc.mic_subset[i] >= z.grid)
+                return fail(ctx, BT_EINVAL, "scenario %d: subset index %lld out of the grid", k, i);
+        z.n_out = sc.n_subset;
+        z.mask_words = (z.grid + 31) / 32;
+    } else {
+        z.n_out = z.grid;
+        z.mask_words = 0;
+    }
+    z.n0 = (long long)sc.n_src * (20ll << (2 * sc.level));
+    z.records = z.n0 * (sc.max_depth + 1);
+    if (z.records > kIndexLimit) return fail(ctx, BT_EINVAL, "scenario %d: too many beams", k);
+    return BT_OK;
+}
 
 extern "C" bt_status bt_batch_run(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *scenarios, int32_t n,
                                   const bt_params *params, const bt_batch_opts *opts, bt_batch_stats *stats)

@@ -560,6 +560,24 @@ extern "C" bt_status bt_mics_reset(bt_ctx *ctx, bt_mics *m)
     return BT_OK;
 }
 
+bt_status mics_fit(bt_ctx *ctx, bt_mics **m, float x0, float y0, float z, float dx, float dy, int32_t nx, int32_t ny)
+{
+    const long long n = (long long)nx * ny;
+    if (*m && (size_t)n * sizeof(double) * 3 <= (*m)->bytes) {
+        bt_mics *g = *m;
+        g->dev.x0 = x0; g->dev.y0 = y0; g->dev.z = z; g->dev.dx = dx; g->dev.dy = dy;
+        g->dev.nx = nx; g->dev.ny = ny;
+        g->dev.e_flag = g->dev.e_strict + n;
+        g->level = g->dev.e_flag + n;
+        return bt_mics_reset(ctx, g);
+    }
+    if (*m) {
+        bt_mics_free(*m);
+        *m = nullptr;
+    }
+    return bt_mics_grid(ctx, x0, y0, z, dx, dy, nx, ny, m);
+}
+
 extern "C" bt_status bt_mics_free(bt_mics *m)
 {
     if (!m) return BT_EINVAL;

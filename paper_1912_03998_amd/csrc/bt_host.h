@@ -107,3 +107,18 @@ bt_status reserve_work(bt_ctx *ctx, bt_beams *b, long long n0);
 
 bt_status check_params(bt_ctx *ctx, const bt_mesh *mesh, const bt_params *p);
 TraceArgs make_args(const bt_params *p, int gen);
+
+// Sizes of a scenario (a batch member or a served request), filled by validate_scenario,
+// which checks it against the mesh (BT_EINVAL with a message naming scenario k).
+struct ScenarioSize {
+    long long n0;          // generation-0 beams
+    long long records;     // n0 (max_depth + 1): queue records at most
+    long long grid;        // grid microphones
+    long long n_out;       // outputs
+    long long mask_words;  // subset bitmap words (0 without a subset)
+};
+bt_status validate_scenario(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario &sc, int k, ScenarioSize &z);
+
+// Point a microphone set at a new grid, reallocating only when it does not fit, and zero
+// its energies (*m may be NULL: created).
+bt_status mics_fit(bt_ctx *ctx, bt_mics **m, float x0, float y0, float z, float dx, float dy, int32_t nx, int32_t ny);

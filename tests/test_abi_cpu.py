@@ -59,7 +59,7 @@ def _c_layout(struct, fields, tmp_path):
 
 
 @pytest.mark.parametrize("name", ["bt_params", "bt_stats", "bt_request", "bt_result", "bt_scenario",
-                                  "bt_batch_opts", "bt_batch_stats"])
+                                  "bt_batch_opts", "bt_batch_stats", "bt_server_opts", "bt_serve_result"])
 def test_struct_layouts_match_header(name, tmp_path):
     cls = getattr(bt, name)
     fields = [f[0] for f in cls._fields_]
