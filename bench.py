@@ -68,6 +68,108 @@ def cpu_baseline(scene):
                       f"in {dt:.2f} s", "mic_updates_per_s": r.counters["mic_updates"] / dt}
 
 
+def batch_bench(sess, seed=0, n=256):
+    """The batched form: n uneven scenarios on the district (sources on streets, 1280 to
+    81920 beams per source, depth 2-10, a random 10 k microphone subset each), autotuned,
+    in one call, against the same scenarios run one by one through the plain path."""
+    import numpy as np
+    from paper_1912_03998_amd import bt
+    from scenegen import batch_scenarios
+
+    specs = batch_scenarios(seed, n)
+
+    def scenarios():
+        return [bt.Scenario(q.sources, q.power, q.level, q.depth, q.grid, q.subset) for q in specs]
+
+    print(f"[bench] batch: {n} scenarios, {sum(q.n_beams0 for q in specs)} generation-0 beams; autotune ...",
+          file=sys.stderr, flush=True)
+    opts, cand = bt.bt_batch_autotune(sess.ctx, sess.mesh, scenarios())
+    scs = scenarios()
+    t0 = time.perf_counter()
+    st = bt.bt_batch_run(sess.ctx, sess.mesh, scs, opts=opts)
+    batched_s = time.perf_counter() - t0
+    print(f"[bench] batch: {batched_s:.3f} s with {opts}; sequential ...", file=sys.stderr, flush=True)
+    grid = tuple(float(v) for v in specs[0].grid[:5]) + tuple(int(v) for v in specs[0].grid[5:])
+    t0 = time.perf_counter()
+    worst = 0.0
+    for q, sc in zip(specs, scs):
+        r = sess.run(q.sources, q.power, q.level, q.depth, grid, parity=False, stats=False)
+        e = (r.e_strict + r.e_flag)[q.subset]
+        worst = max(worst, float(np.abs(e - sc.energy).max() / max(np.abs(e).max(), 1e-300)))
+    seq_s = time.perf_counter() - t0
+    return {"scenarios": n, "beams0": st["beams0"], "segments": st["segments"], "mic_updates": st["mic_updates"],
+            "chunks": st["chunks"], "opts": opts, "autotune_candidate_s": [round(x, 4) for x in cand],
+            "batched_s": round(batched_s, 4), "batched_segments_per_s": st["segments"] / batched_s,
+            "sequential_s": round(seq_s, 4), "sequential_segments_per_s": st["segments"] / seq_s,
+            "speedup_vs_sequential": round(seq_s / batched_s, 3), "max_rel_diff_vs_sequential": worst}
+
+
+def serve_bench(sess, rates, n_of_rate, warm_frac=0.1, seed=0, saturation=400):
+    """The serving form: Poisson request streams (1-32 sources on streets, 5120 or 20480
+    beams per source, depth 3-8, 1 k-50 k microphone rectangles) at each rate, through the
+    continuously batched server and through the plain one-request-at-a-time server; p50 /
+    p99 latency (completion minus submission, server clock) over the requests after the
+    warm-up ones, and the rate at which a closed burst of requests completes."""
+    import numpy as np
+    from paper_1912_03998_amd import bt
+    from scenegen import serving_requests
+
+    def run(mode, reqs, paced):
+        scs = [bt.Scenario(q.sources, q.power, q.level, q.depth, q.grid) for q in reqs]
+        with bt.Server(sess.ctx, sess.mesh, mode=mode) as srv:
+            out, todo = {}, {}
+            t0 = time.perf_counter()
+            for k, sc in enumerate(scs):
+                while paced and time.perf_counter() - t0 < reqs[k].arrival:
+                    for t in list(todo):
+                        r = srv.poll(t)
+                        if r is not None:
+                            out[todo.pop(t)] = r
+                    time.sleep(0.0001)
+                todo[srv.submit(sc)] = k
+            while todo:
+                for t in list(todo):
+                    r = srv.poll(t)
+                    if r is not None:
+                        out[todo.pop(t)] = r
+                time.sleep(0.0001)
+            wall = time.perf_counter() - t0
+        return scs, out, wall
+
+    res = {"rates": {}}
+    energies = {}
+    for rate in rates:
+        n = n_of_rate(rate)
+        reqs = serving_requests(seed, n, rate)
+        w = int(n * warm_frac)
+        row = {"requests": n, "warmup": w, "offered_beams0_per_s": rate * float(np.mean([q.n_beams0 for q in reqs]))}
+        for mode, name in ((bt.BT_SERVE_BATCHED, "batched"), (bt.BT_SERVE_PLAIN, "plain")):
+            print(f"[bench] serve {name} at {rate} req/s, {n} requests ...", file=sys.stderr, flush=True)
+            scs, out, wall = run(mode, reqs, True)
+            lat = np.array([out[k][2] - out[k][0] for k in range(w, n)])
+            span = max(out[k][2] for k in range(w, n)) - min(out[k][0] for k in range(w, n))
+            row[name] = {"p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+                         "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+                         "mean_ms": round(1e3 * float(lat.mean()), 3),
+                         "completed_per_s": round((n - w) / span, 2)}
+            energies[(rate, name)] = [sc.energy for sc in scs]
+        a, b = energies[(rate, "batched")], energies[(rate, "plain")]
+        row["max_rel_diff_batched_vs_plain"] = max(float(np.abs(x - y).max() / max(np.abs(y).max(), 1e-300))
+                                                   for x, y in zip(a, b))
+        res["rates"][str(rate)] = row
+    # closed burst: every request submitted at once, completion rate of each server
+    reqs = serving_requests(seed + 1, saturation, 1e9)
+    sat = {"requests": saturation}
+    for mode, name in ((bt.BT_SERVE_BATCHED, "batched"), (bt.BT_SERVE_PLAIN, "plain")):
+        print(f"[bench] serve {name} burst of {saturation} ...", file=sys.stderr, flush=True)
+        _, out, wall = run(mode, reqs, False)
+        sat[name + "_req_per_s"] = round(saturation / wall, 2)
+        sat[name + "_beams0_per_s"] = sum(q.n_beams0 for q in reqs) / wall
+    sat["speedup"] = round(sat["batched_req_per_s"] / sat["plain_req_per_s"], 3)
+    res["saturation"] = sat
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +178,10 @@ def main():
     ap.add_argument("--config", type=int, default=2, help="0 tiny, 1 block, 2 district (default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tiles", type=int, default=0, help="override the tile partition (n x n)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-scenario measurement")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="serving at the full stream lengths (200 warm-up + 2000 requests per rate)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -201,6 +307,14 @@ def main():
         "end_to_end_segments_per_s": segs / (setup_s + ms_per_step * 1e-3),
         "kernel_sha256_16": kernel_hash(),
     }
+    if args.config == 2 and not args.no_batch:
+        out["batched"] = batch_bench(sess)
+    if args.config == 2 and not args.no_serve:
+        if args.serve_full:
+            n_of_rate, warm = (lambda r: 2200), 200 / 2200
+        else:
+            n_of_rate, warm = (lambda r: int(min(2200, max(300, 4 * r)))), 0.1
+        out["served"] = serve_bench(sess, [50, 200, 800], n_of_rate, warm)
     sess.close()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)

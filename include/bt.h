@@ -237,10 +237,16 @@ typedef struct {
 /* Run n scenarios and write each one's microphone energies to its buffers; synchronises.
  * params: physics (t_min, edge_delta, air_m, e_min; NULL = defaults); its max_depth and
  * parity outputs are not used (each scenario has its own depth).  opts: NULL = defaults.
- * stats: NULL or filled.  Scenarios are taken in order into chunks.  BT_EINVAL on a bad
+ * stats: NULL or filled (seconds: from the first upload to the last output, after the
+ * workspace is in place).  Scenarios are taken in order into chunks.  BT_EINVAL on a bad
  * scenario (nothing is run), BT_ENOMEM when a chunk does not fit the budget. */
 bt_status bt_batch_run(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *scenarios, int32_t n,
                        const bt_params *params, const bt_batch_opts *opts, bt_batch_stats *stats);
+
+/* bt_batch_run keeps its device workspace (queue, microphone arrays, staging, captured
+ * graph) in the context between calls, grown to the largest chunk seen, so repeated
+ * batches allocate nothing; this frees it (bt_destroy does too). */
+bt_status bt_batch_release(bt_ctx *ctx);
 
 /* ------------------------------------------------------------------------------------
  * Serving (paper Section 3: the model is built once and serves many simulations).  A

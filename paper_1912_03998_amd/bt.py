@@ -23,7 +23,7 @@ STATUS = {0: "BT_OK", 1: "BT_PENDING", -1: "BT_EINVAL", -2: "BT_ENOMEM", -3: "BT
 EXPORTED = ["bt_params_default", "bt_status_str", "bt_last_error", "bt_create", "bt_destroy", "bt_memory_used",
             "bt_build_mesh", "bt_mesh_free", "bt_mesh_info", "bt_mics_grid", "bt_mics_reset", "bt_mics_free",
             "bt_emit_beams", "bt_beams_free", "bt_beams_stats", "bt_trace", "bt_accumulate_mics", "bt_levels",
-            "bt_run", "bt_submit", "bt_poll", "bt_cancel", "bt_batch_run", "bt_batch_autotune",
+            "bt_run", "bt_submit", "bt_poll", "bt_cancel", "bt_batch_run", "bt_batch_release", "bt_batch_autotune",
             "bt_server_create", "bt_server_submit", "bt_server_poll", "bt_server_destroy"]
 
 
@@ -94,6 +94,7 @@ def lib():
         "bt_cancel": (C.c_int, [P, C.c_uint64]),
         "bt_batch_run": (C.c_int, [P, P, P, I32, P, P, P]),
         "bt_batch_autotune": (C.c_int, [P, P, P, I32, P, P, P, P]),
+        "bt_batch_release": (C.c_int, [P]),
         "bt_server_create": (C.c_int, [P, P, P, P, P]),
         "bt_server_submit": (C.c_int, [P, P, P]),
         "bt_server_poll": (C.c_int, [P, C.c_uint64, P]),
@@ -319,6 +320,10 @@ def bt_batch_run(ctx, mesh, scenarios, params=None, opts=None) -> dict:
                                    None if o is None else C.byref(o), C.byref(st)), "bt_batch_run")
     return {"chunks": st.chunks, "beams0": st.beams0, "segments": st.segments, "mic_updates": st.mic_updates,
             "seconds": st.seconds}
+
+
+def bt_batch_release(ctx):
+    _check(ctx, lib().bt_batch_release(ctx), "bt_batch_release")
 
 
 def bt_batch_autotune(ctx, mesh, scenarios, params=None):

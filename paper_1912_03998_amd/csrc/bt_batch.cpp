@@ -27,20 +27,25 @@ struct Chunk {
     long long n0 = 0, records = 0, sources = 0, energy = 0, mask_words = 0, n_out = 0;
 };
 
-// Device workspace of one call (sized for its largest chunk) with pinned host mirrors of
-// everything uploaded or read back per chunk.
+}  // namespace
+
+// bt_batch_run's workspace, kept in the context between calls and grown when a batch
+// needs more: the emission table, slot microphone sets, bitmaps, energies, gather
+// indices and outputs (device, with pinned host mirrors), the shared beam set, and the
+// captured launch graph (valid while the buffers, the depth and the physics stay).
 struct BatchWork {
     bt_ctx *ctx = nullptr;
-    long long max_sources = 0, max_slots = 0, max_energy = 0, max_mask = 0, max_out = 0, max_n0 = 0;
+    long long cap_sources = 0, cap_slots = 0, cap_energy = 0, cap_mask = 0, cap_out = 0, cap_n0 = 0, cap_records = 0;
+    int bpc = 0;
     // device
     float *src = nullptr, *power = nullptr;
     int *level = nullptr, *meta = nullptr, *id0 = nullptr;
     long long *first = nullptr, *dims = nullptr;
     DevMics *slots = nullptr;
     unsigned *mask = nullptr;
-    double *energy = nullptr;      // strict [max_energy], then flag [max_energy]
+    double *energy = nullptr;      // per chunk: strict [E], then flag [E]
     long long *gidx = nullptr;
-    double *out = nullptr;         // [2][max_out]: strict + flag, flag
+    double *out = nullptr;         // [2][cap_out]: strict + flag, flag
     BatchDesc *desc = nullptr;
     // pinned host
     float *h_src = nullptr, *h_power = nullptr;
@@ -57,17 +62,31 @@ struct BatchWork {
     bt_beams *beams = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    int graph_depth = -1;
+    bt_params graph_params{};
 
-    ~BatchWork()
+    void drop_graph()
     {
-        // an early return may leave launches in flight that use these buffers
-        if (ctx && ctx->stream) (void)hipStreamSynchronize(ctx->stream);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        graph_depth = -1;
+    }
+    void release()
+    {
+        if (ctx && ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+        drop_graph();
         if (beams) bt_beams_free(beams);
+        beams = nullptr;
         for (auto &d : dev_bufs) dev_free(ctx, d.first, d.second);
         for (void *h : host_bufs) (void)hipHostFree(h);
+        dev_bufs.clear();
+        host_bufs.clear();
+        cap_sources = cap_slots = cap_energy = cap_mask = cap_out = cap_n0 = cap_records = 0;
+        bpc = 0;
     }
+    ~BatchWork() { release(); }
     template <class T> bt_status dev(T **p, long long n)
     {
         const size_t bytes = (size_t)std::max(n, 1ll) * sizeof(T);
@@ -85,19 +104,71 @@ struct BatchWork {
         host_bufs.push_back((void *)*p);
         return BT_OK;
     }
+    // Capacity for chunks up to `need` (sources, slots, energy, mask words, outputs, n0,
+    // records) with blocks_per_cu workgroups per CU; everything is reallocated (grown) if
+    // anything is short.
+    bt_status ensure(const Chunk &need, long long records, int blocks_per_cu)
+    {
+        if (bpc == blocks_per_cu && need.sources <= cap_sources && need.end - need.first <= cap_slots &&
+            need.energy <= cap_energy && need.mask_words <= cap_mask && need.n_out <= cap_out && need.n0 <= cap_n0 &&
+            records <= cap_records)
+            return BT_OK;
+        const long long s_ = std::max(need.sources, cap_sources), sl = std::max<long long>(need.end - need.first, cap_slots);
+        const long long e_ = std::max(need.energy, cap_energy), m_ = std::max(need.mask_words, cap_mask);
+        const long long o_ = std::max(need.n_out, cap_out), n0 = std::max(std::max(need.n0, cap_n0), 1ll);
+        const long long r_ = std::max(std::max(records, cap_records), 1ll);
+        release();
+        bt_status st;
+        if ((st = dev(&src, 3 * s_)) != BT_OK || (st = dev(&power, s_)) != BT_OK || (st = dev(&level, s_)) != BT_OK ||
+            (st = dev(&meta, s_)) != BT_OK || (st = dev(&id0, s_)) != BT_OK || (st = dev(&first, s_ + 1)) != BT_OK ||
+            (st = dev(&dims, 2)) != BT_OK || (st = dev(&slots, sl)) != BT_OK || (st = dev(&mask, m_)) != BT_OK ||
+            (st = dev(&energy, 2 * e_)) != BT_OK || (st = dev(&gidx, o_)) != BT_OK || (st = dev(&out, 2 * o_)) != BT_OK ||
+            (st = dev(&desc, 1)) != BT_OK)
+            return st;
+        if ((st = host(&h_src, 3 * s_)) != BT_OK || (st = host(&h_power, s_)) != BT_OK ||
+            (st = host(&h_level, s_)) != BT_OK || (st = host(&h_meta, s_)) != BT_OK || (st = host(&h_id0, s_)) != BT_OK ||
+            (st = host(&h_first, s_ + 1)) != BT_OK || (st = host(&h_dims, 2)) != BT_OK ||
+            (st = host(&h_slots, sl)) != BT_OK || (st = host(&h_mask, m_)) != BT_OK || (st = host(&h_gidx, o_)) != BT_OK ||
+            (st = host(&h_out, 2 * o_)) != BT_OK || (st = host(&h_desc, 1)) != BT_OK || (st = host(&h_ctr, 1)) != BT_OK)
+            return st;
+        // the shared beam set: every generation of the largest chunk resident
+        beams = new bt_beams();
+        beams->ctx = ctx;
+        if ((st = dev_alloc(ctx, (void **)&beams->ctr, sizeof(DevCounters))) != BT_OK) return st;
+        if ((st = alloc_wave_scratch(ctx, beams, blocks_per_cu)) != BT_OK) return st;
+        if ((st = reserve_queue(ctx, beams, r_, 0)) != BT_OK) return st;
+        if ((st = reserve_work(ctx, beams, n0)) != BT_OK) return st;
+        cap_sources = s_;
+        cap_slots = sl;
+        cap_energy = e_;
+        cap_mask = m_;
+        cap_out = o_;
+        cap_n0 = n0;
+        cap_records = r_;
+        bpc = blocks_per_cu;
+        return BT_OK;
+    }
 };
 
+void batch_work_free(bt_ctx *ctx)
+{
+    delete ctx->batch;
+    ctx->batch = nullptr;
+}
+
+namespace {
 
 // The chunk's launches: counters, emission, zeroed energies, every generation's trace,
-// one microphone pass over all of them, the gather.
+// one microphone pass over all of them, the gather.  Grid sizes follow the capacities;
+// the kernels read the chunk's own sizes from device memory.
 bt_status enqueue_chunk(bt_ctx *ctx, const bt_mesh *mesh, BatchWork &w, const TraceArgs &base, int depth)
 {
     bt_beams *b = w.beams;
     hipStream_t s = ctx->stream;
     const EmitTable t{w.src, w.power, w.level, w.meta, w.id0, w.first, w.dims};
     HIP_TRY(ctx, launch_init_counters(b->ctr, 0, s));
-    HIP_TRY(ctx, launch_emit_table(ctx->base20, t, w.max_n0, b->q, b->ctr, 0, s));
-    HIP_TRY(ctx, launch_fill_desc(w.energy, w.desc, 2 * w.max_energy, s));
+    HIP_TRY(ctx, launch_emit_table(ctx->base20, t, w.cap_n0, b->q, b->ctr, 0, s));
+    HIP_TRY(ctx, launch_fill_desc(w.energy, w.desc, 2 * w.cap_energy, s));
     for (int g = 0; g <= depth; ++g) {
         TraceArgs a = base;
         a.gen = g;
@@ -108,8 +179,13 @@ bt_status enqueue_chunk(bt_ctx *ctx, const bt_mesh *mesh, BatchWork &w, const Tr
     a.gen_end = depth + 1;
     MicWork mw{b->rows, b->rows_cap, b->spans, b->spans_cap, b->big_list + b->cap, b->big_list};
     HIP_TRY(ctx, launch_mics(mesh->dev, b->q, b->segs, b->ctr, DevMics{}, a, mw, b->ws, ctx->n_cu, s));
-    HIP_TRY(ctx, launch_gather(w.energy, w.gidx, w.desc, w.max_out, w.out, w.out + w.max_out, s));
+    HIP_TRY(ctx, launch_gather(w.energy, w.gidx, w.desc, w.cap_out, w.out, w.out + w.cap_out, s));
     return BT_OK;
+}
+
+bool same_physics(const bt_params &a, const bt_params &b)
+{
+    return a.t_min == b.t_min && a.edge_delta == b.edge_delta && a.air_m == b.air_m && a.e_min == b.e_min;
 }
 
 bt_status run_batch(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *sc, int n, const bt_params *params,
@@ -151,53 +227,39 @@ bt_status run_batch(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *sc, int
         c.n_out += z[k].n_out;
     }
     if (c.end > c.first) chunks.push_back(c);
-    // workspace for the largest chunk
-    BatchWork w;
-    w.ctx = ctx;
-    long long max_records = 1;
+    Chunk need;
+    long long records = 1;
     for (const Chunk &ch : chunks) {
-        w.max_sources = std::max(w.max_sources, ch.sources);
-        w.max_slots = std::max(w.max_slots, (long long)(ch.end - ch.first));
-        w.max_energy = std::max(w.max_energy, ch.energy);
-        w.max_mask = std::max(w.max_mask, ch.mask_words);
-        w.max_out = std::max(w.max_out, ch.n_out);
-        w.max_n0 = std::max(w.max_n0, ch.n0);
-        max_records = std::max(max_records, ch.records);
+        need.sources = std::max(need.sources, ch.sources);
+        need.end = std::max(need.end, ch.end - ch.first);
+        need.energy = std::max(need.energy, ch.energy);
+        need.mask_words = std::max(need.mask_words, ch.mask_words);
+        need.n_out = std::max(need.n_out, ch.n_out);
+        need.n0 = std::max(need.n0, ch.n0);
+        records = std::max(records, ch.records);
     }
-    if ((st = w.dev(&w.src, 3 * w.max_sources)) != BT_OK || (st = w.dev(&w.power, w.max_sources)) != BT_OK ||
-        (st = w.dev(&w.level, w.max_sources)) != BT_OK || (st = w.dev(&w.meta, w.max_sources)) != BT_OK ||
-        (st = w.dev(&w.id0, w.max_sources)) != BT_OK || (st = w.dev(&w.first, w.max_sources + 1)) != BT_OK ||
-        (st = w.dev(&w.dims, 2)) != BT_OK || (st = w.dev(&w.slots, w.max_slots)) != BT_OK ||
-        (st = w.dev(&w.mask, w.max_mask)) != BT_OK || (st = w.dev(&w.energy, 2 * w.max_energy)) != BT_OK ||
-        (st = w.dev(&w.gidx, w.max_out)) != BT_OK || (st = w.dev(&w.out, 2 * w.max_out)) != BT_OK ||
-        (st = w.dev(&w.desc, 1)) != BT_OK)
+    if (!ctx->batch) {
+        ctx->batch = new BatchWork();
+        ctx->batch->ctx = ctx;
+    }
+    BatchWork &w = *ctx->batch;
+    if ((st = w.ensure(need, records, o.blocks_per_cu)) != BT_OK) {
+        w.release();
         return st;
-    if ((st = w.host(&w.h_src, 3 * w.max_sources)) != BT_OK || (st = w.host(&w.h_power, w.max_sources)) != BT_OK ||
-        (st = w.host(&w.h_level, w.max_sources)) != BT_OK || (st = w.host(&w.h_meta, w.max_sources)) != BT_OK ||
-        (st = w.host(&w.h_id0, w.max_sources)) != BT_OK || (st = w.host(&w.h_first, w.max_sources + 1)) != BT_OK ||
-        (st = w.host(&w.h_dims, 2)) != BT_OK || (st = w.host(&w.h_slots, w.max_slots)) != BT_OK ||
-        (st = w.host(&w.h_mask, w.max_mask)) != BT_OK || (st = w.host(&w.h_gidx, w.max_out)) != BT_OK ||
-        (st = w.host(&w.h_out, 2 * w.max_out)) != BT_OK || (st = w.host(&w.h_desc, 1)) != BT_OK ||
-        (st = w.host(&w.h_ctr, 1)) != BT_OK)
-        return st;
-    // the shared beam set: every generation of the largest chunk resident
-    w.beams = new bt_beams();
-    w.beams->ctx = ctx;
-    if ((st = w.dev(&w.beams->ctr, 1)) != BT_OK) return st;
-    w.dev_bufs.pop_back();  // owned (and freed) by the beam set
-    if ((st = alloc_wave_scratch(ctx, w.beams, o.blocks_per_cu)) != BT_OK) return st;
-    if ((st = reserve_queue(ctx, w.beams, max_records, 0)) != BT_OK) return st;
-    if ((st = reserve_work(ctx, w.beams, std::max(w.max_n0, 1ll))) != BT_OK) return st;
-
+    }
     TraceArgs base = make_args(&p, 0);
     base.max_depth = depth;
     base.scenarios = 1;
     base.slot_mics = w.slots;
     hipStream_t s = ctx->stream;
+    if (w.exec && (w.graph_depth != depth || !same_physics(w.graph_params, p))) w.drop_graph();
     const auto t0 = std::chrono::steady_clock::now();
     long long segments = 0, updates = 0, beams0 = 0;
     for (const Chunk &ch : chunks) {
-        // emission table, slot microphone sets, subset masks and gather indices
+        // emission table, slot microphone sets, subset masks and gather indices; the flag
+        // energies follow the chunk's E strict ones
+        long long E = 0;
+        for (int k = ch.first; k < ch.end; ++k) E += z[k].grid;
         long long ns = 0, beam = 0, eoff = 0, moff = 0, ooff = 0;
         for (int k = ch.first; k < ch.end; ++k) {
             const bt_scenario &q = sc[k];
@@ -221,7 +283,7 @@ bt_status run_batch(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *sc, int
             m.nx = q.mic_nx;
             m.ny = q.mic_ny;
             m.e_strict = w.energy + eoff;
-            m.e_flag = w.energy + w.max_energy + eoff;
+            m.e_flag = w.energy + E + eoff;
             m.mask = nullptr;
             if (q.mic_subset) {
                 unsigned *mk = w.h_mask + moff;
@@ -243,9 +305,7 @@ bt_status run_batch(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *sc, int
         w.h_first[ns] = beam;
         w.h_dims[0] = beam;
         w.h_dims[1] = ns;
-        w.h_desc[0] = BatchDesc{2 * w.max_energy, ooff, w.max_energy};
-        // the flag energies live max_energy after the strict ones, so the whole buffer is
-        // zeroed; only the chunk's own outputs are gathered
+        w.h_desc[0] = BatchDesc{2 * E, ooff, E};
         const size_t nsrc = (size_t)std::max(ns, 1ll);
         HIP_TRY(ctx, hipMemcpyAsync(w.src, w.h_src, 3 * nsrc * sizeof(float), hipMemcpyHostToDevice, s));
         HIP_TRY(ctx, hipMemcpyAsync(w.power, w.h_power, nsrc * sizeof(float), hipMemcpyHostToDevice, s));
@@ -274,6 +334,8 @@ bt_status run_batch(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *sc, int
                 if (ce != hipSuccess) return hip_fail(ctx, ce, "hipStreamEndCapture");
                 w.graph = g;
                 HIP_TRY(ctx, hipGraphInstantiate(&w.exec, w.graph, nullptr, nullptr, 0));
+                w.graph_depth = depth;
+                w.graph_params = p;
             }
             HIP_TRY(ctx, hipGraphLaunch(w.exec, s));
         } else if ((st = enqueue_chunk(ctx, mesh, w, base, depth)) != BT_OK) {
@@ -281,7 +343,7 @@ bt_status run_batch(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *sc, int
         }
         if (ooff > 0) {
             HIP_TRY(ctx, hipMemcpyAsync(w.h_out, w.out, (size_t)ooff * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIP_TRY(ctx, hipMemcpyAsync(w.h_out + w.max_out, w.out + w.max_out, (size_t)ooff * sizeof(double),
+            HIP_TRY(ctx, hipMemcpyAsync(w.h_out + w.cap_out, w.out + w.cap_out, (size_t)ooff * sizeof(double),
                                         hipMemcpyDeviceToHost, s));
         }
         HIP_TRY(ctx, hipMemcpyAsync(w.h_ctr, w.beams->ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
@@ -290,7 +352,7 @@ bt_status run_batch(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *sc, int
         for (int k = ch.first; k < ch.end; ++k) {
             std::memcpy(sc[k].energy_out, w.h_out + ooff, (size_t)z[k].n_out * sizeof(double));
             if (sc[k].flag_out)
-                std::memcpy(sc[k].flag_out, w.h_out + w.max_out + ooff, (size_t)z[k].n_out * sizeof(double));
+                std::memcpy(sc[k].flag_out, w.h_out + w.cap_out + ooff, (size_t)z[k].n_out * sizeof(double));
             ooff += z[k].n_out;
         }
         for (int g = 0; g <= depth; ++g) segments += (long long)w.h_ctr->count[g];
@@ -376,6 +438,14 @@ extern "C" bt_status bt_batch_run(bt_ctx *ctx, const bt_mesh *mesh, const bt_sce
     return run_batch(ctx, mesh, scenarios, n, params, o, stats);
 }
 
+extern "C" bt_status bt_batch_release(bt_ctx *ctx)
+{
+    if (!ctx) return BT_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    batch_work_free(ctx);
+    return BT_OK;
+}
+
 extern "C" bt_status bt_batch_autotune(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *scenarios, int32_t n,
                                        const bt_params *params, bt_batch_opts *out, double *seconds_out,
                                        int32_t *n_candidates_out)
@@ -395,12 +465,17 @@ extern "C" bt_status bt_batch_autotune(bt_ctx *ctx, const bt_mesh *mesh, const b
                   (20ll << (2 * std::min(std::max(scenarios[m].level, 0), BT_MAX_LEVEL)));
         ++m;
     }
-    std::vector<bt_batch_opts> cand;
+    // largest chunks first for each grid width, so the cached workspace is allocated once
+    // per width rather than grown candidate by candidate
+    std::vector<long long> sizes;
     for (long long cb : {4ll << 20, 8ll << 20, 16ll << 20, 32ll << 20}) {
-        if (cb > 2 * sample && !cand.empty()) break;
-        for (int bpc : {4, 8})
-            for (int g : {0, 1}) cand.push_back(bt_batch_opts{cb, bpc, g});
+        if (cb > 2 * sample && !sizes.empty()) break;
+        sizes.push_back(cb);
     }
+    std::vector<bt_batch_opts> cand;
+    for (int bpc : {8, 4})
+        for (auto it = sizes.rbegin(); it != sizes.rend(); ++it)
+            for (int g : {0, 1}) cand.push_back(bt_batch_opts{*it, bpc, g});
     // an untimed first run pays for code loading and first-touch allocation
     bt_status s = bt_batch_run(ctx, mesh, scenarios, m, params, &cand[0], nullptr);
     if (s != BT_OK) return s;

@@ -181,6 +181,7 @@ extern "C" bt_status bt_destroy(bt_ctx *ctx)
         bt_beams_free(r->beams);
         delete r;
     }
+    batch_work_free(ctx);
     dev_free(ctx, ctx->base20, 20 * 9 * sizeof(double));
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;

@@ -25,6 +25,7 @@ struct bt_ctx {
     std::mutex mtx;            // submit / poll / cancel
     uint64_t next_ticket = 1;
     std::map<uint64_t, struct Request *> requests;
+    struct BatchWork *batch = nullptr;  // bt_batch_run's workspace, kept between calls
 };
 
 struct bt_mesh {
@@ -122,3 +123,6 @@ bt_status validate_scenario(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario 
 // Point a microphone set at a new grid, reallocating only when it does not fit, and zero
 // its energies (*m may be NULL: created).
 bt_status mics_fit(bt_ctx *ctx, bt_mics **m, float x0, float y0, float z, float dx, float dy, int32_t nx, int32_t ny);
+
+// Free bt_batch_run's cached workspace (bt_destroy, bt_batch_release).
+void batch_work_free(bt_ctx *ctx);
