@@ -2,8 +2,9 @@
 //
 // Batched mode: continuous batching over two multi-scenario beam sets ("sessions").  The
 // server thread runs steps; in each step every session that has requests in flight
-// traces one generation, in one set of launches for all its requests, and accumulates
-// that generation's microphone contributions into each request's own arrays.  Requests
+// traces one generation, in one set of launches for all its requests; in a step that
+// finishes a request, one microphone pass accumulates every generation traced since the
+// previous pass into each request's own arrays (all generations stay resident).  Requests
 // are admitted at step boundaries, in arrival order, into the open session while it has
 // free queue records, arena memory, slots and generations: their generation-0 beams are
 // appended to the generation the session traces next.  A request admitted at generation
@@ -85,6 +86,7 @@ struct Session {
     long long arena_used = 0, h_used = 0;
     long long records = 0;
     int n_slots = 0, gen = 0;
+    int acc_gen = 0;               // first generation not yet accumulated at the microphones
     int unfinished = 0;            // admitted and not yet finalized
     bool open = false;
     std::vector<Req *> live, fresh;
@@ -187,6 +189,7 @@ bt_status reset_session(bt_server *s, Session &q)
     q.records = 0;
     q.n_slots = 0;
     q.gen = 0;
+    q.acc_gen = 0;
     return BT_OK;
 }
 
@@ -306,10 +309,18 @@ bt_status step_session(bt_server *s, Session &q, int parity, std::vector<Req *> 
     a.scenarios = 1;
     a.slot_mics = q.slots;
     HIP_TRY(ctx, launch_trace(s->mesh->dev, b->q, b->segs, b->ctr, a, b->ws, ctx->n_cu, st));
-    a.gen_end = q.gen + 1;
-    MicWork mw{b->rows, b->rows_cap, b->spans, b->spans_cap, b->big_list + b->cap, b->big_list};
-    HIP_TRY(ctx, launch_mics(s->mesh->dev, b->q, b->segs, b->ctr, DevMics{}, a, mw, b->ws, ctx->n_cu, st));
     q.dirty = true;
+    // the microphone pass runs only in steps that finish a request, over every generation
+    // traced since the previous pass (all stay resident in the session)
+    bool finishing = false;
+    for (Req *r : q.live) finishing = finishing || r->admit_gen + r->sc.max_depth == q.gen;
+    if (finishing) {
+        a.gen = q.acc_gen;
+        a.gen_end = q.gen + 1;
+        MicWork mw{b->rows, b->rows_cap, b->spans, b->spans_cap, b->big_list + b->cap, b->big_list};
+        HIP_TRY(ctx, launch_mics(s->mesh->dev, b->q, b->segs, b->ctr, DevMics{}, a, mw, b->ws, ctx->n_cu, st));
+        q.acc_gen = q.gen + 1;
+    }
     std::vector<Req *> keep;
     for (Req *r : q.live) {
         if (r->admit_gen + r->sc.max_depth == q.gen) {
