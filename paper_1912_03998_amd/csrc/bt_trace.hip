@@ -123,8 +123,8 @@ __device__ __forceinline__ bool maybe_candidate(const float4 &a, const float4 &b
 //   valid hit:   t in (hit_lo, t_hi], inside, better than the current best
 //   candidate:   t in (cand_lo, t_hi], t < best_t + delta, within delta of the triangle
 __device__ __forceinline__ void test_leaf(const float4 *__restrict__ tris, int first, int count, RayState &r,
-                                          RaySrc src, double hit_lo, double cand_lo, double t_hi, double t_min,
-                                          double delta)
+                                          RaySrc src, double hit_lo, double cand_lo, float flo, double t_hi,
+                                          double t_min, double delta)
 {
     for (int k = first; k < first + count; ++k) {
         const float4 a = tris[3 * k], b = tris[3 * k + 1], cc = tris[3 * k + 2];
@@ -132,7 +132,7 @@ __device__ __forceinline__ void test_leaf(const float4 *__restrict__ tris, int f
         if (id == r.start) continue;
         r.tri_tests++;
         const double upper = fmin(t_hi, r.best_t + delta);
-        if (!maybe_candidate(a, b, cc, r, f32_down(cand_lo), f32_up(upper), (float)delta)) continue;
+        if (!maybe_candidate(a, b, cc, r, flo, f32_up(upper), (float)delta)) continue;
         V3 o, c;
         load_ray64(src, o, c);
         const V3 v0 = {a.x, a.y, a.z}, v1 = {a.w, b.x, b.y}, v2 = {b.z, b.w, cc.x};
@@ -205,6 +205,13 @@ __device__ __forceinline__ bool box1(const float *bx, const RayState &r, float t
 }
 
 // Traverse one tile's hierarchy over the ray window (t_lo, t_hi].
+// The walk of a tile's hierarchy is "while-while": a lane descends interior nodes until it
+// stands at a leaf (or has nothing left), and the wave tests its lanes' leaves together
+// once every lane is there.  Leaf tests are the long code path; taking them in one pass
+// keeps most lanes of the wave busy in it instead of a few lanes in every node step.
+constexpr int kDone = (int)0x80000000;  // no leaf reference can take this value (< 2^28 refs)
+
+// Traverse one tile's hierarchy over the ray window (t_lo, t_hi].
 __device__ void traverse_tile(const DevMesh &M, int tile, RayState &r, RaySrc src, double t_lo, double t_hi,
                               double t_min, double delta, int *stk)
 {
@@ -213,37 +220,40 @@ __device__ void traverse_tile(const DevMesh &M, int tile, RayState &r, RaySrc sr
     const double hit_lo = fmax(t_lo, t_min);
     const double cand_lo = fmax(t_lo, t_min - delta);
     const float flo = f32_down(cand_lo);
-    if (!box1(M.tile_box + 6 * tile, r, flo, f32_up(fmin(t_hi, r.best_t + delta)))) return;
+    // FP32 upper end of the box window, refreshed after every leaf (which may lower best_t)
+    float fhi = f32_up(fmin(t_hi, r.best_t + delta));
+    if (!box1(M.tile_box + 6 * tile, r, flo, fhi)) return;
     const int bdim = blockDim.x;
     const int tid = threadIdx.x;
     int sp = 0;
     int ref = root;
     while (true) {
-        if (ref >= 0) {
+        while (ref >= 0) {
             const float4 *nd = M.nodes + 4 * (long long)ref;
             const float4 nx = nd[0], ny = nd[1], nz = nd[2], nr = nd[3];
             r.node_visits++;
             float t0, t1;
             bool h0, h1;
-            box2(nx, ny, nz, r, flo, f32_up(fmin(t_hi, r.best_t + delta)), t0, t1, h0, h1);
+            box2(nx, ny, nz, r, flo, fhi, t0, t1, h0, h1);
             const int c0 = __float_as_int(nr.x), c1 = __float_as_int(nr.y);
             if (h0 && h1) {
                 const bool first0 = t0 <= t1;
                 stk[sp * bdim + tid] = first0 ? c1 : c0;
                 sp++;
                 ref = first0 ? c0 : c1;
-                continue;
-            } else if (h0) {
-                ref = c0;
-                continue;
-            } else if (h1) {
-                ref = c1;
-                continue;
+            } else if (h0 || h1) {
+                ref = h0 ? c0 : c1;
+            } else if (sp > 0) {
+                sp--;
+                ref = stk[sp * bdim + tid];
+            } else {
+                ref = kDone;
             }
-        } else {
-            const int v = ~ref;
-            test_leaf(M.tris, v >> 3, v & 7, r, src, hit_lo, cand_lo, t_hi, t_min, delta);
         }
+        if (ref == kDone) break;
+        const int v = ~ref;
+        test_leaf(M.tris, v >> 3, v & 7, r, src, hit_lo, cand_lo, flo, t_hi, t_min, delta);
+        fhi = f32_up(fmin(t_hi, r.best_t + delta));
         if (sp == 0) break;
         sp--;
         ref = stk[sp * bdim + tid];
