@@ -276,7 +276,7 @@ __device__ __forceinline__ unsigned long long general_region(unsigned long long 
 }
 
 template <bool kSlots>
-__global__ void __launch_bounds__(256) k_mics(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mc0,
+__global__ void __launch_bounds__(256, 4) k_mics(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mc0,
                                               TraceArgs a, MicWork w, WaveScratch ws)
 {
     const unsigned long long s0 = gen_start(ctr, a.gen);
@@ -344,7 +344,7 @@ __global__ void __launch_bounds__(256) k_mics(DevMesh M, DevQueue q, DevSegs seg
 // polygon; up to kInlineRows rows are finished here, wider footprints become (segment,
 // row) work items.
 template <bool kSlots>
-__global__ void __launch_bounds__(256) k_mics_general(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
+__global__ void __launch_bounds__(256, 3) k_mics_general(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
                                                       DevMics mc0, TraceArgs a, MicWork w, WaveScratch ws)
 {
     // wave w takes the items k_mics wave w put in its region (same grid)

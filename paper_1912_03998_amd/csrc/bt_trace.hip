@@ -336,7 +336,7 @@ __device__ __forceinline__ bool spawns_child(const DevMesh &M, const TraceArgs &
     return !(a.e_min > 0.0) || ((double)Kc * (double)om > a.e_min);
 }
 
-__global__ void __launch_bounds__(256) k_trace(DevMesh M, DevQueue in, DevSegs segs, DevCounters *ctr, TraceArgs a,
+__global__ void __launch_bounds__(256, 4) k_trace(DevMesh M, DevQueue in, DevSegs segs, DevCounters *ctr, TraceArgs a,
                                                WaveScratch ws)
 {
     __shared__ int stk[kStack * 256];
