@@ -196,8 +196,9 @@ extern "C" bt_status bt_memory_used(const bt_ctx *ctx, size_t *bytes)
 }
 
 // ---------------------------------------------------------------------------------------
-// BVH build (host): binned SAH over triangle boxes, 32 bins per axis, leaves of up to 4
-// triangles (7 when forced), flattened so each interior node holds both child boxes.
+// BVH build (host): binned SAH over triangle boxes, 32 bins per axis, leaves of up to 2
+// triangles (up to 7 where the SAH prefers a leaf or the depth limit forces one),
+// flattened so each interior node holds both child boxes.
 // ---------------------------------------------------------------------------------------
 namespace {
 
@@ -260,7 +261,9 @@ struct Builder {
     {
         max_depth = std::max(max_depth, depth);
         int n = e - b;
-        if (n <= 4) return make_leaf(b, e);
+        // two-triangle leaves: with leaves tested together by the wave, a deeper tree of
+        // small leaves beat 1-, 4- and 7-triangle leaves on the district (measured)
+        if (n <= 2) return make_leaf(b, e);
         if (depth >= kStack - 1) {
             if (n <= 7) return make_leaf(b, e);
             overflow = true;
