@@ -302,16 +302,21 @@ __global__ void __launch_bounds__(256, 4) k_mics(DevMesh M, DevQueue q, DevSegs 
             const double zr = mc.z - A.z;
             double xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
             bool proper = zr != 0.0;
+            // the frustum lies in the cone of its edge directions from the apex; when the
+            // apex is off the microphone plane (by far more than the plane tests' rounding)
+            // and no edge direction turns towards the plane, no microphone can be inside
+            bool away = zr > 1e-6 || zr < -1e-6;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const V3 d = ld3(q.dbl + (D_D0 + 3 * k) * cap, cap, i);
                 const double s = zr / d.z;
                 proper = proper && s > 0.0 && isfinite(s);
+                away = away && (zr > 0.0 ? d.z <= 0.0 : d.z >= 0.0);
                 const double px = A.x + s * d.x, py = A.y + s * d.y;
                 xmn = fmin(xmn, px); xmx = fmax(xmx, px);
                 ymn = fmin(ymn, py); ymx = fmax(ymx, py);
             }
-            general = true;
+            general = !away;
             if (proper) {
                 const double relax = 1e-6;
                 const double fi0 = fmax(ceil((xmn - relax - mc.x0) / mc.dx), 0.0);
