@@ -42,14 +42,16 @@ hipError_t launch_fill(double *p, long long n, double v, hipStream_t s)
 // edge midpoints are normalize(x + y) and the child at position j of (a, b, c) is
 // (a, ab, ca), (ab, b, bc), (ca, bc, c) or (ab, bc, ca).
 // ---------------------------------------------------------------------------------------
-// Beam `f` (face index) of a level-`level` source at S with power W, written at queue
-// index j.
-__device__ void emit_one(const double *__restrict__ base20, int level, long long f, V3 S, float W, int meta, int id,
-                         DevQueue q, long long j)
+// Face `f` of the level-`level` icosphere: its three edge directions, the guiding
+// direction and the solid angle.
+__device__ void face_of(const double *__restrict__ base20, int level, long long f, V3 &a, V3 &bb, V3 &c, V3 &cc,
+                        float &om)
 {
     int bf = (int)(f >> (2 * level));
     const double *bp = base20 + 9 * bf;
-    V3 a = {bp[0], bp[1], bp[2]}, bb = {bp[3], bp[4], bp[5]}, c = {bp[6], bp[7], bp[8]};
+    a = {bp[0], bp[1], bp[2]};
+    bb = {bp[3], bp[4], bp[5]};
+    c = {bp[6], bp[7], bp[8]};
     for (int l = level - 1; l >= 0; --l) {
         int k = (int)((f >> (2 * l)) & 3);
         V3 ab = unit(a + bb), bc = unit(bb + c), ca = unit(c + a);
@@ -58,10 +60,17 @@ __device__ void emit_one(const double *__restrict__ base20, int level, long long
         else if (k == 2) { a = ca; bb = bc; }
         else { a = ab; bb = bc; c = ca; }
     }
-    V3 cc = unit((a + bb) + c);
+    cc = unit((a + bb) + c);
     double num = fabs(dot(a, cross(bb, c)));
     double den = 1.0 + dot(a, bb) + dot(bb, c) + dot(c, a);
-    double omega = 2.0 * atan2(num, den);
+    om = (float)(2.0 * atan2(num, den));
+}
+
+// A generation-0 beam record at queue index j: apex and origin at the source S, the face's
+// directions, K = W / (4 pi).
+__device__ __forceinline__ void store_beam(DevQueue q, long long j, V3 S, V3 a, V3 bb, V3 c, V3 cc, float W, float om,
+                                           int meta, int id)
+{
     const long long cap = q.cap;
     st3(q.dbl + D_A * cap, cap, j, S);
     st3(q.dbl + D_D0 * cap, cap, j, a);
@@ -70,30 +79,65 @@ __device__ void emit_one(const double *__restrict__ base20, int level, long long
     st3(q.dbl + D_O * cap, cap, j, S);
     st3(q.dbl + D_C * cap, cap, j, cc);
     q.flt[F_K * cap + j] = (float)((double)W / (4.0 * M_PI));
-    q.flt[F_OMEGA * cap + j] = (float)omega;
+    q.flt[F_OMEGA * cap + j] = om;
     q.ints[I_ID * cap + j] = id;
     q.ints[I_START * cap + j] = -1;
     q.ints[I_META * cap + j] = meta;
 }
 
-__global__ void k_emit(const double *__restrict__ base20, const float *__restrict__ src,
-                       const float *__restrict__ power, int n_src, int level, long long nf, DevQueue q)
+// Beam `f` (face index) of a level-`level` source at S with power W, written at queue
+// index j.
+__device__ void emit_one(const double *__restrict__ base20, int level, long long f, V3 S, float W, int meta, int id,
+                         DevQueue q, long long j)
+{
+    V3 a, bb, c, cc;
+    float om;
+    face_of(base20, level, f, a, bb, c, cc, om);
+    store_beam(q, j, S, a, bb, c, cc, W, om, meta, id);
+}
+
+// The face table of one level, computed once: dirs[k * nf + f] for k = 0..11 (d0, d1, d2,
+// c) and om[f].
+__global__ void k_faces(const double *__restrict__ base20, int level, long long nf, double *dirs, float *om)
+{
+    const long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    V3 a, bb, c, cc;
+    face_of(base20, level, f, a, bb, c, cc, om[f]);
+    st3(dirs, nf, f, a);
+    st3(dirs + 3 * nf, nf, f, bb);
+    st3(dirs + 6 * nf, nf, f, c);
+    st3(dirs + 9 * nf, nf, f, cc);
+}
+
+hipError_t launch_faces(const double *base20, int level, double *dirs, float *om, hipStream_t s)
+{
+    const long long nf = 20ll << (2 * level);
+    k_faces<<<(unsigned)((nf + 255) / 256), 256, 0, s>>>(base20, level, nf, dirs, om);
+    return hipGetLastError();
+}
+
+// Generation 0 of one beam set: beam b = s nf + f is face f of source s, copied from the
+// level's face table.
+__global__ void k_emit(const double *__restrict__ dirs, const float *__restrict__ fom, const float *__restrict__ src,
+                       const float *__restrict__ power, int n_src, long long nf, DevQueue q)
 {
     long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     long long total = nf * n_src;
     if (b >= total) return;
     long long s = b / nf, f = b - s * nf;
     const V3 S = {src[3 * s], src[3 * s + 1], src[3 * s + 2]};
-    emit_one(base20, level, f, S, power[s], 0, (int)b, q, b);
+    store_beam(q, b, S, ld3(dirs, nf, f), ld3(dirs + 3 * nf, nf, f), ld3(dirs + 6 * nf, nf, f),
+               ld3(dirs + 9 * nf, nf, f), power[s], fom[f], 0, (int)b);
 }
 
-hipError_t launch_emit(const double *base20, const float *src, const float *power, int n_src, int level,
+hipError_t launch_emit(const double *dirs, const float *om, const float *src, const float *power, int n_src, int level,
                        DevQueue q, hipStream_t s)
 {
     long long nf = 20ll << (2 * level);
     long long total = nf * n_src;
     if (total <= 0) return hipSuccess;
-    k_emit<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(base20, src, power, n_src, level, nf, q);
+    k_emit<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(dirs, om, src, power, n_src, nf, q);
     return hipGetLastError();
 }
 

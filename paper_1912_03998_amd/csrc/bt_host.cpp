@@ -182,6 +182,11 @@ extern "C" bt_status bt_destroy(bt_ctx *ctx)
         delete r;
     }
     batch_work_free(ctx);
+    for (int l = 0; l <= BT_MAX_LEVEL; ++l) {
+        const long long nf = 20ll << (2 * l);
+        dev_free(ctx, ctx->face_dirs[l], (size_t)nf * 12 * sizeof(double));
+        dev_free(ctx, ctx->face_om[l], (size_t)nf * sizeof(float));
+    }
     dev_free(ctx, ctx->base20, 20 * 9 * sizeof(double));
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -778,7 +783,15 @@ extern "C" bt_status bt_emit_beams(bt_ctx *ctx, const float *src_xyz, const floa
         HIP_TRY(ctx, hipMemcpyAsync(b->pow_dev, src_power, (size_t)n_src * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
     }
     HIP_TRY(ctx, launch_init_counters(b->ctr, n0, ctx->stream));
-    HIP_TRY(ctx, launch_emit(ctx->base20, b->src_dev, b->pow_dev, n_src, level, b->q, ctx->stream));
+    if (!ctx->face_dirs[level]) {
+        // the level's face directions, computed once per context
+        const long long nf = 20ll << (2 * level);
+        if ((s = dev_alloc(ctx, (void **)&ctx->face_dirs[level], (size_t)nf * 12 * sizeof(double))) != BT_OK) return s;
+        if ((s = dev_alloc(ctx, (void **)&ctx->face_om[level], (size_t)nf * sizeof(float))) != BT_OK) return s;
+        HIP_TRY(ctx, launch_faces(ctx->base20, level, ctx->face_dirs[level], ctx->face_om[level], ctx->stream));
+    }
+    HIP_TRY(ctx, launch_emit(ctx->face_dirs[level], ctx->face_om[level], b->src_dev, b->pow_dev, n_src, level, b->q,
+                             ctx->stream));
     // host inputs are borrowed for the call only
     if (n_src > 0) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     b->gen = 0;

@@ -340,6 +340,19 @@ __global__ void __launch_bounds__(256, 4) k_trace(DevMesh M, DevQueue in, DevSeg
                                                WaveScratch ws)
 {
     __shared__ int stk[kStack * 256];
+    // the tile table (roots and root boxes) staged in LDS for up to 256 tiles, so that a
+    // tile change waits on no global load
+    __shared__ int s_root[256];
+    __shared__ float s_box[6 * 256];
+    DevMesh Ml = M;
+    const int n_tiles = M.tiles_x * M.tiles_y;
+    if (n_tiles <= 256) {
+        for (int k = threadIdx.x; k < n_tiles; k += blockDim.x) s_root[k] = M.tile_root[k];
+        for (int k = threadIdx.x; k < 6 * n_tiles; k += blockDim.x) s_box[k] = M.tile_box[k];
+        __syncthreads();
+        Ml.tile_root = s_root;
+        Ml.tile_box = s_box;
+    }
     const unsigned long long n = ctr->count[a.gen];
     const long long s0 = (long long)gen_start(ctr, a.gen);
     const int lane = lane_id();
@@ -378,7 +391,7 @@ __global__ void __launch_bounds__(256, 4) k_trace(DevMesh M, DevQueue in, DevSeg
             r.c1_id = -1;
             r.node_visits = 0;
             r.tri_tests = 0;
-            trace_ray(M, r, src, a.t_min, a.delta, stk);
+            trace_ray(Ml, r, src, a.t_min, a.delta, stk);
             const int meta = in.ints[I_META * icap + i];
             const int id = in.ints[I_ID * icap + i];
             const float K = in.flt[F_K * icap + i];
