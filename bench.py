@@ -296,6 +296,7 @@ def main():
                                f"{scene.n_mic} microphones, "
                                f"{args.tiles or scene.tiles_x}x{args.tiles or scene.tiles_y} tiles",
                    "segments_per_step": segs, "mic_updates_per_step": upd,
+                   "mic_tests_per_step": st["mic_tests"],
                    "generation_counts": st["count"].tolist(),
                    "flagged_per_generation": st["flagged"].tolist()},
         "roofline": roofline,
