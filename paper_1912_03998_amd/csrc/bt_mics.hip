@@ -300,29 +300,41 @@ __global__ void __launch_bounds__(256, 4) k_mics(DevMesh M, DevQueue q, DevSegs 
             const DevMics mc = seg_mics<kSlots>(mc0, a, q, i);
             const V3 A = ld3(q.dbl + D_A * cap, cap, i);
             const double zr = mc.z - A.z;
-            double xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
             bool proper = zr != 0.0;
             // the frustum lies in the cone of its edge directions from the apex; when the
             // apex is off the microphone plane (by far more than the plane tests' rounding)
             // and no edge direction turns towards the plane, no microphone can be inside
             bool away = zr > 1e-6 || zr < -1e-6;
+            // The crossing points are only used to bound the candidate lattice, so they are
+            // found in FP32: each coordinate is within 16 x 2^-24 of `mag` (the largest
+            // magnitude involved) of its exact value, and the box is widened by 1e-5 mag.
+            // The exact FP64 membership test decides every candidate.
+            const float zrf = (float)zr, axf = (float)A.x, ayf = (float)A.y;
+            float xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
+            float mag = fmaxf(fabsf(axf), fabsf(ayf));
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const V3 d = ld3(q.dbl + (D_D0 + 3 * k) * cap, cap, i);
-                const double s = zr / d.z;
-                proper = proper && s > 0.0 && isfinite(s);
+                proper = proper && (zr > 0.0 ? d.z > 0.0 : d.z < 0.0);
                 away = away && (zr > 0.0 ? d.z <= 0.0 : d.z >= 0.0);
-                const double px = A.x + s * d.x, py = A.y + s * d.y;
-                xmn = fmin(xmn, px); xmx = fmax(xmx, px);
-                ymn = fmin(ymn, py); ymx = fmax(ymx, py);
+                const float s = zrf / (float)d.z;
+                proper = proper && isfinite(s);  // FP32 overflow: the general path decides
+                const float sx = s * (float)d.x, sy = s * (float)d.y;
+                const float px = axf + sx, py = ayf + sy;
+                xmn = fminf(xmn, px); xmx = fmaxf(xmx, px);
+                ymn = fminf(ymn, py); ymx = fmaxf(ymx, py);
+                mag = fmaxf(mag, fmaxf(fabsf(sx), fabsf(sy)));
             }
             general = !away;
             if (proper) {
-                const double relax = 1e-6;
-                const double fi0 = fmax(ceil((xmn - relax - mc.x0) / mc.dx), 0.0);
-                const double fi1 = fmin(floor((xmx + relax - mc.x0) / mc.dx), (double)(mc.nx - 1));
-                const double fj0 = fmax(ceil((ymn - relax - mc.y0) / mc.dy), 0.0);
-                const double fj1 = fmin(floor((ymx + relax - mc.y0) / mc.dy), (double)(mc.ny - 1));
+                // lattice range by a reciprocal multiply, widened by 1e-9 cells for its
+                // rounding
+                const double relax = 1e-6 + 1e-5 * (double)mag;
+                const double idx = 1.0 / mc.dx, idy = 1.0 / mc.dy;
+                const double fi0 = fmax(ceil(((double)xmn - relax - mc.x0) * idx - 1e-9), 0.0);
+                const double fi1 = fmin(floor(((double)xmx + relax - mc.x0) * idx + 1e-9), (double)(mc.nx - 1));
+                const double fj0 = fmax(ceil(((double)ymn - relax - mc.y0) * idy - 1e-9), 0.0);
+                const double fj1 = fmin(floor(((double)ymx + relax - mc.y0) * idy + 1e-9), (double)(mc.ny - 1));
                 if (!(fi0 <= fi1 && fj0 <= fj1)) {
                     general = false;  // no lattice point under the footprint
                 } else if ((fi1 - fi0 + 1.0) * (fj1 - fj0 + 1.0) <= (double)kSpan) {
