@@ -176,6 +176,12 @@ typedef struct {
     const float *src; const float *power; int32_t n_src;
     double mic_x0, mic_y0, mic_z, mic_dx, mic_dy;
     int32_t mic_nx, mic_ny;
+    /* optional [n_src][n_faces] relative intensity of each source per icosphere face;
+       NULL = omni.  Reading of "split between beams according to its power in each
+       direction" (Section 2) for a directional source: beam b of source s gets
+       K_b = W_s w_b / sum_f(w_f Omega_f), so its power K_b Omega_b is W_s's share in
+       proportion to w_b Omega_b and the beams' powers add up to W_s. */
+    const float *src_weight;
 } orc_scene;
 
 typedef struct {
@@ -814,6 +820,7 @@ typedef struct {
     const obvh *bvh;
     const double *dirs;
     int64_t nf;
+    const double *wnorm;  /* [n_src] sum over faces of weight x solid angle (directional sources) */
     int64_t b0, b1;
     orc_result *res;
     double *e_strict, *e_flag;
@@ -842,8 +849,13 @@ static void *run_worker(void *arg)
         v_add(bm.d[0], bm.d[1], sum01);
         v_add(sum01, bm.d[2], sum);
         v_normalize(sum, bm.c);
-        bm.K = (double)s->power[src] / (4.0 * M_PI);   /* reading: omni source, power W * Omega / (4 pi) */
         bm.omega = orc_solid_angle(bm.d[0], bm.d[1], bm.d[2]);
+        if (s->src_weight) {
+            const double wn = w->wnorm[src];
+            bm.K = wn > 0.0 ? (double)s->power[src] * (double)s->src_weight[src * w->nf + face] / wn : 0.0;
+        } else {
+            bm.K = (double)s->power[src] / (4.0 * M_PI);   /* reading: omni source, power W * Omega / (4 pi) */
+        }
         bm.start = -1; bm.depth = 0; bm.near_sign = 0; bm.flag = 0;
         for (int g = 0; g <= D; ++g) {
             orc_hitres hr;
@@ -884,6 +896,16 @@ int orc_trace(const orc_scene *s, const orc_params *p, orc_result *res)
     double *dirs = (double *)malloc(sizeof(double) * 9 * (size_t)nf);
     if (!dirs) return -2;
     if (orc_icosphere(p->level, dirs) != 0) { free(dirs); return -3; }
+    double *wnorm = NULL;
+    if (s->src_weight) {
+        wnorm = (double *)calloc((size_t)(s->n_src > 0 ? s->n_src : 1), sizeof(double));
+        if (!wnorm) { free(dirs); return -2; }
+        for (int64_t f = 0; f < nf; ++f) {
+            const double *fd = dirs + 9 * f;
+            const double om = orc_solid_angle(fd, fd + 3, fd + 6);
+            for (int32_t k = 0; k < s->n_src; ++k) wnorm[k] += (double)s->src_weight[k * nf + f] * om;
+        }
+    }
     obvh *bvh = p->use_bvh ? bvh_build(s, p->delta + 1e-6) : NULL;
     int T = p->n_threads > 0 ? p->n_threads : 1;
     if (T > b1 - b0 && b1 > b0) T = (int)(b1 - b0);
@@ -891,7 +913,7 @@ int orc_trace(const orc_scene *s, const orc_params *p, orc_result *res)
     oworker *w = (oworker *)calloc((size_t)T, sizeof(oworker));
     pthread_t *th = (pthread_t *)calloc((size_t)T, sizeof(pthread_t));
     for (int k = 0; k < T; ++k) {
-        w[k].s = s; w[k].p = p; w[k].bvh = bvh; w[k].dirs = dirs; w[k].nf = nf; w[k].res = res;
+        w[k].s = s; w[k].p = p; w[k].bvh = bvh; w[k].dirs = dirs; w[k].nf = nf; w[k].res = res; w[k].wnorm = wnorm;
         w[k].b0 = b0 + (b1 - b0) * k / T;
         w[k].b1 = b0 + (b1 - b0) * (k + 1) / T;
         w[k].e_strict = (double *)calloc((size_t)(nmic > 0 ? nmic : 1), sizeof(double));
@@ -922,6 +944,7 @@ int orc_trace(const orc_scene *s, const orc_params *p, orc_result *res)
     free(w);
     free(th);
     bvh_free(bvh);
+    free(wnorm);
     free(dirs);
     return 0;
 }

@@ -50,7 +50,8 @@ class _Scene(C.Structure):
     _fields_ = [("xyz", C.c_void_p), ("n_vert", C.c_int64), ("tri", C.c_void_p), ("n_tri", C.c_int64),
                 ("alpha", C.c_void_p), ("src", C.c_void_p), ("power", C.c_void_p), ("n_src", C.c_int32),
                 ("mic_x0", C.c_double), ("mic_y0", C.c_double), ("mic_z", C.c_double),
-                ("mic_dx", C.c_double), ("mic_dy", C.c_double), ("mic_nx", C.c_int32), ("mic_ny", C.c_int32)]
+                ("mic_dx", C.c_double), ("mic_dy", C.c_double), ("mic_nx", C.c_int32), ("mic_ny", C.c_int32),
+                ("src_weight", C.c_void_p)]
 
 
 class _Params(C.Structure):
@@ -95,7 +96,7 @@ def _ptr(a):
     return None if a is None else a.ctypes.data
 
 
-def _scene_struct(scene, keep):
+def _scene_struct(scene, keep, weights=None):
     v = np.ascontiguousarray(scene.vertices, np.float32)
     t = np.ascontiguousarray(scene.triangles, np.int32)
     a = np.ascontiguousarray(scene.absorption, np.float32)
@@ -103,9 +104,13 @@ def _scene_struct(scene, keep):
     w = np.ascontiguousarray(scene.power, np.float32)
     keep.extend([v, t, a, s, w])
     f32 = lambda x: float(np.float32(x))  # noqa: E731  the grid values are float32 inputs
+    wt = None
+    if weights is not None:
+        wt = np.ascontiguousarray(weights, np.float32)
+        keep.append(wt)
     return _Scene(_ptr(v), v.shape[0], _ptr(t), t.shape[0], _ptr(a), _ptr(s), _ptr(w), s.shape[0],
                   f32(scene.mic_x0), f32(scene.mic_y0), f32(scene.mic_z), f32(scene.mic_dx), f32(scene.mic_dy),
-                  scene.mic_nx, scene.mic_ny)
+                  scene.mic_nx, scene.mic_ny, _ptr(wt))
 
 
 def icosphere(level: int) -> np.ndarray:
@@ -143,14 +148,19 @@ class TraceResult:
 
 
 def trace(scene, *, level=None, depth=None, t_min=T_MIN, delta=DELTA, m_air=0.0, e_min=0.0, use_bvh=True,
-          mic_mode=1, n_threads=None, beam_begin=0, beam_end=-1, keep_paths=True) -> TraceResult:
-    """Trace the whole scene (or the initial beams [beam_begin, beam_end)) in FP64."""
+          mic_mode=1, n_threads=None, beam_begin=0, beam_end=-1, keep_paths=True, weights=None) -> TraceResult:
+    """Trace the whole scene (or the initial beams [beam_begin, beam_end)) in FP64.
+    weights: optional float32 [n_src][20 * 4**level] relative intensity of each source per
+    icosphere face (a directional source); None = omni."""
     level = scene.level if level is None else level
     depth = scene.depth if depth is None else depth
     n_threads = n_threads or default_threads()
     nb = scene.n_src * 20 * 4 ** level
+    if weights is not None:
+        weights = np.asarray(weights, np.float32)
+        assert weights.shape == (scene.n_src, 20 * 4 ** level), weights.shape
     keep = []
-    sc = _scene_struct(scene, keep)
+    sc = _scene_struct(scene, keep, weights)
     pr = _Params(level, depth, t_min, delta, m_air, e_min, int(use_bvh), int(mic_mode), int(n_threads),
                  beam_begin, beam_end)
     hit = flag = th = None

@@ -217,6 +217,42 @@ def test_direct_path_free_field(level):
     assert r.counters["mic_updates"] == sc.n_mic
 
 
+def test_directional_source_uniform_weights_is_omni():
+    """Equal weights give the omni split (K = W / (4 pi)) up to the rounding of the solid
+    angles' sum; any weights conserve the emitted power."""
+    sc = empty_scene(level=3, src=(0.3, -0.2, 1.0))
+    ref = O.trace(sc)
+    r = O.trace(sc, weights=np.full((1, 1280), 3.0, np.float32))
+    assert np.abs(r.energy / ref.energy - 1).max() < 1e-12
+    w = np.random.default_rng(2).uniform(0.0, 5.0, (1, 1280)).astype(np.float32)
+    r = O.trace(sc, weights=w)
+    assert abs(r.power[0] - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("level", [2, 4])
+def test_directional_source_hemisphere_closed_form(level):
+    """Weight 1 on the faces whose guiding direction points up, 0 on the others: a
+    microphone well above the source receives W / (Omega_up d^2), Omega_up being those
+    faces' total solid angle (half of the sphere less the faces whose guiding direction is
+    horizontal), and one well below receives nothing."""
+    dirs = O.icosphere(level)
+    c = dirs.sum(1)
+    up = c[:, 2] > 0.0
+    flat = c[:, 2] == 0.0
+    om = np.array([O.solid_angle(*dirs[f]) for f in range(len(dirs))])
+    om_up = om[up].sum()
+    assert abs(2.0 * om_up + om[flat].sum() - 4.0 * np.pi) < 1e-11   # mirror symmetry in z
+    w = up.astype(np.float32)[None, :]
+    src = (0.3, -0.2, 1.0)
+    sc = empty_scene(level=level, src=src, n_mic=9, spacing=0.5, mic_z=4.0)   # elevations above 45 degrees
+    r = O.trace(sc, weights=w, use_bvh=False, mic_mode=0)
+    d2 = ((sc.mic_positions() - np.array(src, np.float32).astype(np.float64)) ** 2).sum(1)
+    assert np.abs(r.energy * om_up * d2 - 1.0).max() < 1e-12
+    below = O.trace(empty_scene(level=level, src=src, n_mic=9, spacing=0.5, mic_z=-10.0), weights=w, use_bvh=False,
+                    mic_mode=0)
+    assert (below.energy == 0.0).all()
+
+
 def test_direct_path_two_sources_and_air_damping():
     sc = empty_scene(level=3, src=(0.3, -0.2, 1.0))
     sc = sc.with_(sources=np.array([[0.3, -0.2, 1.0], [-2.1, 3.3, 0.4]], np.float32),
