@@ -131,6 +131,14 @@ bt_status bt_mics_free(bt_mics *mics);
  * if needed).  Resets the set's statistics. */
 bt_status bt_emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_power, int32_t n_src,
                         int32_t level, bt_beams **inout);
+/* Generation-0 beams of directional sources (paper Section 2: a source's power is split
+ * between beams according to its power in each direction).  src_weight: host
+ * float[n_src][20 4^level], the relative intensity of each source towards each face (in
+ * emission order), finite and >= 0.  Beam b of source s gets K_b = W_s w_b /
+ * sum_f(w_f Omega_f), so the beams' powers K_b Omega_b add up to W_s; equal weights give
+ * the omni split of bt_emit_beams.  Otherwise as bt_emit_beams. */
+bt_status bt_emit_beams_directional(bt_ctx *ctx, const float *src_xyz, const float *src_power,
+                                    const float *src_weight, int32_t n_src, int32_t level, bt_beams **inout);
 bt_status bt_beams_free(bt_beams *beams);
 bt_status bt_beams_stats(bt_ctx *ctx, const bt_beams *beams, bt_stats *out);
 

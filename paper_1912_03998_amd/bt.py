@@ -22,7 +22,7 @@ STATUS = {0: "BT_OK", 1: "BT_PENDING", -1: "BT_EINVAL", -2: "BT_ENOMEM", -3: "BT
 
 EXPORTED = ["bt_params_default", "bt_status_str", "bt_last_error", "bt_create", "bt_destroy", "bt_memory_used",
             "bt_build_mesh", "bt_mesh_free", "bt_mesh_info", "bt_mics_grid", "bt_mics_reset", "bt_mics_free",
-            "bt_emit_beams", "bt_beams_free", "bt_beams_stats", "bt_trace", "bt_accumulate_mics", "bt_levels",
+            "bt_emit_beams", "bt_emit_beams_directional", "bt_beams_free", "bt_beams_stats", "bt_trace", "bt_accumulate_mics", "bt_levels",
             "bt_run", "bt_submit", "bt_poll", "bt_cancel", "bt_batch_run", "bt_batch_release", "bt_batch_autotune",
             "bt_server_create", "bt_server_submit", "bt_server_poll", "bt_server_destroy"]
 
@@ -83,6 +83,7 @@ def lib():
         "bt_mics_reset": (C.c_int, [P, P]),
         "bt_mics_free": (C.c_int, [P]),
         "bt_emit_beams": (C.c_int, [P, P, P, I32, I32, P]),
+        "bt_emit_beams_directional": (C.c_int, [P, P, P, P, I32, I32, P]),
         "bt_beams_free": (C.c_int, [P]),
         "bt_beams_stats": (C.c_int, [P, P, P]),
         "bt_trace": (C.c_int, [P, P, P, P, P]),
@@ -196,6 +197,19 @@ def bt_emit_beams(ctx, src_xyz, src_power, level, beams=None):
     h = C.c_void_p(beams.value if beams is not None else None)
     _check(ctx, lib().bt_emit_beams(ctx, _ptr(src_xyz), _ptr(src_power), src_xyz.shape[0], level, C.byref(h)),
            "bt_emit_beams")
+    return h
+
+
+def bt_emit_beams_directional(ctx, src_xyz, src_power, src_weight, level, beams=None):
+    """src_weight: float32 [n_src][20 * 4**level] relative intensities per face."""
+    src_xyz = np.ascontiguousarray(src_xyz, np.float32).reshape(-1, 3)
+    src_power = np.ascontiguousarray(src_power, np.float32)
+    src_weight = np.ascontiguousarray(src_weight, np.float32)
+    if src_weight.shape != (src_xyz.shape[0], 20 * 4 ** level):
+        raise ValueError(f"src_weight shape {src_weight.shape}")
+    h = C.c_void_p(beams.value if beams is not None else None)
+    _check(ctx, lib().bt_emit_beams_directional(ctx, _ptr(src_xyz), _ptr(src_power), _ptr(src_weight),
+                                                src_xyz.shape[0], level, C.byref(h)), "bt_emit_beams_directional")
     return h
 
 

@@ -67,8 +67,8 @@ __device__ void face_of(const double *__restrict__ base20, int level, long long 
 }
 
 // A generation-0 beam record at queue index j: apex and origin at the source S, the face's
-// directions, K = W / (4 pi).
-__device__ __forceinline__ void store_beam(DevQueue q, long long j, V3 S, V3 a, V3 bb, V3 c, V3 cc, float W, float om,
+// directions, intensity constant K.
+__device__ __forceinline__ void store_beam(DevQueue q, long long j, V3 S, V3 a, V3 bb, V3 c, V3 cc, float K, float om,
                                            int meta, int id)
 {
     const long long cap = q.cap;
@@ -78,7 +78,7 @@ __device__ __forceinline__ void store_beam(DevQueue q, long long j, V3 S, V3 a, 
     st3(q.dbl + D_D2 * cap, cap, j, c);
     st3(q.dbl + D_O * cap, cap, j, S);
     st3(q.dbl + D_C * cap, cap, j, cc);
-    q.flt[F_K * cap + j] = (float)((double)W / (4.0 * M_PI));
+    q.flt[F_K * cap + j] = K;
     q.flt[F_OMEGA * cap + j] = om;
     q.ints[I_ID * cap + j] = id;
     q.ints[I_START * cap + j] = -1;
@@ -93,7 +93,7 @@ __device__ void emit_one(const double *__restrict__ base20, int level, long long
     V3 a, bb, c, cc;
     float om;
     face_of(base20, level, f, a, bb, c, cc, om);
-    store_beam(q, j, S, a, bb, c, cc, W, om, meta, id);
+    store_beam(q, j, S, a, bb, c, cc, (float)((double)W / (4.0 * M_PI)), om, meta, id);
 }
 
 // The face table of one level, computed once: dirs[k * nf + f] for k = 0..11 (d0, d1, d2,
@@ -118,26 +118,55 @@ hipError_t launch_faces(const double *base20, int level, double *dirs, float *om
 }
 
 // Generation 0 of one beam set: beam b = s nf + f is face f of source s, copied from the
-// level's face table.
+// level's face table.  An omni source has K = W / (4 pi); a directional one (weights
+// w[s nf + f]) K = W w / norm[s], norm[s] = sum over faces of w Omega, so that its beams'
+// powers K Omega add up to W.
 __global__ void k_emit(const double *__restrict__ dirs, const float *__restrict__ fom, const float *__restrict__ src,
-                       const float *__restrict__ power, int n_src, long long nf, DevQueue q)
+                       const float *__restrict__ power, const float *__restrict__ wt, const double *__restrict__ norm,
+                       int n_src, long long nf, DevQueue q)
 {
     long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     long long total = nf * n_src;
     if (b >= total) return;
     long long s = b / nf, f = b - s * nf;
     const V3 S = {src[3 * s], src[3 * s + 1], src[3 * s + 2]};
+    float K;
+    if (wt) K = norm[s] > 0.0 ? (float)((double)power[s] * (double)wt[b] / norm[s]) : 0.0f;
+    else K = (float)((double)power[s] / (4.0 * M_PI));
     store_beam(q, b, S, ld3(dirs, nf, f), ld3(dirs + 3 * nf, nf, f), ld3(dirs + 6 * nf, nf, f),
-               ld3(dirs + 9 * nf, nf, f), power[s], fom[f], 0, (int)b);
+               ld3(dirs + 9 * nf, nf, f), K, fom[f], 0, (int)b);
 }
 
-hipError_t launch_emit(const double *dirs, const float *om, const float *src, const float *power, int n_src, int level,
-                       DevQueue q, hipStream_t s)
+// norm[s] = sum over faces f of wt[s nf + f] Omega_f (FP64, one block per source, a fixed
+// reduction order).
+__global__ void __launch_bounds__(256) k_source_norms(const float *__restrict__ fom, const float *__restrict__ wt,
+                                                      long long nf, double *norm)
+{
+    __shared__ double part[256];
+    const long long s = blockIdx.x;
+    double acc = 0.0;
+    for (long long f = threadIdx.x; f < nf; f += blockDim.x) acc += (double)wt[s * nf + f] * (double)fom[f];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) norm[s] = part[0];
+}
+
+hipError_t launch_emit(const double *dirs, const float *om, const float *src, const float *power, const float *wt,
+                       double *norm, int n_src, int level, DevQueue q, hipStream_t s)
 {
     long long nf = 20ll << (2 * level);
     long long total = nf * n_src;
     if (total <= 0) return hipSuccess;
-    k_emit<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(dirs, om, src, power, n_src, nf, q);
+    if (wt) {
+        k_source_norms<<<(unsigned)n_src, 256, 0, s>>>(om, wt, nf, norm);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    k_emit<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(dirs, om, src, power, wt, norm, n_src, nf, q);
     return hipGetLastError();
 }
 

@@ -728,8 +728,9 @@ bt_status reserve_work(bt_ctx *ctx, bt_beams *b, long long n0)
     return BT_OK;
 }
 
-extern "C" bt_status bt_emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_power, int32_t n_src,
-                                   int32_t level, bt_beams **inout)
+// Generation 0 of a beam set; src_weight NULL (omni sources) or host float[n_src][nf].
+static bt_status emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_power, const float *src_weight,
+                            int32_t n_src, int32_t level, bt_beams **inout)
 {
     if (!ctx) return BT_EINVAL;
     if (!inout) return fail(ctx, BT_EINVAL, "inout is NULL");
@@ -738,6 +739,10 @@ extern "C" bt_status bt_emit_beams(bt_ctx *ctx, const float *src_xyz, const floa
     long long nf = 20ll << (2 * level);
     long long n0 = nf * n_src;
     if (n0 > (1ll << 31) - 1) return fail(ctx, BT_EINVAL, "too many beams (%lld)", n0);
+    if (src_weight)
+        for (long long k = 0; k < n0; ++k)
+            if (!(src_weight[k] >= 0.f) || !std::isfinite(src_weight[k]))
+                return fail(ctx, BT_EINVAL, "weight %lld (source %lld, face %lld) invalid", k, k / nf, k % nf);
     double r_src = 0.0;
     for (int i = 0; i < n_src; ++i) {
         for (int c = 0; c < 3; ++c) {
@@ -768,11 +773,21 @@ extern "C" bt_status bt_emit_beams(bt_ctx *ctx, const float *src_xyz, const floa
     if (s == BT_OK && n_src > b->src_cap) {
         dev_free(ctx, b->src_dev, (size_t)b->src_cap * 3 * sizeof(float));
         dev_free(ctx, b->pow_dev, (size_t)b->src_cap * sizeof(float));
+        dev_free(ctx, b->norm_dev, (size_t)b->src_cap * sizeof(double));
         b->src_dev = b->pow_dev = nullptr;
+        b->norm_dev = nullptr;
         b->src_cap = 0;
         s = dev_alloc(ctx, (void **)&b->src_dev, (size_t)n_src * 3 * sizeof(float));
         if (s == BT_OK) s = dev_alloc(ctx, (void **)&b->pow_dev, (size_t)n_src * sizeof(float));
+        if (s == BT_OK) s = dev_alloc(ctx, (void **)&b->norm_dev, (size_t)n_src * sizeof(double));
         if (s == BT_OK) b->src_cap = n_src;
+    }
+    if (s == BT_OK && src_weight && n0 > b->wt_cap) {
+        dev_free(ctx, b->wt_dev, (size_t)b->wt_cap * sizeof(float));
+        b->wt_dev = nullptr;
+        b->wt_cap = 0;
+        s = dev_alloc(ctx, (void **)&b->wt_dev, (size_t)n0 * sizeof(float));
+        if (s == BT_OK) b->wt_cap = n0;
     }
     if (s != BT_OK) {
         if (fresh) bt_beams_free(b);
@@ -781,6 +796,9 @@ extern "C" bt_status bt_emit_beams(bt_ctx *ctx, const float *src_xyz, const floa
     if (n_src > 0) {
         HIP_TRY(ctx, hipMemcpyAsync(b->src_dev, src_xyz, (size_t)n_src * 3 * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
         HIP_TRY(ctx, hipMemcpyAsync(b->pow_dev, src_power, (size_t)n_src * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+        if (src_weight)
+            HIP_TRY(ctx, hipMemcpyAsync(b->wt_dev, src_weight, (size_t)n0 * sizeof(float), hipMemcpyHostToDevice,
+                                        ctx->stream));
     }
     HIP_TRY(ctx, launch_init_counters(b->ctr, n0, ctx->stream));
     if (!ctx->face_dirs[level]) {
@@ -790,8 +808,8 @@ extern "C" bt_status bt_emit_beams(bt_ctx *ctx, const float *src_xyz, const floa
         if ((s = dev_alloc(ctx, (void **)&ctx->face_om[level], (size_t)nf * sizeof(float))) != BT_OK) return s;
         HIP_TRY(ctx, launch_faces(ctx->base20, level, ctx->face_dirs[level], ctx->face_om[level], ctx->stream));
     }
-    HIP_TRY(ctx, launch_emit(ctx->face_dirs[level], ctx->face_om[level], b->src_dev, b->pow_dev, n_src, level, b->q,
-                             ctx->stream));
+    HIP_TRY(ctx, launch_emit(ctx->face_dirs[level], ctx->face_om[level], b->src_dev, b->pow_dev,
+                             src_weight ? b->wt_dev : nullptr, b->norm_dev, n_src, level, b->q, ctx->stream));
     // host inputs are borrowed for the call only
     if (n_src > 0) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     b->gen = 0;
@@ -803,6 +821,20 @@ extern "C" bt_status bt_emit_beams(bt_ctx *ctx, const float *src_xyz, const floa
     return BT_OK;
 }
 
+extern "C" bt_status bt_emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_power, int32_t n_src,
+                                   int32_t level, bt_beams **inout)
+{
+    return emit_beams(ctx, src_xyz, src_power, nullptr, n_src, level, inout);
+}
+
+extern "C" bt_status bt_emit_beams_directional(bt_ctx *ctx, const float *src_xyz, const float *src_power,
+                                               const float *src_weight, int32_t n_src, int32_t level,
+                                               bt_beams **inout)
+{
+    if (ctx && !src_weight) return fail(ctx, BT_EINVAL, "src_weight is NULL");
+    return emit_beams(ctx, src_xyz, src_power, src_weight, n_src, level, inout);
+}
+
 extern "C" bt_status bt_beams_free(bt_beams *b)
 {
     if (!b) return BT_EINVAL;
@@ -811,6 +843,8 @@ extern "C" bt_status bt_beams_free(bt_beams *b)
     dev_free(b->ctx, b->ws_buf, b->ws_bytes);
     dev_free(b->ctx, b->src_dev, (size_t)b->src_cap * 3 * sizeof(float));
     dev_free(b->ctx, b->pow_dev, (size_t)b->src_cap * sizeof(float));
+    dev_free(b->ctx, b->norm_dev, (size_t)b->src_cap * sizeof(double));
+    dev_free(b->ctx, b->wt_dev, (size_t)b->wt_cap * sizeof(float));
     delete b;
     return BT_OK;
 }

@@ -66,7 +66,10 @@ struct bt_beams {
     int acc_gen = 0;          // first generation not yet accumulated at the microphones
     int depth_hint = 0;       // max_depth of the previous run, to size the queue at emission
     float *src_dev = nullptr, *pow_dev = nullptr;
+    double *norm_dev = nullptr;   // per source: sum of weight x solid angle (directional)
     int src_cap = 0;
+    float *wt_dev = nullptr;      // directional sources' face weights
+    long long wt_cap = 0;
     size_t bytes = 0;
     int gen = 0;              // generations traced
     int max_depth = -1;       // fixed by the first trace

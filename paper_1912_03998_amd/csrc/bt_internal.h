@@ -172,8 +172,10 @@ hipError_t launch_init_counters(DevCounters *ctr, long long n0, hipStream_t s);
 // The face table of an icosphere level (dirs: 12 nf doubles, om: nf floats), and the
 // emission of one beam set's generation 0 from it.
 hipError_t launch_faces(const double *base20, int level, double *dirs, float *om, hipStream_t s);
-hipError_t launch_emit(const double *dirs, const float *om, const float *src, const float *power, int n_src, int level,
-                       DevQueue q, hipStream_t s);
+// wt: NULL (omni) or [n_src][nf] face weights of directional sources, with norm a device
+// double[n_src] filled here.
+hipError_t launch_emit(const double *dirs, const float *om, const float *src, const float *power, const float *wt,
+                       double *norm, int n_src, int level, DevQueue q, hipStream_t s);
 // Appends the table's beams to generation `gen` (after its current beams) and adds their
 // number to count[gen].
 hipError_t launch_emit_table(const double *base20, const EmitTable &t, long long max_total, DevQueue q,

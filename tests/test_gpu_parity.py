@@ -383,3 +383,31 @@ def test_mic_work_buffer_overflow(torch_cuda, monkeypatch, env):
     with session(sc) as s:
         g = gpu_run(s, sc)
     full_verdict(sc, g, o)
+
+
+def test_directional_sources_parity(torch_cuda):
+    """Directional sources (a smooth per-face intensity pattern): energies against the
+    oracle with the same weights, and generation-0 power equal to the sources' power."""
+    from paper_1912_03998_amd import bt
+    sc = block_scene(0).with_(level=4, depth=4)
+    say("directional sources, block scene")
+    c = O.icosphere(sc.level).sum(1)
+    c /= np.linalg.norm(c, axis=1, keepdims=True)
+    axis = np.array([1.0, 0.5, 0.2]) / np.linalg.norm([1.0, 0.5, 0.2])
+    w = np.tile((1.0 + 0.8 * (c @ axis)) ** 2, (sc.n_src, 1)).astype(np.float32)
+    o = O.trace(sc, weights=w, keep_paths=False)
+    with session(sc) as s:
+        p = s.params(sc.depth)
+        mics = s._mics(grid(sc))
+        s.beams = bt.bt_emit_beams_directional(s.ctx, sc.sources, sc.power, w, sc.level, s.beams)
+        for _ in range(sc.depth + 1):
+            bt.bt_trace(s.ctx, s.mesh, s.beams, p)
+        bt.bt_accumulate_mics(s.ctx, s.mesh, s.beams, p, mics)
+        es, ef = np.zeros(sc.n_mic), np.zeros(sc.n_mic)
+        bt.bt_levels(s.ctx, mics, es, ef, None)
+        st = bt.bt_beams_stats(s.ctx, s.beams)
+        with pytest.raises(bt.BTError):
+            bt.bt_emit_beams_directional(s.ctx, sc.sources, sc.power, -w, sc.level, s.beams)
+    check_mics(o.e_strict, o.e_flag, es, ef)
+    assert abs(st["power"][0] - float(sc.power.sum())) < 1e-6 * float(sc.power.sum())
+    assert abs(st["power"][1] - o.power[1]) < 1e-5 * o.power[1]
