@@ -123,16 +123,16 @@ bt_status bt_mics_grid(bt_ctx *ctx, float x0, float y0, float z, float dx, float
 bt_status bt_mics_reset(bt_ctx *ctx, bt_mics *mics);   /* zero the energies (kernel, no memset) */
 bt_status bt_mics_free(bt_mics *mics);
 
-/* Generation-0 beams (paper Section 2: the source energy is split between beams
- * according to its power in each direction): for each source and each face of the
+/* Generation-0 beams (paper Section 2: a source's energy is shared between beams by
+ * direction): for each source and each face of the
  * level-`level` icosphere, one frustum beam with apex at the source and intensity
  * constant K = W / (4 pi).  src_xyz host float[n_src][3]; src_power host float[n_src].
  * *inout: NULL to create a beam set, or an existing set to reuse (its capacity grows
  * if needed).  Resets the set's statistics. */
 bt_status bt_emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_power, int32_t n_src,
                         int32_t level, bt_beams **inout);
-/* Generation-0 beams of directional sources (paper Section 2: a source's power is split
- * between beams according to its power in each direction).  src_weight: host
+/* Generation-0 beams of directional sources (paper Section 2: a source's power is shared
+ * between beams by direction).  src_weight: host
  * float[n_src][20 4^level], the relative intensity of each source towards each face (in
  * emission order), finite and >= 0.  Beam b of source s gets K_b = W_s w_b /
  * sum_f(w_f Omega_f), so the beams' powers K_b Omega_b add up to W_s; equal weights give

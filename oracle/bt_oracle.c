@@ -58,8 +58,8 @@ static double v_det(const double a[3], const double b[3], const double c[3])
 }
 
 /* ------------------------------------------------------------------------- */
-/* Icosphere: the beam directions (paper Section 2: the source energy is split   */
-/* between beams according to its power in each direction).                  */
+/* Icosphere: the beam directions (paper Section 2: a source's energy is shared */
+/* between beams by direction).                                               */
 /* Reading: one triangular beam per face of a level-L geodesic icosphere.      */
 /*   base vertices: the cyclic permutations (0,a,b), (a,b,0), (b,0,a) of        */
 /*     (0, +-1, +-phi), in that permutation order, then a = -1, +1, then        */
@@ -177,8 +177,8 @@ typedef struct {
     double mic_x0, mic_y0, mic_z, mic_dx, mic_dy;
     int32_t mic_nx, mic_ny;
     /* optional [n_src][n_faces] relative intensity of each source per icosphere face;
-       NULL = omni.  Reading of "split between beams according to its power in each
-       direction" (Section 2) for a directional source: beam b of source s gets
+       NULL = omni.  Reading of Section 2's sharing of a source's power between beams by
+       direction, for a directional source: beam b of source s gets
        K_b = W_s w_b / sum_f(w_f Omega_f), so its power K_b Omega_b is W_s's share in
        proportion to w_b Omega_b and the beams' powers add up to W_s. */
     const float *src_weight;
