@@ -182,6 +182,11 @@ typedef struct {
        K_b = W_s w_b / sum_f(w_f Omega_f), so its power K_b Omega_b is W_s's share in
        proportion to w_b Omega_b and the beams' powers add up to W_s. */
     const float *src_weight;
+    /* microphone layers: layer k sits at height mic_z + k mic_dz, k < mic_nz (a volumetric
+       grid filling a box, as in Section 4's experiment; mic_nz = 1 is a planar grid).
+       Microphone (i, j, k) has index (k mic_ny + j) mic_nx + i. */
+    double mic_dz;
+    int32_t mic_nz;
 } orc_scene;
 
 typedef struct {
@@ -701,34 +706,26 @@ static void add_contribution(const orc_scene *s, const orc_params *p, const obea
     acc->counters[C_MIC_UPDATES]++;
 }
 
-static void accumulate_mics(const orc_scene *s, const orc_params *p, const obeam *bm, int32_t hit, oaccum *acc)
+/* Microphones of layer k inside the segment's frustum: the grid rectangle at that height
+ * is clipped by the (relaxed) keep half-planes, then the rows inside the clipped polygon
+ * are scanned, one row and one column of slack on each side; membership is decided by
+ * the exact plane tests. */
+static void accumulate_layer(const orc_scene *s, const orc_params *p, const obeam *bm, const ofrustum *f,
+                             int64_t k, oaccum *acc)
 {
-    ofrustum f;
-    make_frustum(s, bm, hit, bm->c, &f);
-    int64_t nmic = (int64_t)s->mic_nx * s->mic_ny;
-    if (p->mic_mode == 0) {
-        for (int64_t mi = 0; mi < nmic; ++mi) {
-            int64_t i = mi % s->mic_nx, j = mi / s->mic_nx;
-            double m[3] = { s->mic_x0 + (double)i * s->mic_dx, s->mic_y0 + (double)j * s->mic_dy, s->mic_z };
-            int amb;
-            acc->counters[C_MIC_TESTS]++;
-            if (mic_inside(&f, bm->A, m, p->delta, &amb)) add_contribution(s, p, bm, mi, m, amb, acc);
-        }
-        return;
-    }
-    /* grid rasterisation: clip the grid rectangle by the (relaxed) keep half-planes,
-     * then scan the rows inside the clipped polygon. */
+    const double z = s->mic_z + (double)k * s->mic_dz;
+    const int64_t layer0 = k * (int64_t)s->mic_ny;
     const double eps = 1e-6;
     hplane hp[5];
     int nh = 0;
-    for (int i = 0; i < 3; ++i) hp[nh++] = make_hplane(f.n[i], bm->A, s->mic_z, eps);
-    if (f.has_near) {
-        double g[3] = { f.near_sign * f.Nn[0], f.near_sign * f.Nn[1], f.near_sign * f.Nn[2] };
-        hp[nh++] = make_hplane(g, f.Pn, s->mic_z, eps);
+    for (int i = 0; i < 3; ++i) hp[nh++] = make_hplane(f->n[i], bm->A, z, eps);
+    if (f->has_near) {
+        double g[3] = { f->near_sign * f->Nn[0], f->near_sign * f->Nn[1], f->near_sign * f->Nn[2] };
+        hp[nh++] = make_hplane(g, f->Pn, z, eps);
     }
-    if (f.has_far) {
-        double g[3] = { -f.far_sign * f.Nf[0], -f.far_sign * f.Nf[1], -f.far_sign * f.Nf[2] };
-        hp[nh++] = make_hplane(g, f.Pf, s->mic_z, eps);
+    if (f->has_far) {
+        double g[3] = { -f->far_sign * f->Nf[0], -f->far_sign * f->Nf[1], -f->far_sign * f->Nf[2] };
+        hp[nh++] = make_hplane(g, f->Pf, z, eps);
     }
     double xlo = s->mic_x0 - 0.5 * s->mic_dx, xhi = s->mic_x0 + ((double)s->mic_nx - 0.5) * s->mic_dx;
     double ylo = s->mic_y0 - 0.5 * s->mic_dy, yhi = s->mic_y0 + ((double)s->mic_ny - 0.5) * s->mic_dy;
@@ -765,12 +762,34 @@ static void accumulate_mics(const orc_scene *s, const orc_params *p, const obeam
         if (i0 < 0) i0 = 0;
         if (i1 > s->mic_nx - 1) i1 = s->mic_nx - 1;
         for (int64_t i = i0; i <= i1; ++i) {
-            double m[3] = { s->mic_x0 + (double)i * s->mic_dx, y, s->mic_z };
+            double m[3] = { s->mic_x0 + (double)i * s->mic_dx, y, z };
             int amb;
             acc->counters[C_MIC_TESTS]++;
-            if (mic_inside(&f, bm->A, m, p->delta, &amb)) add_contribution(s, p, bm, j * s->mic_nx + i, m, amb, acc);
+            if (mic_inside(f, bm->A, m, p->delta, &amb)) add_contribution(s, p, bm, (layer0 + j) * s->mic_nx + i, m, amb, acc);
         }
     }
+}
+
+static void accumulate_mics(const orc_scene *s, const orc_params *p, const obeam *bm, int32_t hit, oaccum *acc)
+{
+    ofrustum f;
+    make_frustum(s, bm, hit, bm->c, &f);
+    const int64_t nz = s->mic_nz > 0 ? s->mic_nz : 1;
+    if (p->mic_mode == 0) {
+        /* every microphone of every layer */
+        const int64_t nmic = (int64_t)s->mic_nx * s->mic_ny * nz;
+        for (int64_t mi = 0; mi < nmic; ++mi) {
+            int64_t i = mi % s->mic_nx, j = (mi / s->mic_nx) % s->mic_ny, k = mi / ((int64_t)s->mic_nx * s->mic_ny);
+            double m[3] = { s->mic_x0 + (double)i * s->mic_dx, s->mic_y0 + (double)j * s->mic_dy,
+                            s->mic_z + (double)k * s->mic_dz };
+            int amb;
+            acc->counters[C_MIC_TESTS]++;
+            if (mic_inside(&f, bm->A, m, p->delta, &amb)) add_contribution(s, p, bm, mi, m, amb, acc);
+        }
+        return;
+    }
+    /* grid rasterisation, layer by layer */
+    for (int64_t k = 0; k < nz; ++k) accumulate_layer(s, p, bm, &f, k, acc);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -892,7 +911,7 @@ int orc_trace(const orc_scene *s, const orc_params *p, orc_result *res)
     int64_t b0 = p->beam_begin < 0 ? 0 : p->beam_begin;
     int64_t b1 = p->beam_end > nb || p->beam_end < 0 ? nb : p->beam_end;
     int D = p->depth;
-    int64_t nmic = (int64_t)s->mic_nx * s->mic_ny;
+    int64_t nmic = (int64_t)s->mic_nx * s->mic_ny * (s->mic_nz > 0 ? s->mic_nz : 1);
     double *dirs = (double *)malloc(sizeof(double) * 9 * (size_t)nf);
     if (!dirs) return -2;
     if (orc_icosphere(p->level, dirs) != 0) { free(dirs); return -3; }

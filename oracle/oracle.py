@@ -51,7 +51,7 @@ class _Scene(C.Structure):
                 ("alpha", C.c_void_p), ("src", C.c_void_p), ("power", C.c_void_p), ("n_src", C.c_int32),
                 ("mic_x0", C.c_double), ("mic_y0", C.c_double), ("mic_z", C.c_double),
                 ("mic_dx", C.c_double), ("mic_dy", C.c_double), ("mic_nx", C.c_int32), ("mic_ny", C.c_int32),
-                ("src_weight", C.c_void_p)]
+                ("src_weight", C.c_void_p), ("mic_dz", C.c_double), ("mic_nz", C.c_int32)]
 
 
 class _Params(C.Structure):
@@ -110,7 +110,7 @@ def _scene_struct(scene, keep, weights=None):
         keep.append(wt)
     return _Scene(_ptr(v), v.shape[0], _ptr(t), t.shape[0], _ptr(a), _ptr(s), _ptr(w), s.shape[0],
                   f32(scene.mic_x0), f32(scene.mic_y0), f32(scene.mic_z), f32(scene.mic_dx), f32(scene.mic_dy),
-                  scene.mic_nx, scene.mic_ny, _ptr(wt))
+                  scene.mic_nx, scene.mic_ny, _ptr(wt), f32(scene.mic_dz), scene.mic_nz)
 
 
 def icosphere(level: int) -> np.ndarray:

@@ -27,8 +27,9 @@ class Scene:
     absorption float32 [n_t], energy fraction lost on reflection, in [0, 1]
     sources    float32 [n_s, 3], point sources
     power      float32 [n_s], watts
-    mic grid   x0 + i*dx, y0 + j*dy at height mic_z, i < mic_nx, j < mic_ny;
-               microphone index is j*mic_nx + i
+    mic grid   x0 + i*dx, y0 + j*dy at height mic_z + k*mic_dz, i < mic_nx, j < mic_ny,
+               k < mic_nz (mic_nz = 1: a planar grid); microphone index is
+               (k*mic_ny + j)*mic_nx + i
     level      icosphere subdivision level (20*4**level beams per source)
     depth      maximum number of reflections
     tiles      on-device partition of the mesh footprint (tiles_x x tiles_y)
@@ -51,6 +52,8 @@ class Scene:
     depth: int
     tiles_x: int = 1
     tiles_y: int = 1
+    mic_dz: float = 4.0
+    mic_nz: int = 1
 
     @property
     def n_tri(self) -> int:
@@ -62,20 +65,21 @@ class Scene:
 
     @property
     def n_mic(self) -> int:
-        return self.mic_nx * self.mic_ny
+        return self.mic_nx * self.mic_ny * self.mic_nz
 
     @property
     def n_beams0(self) -> int:
         return self.n_src * 20 * 4 ** self.level
 
     def mic_positions(self) -> np.ndarray:
-        """float64 [n_mic, 3] positions of the grid microphones (index j*nx+i)."""
+        """float64 [n_mic, 3] positions of the grid microphones (index (k*ny + j)*nx + i)."""
         i = np.arange(self.mic_nx, dtype=np.float64)
         j = np.arange(self.mic_ny, dtype=np.float64)
+        k = np.arange(self.mic_nz, dtype=np.float64)
         x = np.float64(np.float32(self.mic_x0)) + i * np.float64(np.float32(self.mic_dx))
         y = np.float64(np.float32(self.mic_y0)) + j * np.float64(np.float32(self.mic_dy))
-        xx, yy = np.meshgrid(x, y)
-        zz = np.full_like(xx, np.float64(np.float32(self.mic_z)))
+        z = np.float64(np.float32(self.mic_z)) + k * np.float64(np.float32(self.mic_dz))
+        zz, yy, xx = np.meshgrid(z, y, x, indexing="ij")
         return np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
 
     def with_(self, **kw) -> "Scene":

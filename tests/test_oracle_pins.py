@@ -217,6 +217,54 @@ def test_direct_path_free_field(level):
     assert r.counters["mic_updates"] == sc.n_mic
 
 
+@pytest.mark.parametrize("mic_mode", [0, 1])
+def test_direct_path_free_field_volumetric(mic_mode):
+    """A volumetric grid (layers below, across and above the source): every microphone of
+    every layer gets W / (4 pi d^2) exactly once.  (One microphone lies within delta of a
+    shared beam face and is reported as ambiguous; its energy is still the closed form.)"""
+    sc = empty_scene(level=3, src=(0.3, -0.2, 1.0), n_mic=7, spacing=3.0, mic_z=-5.5).with_(mic_nz=5, mic_dz=4.0)
+    r = O.trace(sc, use_bvh=False, mic_mode=mic_mode)
+    m = sc.mic_positions()
+    assert m.shape == (245, 3) and m[:, 2].min() == -5.5 and m[:, 2].max() == 10.5
+    ref = 1.0 / (FOUR_PI * ((m - sc.sources[0].astype(np.float64)) ** 2).sum(1))
+    assert (r.e_flag > 0).sum() <= 1
+    assert np.abs(r.energy / ref - 1).max() < 1e-13
+    assert r.counters["mic_updates"] == sc.n_mic
+
+
+def test_ground_reflection_volumetric():
+    """Ground plane, one reflection, microphones in layers below and above it: layers above
+    get the direct plus the image-source term, the layer below the ground gets nothing."""
+    alpha = 0.3
+    sc = ground_scene(level=4, alpha=alpha, mic_z=-2.5).with_(mic_nz=4, mic_dz=4.0)
+    r = O.trace(sc)
+    m = sc.mic_positions()
+    s = sc.sources[0].astype(np.float64)
+    img = s * np.array([1, 1, -1.0])
+    a32 = float(np.float32(alpha))
+    ref = (1.0 / ((m - s) ** 2).sum(1) + (1 - a32) / ((m - img) ** 2).sum(1)) / FOUR_PI
+    below = m[:, 2] < 0
+    assert below.sum() == sc.mic_nx * sc.mic_ny
+    assert (r.energy[below] == 0).all()
+    elev = np.degrees(np.arctan2(m[:, 2] + s[2], np.hypot(m[:, 0] - s[0], m[:, 1] - s[1])))
+    ok = ~below & (elev > 15) & (r.e_flag == 0)
+    assert ok.sum() > 150
+    assert np.abs(r.energy[ok] / ref[ok] - 1).max() < 1e-13
+
+
+def test_volumetric_layers_equal_planar_runs():
+    """Layer k of a volumetric grid holds exactly what a planar grid at height z0 + k dz gets."""
+    sc = tiny_scene().with_(mic_z=-2.5, mic_nz=5, mic_dz=4.0)
+    r = O.trace(sc, n_threads=1)
+    per = sc.mic_nx * sc.mic_ny
+    for k in range(sc.mic_nz):
+        p = O.trace(sc.with_(mic_z=-2.5 + 4.0 * k, mic_nz=1), n_threads=1)
+        assert np.array_equal(r.e_strict[k * per:(k + 1) * per], p.e_strict)
+        assert np.array_equal(r.e_flag[k * per:(k + 1) * per], p.e_flag)
+    assert (r.energy[:per] == 0).all()   # below the ground
+    assert (r.energy[per:] > 0).any()
+
+
 def test_directional_source_uniform_weights_is_omni():
     """Equal weights give the omni split (K = W / (4 pi)) up to the rounding of the solid
     angles' sum; any weights conserve the emitted power."""
@@ -342,7 +390,15 @@ def test_energy_bookkeeping_block():
 # Microphone enumeration and symmetry
 # ----------------------------------------------------------------------------
 
-@pytest.mark.parametrize("maker,kw", [(tiny_scene, {}), (mirror_scene, {}), (block_scene, {"beam_end": 3000})])
+def _volumetric(sc, nz, dz):
+    return sc.with_(mic_nz=nz, mic_dz=dz)
+
+
+@pytest.mark.parametrize("maker,kw", [(tiny_scene, {}), (mirror_scene, {}), (block_scene, {"beam_end": 3000}),
+                                      (lambda: _volumetric(tiny_scene(), 6, 5.0), {}),
+                                      (lambda: _volumetric(block_scene().with_(mic_nx=40, mic_ny=40, mic_dx=5.0,
+                                                                               mic_dy=5.0), 8, 7.0),
+                                       {"beam_end": 3000})])
 def test_grid_rasterisation_equals_brute_force(maker, kw):
     sc = maker()
     a = O.trace(sc, mic_mode=1, n_threads=1, **kw)
