@@ -120,6 +120,15 @@ bt_status bt_mesh_info(const bt_mesh *mesh, int64_t *n_nodes, int32_t *max_depth
  * index j * nx + i.  Energies are owned by the set and start at zero. */
 bt_status bt_mics_grid(bt_ctx *ctx, float x0, float y0, float z, float dx, float dy, int32_t nx, int32_t ny,
                        bt_mics **out);
+/* Microphones on a regular volumetric grid (paper Section 4: the experiment fills the
+ * model's bounding box with microphones, one every 4 m in each direction):
+ * positions (x0 + i dx, y0 + j dy, z0 + k dz), i < nx, j < ny, k < nz, index
+ * (k ny + j) nx + i; nx ny nz <= 2^31, dz > 0 when nz > 1.  nz = 1 is bt_mics_grid.
+ * Energies (bt_levels returns nx ny nz values) are owned by the set and start at zero.
+ * Usable with bt_accumulate_mics and bt_run; the scenario and serving interfaces take
+ * planar grids. */
+bt_status bt_mics_grid3d(bt_ctx *ctx, float x0, float y0, float z0, float dx, float dy, float dz, int32_t nx,
+                         int32_t ny, int32_t nz, bt_mics **out);
 bt_status bt_mics_reset(bt_ctx *ctx, bt_mics *mics);   /* zero the energies (kernel, no memset) */
 bt_status bt_mics_free(bt_mics *mics);
 

@@ -282,6 +282,7 @@ bt_status run_batch(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *sc, int
             m.dy = q.mic_dy;
             m.nx = q.mic_nx;
             m.ny = q.mic_ny;
+            m.nz = 1;
             m.e_strict = w.energy + eoff;
             m.e_flag = w.energy + E + eoff;
             m.mask = nullptr;

@@ -531,27 +531,29 @@ extern "C" bt_status bt_mesh_info(const bt_mesh *m, int64_t *n_nodes, int32_t *m
 // ---------------------------------------------------------------------------------------
 // microphones
 // ---------------------------------------------------------------------------------------
-extern "C" bt_status bt_mics_grid(bt_ctx *ctx, float x0, float y0, float z, float dx, float dy, int32_t nx, int32_t ny,
-                                  bt_mics **out)
+extern "C" bt_status bt_mics_grid3d(bt_ctx *ctx, float x0, float y0, float z0, float dx, float dy, float dz,
+                                    int32_t nx, int32_t ny, int32_t nz, bt_mics **out)
 {
     if (!ctx) return BT_EINVAL;
     if (!out) return fail(ctx, BT_EINVAL, "out is NULL");
     *out = nullptr;
-    if (nx < 1 || ny < 1 || (int64_t)nx * ny > (1ll << 31))
-        return fail(ctx, BT_EINVAL, "bad microphone grid %d x %d", nx, ny);
-    if (!std::isfinite(x0) || !std::isfinite(y0) || !std::isfinite(z) || !(dx > 0.f) || !(dy > 0.f) ||
-        !std::isfinite(dx) || !std::isfinite(dy))
+    if (nx < 1 || ny < 1 || nz < 1 || (int64_t)nx * ny * nz > (1ll << 31))
+        return fail(ctx, BT_EINVAL, "bad microphone grid %d x %d x %d", nx, ny, nz);
+    if (!std::isfinite(x0) || !std::isfinite(y0) || !std::isfinite(z0) || !(dx > 0.f) || !(dy > 0.f) ||
+        !std::isfinite(dx) || !std::isfinite(dy) || (nz > 1 && (!(dz > 0.f) || !std::isfinite(dz))))
         return fail(ctx, BT_EINVAL, "bad microphone grid geometry");
     (void)hipSetDevice(ctx->device);
     bt_mics *m = new bt_mics();
     m->ctx = ctx;
-    long long n = (long long)nx * ny;
+    long long n = (long long)nx * ny * nz;
     m->bytes = (size_t)n * sizeof(double) * 3;
     void *p = nullptr;
     bt_status s = dev_alloc(ctx, &p, m->bytes);
     if (s != BT_OK) { delete m; return s; }
-    m->dev.x0 = x0; m->dev.y0 = y0; m->dev.z = z; m->dev.dx = dx; m->dev.dy = dy;
+    m->dev.x0 = x0; m->dev.y0 = y0; m->dev.z = z0; m->dev.dx = dx; m->dev.dy = dy;
     m->dev.nx = nx; m->dev.ny = ny;
+    m->dev.nz = nz;
+    m->dev.dz = nz > 1 ? (double)dz : 0.0;
     m->dev.e_strict = (double *)p;
     m->dev.e_flag = m->dev.e_strict + n;
     m->level = m->dev.e_flag + n;
@@ -561,10 +563,16 @@ extern "C" bt_status bt_mics_grid(bt_ctx *ctx, float x0, float y0, float z, floa
     return BT_OK;
 }
 
+extern "C" bt_status bt_mics_grid(bt_ctx *ctx, float x0, float y0, float z, float dx, float dy, int32_t nx, int32_t ny,
+                                  bt_mics **out)
+{
+    return bt_mics_grid3d(ctx, x0, y0, z, dx, dy, 0.f, nx, ny, 1, out);
+}
+
 extern "C" bt_status bt_mics_reset(bt_ctx *ctx, bt_mics *m)
 {
     if (!ctx || !m) return BT_EINVAL;
-    long long n = (long long)m->dev.nx * m->dev.ny;
+    long long n = (long long)m->dev.nx * m->dev.ny * m->dev.nz;
     HIP_TRY(ctx, launch_fill(m->dev.e_strict, 2 * n, 0.0, ctx->stream));
     return BT_OK;
 }
@@ -576,6 +584,7 @@ bt_status mics_fit(bt_ctx *ctx, bt_mics **m, float x0, float y0, float z, float 
         bt_mics *g = *m;
         g->dev.x0 = x0; g->dev.y0 = y0; g->dev.z = z; g->dev.dx = dx; g->dev.dy = dy;
         g->dev.nx = nx; g->dev.ny = ny;
+        g->dev.nz = 1; g->dev.dz = 0.0;
         g->dev.e_flag = g->dev.e_strict + n;
         g->level = g->dev.e_flag + n;
         return bt_mics_reset(ctx, g);
@@ -650,7 +659,30 @@ void beams_release(bt_beams *b)
     dev_free(ctx, b->spans, (size_t)b->spans_cap * sizeof(int4));
     b->spans = nullptr;
     b->spans_cap = 0;
+    dev_free(ctx, b->layers, (size_t)b->layers_cap * sizeof(int2));
+    b->layers = nullptr;
+    b->layers_cap = 0;
     b->work_n0 = 0;
+}
+
+// (segment, layer) item buffer of the volumetric microphone pass, sized from the
+// generation-0 count; a full buffer sends the remaining layers of a segment to the
+// one-lane-per-segment fallback.
+static bt_status reserve_layers(bt_ctx *ctx, bt_beams *b)
+{
+    long long want = std::max(b->n0, 1ll << 20);
+    if (const char *env = std::getenv("BT_MIC_LAYER_CAPACITY")) {  // testing the full-buffer path
+        long long v = std::atoll(env);
+        if (v > 0) want = v;
+    }
+    if (b->layers && b->layers_cap == want) return BT_OK;
+    dev_free(ctx, b->layers, (size_t)b->layers_cap * sizeof(int2));
+    b->layers = nullptr;
+    b->layers_cap = 0;
+    bt_status s = dev_alloc(ctx, (void **)&b->layers, (size_t)want * sizeof(int2));
+    if (s != BT_OK) return s;
+    b->layers_cap = want;
+    return BT_OK;
 }
 
 // Queue, segment and overflow-list capacity of at least n records.  When the arrays
@@ -945,7 +977,9 @@ extern "C" bt_status bt_accumulate_mics(bt_ctx *ctx, const bt_mesh *mesh, bt_bea
     // all generations traced since the previous call, in one pass
     TraceArgs a = make_args(p, b->acc_gen);
     a.gen_end = b->gen;
-    MicWork w{b->rows, b->rows_cap, b->spans, b->spans_cap, b->big_list + b->cap, b->big_list};
+    if (mics->dev.nz > 1 && (s = reserve_layers(ctx, b)) != BT_OK) return s;
+    MicWork w{b->rows, b->rows_cap, b->spans, b->spans_cap, b->big_list + b->cap, b->big_list, b->layers,
+              b->layers_cap};
     HIP_TRY(ctx, launch_mics(mesh->dev, b->q, b->segs, b->ctr, mics->dev, a, w, b->ws, ctx->n_cu, ctx->stream));
     b->acc_gen = b->gen;
     return BT_OK;
@@ -955,7 +989,7 @@ extern "C" bt_status bt_levels(bt_ctx *ctx, const bt_mics *m, double *strict_out
 {
     if (!ctx || !m) return BT_EINVAL;
     (void)hipSetDevice(ctx->device);
-    long long n = (long long)m->dev.nx * m->dev.ny;
+    long long n = (long long)m->dev.nx * m->dev.ny * m->dev.nz;
     size_t bytes = (size_t)n * sizeof(double);
     if (level_db_out) {
         HIP_TRY(ctx, launch_levels(m->dev.e_strict, m->dev.e_flag, m->level, n, ctx->stream));

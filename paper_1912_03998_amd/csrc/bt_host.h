@@ -62,6 +62,8 @@ struct bt_beams {
     long long rows_cap = 0;
     int4 *spans = nullptr;
     long long spans_cap = 0;
+    int2 *layers = nullptr;   // volumetric grids: (segment, layer) items, allocated on first use
+    long long layers_cap = 0;
     long long work_n0 = 0;    // generation-0 size the work buffers were sized for
     int acc_gen = 0;          // first generation not yet accumulated at the microphones
     int depth_hint = 0;       // max_depth of the previous run, to size the queue at emission

@@ -93,16 +93,23 @@ struct DevCounters {
     unsigned long long n_big[BT_MAX_DEPTH + 2];      // segments for the wave-per-segment fallback
     unsigned long long n_rows[BT_MAX_DEPTH + 2];     // (segment, row) work items requested
     unsigned long long n_spans[BT_MAX_DEPTH + 2];    // (segment, row, columns) work items
+    unsigned long long n_layers[BT_MAX_DEPTH + 2];   // volumetric: (segment, layer) items requested
+    unsigned long long n_late[BT_MAX_DEPTH + 2];     // volumetric: segments past a full item buffer
     unsigned long long node_visits, tri_tests, mic_tests, mic_updates;
 };
 
+// Microphone (i, j, k) sits at (x0 + i dx, y0 + j dy, z + k dz) and has index
+// (k ny + j) nx + i; a planar grid has nz = 1.  Work items name a microphone row by its
+// global row k ny + j.
 struct DevMics {
     double x0, y0, z, dx, dy;  // float32 grid values, widened
     int nx, ny;
-    double *e_strict;          // [nx*ny]
-    double *e_flag;            // [nx*ny]
-    const unsigned *mask;      // scenario sets only: bit (j nx + i) set for the microphones of
-                               // the set's subset; NULL = every grid point
+    double *e_strict;          // [nx*ny*nz]
+    double *e_flag;            // [nx*ny*nz]
+    const unsigned *mask;      // scenario sets only (planar): bit (j nx + i) set for the
+                               // microphones of the set's subset; NULL = every grid point
+    double dz;                 // layer spacing (float32 value, widened); 0 when nz = 1
+    int nz;                    // layers
 };
 
 // Work buffers of the microphone stage: (segment, row) items of wide footprints,
@@ -114,7 +121,10 @@ struct MicWork {
     int4 *spans;
     long long spans_cap;
     int *general;      // segments for the general footprint path; capacity: the queue's
-    int *big_list;     // capacity: the queue capacity
+    int *big_list;     // capacity: the queue capacity; volumetric grids use the 2 x capacity
+                       // ints from here as (segment, first layer) fallback pairs
+    int2 *layers;      // volumetric grids: (segment, layer) items of the general path
+    long long layers_cap;
 };
 
 // Per-wave records of the statically partitioned kernels (wave w of a grid of W waves

@@ -18,6 +18,9 @@ namespace bt {
 //   k_mic_rows:  one lane per (segment, row) work item
 //   k_mics_big:  one wave per segment, for segments whose rows did not fit the item
 //                buffer (overflow fallback)
+// A volumetric grid (Section 4's experiment fills the model's bounding box with
+// microphones) is a stack of such planes: k_mics3d bounds the layers a segment's frustum
+// can reach and runs the same footprint logic on each of them.
 // ---------------------------------------------------------------------------------------
 struct Frustum {
     V3 A;
@@ -91,15 +94,16 @@ __device__ void load_frustum(const DevMesh &M, const DevQueue &q, const DevSegs 
     }
 }
 
-// The frustum's half-planes plus the grid rectangle (grown by half a cell) as 9 lines;
-// unused slots are the always-true constraint 0 x + 0 y + 1 >= 0.
-__device__ __forceinline__ void footprint_lines(const Frustum &f, const DevMics &mc, HalfPlane *L)
+// The frustum's half-planes on the microphone plane at height z, plus the grid rectangle
+// (grown by half a cell) as 9 lines; unused slots are the always-true constraint
+// 0 x + 0 y + 1 >= 0.
+__device__ __forceinline__ void footprint_lines(const Frustum &f, const DevMics &mc, double z, HalfPlane *L)
 {
     const double eps = 1e-6;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) L[k] = make_hp(f.n[k], f.A, mc.z, eps);
-    L[3] = f.has_near ? make_hp(f.near_sign * f.Nn, f.Pn, mc.z, eps) : HalfPlane{0.0, 0.0, 1.0};
-    L[4] = f.has_far ? make_hp((-f.far_sign) * f.Nf, f.Pf, mc.z, eps) : HalfPlane{0.0, 0.0, 1.0};
+    for (int k = 0; k < 3; ++k) L[k] = make_hp(f.n[k], f.A, z, eps);
+    L[3] = f.has_near ? make_hp(f.near_sign * f.Nn, f.Pn, z, eps) : HalfPlane{0.0, 0.0, 1.0};
+    L[4] = f.has_far ? make_hp((-f.far_sign) * f.Nf, f.Pf, z, eps) : HalfPlane{0.0, 0.0, 1.0};
     double xlo = mc.x0 - 0.5 * mc.dx, xhi = mc.x0 + ((double)mc.nx - 0.5) * mc.dx;
     double ylo = mc.y0 - 0.5 * mc.dy, yhi = mc.y0 + ((double)mc.ny - 0.5) * mc.dy;
     L[5] = HalfPlane{1.0, 0.0, -xlo};
@@ -176,12 +180,13 @@ __device__ __forceinline__ bool row_cols(const HalfPlane *L, const DevMics &mc, 
     return true;
 }
 
-// Membership of grid microphone (i, j) and its contribution; returns 1 if accumulated.
-// Ambiguous: every active test passes within -delta and one is within delta of its plane.
+// Membership of grid microphone (i, j) of layer k and its contribution; returns 1 if
+// accumulated.  Ambiguous: every active test passes within -delta and one is within delta
+// of its plane.
 template <bool kSlots>
-__device__ __forceinline__ int mic_apply(const Frustum &f, const DevMics &mc, int i, int j, double air_m)
+__device__ __forceinline__ int mic_apply(const Frustum &f, const DevMics &mc, int i, int j, int k, double air_m)
 {
-    const V3 m = {mc.x0 + (double)i * mc.dx, mc.y0 + (double)j * mc.dy, mc.z};
+    const V3 m = {mc.x0 + (double)i * mc.dx, mc.y0 + (double)j * mc.dy, mc.z + (double)k * mc.dz};
     const V3 r = m - f.A;
     bool inside = true, far_out = false, near_any = false;
 #pragma unroll
@@ -207,7 +212,7 @@ __device__ __forceinline__ int mic_apply(const Frustum &f, const DevMics &mc, in
         near_any = near_any || s2 < f.amb2_far;
     }
     if (!inside) return 0;
-    const long long idx = (long long)j * mc.nx + i;
+    const long long idx = ((long long)k * mc.ny + j) * mc.nx + i;
     if (kSlots && mc.mask && !((mc.mask[idx >> 5] >> (idx & 31)) & 1u)) return 0;
     const double d2 = dot(r, r);
     float e = f.K / (float)d2;
@@ -220,11 +225,11 @@ __device__ __forceinline__ int mic_apply(const Frustum &f, const DevMics &mc, in
 constexpr int kInlineRows = 4;
 constexpr int kSpan = 32;   // longest column run one lane processes in place
 
-// Columns [c0, c1] of row j: processed here when short, else split into kSpan-column
-// span items (processed here anyway if the span buffer is full).
+// Columns [c0, c1] of row j of layer k: processed here when short, else split into
+// kSpan-column span items (processed here anyway if the span buffer is full).
 template <bool kSlots>
 __device__ __forceinline__ void process_row(const Frustum &f, const DevMics &mc, const MicWork &w, DevCounters *ctr,
-                                            int gen, long long seg, int j, int c0, int c1, double air_m,
+                                            int gen, long long seg, int j, int k, int c0, int c1, double air_m,
                                             unsigned &tests, unsigned &updates)
 {
     const int ncol = c1 - c0 + 1;
@@ -232,9 +237,9 @@ __device__ __forceinline__ void process_row(const Frustum &f, const DevMics &mc,
         const int nsp = (ncol + kSpan - 1) / kSpan;
         const unsigned long long b = atomicAdd(&ctr->n_spans[gen], (unsigned long long)nsp);
         if (b + (unsigned long long)nsp <= (unsigned long long)w.spans_cap) {
-            for (int k = 0; k < nsp; ++k) {
-                const int a0 = c0 + k * kSpan;
-                w.spans[b + k] = make_int4((int)seg, j, a0, min(a0 + kSpan - 1, c1));
+            for (int s = 0; s < nsp; ++s) {
+                const int a0 = c0 + s * kSpan;
+                w.spans[b + s] = make_int4((int)seg, k * mc.ny + j, a0, min(a0 + kSpan - 1, c1));
             }
             return;
         }
@@ -242,7 +247,7 @@ __device__ __forceinline__ void process_row(const Frustum &f, const DevMics &mc,
     }
     for (int c = c0; c <= c1; ++c) {
         tests++;
-        updates += mic_apply<kSlots>(f, mc, c, j, air_m);
+        updates += mic_apply<kSlots>(f, mc, c, j, k, air_m);
     }
 }
 
@@ -343,7 +348,7 @@ __global__ void __launch_bounds__(256, 4) k_mics(DevMesh M, DevQueue q, DevSegs 
                     for (int j = (int)fj0; j <= (int)fj1; ++j)
                         for (int c = (int)fi0; c <= (int)fi1; ++c) {
                             tests++;
-                            updates += mic_apply<kSlots>(f, mc, c, j, a.air_m);
+                            updates += mic_apply<kSlots>(f, mc, c, j, 0, a.air_m);
                         }
                 }
             }
@@ -382,14 +387,14 @@ __global__ void __launch_bounds__(256, 3) k_mics_general(DevMesh M, DevQueue q, 
             Frustum f;
             load_frustum(M, q, segs, i, a.delta, f);
             HalfPlane L[9];
-            footprint_lines(f, mc, L);
+            footprint_lines(f, mc, mc.z, L);
             if (footprint_rows(L, mc, j0, j1)) {
                 nrows = j1 - j0 + 1;
                 if (nrows <= kInlineRows) {
                     for (int j = j0; j <= j1; ++j) {
                         int c0, c1;
                         if (!row_cols(L, mc, j, c0, c1)) continue;
-                        process_row<kSlots>(f, mc, w, ctr, a.gen, i, j, c0, c1, a.air_m, tests, updates);
+                        process_row<kSlots>(f, mc, w, ctr, a.gen, i, j, 0, c0, c1, a.air_m, tests, updates);
                     }
                 } else {
                     wide = true;
@@ -442,13 +447,15 @@ __global__ void __launch_bounds__(256) k_mic_rows(DevMesh M, DevQueue q, DevSegs
         const int2 it = r < n ? w.rows[r] : make_int2(-1, 0);
         if (it.x >= 0) {
             const DevMics mc = seg_mics<kSlots>(mc0, a, q, it.x);
+            const int k = mc.nz > 1 ? it.y / mc.ny : 0;  // global row k ny + j
+            const int j = it.y - k * mc.ny;
             Frustum f;
             load_frustum(M, q, segs, it.x, a.delta, f);
             HalfPlane L[9];
-            footprint_lines(f, mc, L);
+            footprint_lines(f, mc, mc.z + (double)k * mc.dz, L);
             int c0, c1;
-            if (row_cols(L, mc, it.y, c0, c1))
-                process_row<kSlots>(f, mc, w, ctr, a.gen, it.x, it.y, c0, c1, a.air_m, tests, updates);
+            if (row_cols(L, mc, j, c0, c1))
+                process_row<kSlots>(f, mc, w, ctr, a.gen, it.x, j, k, c0, c1, a.air_m, tests, updates);
         }
     }
     flush_mic_counters(ctr, tests, updates);
@@ -466,11 +473,13 @@ __global__ void __launch_bounds__(256) k_mic_spans(DevMesh M, DevQueue q, DevSeg
         const int4 sp = r < n ? w.spans[r] : make_int4(-1, 0, 0, -1);
         if (sp.x >= 0) {
             const DevMics mc = seg_mics<kSlots>(mc0, a, q, sp.x);
+            const int k = mc.nz > 1 ? sp.y / mc.ny : 0;  // global row k ny + j
+            const int j = sp.y - k * mc.ny;
             Frustum f;
             load_frustum(M, q, segs, sp.x, a.delta, f);
             for (int c = sp.z; c <= sp.w; ++c) {
                 tests++;
-                updates += mic_apply<kSlots>(f, mc, c, sp.y, a.air_m);
+                updates += mic_apply<kSlots>(f, mc, c, j, k, a.air_m);
             }
         }
     }
@@ -492,13 +501,271 @@ __global__ void __launch_bounds__(256) k_mics_big(DevMesh M, DevQueue q, DevSegs
         Frustum f;
         load_frustum(M, q, segs, i, a.delta, f);
         HalfPlane L[9];
-        footprint_lines(f, mc, L);
+        footprint_lines(f, mc, mc.z, L);
         int j0, j1;
         if (footprint_rows(L, mc, j0, j1)) {
             for (int j = j0 + lane; j <= j1; j += 64) {
                 int c0, c1;
                 if (!row_cols(L, mc, j, c0, c1)) continue;
-                process_row<kSlots>(f, mc, w, ctr, a.gen, i, j, c0, c1, a.air_m, tests, updates);
+                process_row<kSlots>(f, mc, w, ctr, a.gen, i, j, 0, c0, c1, a.air_m, tests, updates);
+            }
+        }
+    }
+    flush_mic_counters(ctr, tests, updates);
+}
+
+// ---------------------------------------------------------------------------------------
+// Volumetric grids
+//   k_mics3d:         one lane per segment: the layers its frustum can reach, the planar
+//                     fast path on each; layers that need the clipped footprint become
+//                     (segment, layer) items
+//   k_mics3d_general: one lane per (segment, layer) item: rows of the clipped footprint,
+//                     finished here when few, else (segment, global row) items for
+//                     k_mic_rows (done here when the row buffer is full)
+//   k_mics3d_late:    segments whose items did not fit the item buffer: every layer from
+//                     the first one not listed, both paths in one lane (overflow fallback)
+// ---------------------------------------------------------------------------------------
+
+// Layers [k0, k1] a segment's frustum can reach, from its z-extent widened for rounding.
+// When the apex is on the incoming side of the hit plane and all three edge rays cross
+// that plane ahead of the apex, the frustum (cone cut by the hit plane) lies in the
+// tetrahedron of the apex and the three crossing points; otherwise the cone of the edge
+// directions is the bound (unbounded above if an edge rises, below if one falls).
+__device__ __forceinline__ bool seg_layers(const DevMesh &M, const DevQueue &q, long long i, int hit, V3 A,
+                                           const V3 *d, const DevMics &mc, int &k0, int &k1)
+{
+    double zlo = A.z, zhi = A.z, mag = fabs(A.z);
+    bool cut = hit >= 0;
+    bool up = false, down = false;
+    V3 Nf = {0.0, 0.0, 0.0};
+    double c0 = 0.0;
+    if (cut) {
+        V3 v0, v1, v2;
+        tri_vertices(M.tri_g, hit, v0, v1, v2);
+        const V3 c = ld3(q.dbl + D_C * q.cap, q.cap, i);
+        Nf = cross(v1 - v0, v2 - v0);
+        if (!(dot(c, Nf) > 0.0)) Nf = -1.0 * Nf;  // oriented along the guiding ray
+        c0 = dot(Nf, v0 - A);
+        cut = c0 > 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        up = up || d[k].z > 0.0;
+        down = down || d[k].z < 0.0;
+        const double g = dot(Nf, d[k]);  // rate of approach to the hit plane
+        cut = cut && g > 0.0;
+        if (cut && d[k].z != 0.0) {
+            const double z = A.z + (c0 / g) * d[k].z;
+            zlo = fmin(zlo, z);
+            zhi = fmax(zhi, z);
+            mag = fmax(mag, fabs(z));
+        }
+    }
+    if (!cut) {
+        zlo = down ? -INFINITY : A.z;
+        zhi = up ? INFINITY : A.z;
+    }
+    const double slack = 1e-6 + 1e-9 * mag;
+    const double fk0 = fmax(ceil((zlo - slack - mc.z) / mc.dz), 0.0);
+    const double fk1 = fmin(floor((zhi + slack - mc.z) / mc.dz), (double)(mc.nz - 1));
+    if (!(fk0 <= fk1)) return false;
+    k0 = (int)fk0;
+    k1 = (int)fk1;
+    return true;
+}
+
+// What the per-layer fast path needs of a segment: the apex and edge directions, x and
+// y in FP32 (they only bound the candidate lattice), z in FP64 (their signs decide).
+struct Cone {
+    double az;
+    double dz[3];
+    float ax, ay;
+    float dx[3], dy[3];
+};
+
+__device__ __forceinline__ Cone make_cone(V3 A, const V3 *d)
+{
+    Cone c;
+    c.az = A.z;
+    c.ax = (float)A.x;
+    c.ay = (float)A.y;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        c.dz[e] = d[e].z;
+        c.dx[e] = (float)d[e].x;
+        c.dy[e] = (float)d[e].y;
+    }
+    return c;
+}
+
+// The planar fast path on layer k: 0 = no microphone can be inside, 1 = the candidates
+// are the lattice box [i0, i1] x [j0, j1] (at most kSpan points), 2 = the clipped
+// footprint is needed.
+__device__ __forceinline__ int layer_fast(const Cone &cn, const DevMics &mc, int k, int &i0, int &i1, int &j0,
+                                          int &j1)
+{
+    const double zr = (mc.z + (double)k * mc.dz) - cn.az;
+    bool proper = zr != 0.0;
+    bool away = zr > 1e-6 || zr < -1e-6;
+    const float zrf = (float)zr;
+    float xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
+    float mag = fmaxf(fabsf(cn.ax), fabsf(cn.ay));
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        proper = proper && (zr > 0.0 ? cn.dz[e] > 0.0 : cn.dz[e] < 0.0);
+        away = away && (zr > 0.0 ? cn.dz[e] <= 0.0 : cn.dz[e] >= 0.0);
+        const float s = zrf / (float)cn.dz[e];
+        proper = proper && isfinite(s);
+        const float sx = s * cn.dx[e], sy = s * cn.dy[e];
+        const float px = cn.ax + sx, py = cn.ay + sy;
+        xmn = fminf(xmn, px); xmx = fmaxf(xmx, px);
+        ymn = fminf(ymn, py); ymx = fmaxf(ymx, py);
+        mag = fmaxf(mag, fmaxf(fabsf(sx), fabsf(sy)));
+    }
+    if (away) return 0;
+    if (!proper) return 2;
+    // as in the planar fast path: FP32 crossings widened by 1e-5 of their magnitude
+    const double relax = 1e-6 + 1e-5 * (double)mag;
+    const double idx = 1.0 / mc.dx, idy = 1.0 / mc.dy;
+    const double fi0 = fmax(ceil(((double)xmn - relax - mc.x0) * idx - 1e-9), 0.0);
+    const double fi1 = fmin(floor(((double)xmx + relax - mc.x0) * idx + 1e-9), (double)(mc.nx - 1));
+    const double fj0 = fmax(ceil(((double)ymn - relax - mc.y0) * idy - 1e-9), 0.0);
+    const double fj1 = fmin(floor(((double)ymx + relax - mc.y0) * idy + 1e-9), (double)(mc.ny - 1));
+    if (!(fi0 <= fi1 && fj0 <= fj1)) return 0;
+    if ((fi1 - fi0 + 1.0) * (fj1 - fj0 + 1.0) > (double)kSpan) return 2;
+    i0 = (int)fi0; i1 = (int)fi1; j0 = (int)fj0; j1 = (int)fj1;
+    return 1;
+}
+
+// Rows of the clipped footprint of layer k: finished here when few (or when the row
+// buffer is full), else handed out as (segment, global row) items.
+__device__ __forceinline__ void layer_general(const Frustum &f, const DevMics &mc, const MicWork &w, DevCounters *ctr,
+                                              const TraceArgs &a, long long seg, int k, unsigned &tests,
+                                              unsigned &updates)
+{
+    HalfPlane L[9];
+    footprint_lines(f, mc, mc.z + (double)k * mc.dz, L);
+    int j0, j1;
+    if (!footprint_rows(L, mc, j0, j1)) return;
+    const int nrows = j1 - j0 + 1;
+    if (nrows > kInlineRows) {
+        const unsigned long long b = atomicAdd(&ctr->n_rows[a.gen], (unsigned long long)nrows);
+        if (b + (unsigned long long)nrows <= (unsigned long long)w.rows_cap) {
+            for (int r = 0; r < nrows; ++r) w.rows[b + r] = make_int2((int)seg, k * mc.ny + j0 + r);
+            return;
+        }
+        // no room: slots of the reservation inside the buffer are marked empty and the
+        // rows are done here
+        for (unsigned long long r = b; r < (unsigned long long)w.rows_cap; ++r) w.rows[r] = make_int2(-1, 0);
+    }
+    for (int j = j0; j <= j1; ++j) {
+        int c0, c1;
+        if (!row_cols(L, mc, j, c0, c1)) continue;
+        process_row<false>(f, mc, w, ctr, a.gen, seg, j, k, c0, c1, a.air_m, tests, updates);
+    }
+}
+
+__device__ __forceinline__ void load_dirs(const DevQueue &q, long long i, V3 *d)
+{
+    d[0] = ld3(q.dbl + D_D0 * q.cap, q.cap, i);
+    d[1] = ld3(q.dbl + D_D1 * q.cap, q.cap, i);
+    d[2] = ld3(q.dbl + D_D2 * q.cap, q.cap, i);
+}
+
+__global__ void __launch_bounds__(256, 4) k_mics3d(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mc,
+                                                  TraceArgs a, MicWork w)
+{
+    const unsigned long long s0 = gen_start(ctr, a.gen);
+    const unsigned long long n = gen_start(ctr, a.gen_end) - s0;
+    int2 *items = w.layers;
+    int2 *late = reinterpret_cast<int2 *>(w.big_list);
+    unsigned tests = 0, updates = 0;
+    for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
+        if (base + (unsigned long long)lane_id() >= n) continue;
+        const long long i = (long long)(s0 + base) + lane_id();
+        const V3 A = ld3(q.dbl + D_A * q.cap, q.cap, i);
+        V3 d[3];
+        load_dirs(q, i, d);
+        int k0, k1;
+        if (!seg_layers(M, q, i, segs.hit[i], A, d, mc, k0, k1)) continue;
+        const Cone cn = make_cone(A, d);
+        for (int k = k0; k <= k1; ++k) {
+            int i0, i1, j0, j1;
+            const int kind = layer_fast(cn, mc, k, i0, i1, j0, j1);
+            if (kind == 1) {
+                // few layers of a segment have candidates: the frustum is (re)loaded here
+                // rather than held across the layer loop
+                Frustum f;
+                load_frustum(M, q, segs, i, a.delta, f);
+                for (int j = j0; j <= j1; ++j)
+                    for (int c = i0; c <= i1; ++c) {
+                        tests++;
+                        updates += mic_apply<false>(f, mc, c, j, k, a.air_m);
+                    }
+            } else if (kind == 2) {
+                const unsigned long long b = atomicAdd(&ctr->n_layers[a.gen], 1ull);
+                if (b < (unsigned long long)w.layers_cap) {
+                    items[b] = make_int2((int)i, k);
+                } else {
+                    // the item buffer is full: this layer and all later ones of the
+                    // segment go to the fallback (at most one entry per segment)
+                    const unsigned long long e = atomicAdd(&ctr->n_late[a.gen], 1ull);
+                    late[e] = make_int2((int)i, k);
+                    break;
+                }
+            }
+        }
+    }
+    flush_mic_counters(ctr, tests, updates);
+}
+
+__global__ void __launch_bounds__(256, 3) k_mics3d_general(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
+                                                          DevMics mc, TraceArgs a, MicWork w)
+{
+    unsigned long long n = ctr->n_layers[a.gen];
+    if (n > (unsigned long long)w.layers_cap) n = (unsigned long long)w.layers_cap;
+    unsigned tests = 0, updates = 0;
+    for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
+        const unsigned long long r = base + (unsigned long long)lane_id();
+        if (r >= n) continue;
+        const int2 it = w.layers[r];
+        Frustum f;
+        load_frustum(M, q, segs, it.x, a.delta, f);
+        layer_general(f, mc, w, ctr, a, it.x, it.y, tests, updates);
+    }
+    flush_mic_counters(ctr, tests, updates);
+}
+
+__global__ void __launch_bounds__(256) k_mics3d_late(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
+                                                     DevMics mc, TraceArgs a, MicWork w)
+{
+    const unsigned long long n = ctr->n_late[a.gen];
+    const int2 *late = reinterpret_cast<const int2 *>(w.big_list);
+    unsigned tests = 0, updates = 0;
+    for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
+        const unsigned long long r = base + (unsigned long long)lane_id();
+        if (r >= n) continue;
+        const int2 it = late[r];
+        const long long i = it.x;
+        const V3 A = ld3(q.dbl + D_A * q.cap, q.cap, i);
+        V3 d[3];
+        load_dirs(q, i, d);
+        int k0, k1;
+        if (!seg_layers(M, q, i, segs.hit[i], A, d, mc, k0, k1)) continue;
+        Frustum f;
+        load_frustum(M, q, segs, i, a.delta, f);
+        const Cone cn = make_cone(A, d);
+        for (int k = max(k0, it.y); k <= k1; ++k) {
+            int i0, i1, j0, j1;
+            const int kind = layer_fast(cn, mc, k, i0, i1, j0, j1);
+            if (kind == 1) {
+                for (int j = j0; j <= j1; ++j)
+                    for (int c = i0; c <= i1; ++c) {
+                        tests++;
+                        updates += mic_apply<false>(f, mc, c, j, k, a.air_m);
+                    }
+            } else if (kind == 2) {
+                layer_general(f, mc, w, ctr, a, i, k, tests, updates);
             }
         }
     }
@@ -528,6 +795,21 @@ static hipError_t launch_mics_t(const DevMesh &m, DevQueue q, DevSegs segs, DevC
 hipError_t launch_mics(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mics,
                        const TraceArgs &a, MicWork w, WaveScratch ws, int n_cu, hipStream_t s)
 {
+    if (!a.scenarios && mics.nz > 1) {
+        if (!(mics.dz > 0.0)) return hipErrorInvalidValue;
+        if (!w.layers || w.layers_cap <= 0) return hipErrorInvalidValue;
+        k_mics3d<<<n_cu * kBlocksPerCU, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, mics, a, w);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        k_mics3d_general<<<n_cu * kBlocksPerCU, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, mics, a, w);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        k_mics3d_late<<<n_cu * 4, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        k_mic_rows<false><<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        k_mic_spans<false><<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
+        return hipGetLastError();
+    }
     if (a.scenarios) {
         if (!a.slot_mics) return hipErrorInvalidValue;
         return launch_mics_t<true>(m, q, segs, ctr, mics, a, w, ws, n_cu, s);

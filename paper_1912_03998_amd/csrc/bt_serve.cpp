@@ -244,6 +244,7 @@ void admit(bt_server *s, Session &q, int qi, Req *r)
     m.dy = r->sc.mic_dy;
     m.nx = r->sc.mic_nx;
     m.ny = r->sc.mic_ny;
+    m.nz = 1;
     m.e_strict = r->energy;
     m.e_flag = r->energy + z.grid;
     m.mask = r->mask;

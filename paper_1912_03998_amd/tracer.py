@@ -58,7 +58,7 @@ class Session:
         if self._grid != grid:
             if self.mics is not None:
                 bt.bt_mics_free(self.mics)
-            self.mics = bt.bt_mics_grid(self.ctx, *grid)
+            self.mics = bt.bt_mics_grid(self.ctx, *grid) if len(grid) == 7 else bt.bt_mics_grid3d(self.ctx, *grid)
             self._grid = grid
         else:
             bt.bt_mics_reset(self.ctx, self.mics)
@@ -89,7 +89,7 @@ class Session:
                 outs["t_out"] = torch.full((n0, depth + 1), float("nan"), dtype=torch.float64, device=dev)
         p = self.params(depth, **kw, **outs)
         mics = self.enqueue(sources, power, level, depth, grid, p)
-        n_mic = grid[5] * grid[6]
+        n_mic = grid_size(grid)
         es = np.empty(n_mic, np.float64)
         ef = np.empty(n_mic, np.float64)
         lv = np.empty(n_mic, np.float64)
@@ -122,6 +122,15 @@ class Session:
 
 
 def scene_grid(scene):
-    """(x0, y0, z, dx, dy, nx, ny) of a scene's microphone grid."""
+    """A scene's microphone grid: (x0, y0, z, dx, dy, nx, ny) when planar, else
+    (x0, y0, z0, dx, dy, dz, nx, ny, nz)."""
+    if int(getattr(scene, "mic_nz", 1)) == 1:
+        return (float(scene.mic_x0), float(scene.mic_y0), float(scene.mic_z), float(scene.mic_dx),
+                float(scene.mic_dy), int(scene.mic_nx), int(scene.mic_ny))
     return (float(scene.mic_x0), float(scene.mic_y0), float(scene.mic_z), float(scene.mic_dx), float(scene.mic_dy),
-            int(scene.mic_nx), int(scene.mic_ny))
+            float(scene.mic_dz), int(scene.mic_nx), int(scene.mic_ny), int(scene.mic_nz))
+
+
+def grid_size(grid):
+    """Microphones in a planar (7-tuple) or volumetric (9-tuple) grid."""
+    return grid[5] * grid[6] if len(grid) == 7 else grid[6] * grid[7] * grid[8]

@@ -230,6 +230,48 @@ def block_scene(seed: int = 0) -> Scene:
                  level=5, depth=6)
 
 
+def _fill_block(mb: _MeshBuilder, rng, x0, y0, x1, y1, n_buildings, taken=()):
+    """`n_buildings` extruded convex prisms in the block [x0,x1]x[y0,y1]: circumscribed
+    disks (radius U(6, 14) m) placed by dart throwing with a 1 m gap to each other and to
+    the disks in `taken`, and a 2 m setback; U{6..10} footprint vertices at sorted jittered
+    angles; height lognormal (median 20 m, sigma 0.5), walls in ceil(h/10) bands."""
+    disks = []
+    attempts = 0
+    while len(disks) < n_buildings:
+        attempts += 1
+        if attempts > 200_000:
+            raise RuntimeError("block placement did not converge")
+        r = rng.uniform(6.0, 14.0)
+        cx = rng.uniform(x0 + 2.0 + r, x1 - 2.0 - r)
+        cy = rng.uniform(y0 + 2.0 + r, y1 - 2.0 - r)
+        ok = True
+        for (qx, qy, qr) in list(taken) + disks:
+            if (cx - qx) ** 2 + (cy - qy) ** 2 < (r + qr + 1.0) ** 2:
+                ok = False
+                break
+        if ok:
+            disks.append((cx, cy, r))
+    for (cx, cy, r) in disks:
+        _random_prism(mb, rng, cx, cy, r)
+
+
+def _random_prism(mb: _MeshBuilder, rng, cx, cy, r, h=None):
+    """Convex prism on U{6..10} jittered vertices of the circle (cx, cy, r), of height `h`
+    or, when None, a lognormal one (median 20 m, sigma 0.5) drawn after the footprint."""
+    n = int(rng.integers(6, 11))
+    rot = rng.uniform(0.0, 2.0 * math.pi)
+    jit = rng.uniform(-0.35, 0.35, size=n)
+    ang = rot + 2.0 * math.pi * (np.arange(n) + 0.5 + jit) / n
+    px = cx + r * np.cos(ang)
+    py = cy + r * np.sin(ang)
+    if h is None:
+        h = float(rng.lognormal(math.log(20.0), 0.5))
+    bands = max(1, int(math.ceil(h / 10.0)))
+    wall_alpha = rng.uniform(0.05, 0.3, size=n)
+    roof_alpha = float(rng.uniform(0.05, 0.3))
+    _prism(mb, px, py, h, bands, wall_alpha, roof_alpha)
+
+
 def district_scene(seed: int = 0, n_sources: int = 64, level: int = 6, depth: int = 8,
                    tiles: int = 4, buildings_per_block: int = 50) -> Scene:
     """2 x 2 km district: 10 x 10 street grid, 5000 extruded convex-polygon buildings.
@@ -250,35 +292,7 @@ def district_scene(seed: int = 0, n_sources: int = 64, level: int = 6, depth: in
         for bi in range(10):
             x0 = -1000.0 + 200.0 * bi + 10.0
             y0 = -1000.0 + 200.0 * bj + 10.0
-            x1, y1 = x0 + 180.0, y0 + 180.0
-            disks = []
-            attempts = 0
-            while len(disks) < buildings_per_block:
-                attempts += 1
-                if attempts > 200_000:
-                    raise RuntimeError("district placement did not converge")
-                r = rng.uniform(6.0, 14.0)
-                cx = rng.uniform(x0 + 2.0 + r, x1 - 2.0 - r)
-                cy = rng.uniform(y0 + 2.0 + r, y1 - 2.0 - r)
-                ok = True
-                for (qx, qy, qr) in disks:
-                    if (cx - qx) ** 2 + (cy - qy) ** 2 < (r + qr + 1.0) ** 2:
-                        ok = False
-                        break
-                if ok:
-                    disks.append((cx, cy, r))
-            for (cx, cy, r) in disks:
-                n = int(rng.integers(6, 11))
-                rot = rng.uniform(0.0, 2.0 * math.pi)
-                jit = rng.uniform(-0.35, 0.35, size=n)
-                ang = rot + 2.0 * math.pi * (np.arange(n) + 0.5 + jit) / n
-                px = cx + r * np.cos(ang)
-                py = cy + r * np.sin(ang)
-                h = float(rng.lognormal(math.log(20.0), 0.5))
-                bands = max(1, int(math.ceil(h / 10.0)))
-                wall_alpha = rng.uniform(0.05, 0.3, size=n)
-                roof_alpha = float(rng.uniform(0.05, 0.3))
-                _prism(mb, px, py, h, bands, wall_alpha, roof_alpha)
+            _fill_block(mb, rng, x0, y0, x0 + 180.0, y0 + 180.0, buildings_per_block)
     v, t, a = mb.arrays()
     cross = rng.choice(81, size=n_sources, replace=False)
     src = np.array([[-1000.0 + 200.0 * (1 + c % 9), -1000.0 + 200.0 * (1 + c // 9), 0.5] for c in cross],
@@ -286,6 +300,54 @@ def district_scene(seed: int = 0, n_sources: int = 64, level: int = 6, depth: in
     return Scene(f"district_s{seed}", v, t, a, sources=src, power=np.ones(n_sources, np.float32),
                  mic_x0=-998.0, mic_y0=-998.0, mic_z=1.5, mic_dx=4.0, mic_dy=4.0, mic_nx=500, mic_ny=500,
                  level=level, depth=depth, tiles_x=tiles, tiles_y=tiles)
+
+
+def volumetric_scene(seed: int = 0, n_sources: int = 49, level: int = 8, depth: int = 8, n_towers: int = 10,
+                     buildings_per_block: int = 80) -> Scene:
+    """The paper's experiment shape (Section 4): a 2.5 x 1.5 km district with about ten
+    towers of 200 m and more, and microphones every 4 m in all three directions filling
+    the model's bounding box.
+
+    Streets are 20 m wide on the lines x = -1250 + 250k (k = 0..10) and y = -750 + 250l
+    (l = 0..6), leaving 60 blocks of 230 x 230 m.  `n_towers` distinct blocks get one tower
+    near their centre: a convex prism of radius U(20, 30) m and height U(200, 235) m.  Each
+    block is then filled with `buildings_per_block` buildings as in the district (same
+    footprint and height laws, so about the district's density).  The ground is a 10 m
+    grid.  Sources sit 0.5 m above the 45 interior crossings and, past those, at random
+    points of interior street centre lines.  Microphones form the 4 m grid x = -1248 + 4i,
+    y = -748 + 4j, z = 2 + 4k up to the tallest roof (625 x 375 x ceil(h_max / 4)).
+    """
+    rng = np.random.default_rng(seed)
+    mb = _MeshBuilder()
+    _ground(mb, -1250.0, -750.0, 1250.0, 750.0, 0.1, cell=10.0)
+    blocks = [(bi, bj) for bj in range(6) for bi in range(10)]
+    towers = set(int(b) for b in rng.choice(len(blocks), size=n_towers, replace=False))
+    for b, (bi, bj) in enumerate(blocks):
+        x0 = -1250.0 + 250.0 * bi + 10.0
+        y0 = -750.0 + 250.0 * bj + 10.0
+        taken = []
+        if b in towers:
+            r = rng.uniform(20.0, 30.0)
+            cx = x0 + 115.0 + rng.uniform(-40.0, 40.0)
+            cy = y0 + 115.0 + rng.uniform(-40.0, 40.0)
+            h = float(rng.uniform(200.0, 235.0))
+            _random_prism(mb, rng, cx, cy, r, h)
+            taken.append((cx, cy, r))
+        _fill_block(mb, rng, x0, y0, x0 + 230.0, y0 + 230.0, buildings_per_block, taken)
+    v, t, a = mb.arrays()
+    h_max = float(v[:, 2].max())
+    pts = [(-1250.0 + 250.0 * k, -750.0 + 250.0 * l) for l in range(1, 6) for k in range(1, 10)]
+    rng_src = np.random.default_rng(seed + 1)
+    while len(pts) < n_sources:
+        if rng_src.uniform() < 0.5:   # on a line x = const, between two crossings
+            pts.append((-1250.0 + 250.0 * int(rng_src.integers(1, 10)), rng_src.uniform(-750.0, 750.0)))
+        else:
+            pts.append((rng_src.uniform(-1250.0, 1250.0), -750.0 + 250.0 * int(rng_src.integers(1, 6))))
+    src = np.array([[x, y, 0.5] for (x, y) in pts[:n_sources]], np.float32).reshape(-1, 3)
+    nz = int(math.ceil(h_max / 4.0))
+    return Scene(f"volumetric_s{seed}", v, t, a, sources=src, power=np.ones(n_sources, np.float32),
+                 mic_x0=-1248.0, mic_y0=-748.0, mic_z=2.0, mic_dx=4.0, mic_dy=4.0, mic_nx=625, mic_ny=375,
+                 level=level, depth=depth, tiles_x=5, tiles_y=3, mic_dz=4.0, mic_nz=nz)
 
 
 # ----------------------------------------------------------------------------------------
