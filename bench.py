@@ -170,6 +170,102 @@ def serve_bench(sess, rates, n_of_rate, warm_frac=0.1, seed=0, saturation=400):
     return res
 
 
+def volumetric_bench(steps, warmup, chunk=7, level=8, oracle_sample=True):
+    """The paper's experiment shape: the tall 2.5 x 1.5 km district (towers of 200 m and
+    more), 49 street sources x 20 * 4**level beams, depth 8, microphones every 4 m filling
+    the bounding box.  A step traces all sources, `chunk` sources per beam set (the queue
+    holds every generation of a chunk), into one volumetric grid, then the levels."""
+    import numpy as np
+    import torch
+    from paper_1912_03998_amd import bt
+    from paper_1912_03998_amd.tracer import Session, scene_grid
+    from scenegen import volumetric_scene
+
+    t0 = time.perf_counter()
+    scene = volumetric_scene(0, level=level)
+    print(f"[bench] {scene.name}: {scene.n_tri} triangles, {scene.n_src} x {20 * 4 ** level} beams, depth "
+          f"{scene.depth}, {scene.mic_nx} x {scene.mic_ny} x {scene.mic_nz} = {scene.n_mic} mics", file=sys.stderr,
+          flush=True)
+    sess = Session.from_scene(scene)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    ctx, mesh, stream = sess.ctx, sess.mesh, sess.stream
+    mics = sess._mics(scene_grid(scene))
+    params = sess.params(scene.depth)
+    with torch.cuda.stream(stream):
+        level_out = torch.empty(scene.n_mic, dtype=torch.float64, device="cuda")
+    src = np.ascontiguousarray(scene.sources, np.float32)
+    pw = np.ascontiguousarray(scene.power, np.float32)
+    groups = [slice(k, min(k + chunk, scene.n_src)) for k in range(0, scene.n_src, chunk)]
+    totals = {"segments": 0, "mic_updates": 0, "mic_tests": 0, "mic_layer_visits": 0, "mic_general": 0,
+              "mic_fallback": 0}
+
+    def step(ev=None, count=False):
+        bt.bt_mics_reset(ctx, mics)
+        for gi, g in enumerate(groups):
+            sess.beams = bt.bt_emit_beams(ctx, src[g], pw[g], scene.level, sess.beams)
+            if ev is not None:
+                ev[gi][0].record(stream)
+            for _ in range(scene.depth + 1):
+                bt.bt_trace(ctx, mesh, sess.beams, params)
+            if ev is not None:
+                ev[gi][1].record(stream)
+            bt.bt_accumulate_mics(ctx, mesh, sess.beams, params, mics)
+            if ev is not None:
+                ev[gi][2].record(stream)
+            if count:
+                st = bt.bt_beams_stats(ctx, sess.beams)
+                for k in totals:
+                    totals[k] += st[k]
+        bt.bt_levels(ctx, mics, None, None, level_out)
+
+    step(count=True)
+    for _ in range(max(warmup - 1, 0)):
+        step()
+    events = [[[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in groups] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    trace_ms = sum(e[0].elapsed_time(e[1]) for ev in events for e in ev) / steps
+    mic_ms = sum(e[1].elapsed_time(e[2]) for ev in events for e in ev) / steps
+    e = level_out.cpu().numpy()
+    out = {
+        "workload": f"{scene.name}: {scene.n_tri} triangles, {scene.n_src} sources x {20 * 4 ** level} beams "
+                    f"(icosphere level {level}), depth {scene.depth}, {scene.mic_nx} x {scene.mic_ny} x "
+                    f"{scene.mic_nz} = {scene.n_mic} microphones (4 m lattice filling the bounding box), "
+                    f"{len(groups)} beam sets of <= {chunk} sources",
+        "ms_per_step": round(elapsed * 1000.0 / steps, 2),
+        "beam_segments_per_s": totals["segments"] * steps / elapsed,
+        "mic_updates_per_s": totals["mic_updates"] * steps / elapsed,
+        "segments_per_step": totals["segments"], "mic_updates_per_step": totals["mic_updates"],
+        "mic_tests_per_step": totals["mic_tests"],
+        "mic_layer_visits_per_step": totals["mic_layer_visits"],
+        "mic_general_items_per_step": totals["mic_general"], "mic_general_in_place_per_step": totals["mic_fallback"],
+        "kernel_ms_per_step": {"trace": round(trace_ms, 2), "mics": round(mic_ms, 2)},
+        "mic_stage_effective_GBps": round(B_MIC * totals["mic_updates"] / (mic_ms * 1e-3) / 1e9, 1),
+        "mics_reached": int(np.isfinite(e).sum()),
+        "setup_s": round(setup_s, 2),
+    }
+    sess.close()
+    if oracle_sample:
+        # the oracle on one whole source of the same workload (bounded CPU time)
+        from oracle import oracle as O
+        one = scene.with_(sources=scene.sources[20:21], power=scene.power[20:21])
+        threads = O.default_threads()
+        print("[bench] volumetric cpu baseline (oracle, one source) ...", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        r = O.trace(one, keep_paths=False, n_threads=threads)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": r.counters["segments"] / dt, "unit": "beam-segments/s", "cores": threads,
+                               "kind": "oracle", "mic_updates_per_s": r.counters["mic_updates"] / dt,
+                               "sample": f"one source (index 20) of the workload: {r.counters['segments']} "
+                                         f"segments, {r.counters['mic_updates']} mic updates in {dt:.2f} s"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +278,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-full", action="store_true",
                     help="serving at the full stream lengths (200 warm-up + 2000 requests per rate)")
+    ap.add_argument("--no-volumetric", action="store_true", help="skip the volumetric (tall district) measurement")
+    ap.add_argument("--vol-chunk", type=int, default=7, help="sources per beam set in the volumetric measurement")
+    ap.add_argument("--vol-level", type=int, default=8, help="icosphere level of the volumetric measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -317,6 +416,9 @@ def main():
             n_of_rate, warm = (lambda r: int(min(2200, max(300, 4 * r)))), 0.1
         out["served"] = serve_bench(sess, [50, 200, 800], n_of_rate, warm)
     sess.close()
+    if args.config == 2 and not args.no_volumetric:
+        out["volumetric"] = volumetric_bench(max(2, min(args.steps, 5)), max(1, min(args.warmup, 2)), args.vol_chunk,
+                                             args.vol_level, oracle_sample=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scene)

@@ -81,6 +81,9 @@ typedef struct {
     int64_t tri_tests;                   /* ray/triangle tests */
     int64_t mic_tests;                   /* (segment, microphone) candidates tested */
     int64_t mic_updates;                 /* (segment, microphone) pairs accumulated */
+    int64_t mic_layer_visits;            /* volumetric grids: (segment, layer) pairs examined */
+    int64_t mic_general;                 /* volumetric grids: of which on the clipped-footprint path */
+    int64_t mic_fallback;                /* volumetric grids: of which done in place (item buffer full) */
 } bt_stats;
 
 /* Defaults: max_depth 3, t_min 1e-3, edge_delta 1e-5, air_m 0, e_min 0, no outputs. */

@@ -43,7 +43,8 @@ class bt_stats(C.Structure):
     _fields_ = [("generations", C.c_int32), ("count", C.c_int64 * (BT_MAX_DEPTH + 1)),
                 ("flagged", C.c_int64 * (BT_MAX_DEPTH + 1)), ("power", C.c_double * (BT_MAX_DEPTH + 1)),
                 ("segments", C.c_int64), ("node_visits", C.c_int64), ("tri_tests", C.c_int64),
-                ("mic_tests", C.c_int64), ("mic_updates", C.c_int64)]
+                ("mic_tests", C.c_int64), ("mic_updates", C.c_int64), ("mic_layer_visits", C.c_int64),
+                ("mic_general", C.c_int64), ("mic_fallback", C.c_int64)]
 
 
 class bt_request(C.Structure):
@@ -230,7 +231,8 @@ def bt_beams_stats(ctx, beams) -> dict:
     g = s.generations
     return {"generations": g, "count": np.array(s.count[:g], np.int64), "flagged": np.array(s.flagged[:g], np.int64),
             "power": np.array(s.power[:g], np.float64), "segments": s.segments, "node_visits": s.node_visits,
-            "tri_tests": s.tri_tests, "mic_tests": s.mic_tests, "mic_updates": s.mic_updates}
+            "tri_tests": s.tri_tests, "mic_tests": s.mic_tests, "mic_updates": s.mic_updates,
+            "mic_layer_visits": s.mic_layer_visits, "mic_general": s.mic_general, "mic_fallback": s.mic_fallback}
 
 
 def bt_trace(ctx, mesh, beams, params, want_next=False):

@@ -666,11 +666,11 @@ void beams_release(bt_beams *b)
 }
 
 // (segment, layer) item buffer of the volumetric microphone pass, sized from the
-// generation-0 count; a full buffer sends the remaining layers of a segment to the
-// one-lane-per-segment fallback.
+// generation-0 count: 4 per initial beam covers the tall district workload (1.2 per beam)
+// with room; items past a full buffer are done in place by the lane that found them.
 static bt_status reserve_layers(bt_ctx *ctx, bt_beams *b)
 {
-    long long want = std::max(b->n0, 1ll << 20);
+    long long want = std::max(4 * b->n0, 1ll << 20);
     if (const char *env = std::getenv("BT_MIC_LAYER_CAPACITY")) {  // testing the full-buffer path
         long long v = std::atoll(env);
         if (v > 0) want = v;
@@ -901,6 +901,11 @@ extern "C" bt_status bt_beams_stats(bt_ctx *ctx, const bt_beams *b, bt_stats *ou
     out->tri_tests = (int64_t)h.tri_tests;
     out->mic_tests = (int64_t)h.mic_tests;
     out->mic_updates = (int64_t)h.mic_updates;
+    out->mic_layer_visits = (int64_t)h.mic_layer_visits;
+    for (int g = 0; g <= BT_MAX_DEPTH; ++g) {
+        out->mic_general += (int64_t)h.n_layers[g];
+        if ((long long)h.n_layers[g] > b->layers_cap) out->mic_fallback += (int64_t)h.n_layers[g] - b->layers_cap;
+    }
     return BT_OK;
 }
 

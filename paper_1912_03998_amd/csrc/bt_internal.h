@@ -94,8 +94,8 @@ struct DevCounters {
     unsigned long long n_rows[BT_MAX_DEPTH + 2];     // (segment, row) work items requested
     unsigned long long n_spans[BT_MAX_DEPTH + 2];    // (segment, row, columns) work items
     unsigned long long n_layers[BT_MAX_DEPTH + 2];   // volumetric: (segment, layer) items requested
-    unsigned long long n_late[BT_MAX_DEPTH + 2];     // volumetric: segments past a full item buffer
     unsigned long long node_visits, tri_tests, mic_tests, mic_updates;
+    unsigned long long mic_layer_visits;             // volumetric: (segment, layer) pairs examined
 };
 
 // Microphone (i, j, k) sits at (x0 + i dx, y0 + j dy, z + k dz) and has index
@@ -121,8 +121,7 @@ struct MicWork {
     int4 *spans;
     long long spans_cap;
     int *general;      // segments for the general footprint path; capacity: the queue's
-    int *big_list;     // capacity: the queue capacity; volumetric grids use the 2 x capacity
-                       // ints from here as (segment, first layer) fallback pairs
+    int *big_list;     // capacity: the queue capacity
     int2 *layers;      // volumetric grids: (segment, layer) items of the general path
     long long layers_cap;
 };

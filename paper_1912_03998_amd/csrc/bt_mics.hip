@@ -516,14 +516,18 @@ __global__ void __launch_bounds__(256) k_mics_big(DevMesh M, DevQueue q, DevSegs
 
 // ---------------------------------------------------------------------------------------
 // Volumetric grids
-//   k_mics3d:         one lane per segment: the layers its frustum can reach, the planar
-//                     fast path on each; layers that need the clipped footprint become
-//                     (segment, layer) items
+//   k_mics3d:         one wave per 64 segments: the layers each frustum can reach, then
+//                     the (segment, layer) pairs spread evenly over the lanes for the
+//                     planar fast path, then the candidate microphones of the pairs'
+//                     lattice boxes spread evenly over the lanes again, each lane reading
+//                     its frustum from the wave's LDS staging.  Pairs that need the
+//                     clipped footprint become (segment, layer) items (done in place when
+//                     the item buffer is full).
 //   k_mics3d_general: one lane per (segment, layer) item: rows of the clipped footprint,
 //                     finished here when few, else (segment, global row) items for
 //                     k_mic_rows (done here when the row buffer is full)
-//   k_mics3d_late:    segments whose items did not fit the item buffer: every layer from
-//                     the first one not listed, both paths in one lane (overflow fallback)
+// A segment spans from one to every layer and a layer box from none to kSpan candidates,
+// so a lane per segment would leave most lanes idle; the two even spreads keep them busy.
 // ---------------------------------------------------------------------------------------
 
 // Layers [k0, k1] a segment's frustum can reach, from its z-extent widened for rounding.
@@ -574,69 +578,6 @@ __device__ __forceinline__ bool seg_layers(const DevMesh &M, const DevQueue &q, 
     return true;
 }
 
-// What the per-layer fast path needs of a segment: the apex and edge directions, x and
-// y in FP32 (they only bound the candidate lattice), z in FP64 (their signs decide).
-struct Cone {
-    double az;
-    double dz[3];
-    float ax, ay;
-    float dx[3], dy[3];
-};
-
-__device__ __forceinline__ Cone make_cone(V3 A, const V3 *d)
-{
-    Cone c;
-    c.az = A.z;
-    c.ax = (float)A.x;
-    c.ay = (float)A.y;
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-        c.dz[e] = d[e].z;
-        c.dx[e] = (float)d[e].x;
-        c.dy[e] = (float)d[e].y;
-    }
-    return c;
-}
-
-// The planar fast path on layer k: 0 = no microphone can be inside, 1 = the candidates
-// are the lattice box [i0, i1] x [j0, j1] (at most kSpan points), 2 = the clipped
-// footprint is needed.
-__device__ __forceinline__ int layer_fast(const Cone &cn, const DevMics &mc, int k, int &i0, int &i1, int &j0,
-                                          int &j1)
-{
-    const double zr = (mc.z + (double)k * mc.dz) - cn.az;
-    bool proper = zr != 0.0;
-    bool away = zr > 1e-6 || zr < -1e-6;
-    const float zrf = (float)zr;
-    float xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
-    float mag = fmaxf(fabsf(cn.ax), fabsf(cn.ay));
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-        proper = proper && (zr > 0.0 ? cn.dz[e] > 0.0 : cn.dz[e] < 0.0);
-        away = away && (zr > 0.0 ? cn.dz[e] <= 0.0 : cn.dz[e] >= 0.0);
-        const float s = zrf / (float)cn.dz[e];
-        proper = proper && isfinite(s);
-        const float sx = s * cn.dx[e], sy = s * cn.dy[e];
-        const float px = cn.ax + sx, py = cn.ay + sy;
-        xmn = fminf(xmn, px); xmx = fmaxf(xmx, px);
-        ymn = fminf(ymn, py); ymx = fmaxf(ymx, py);
-        mag = fmaxf(mag, fmaxf(fabsf(sx), fabsf(sy)));
-    }
-    if (away) return 0;
-    if (!proper) return 2;
-    // as in the planar fast path: FP32 crossings widened by 1e-5 of their magnitude
-    const double relax = 1e-6 + 1e-5 * (double)mag;
-    const double idx = 1.0 / mc.dx, idy = 1.0 / mc.dy;
-    const double fi0 = fmax(ceil(((double)xmn - relax - mc.x0) * idx - 1e-9), 0.0);
-    const double fi1 = fmin(floor(((double)xmx + relax - mc.x0) * idx + 1e-9), (double)(mc.nx - 1));
-    const double fj0 = fmax(ceil(((double)ymn - relax - mc.y0) * idy - 1e-9), 0.0);
-    const double fj1 = fmin(floor(((double)ymx + relax - mc.y0) * idy + 1e-9), (double)(mc.ny - 1));
-    if (!(fi0 <= fi1 && fj0 <= fj1)) return 0;
-    if ((fi1 - fi0 + 1.0) * (fj1 - fj0 + 1.0) > (double)kSpan) return 2;
-    i0 = (int)fi0; i1 = (int)fi1; j0 = (int)fj0; j1 = (int)fj1;
-    return 1;
-}
-
 // Rows of the clipped footprint of layer k: finished here when few (or when the row
 // buffer is full), else handed out as (segment, global row) items.
 __device__ __forceinline__ void layer_general(const Frustum &f, const DevMics &mc, const MicWork &w, DevCounters *ctr,
@@ -665,58 +606,286 @@ __device__ __forceinline__ void layer_general(const Frustum &f, const DevMics &m
     }
 }
 
-__device__ __forceinline__ void load_dirs(const DevQueue &q, long long i, V3 *d)
+// LDS staging of one wave of k_mics3d (structure of arrays: lanes reading the same
+// segment share an address, lanes reading different ones mostly different banks).  A
+// batch is kVolSeg segments (slots): half a wave, so that a CU holds 16 waves' staging.
+constexpr int kVolF = 24;  // frustum doubles: A, n0, n1, n2, near N and P, far N and P
+constexpr int kVolSeg = 32;
+struct VolStage {
+    double f[kVolF][kVolSeg];   // caps with their keep sides folded into N: near
+                                // N.(m - P) > 0, far N.(m - P) >= 0
+    double az[kVolSeg];         // apex height
+    float ax[kVolSeg], ay[kVolSeg];  // apex x, y (FP32: the fast path only bounds candidates)
+    float sx[3][kVolSeg], sy[3][kVolSeg];  // edge slopes dx/dz, dy/dz
+    float K[kVolSeg];
+    int bits[kVolSeg];          // 1 has near cap, 2 has far cap, 4 flagged, 8-10 dz_e > 0,
+                                // 16-18 dz_e < 0
+    int k0[kVolSeg];
+    int prefix[kVolSeg + 1];    // exclusive scan of the batch's pair counts
+    int cprefix[65];            // exclusive scan of the pair chunk's candidate counts
+    int4 box[64];               // pair chunk: (slot | layer << 6, i0, j0, columns)
+};
+
+__device__ __forceinline__ int wave_excl_scan(int v, int &total)
 {
-    d[0] = ld3(q.dbl + D_D0 * q.cap, q.cap, i);
-    d[1] = ld3(q.dbl + D_D1 * q.cap, q.cap, i);
-    d[2] = ld3(q.dbl + D_D2 * q.cap, q.cap, i);
+    const int lane = lane_id();
+    int incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += u;
+    }
+    total = __shfl(incl, 63, 64);
+    return incl - v;
 }
 
-__global__ void __launch_bounds__(256, 4) k_mics3d(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mc,
-                                                  TraceArgs a, MicWork w)
+// Largest l in [0, 2^bits - 1] with pre[l] <= x (pre nondecreasing, pre[0] = 0 <= x).
+template <int kBits>
+__device__ __forceinline__ int owner_of(const int *pre, int x)
 {
+    int lo = 0, hi = (1 << kBits) - 1;
+#pragma unroll
+    for (int it = 0; it < kBits; ++it) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void stage_frustum(VolStage &st, int l, const Frustum &f)
+{
+    const double v[kVolF] = {f.A.x, f.A.y, f.A.z,
+                             f.n[0].x, f.n[0].y, f.n[0].z, f.n[1].x, f.n[1].y, f.n[1].z, f.n[2].x, f.n[2].y, f.n[2].z,
+                             f.near_sign * f.Nn.x, f.near_sign * f.Nn.y, f.near_sign * f.Nn.z, f.Pn.x, f.Pn.y, f.Pn.z,
+                             -f.far_sign * f.Nf.x, -f.far_sign * f.Nf.y, -f.far_sign * f.Nf.z, f.Pf.x, f.Pf.y, f.Pf.z};
+#pragma unroll
+    for (int c = 0; c < kVolF; ++c) st.f[c][l] = v[c];
+}
+
+// The staged frustum of slot l, as mic_apply takes it (cap signs folded into the
+// normals: near_sign = 1, far_sign = -1; the same products and sums as load_frustum's).
+__device__ __forceinline__ void unstage_frustum(const VolStage &st, int l, double delta, Frustum &f)
+{
+    const double d2 = delta * delta;
+    f.A = {st.f[0][l], st.f[1][l], st.f[2][l]};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        f.n[k] = {st.f[3 + 3 * k][l], st.f[4 + 3 * k][l], st.f[5 + 3 * k][l]};
+        f.amb2[k] = d2 * dot(f.n[k], f.n[k]);
+    }
+    const int bits = st.bits[l];
+    f.has_near = (bits & 1) != 0;
+    f.has_far = (bits & 2) != 0;
+    f.flag = (bits & 4) ? 1 : 0;
+    f.K = st.K[l];
+    f.Nn = {st.f[12][l], st.f[13][l], st.f[14][l]};
+    f.Pn = {st.f[15][l], st.f[16][l], st.f[17][l]};
+    f.near_sign = 1.0;
+    f.amb2_near = d2 * dot(f.Nn, f.Nn);
+    f.Nf = {st.f[18][l], st.f[19][l], st.f[20][l]};
+    f.Pf = {st.f[21][l], st.f[22][l], st.f[23][l]};
+    f.far_sign = -1.0;
+    f.amb2_far = d2 * dot(f.Nf, f.Nf);
+}
+
+// Largest lattice box of a layer taken as candidates directly; larger footprints take the
+// clipped-footprint path, whose rows bound the candidates tightly.
+constexpr int kBox3 = 32;
+
+// The planar fast path on layer k for staged segment l: 0 = no microphone can be inside,
+// 1 = the candidates are the lattice box [i0, i1] x [j0, j1] (at most kBox3 points),
+// 2 = the clipped footprint is needed.
+__device__ __forceinline__ int layer_fast(const VolStage &st, int l, const DevMics &mc, int k, int &i0, int &i1,
+                                          int &j0, int &j1)
+{
+    const double zr = (mc.z + (double)k * mc.dz) - st.az[l];
+    const int bits = st.bits[l];
+    const int pos = (bits >> 8) & 7, neg = (bits >> 16) & 7;
+    const bool away = (zr > 1e-6 && pos == 0) || (zr < -1e-6 && neg == 0);
+    if (away) return 0;
+    // all three edge rays cross the layer ahead of the apex: the frustum meets it inside
+    // the triangle of the crossing points (the caps only cut it down)
+    const bool proper = zr > 0.0 ? pos == 7 : (zr < 0.0 && neg == 7);
+    if (!proper) return 2;
+    // crossings in FP32 from the slopes: each coordinate within 6 x 2^-24 of `mag` (the
+    // largest magnitude involved) of its exact value; the box is widened by 1e-5 mag and
+    // the exact FP64 membership test decides every candidate
+    const float zrf = (float)zr, axf = st.ax[l], ayf = st.ay[l];
+    float xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
+    float mag = fmaxf(fabsf(axf), fabsf(ayf));
+    bool finite = true;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const float sx = zrf * st.sx[e][l], sy = zrf * st.sy[e][l];
+        const float px = axf + sx, py = ayf + sy;
+        finite = finite && isfinite(px) && isfinite(py);  // FP32 overflow: the clipped footprint decides
+        xmn = fminf(xmn, px); xmx = fmaxf(xmx, px);
+        ymn = fminf(ymn, py); ymx = fmaxf(ymx, py);
+        mag = fmaxf(mag, fmaxf(fabsf(sx), fabsf(sy)));
+    }
+    if (!finite) return 2;
+    const double relax = 1e-6 + 1e-5 * (double)mag;
+    const double idx = 1.0 / mc.dx, idy = 1.0 / mc.dy;
+    const double fi0 = fmax(ceil(((double)xmn - relax - mc.x0) * idx - 1e-9), 0.0);
+    const double fi1 = fmin(floor(((double)xmx + relax - mc.x0) * idx + 1e-9), (double)(mc.nx - 1));
+    const double fj0 = fmax(ceil(((double)ymn - relax - mc.y0) * idy - 1e-9), 0.0);
+    const double fj1 = fmin(floor(((double)ymx + relax - mc.y0) * idy + 1e-9), (double)(mc.ny - 1));
+    if (!(fi0 <= fi1 && fj0 <= fj1)) return 0;
+    if ((fi1 - fi0 + 1.0) * (fj1 - fj0 + 1.0) > (double)kBox3) return 2;
+    i0 = (int)fi0; i1 = (int)fi1; j0 = (int)fj0; j1 = (int)fj1;
+    return 1;
+}
+
+// mic_apply for staged slot l, reading the staged frustum lazily: the side planes first
+// (most candidates fail one of them), then the caps; the ambiguity distances only for
+// microphones inside.  Same products, sums and decisions as mic_apply (for a microphone
+// inside, no plane test is negative, so only `near_any` decides ambiguity).
+__device__ __forceinline__ int mic_apply_staged(const VolStage &st, int l, const DevMics &mc, int i, int j, int k,
+                                                double delta, double air_m)
+{
+    const V3 m = {mc.x0 + (double)i * mc.dx, mc.y0 + (double)j * mc.dy, mc.z + (double)k * mc.dz};
+    const V3 A = {st.f[0][l], st.f[1][l], st.f[2][l]};
+    const V3 r = m - A;
+    double sd[3];
+    V3 n[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        n[e] = {st.f[3 + 3 * e][l], st.f[4 + 3 * e][l], st.f[5 + 3 * e][l]};
+        const double s = dot(n[e], r);
+        if (!(s > 0.0 || (s == 0.0 && lex_positive(n[e])))) return 0;
+        sd[e] = s;
+    }
+    const int bits = st.bits[l];
+    double sn = 0.0, sf = 0.0;
+    V3 Nn = {0.0, 0.0, 0.0}, Nf = {0.0, 0.0, 0.0};
+    if (bits & 1) {
+        Nn = {st.f[12][l], st.f[13][l], st.f[14][l]};
+        sn = dot(Nn, m - V3{st.f[15][l], st.f[16][l], st.f[17][l]});
+        if (!(sn > 0.0)) return 0;
+    }
+    if (bits & 2) {
+        Nf = {st.f[18][l], st.f[19][l], st.f[20][l]};
+        sf = dot(Nf, m - V3{st.f[21][l], st.f[22][l], st.f[23][l]});
+        if (!(sf >= 0.0)) return 0;
+    }
+    const double d2 = delta * delta;
+    bool near_any = false;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) near_any = near_any || sd[e] * sd[e] < d2 * dot(n[e], n[e]);
+    if (bits & 1) near_any = near_any || sn * sn < d2 * dot(Nn, Nn);
+    if (bits & 2) near_any = near_any || sf * sf < d2 * dot(Nf, Nf);
+    const long long idx = ((long long)k * mc.ny + j) * mc.nx + i;
+    const double dd = dot(r, r);
+    float e = st.K[l] / (float)dd;
+    if (air_m > 0.0) e *= expf(-(float)(air_m * sqrt(dd)));
+    atomicAdd(((bits & 4) || near_any) ? &mc.e_flag[idx] : &mc.e_strict[idx], (double)e);
+    return 1;
+}
+
+// One wave per block (the block's LDS is its staging), 4 waves per SIMD: at most 128 VGPRs.
+__global__ void __launch_bounds__(64, 4) k_mics3d(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
+                                                   DevMics mc, TraceArgs a, MicWork w)
+{
+    __shared__ VolStage st;
     const unsigned long long s0 = gen_start(ctr, a.gen);
     const unsigned long long n = gen_start(ctr, a.gen_end) - s0;
-    int2 *items = w.layers;
-    int2 *late = reinterpret_cast<int2 *>(w.big_list);
-    unsigned tests = 0, updates = 0;
-    for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
-        if (base + (unsigned long long)lane_id() >= n) continue;
-        const long long i = (long long)(s0 + base) + lane_id();
-        const V3 A = ld3(q.dbl + D_A * q.cap, q.cap, i);
-        V3 d[3];
-        load_dirs(q, i, d);
-        int k0, k1;
-        if (!seg_layers(M, q, i, segs.hit[i], A, d, mc, k0, k1)) continue;
-        const Cone cn = make_cone(A, d);
-        for (int k = k0; k <= k1; ++k) {
-            int i0, i1, j0, j1;
-            const int kind = layer_fast(cn, mc, k, i0, i1, j0, j1);
-            if (kind == 1) {
-                // few layers of a segment have candidates: the frustum is (re)loaded here
-                // rather than held across the layer loop
-                Frustum f;
+    const int lane = lane_id();
+    unsigned tests = 0, updates = 0, visits = 0;
+    for (unsigned long long base = (unsigned long long)blockIdx.x * kVolSeg; base < n;
+         base += (unsigned long long)gridDim.x * kVolSeg) {
+        // stage the batch's segments (lanes 0..kVolSeg-1) and count their layers
+        const long long i = (long long)(s0 + base) + lane;
+        int cnt = 0, k0 = 0;
+        if (lane < kVolSeg && base + (unsigned long long)lane < n) {
+            const V3 A = ld3(q.dbl + D_A * q.cap, q.cap, i);
+            V3 d[3];
+            d[0] = ld3(q.dbl + D_D0 * q.cap, q.cap, i);
+            d[1] = ld3(q.dbl + D_D1 * q.cap, q.cap, i);
+            d[2] = ld3(q.dbl + D_D2 * q.cap, q.cap, i);
+            int k1;
+            if (seg_layers(M, q, i, segs.hit[i], A, d, mc, k0, k1)) {
+                cnt = k1 - k0 + 1;
+                Frustum f{};  // caps the segment lacks are staged as zeros
                 load_frustum(M, q, segs, i, a.delta, f);
-                for (int j = j0; j <= j1; ++j)
-                    for (int c = i0; c <= i1; ++c) {
-                        tests++;
-                        updates += mic_apply<false>(f, mc, c, j, k, a.air_m);
-                    }
-            } else if (kind == 2) {
-                const unsigned long long b = atomicAdd(&ctr->n_layers[a.gen], 1ull);
-                if (b < (unsigned long long)w.layers_cap) {
-                    items[b] = make_int2((int)i, k);
-                } else {
-                    // the item buffer is full: this layer and all later ones of the
-                    // segment go to the fallback (at most one entry per segment)
-                    const unsigned long long e = atomicAdd(&ctr->n_late[a.gen], 1ull);
-                    late[e] = make_int2((int)i, k);
-                    break;
+                stage_frustum(st, lane, f);
+                int bits = (f.has_near ? 1 : 0) | (f.has_far ? 2 : 0) | (f.flag ? 4 : 0);
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    bits |= (d[e].z > 0.0 ? 256 : 0) << e;
+                    bits |= (d[e].z < 0.0 ? 65536 : 0) << e;
+                    st.sx[e][lane] = (float)(d[e].x / d[e].z);
+                    st.sy[e][lane] = (float)(d[e].y / d[e].z);
                 }
+                st.bits[lane] = bits;
+                st.K[lane] = f.K;
+                st.az[lane] = A.z;
+                st.ax[lane] = (float)A.x;
+                st.ay[lane] = (float)A.y;
             }
         }
+        visits += (unsigned)cnt;
+        int total;
+        const int pre = wave_excl_scan(cnt, total);
+        if (lane < kVolSeg) {
+            st.prefix[lane] = pre;
+            st.k0[lane] = k0;
+        }
+        if (lane == 0) st.prefix[kVolSeg] = total;
+        __syncthreads();
+        // (segment, layer) pairs, 64 at a time
+        for (int pb = 0; pb < total; pb += 64) {
+            const int p = pb + lane;
+            int kind = 0, slot = 0, k = 0, i0 = 0, i1 = -1, j0 = 0, j1 = -1;
+            if (p < total) {
+                slot = owner_of<5>(st.prefix, p);
+                k = st.k0[slot] + (p - st.prefix[slot]);
+                kind = layer_fast(st, slot, mc, k, i0, i1, j0, j1);
+            }
+            // clipped-footprint pairs become items (wave-aggregated reservation)
+            const bool gen_item = kind == 2;
+            const unsigned long long gm = __ballot(gen_item);
+            unsigned long long gb = 0;
+            if (lane == 0 && gm) gb = atomicAdd(&ctr->n_layers[a.gen], (unsigned long long)__popcll(gm));
+            gb = __shfl(gb, 0, 64);
+            if (gen_item) {
+                const unsigned long long e = gb + (unsigned long long)__popcll(gm & ((1ull << lane) - 1ull));
+                const long long seg = (long long)(s0 + base) + slot;
+                if (e < (unsigned long long)w.layers_cap) {
+                    w.layers[e] = make_int2((int)seg, k);
+                } else {
+                    Frustum f;  // the item buffer is full: done here
+                    unstage_frustum(st, slot, a.delta, f);
+                    layer_general(f, mc, w, ctr, a, seg, k, tests, updates);
+                }
+            }
+            // candidates of the lattice boxes, 64 at a time
+            const int nc = kind == 1 ? (i1 - i0 + 1) * (j1 - j0 + 1) : 0;
+            int ctotal;
+            const int cpre = wave_excl_scan(nc, ctotal);
+            st.cprefix[lane] = cpre;
+            st.box[lane] = make_int4(slot | (k << 6), i0, j0, i1 - i0 + 1);
+            if (lane == 0) st.cprefix[64] = ctotal;
+            __syncthreads();
+            for (int cb = 0; cb < ctotal; cb += 64) {
+                const int c = cb + lane;
+                if (c < ctotal) {
+                    const int pl = owner_of<6>(st.cprefix, c);
+                    const int o = c - st.cprefix[pl];
+                    const int4 bx = st.box[pl];
+                    const int row = o / bx.w;
+                    tests++;
+                    updates += mic_apply_staged(st, bx.x & 63, mc, bx.y + (o - row * bx.w), bx.z + row, bx.x >> 6,
+                                                a.delta, a.air_m);
+                }
+            }
+            __syncthreads();
+        }
+        __syncthreads();
     }
     flush_mic_counters(ctr, tests, updates);
+    const unsigned long long sv = wave_sum_u64(visits);
+    if (lane == 0 && sv) atomicAdd(&ctr->mic_layer_visits, sv);
 }
 
 __global__ void __launch_bounds__(256, 3) k_mics3d_general(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
@@ -732,42 +901,6 @@ __global__ void __launch_bounds__(256, 3) k_mics3d_general(DevMesh M, DevQueue q
         Frustum f;
         load_frustum(M, q, segs, it.x, a.delta, f);
         layer_general(f, mc, w, ctr, a, it.x, it.y, tests, updates);
-    }
-    flush_mic_counters(ctr, tests, updates);
-}
-
-__global__ void __launch_bounds__(256) k_mics3d_late(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
-                                                     DevMics mc, TraceArgs a, MicWork w)
-{
-    const unsigned long long n = ctr->n_late[a.gen];
-    const int2 *late = reinterpret_cast<const int2 *>(w.big_list);
-    unsigned tests = 0, updates = 0;
-    for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
-        const unsigned long long r = base + (unsigned long long)lane_id();
-        if (r >= n) continue;
-        const int2 it = late[r];
-        const long long i = it.x;
-        const V3 A = ld3(q.dbl + D_A * q.cap, q.cap, i);
-        V3 d[3];
-        load_dirs(q, i, d);
-        int k0, k1;
-        if (!seg_layers(M, q, i, segs.hit[i], A, d, mc, k0, k1)) continue;
-        Frustum f;
-        load_frustum(M, q, segs, i, a.delta, f);
-        const Cone cn = make_cone(A, d);
-        for (int k = max(k0, it.y); k <= k1; ++k) {
-            int i0, i1, j0, j1;
-            const int kind = layer_fast(cn, mc, k, i0, i1, j0, j1);
-            if (kind == 1) {
-                for (int j = j0; j <= j1; ++j)
-                    for (int c = i0; c <= i1; ++c) {
-                        tests++;
-                        updates += mic_apply<false>(f, mc, c, j, k, a.air_m);
-                    }
-            } else if (kind == 2) {
-                layer_general(f, mc, w, ctr, a, i, k, tests, updates);
-            }
-        }
     }
     flush_mic_counters(ctr, tests, updates);
 }
@@ -798,12 +931,11 @@ hipError_t launch_mics(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *
     if (!a.scenarios && mics.nz > 1) {
         if (!(mics.dz > 0.0)) return hipErrorInvalidValue;
         if (!w.layers || w.layers_cap <= 0) return hipErrorInvalidValue;
-        k_mics3d<<<n_cu * kBlocksPerCU, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, mics, a, w);
+        // one wave per block: a block's LDS is its wave's staging area
+        k_mics3d<<<n_cu * 16, 64, 0, s>>>(m, q, segs, ctr, mics, a, w);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         k_mics3d_general<<<n_cu * kBlocksPerCU, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, mics, a, w);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        k_mics3d_late<<<n_cu * 4, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         k_mic_rows<false><<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
         if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -115,7 +115,7 @@ def test_block_scene_volumetric_parity(torch_cuda):
                                        ("BT_MIC_SPAN_CAPACITY", "100")])
 def test_volumetric_work_list_overflow(torch_cuda, monkeypatch, env, value):
     """Tiny (segment, layer), row and span buffers push work onto the fallback paths
-    (remaining layers in one lane, rows and columns in place); results must not change."""
+    (items, rows and columns done in place); results must not change."""
     sc = block_scene(0).with_(level=4, mic_x0=-98.0, mic_y0=-98.0, mic_dx=4.0, mic_dy=4.0, mic_nx=50, mic_ny=50,
                               mic_z=1.5, mic_nz=16, mic_dz=4.0)
     say("volumetric overflow", env, value)
@@ -124,6 +124,10 @@ def test_volumetric_work_list_overflow(torch_cuda, monkeypatch, env, value):
     with session(sc) as s:
         g = gpu_run(s, sc)
     verdict(g, o)
+    assert g.stats["mic_layer_visits"] > 0 and g.stats["mic_general"] > 0
+    if env == "BT_MIC_LAYER_CAPACITY":   # the in-place path did run
+        assert g.stats["mic_general"] > int(value)
+        assert g.stats["mic_fallback"] == g.stats["mic_general"] - int(value)
 
 
 @pytest.fixture(scope="module")
