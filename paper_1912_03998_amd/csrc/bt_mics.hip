@@ -691,7 +691,7 @@ __device__ __forceinline__ void unstage_frustum(const VolStage &st, int l, doubl
 
 // Largest lattice box of a layer taken as candidates directly; larger footprints take the
 // clipped-footprint path, whose rows bound the candidates tightly.
-constexpr int kBox3 = 32;
+constexpr int kBox3 = 64;
 
 // The planar fast path on layer k for staged segment l: 0 = no microphone can be inside,
 // 1 = the candidates are the lattice box [i0, i1] x [j0, j1] (at most kBox3 points),
@@ -725,14 +725,20 @@ __device__ __forceinline__ int layer_fast(const VolStage &st, int l, const DevMi
         mag = fmaxf(mag, fmaxf(fabsf(sx), fabsf(sy)));
     }
     if (!finite) return 2;
-    const double relax = 1e-6 + 1e-5 * (double)mag;
-    const double idx = 1.0 / mc.dx, idy = 1.0 / mc.dy;
-    const double fi0 = fmax(ceil(((double)xmn - relax - mc.x0) * idx - 1e-9), 0.0);
-    const double fi1 = fmin(floor(((double)xmx + relax - mc.x0) * idx + 1e-9), (double)(mc.nx - 1));
-    const double fj0 = fmax(ceil(((double)ymn - relax - mc.y0) * idy - 1e-9), 0.0);
-    const double fj1 = fmin(floor(((double)ymx + relax - mc.y0) * idy + 1e-9), (double)(mc.ny - 1));
+    // lattice range in FP32 too: the grid values are FP32, and the index arithmetic
+    // (two subtractions and a product) is within 2e-7 of |index| + 1e-4 cells of exact,
+    // far inside the added 1e-6 |index| + 1e-3 cells
+    const float relax = 1e-6f + 1e-5f * mag;
+    const float gx = ((xmn - relax) - (float)mc.x0) * (float)(1.0 / mc.dx);
+    const float hx = ((xmx + relax) - (float)mc.x0) * (float)(1.0 / mc.dx);
+    const float gy = ((ymn - relax) - (float)mc.y0) * (float)(1.0 / mc.dy);
+    const float hy = ((ymx + relax) - (float)mc.y0) * (float)(1.0 / mc.dy);
+    const float fi0 = fmaxf(ceilf(gx - (1e-3f + 1e-6f * fabsf(gx))), 0.0f);
+    const float fi1 = fminf(floorf(hx + (1e-3f + 1e-6f * fabsf(hx))), (float)(mc.nx - 1));
+    const float fj0 = fmaxf(ceilf(gy - (1e-3f + 1e-6f * fabsf(gy))), 0.0f);
+    const float fj1 = fminf(floorf(hy + (1e-3f + 1e-6f * fabsf(hy))), (float)(mc.ny - 1));
     if (!(fi0 <= fi1 && fj0 <= fj1)) return 0;
-    if ((fi1 - fi0 + 1.0) * (fj1 - fj0 + 1.0) > (double)kBox3) return 2;
+    if ((fi1 - fi0 + 1.0f) * (fj1 - fj0 + 1.0f) > (float)kBox3) return 2;
     i0 = (int)fi0; i1 = (int)fi1; j0 = (int)fj0; j1 = (int)fj1;
     return 1;
 }

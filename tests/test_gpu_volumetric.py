@@ -179,7 +179,8 @@ def test_volumetric_grid_errors(torch_cuda):
     sc = tiny_scene()
     with session(sc) as s:
         for bad in [(0.0, 0.0, 1.5, 1.0, 1.0, 1.0, 4, 4, 0), (0.0, 0.0, 1.5, 1.0, 1.0, 0.0, 4, 4, 3),
-                    (0.0, 0.0, 1.5, 1.0, 1.0, float("nan"), 4, 4, 3), (0.0, 0.0, 1.5, 1.0, 1.0, 1.0, 65536, 65536, 2)]:
+                    (0.0, 0.0, 1.5, 1.0, 1.0, float("nan"), 4, 4, 3), (0.0, 0.0, 1.5, 1.0, 1.0, 1.0, 65536, 65536, 2),
+                    (0.0, 0.0, 1.5, 1.0, 1.0, 1.0, 1 << 24, 2, 2)]:
             with pytest.raises(bt.BTError):
                 bt.bt_mics_grid3d(s.ctx, *bad)
         # nz = 1 ignores dz and is the planar grid
