@@ -279,6 +279,8 @@ def main():
     ap.add_argument("--serve-full", action="store_true",
                     help="serving at the full stream lengths (200 warm-up + 2000 requests per rate)")
     ap.add_argument("--no-volumetric", action="store_true", help="skip the volumetric (tall district) measurement")
+    ap.add_argument("--volumetric-only", action="store_true",
+                    help="only the volumetric measurement (prints its JSON object; for profiling)")
     ap.add_argument("--vol-chunk", type=int, default=7, help="sources per beam set in the volumetric measurement")
     ap.add_argument("--vol-level", type=int, default=8, help="icosphere level of the volumetric measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -305,6 +307,11 @@ def main():
     from paper_1912_03998_amd import bt
     from paper_1912_03998_amd.tracer import Session, scene_grid
     from scenegen import config_scene
+
+    if args.volumetric_only:
+        print(json.dumps(volumetric_bench(args.steps, args.warmup, args.vol_chunk, args.vol_level,
+                                          oracle_sample=not args.no_cpu_baseline)), flush=True)
+        return
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     scene = config_scene(args.config)
