@@ -556,6 +556,12 @@ extern "C" bt_status bt_mics_grid3d(bt_ctx *ctx, float x0, float y0, float z0, f
     m->dev.nx = nx; m->dev.ny = ny;
     m->dev.nz = nz;
     m->dev.dz = nz > 1 ? (double)dz : 0.0;
+    m->dev.fx0 = x0;
+    m->dev.fy0 = y0;
+    m->dev.fidx = (float)(1.0 / (double)dx);
+    m->dev.fidy = (float)(1.0 / (double)dy);
+    m->dev.fnx1 = (float)(nx - 1);
+    m->dev.fny1 = (float)(ny - 1);
     m->dev.e_strict = (double *)p;
     m->dev.e_flag = m->dev.e_strict + n;
     m->level = m->dev.e_flag + n;
@@ -930,6 +936,7 @@ TraceArgs make_args(const bt_params *p, int gen)
     a.max_depth = p->max_depth;
     a.t_min = p->t_min;
     a.delta = p->edge_delta;
+    a.delta2 = p->edge_delta * p->edge_delta;
     a.air_m = p->air_m;
     a.e_min = p->e_min;
     a.hit_out = p->hit_out;

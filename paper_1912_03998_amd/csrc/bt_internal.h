@@ -110,6 +110,9 @@ struct DevMics {
                                // microphones of the set's subset; NULL = every grid point
     double dz;                 // layer spacing (float32 value, widened); 0 when nz = 1
     int nz;                    // layers
+    float fx0, fy0;            // volumetric fast path: x0, y0, 1/dx, 1/dy, nx - 1, ny - 1
+    float fidx, fidy;          // in FP32, set with the grid
+    float fnx1, fny1;
 };
 
 // Work buffers of the microphone stage: (segment, row) items of wide footprints,
@@ -149,6 +152,7 @@ struct TraceArgs {
     int scenarios;   // 1: a multi-scenario set (per-beam max_depth and slot in meta)
     const DevMics *slot_mics;  // scenario sets: microphone set of each slot
     double t_min, delta, air_m, e_min;
+    double delta2;   // delta^2, formed on the host (a kernel argument, so no register holds it)
     int *hit_out;
     uint8_t *flag_out;
     double *t_out;

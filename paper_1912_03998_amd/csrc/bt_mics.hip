@@ -616,10 +616,12 @@ struct VolStage {
                                 // N.(m - P) > 0, far N.(m - P) >= 0
     double az[kVolSeg];         // apex height
     float ax[kVolSeg], ay[kVolSeg];  // apex x, y (FP32: the fast path only bounds candidates)
-    float sx[3][kVolSeg], sy[3][kVolSeg];  // edge slopes dx/dz, dy/dz
+    float sxlo[kVolSeg], sxhi[kVolSeg];    // least and greatest edge slope dx/dz
+    float sylo[kVolSeg], syhi[kVolSeg];    // the same for dy/dz
+    float smag[kVolSeg];                   // largest |slope|
     float K[kVolSeg];
-    int bits[kVolSeg];          // 1 has near cap, 2 has far cap, 4 flagged, 8-10 dz_e > 0,
-                                // 16-18 dz_e < 0
+    int bits[kVolSeg];          // 1 has near cap, 2 has far cap, 4 flagged; every edge dz > 0:
+                                // 8, every dz < 0: 16, no dz > 0: 32, no dz < 0: 64
     int k0[kVolSeg];
     int prefix[kVolSeg + 1];    // exclusive scan of the batch's pair counts
     int cprefix[65];            // exclusive scan of the pair chunk's candidate counts
@@ -701,42 +703,37 @@ __device__ __forceinline__ int layer_fast(const VolStage &st, int l, const DevMi
 {
     const double zr = (mc.z + (double)k * mc.dz) - st.az[l];
     const int bits = st.bits[l];
-    const int pos = (bits >> 8) & 7, neg = (bits >> 16) & 7;
-    const bool away = (zr > 1e-6 && pos == 0) || (zr < -1e-6 && neg == 0);
+    const bool away = (zr > 1e-6 && (bits & 32)) || (zr < -1e-6 && (bits & 64));
     if (away) return 0;
     // all three edge rays cross the layer ahead of the apex: the frustum meets it inside
     // the triangle of the crossing points (the caps only cut it down)
-    const bool proper = zr > 0.0 ? pos == 7 : (zr < 0.0 && neg == 7);
+    const bool proper = zr > 0.0 ? (bits & 8) != 0 : (zr < 0.0 && (bits & 16));
     if (!proper) return 2;
-    // crossings in FP32 from the slopes: each coordinate within 6 x 2^-24 of `mag` (the
-    // largest magnitude involved) of its exact value; the box is widened by 1e-5 mag and
-    // the exact FP64 membership test decides every candidate
+    // crossings in FP32: each coordinate within 6 x 2^-24 of `mag` (the largest magnitude
+    // involved) of its exact value; the box is widened by 1e-5 mag and the exact FP64
+    // membership test decides every candidate.  Rounding is monotone, so the extreme
+    // crossings come from the extreme slopes (the least for zr > 0 giving the least x).
     const float zrf = (float)zr, axf = st.ax[l], ayf = st.ay[l];
-    float xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
-    float mag = fmaxf(fabsf(axf), fabsf(ayf));
-    bool finite = true;
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-        const float sx = zrf * st.sx[e][l], sy = zrf * st.sy[e][l];
-        const float px = axf + sx, py = ayf + sy;
-        finite = finite && isfinite(px) && isfinite(py);  // FP32 overflow: the clipped footprint decides
-        xmn = fminf(xmn, px); xmx = fmaxf(xmx, px);
-        ymn = fminf(ymn, py); ymx = fmaxf(ymx, py);
-        mag = fmaxf(mag, fmaxf(fabsf(sx), fabsf(sy)));
-    }
-    if (!finite) return 2;
+    const bool up = zrf > 0.0f;
+    const float xmn = axf + zrf * (up ? st.sxlo[l] : st.sxhi[l]);
+    const float xmx = axf + zrf * (up ? st.sxhi[l] : st.sxlo[l]);
+    const float ymn = ayf + zrf * (up ? st.sylo[l] : st.syhi[l]);
+    const float ymx = ayf + zrf * (up ? st.syhi[l] : st.sylo[l]);
+    const float mag = fmaxf(fmaxf(fabsf(axf), fabsf(ayf)), fabsf(zrf) * st.smag[l]);
+    // FP32 overflow: the clipped footprint decides
+    if (!(isfinite(xmn) && isfinite(xmx) && isfinite(ymn) && isfinite(ymx))) return 2;
     // lattice range in FP32 too: the grid values are FP32, and the index arithmetic
     // (two subtractions and a product) is within 2e-7 of |index| + 1e-4 cells of exact,
     // far inside the added 1e-6 |index| + 1e-3 cells
     const float relax = 1e-6f + 1e-5f * mag;
-    const float gx = ((xmn - relax) - (float)mc.x0) * (float)(1.0 / mc.dx);
-    const float hx = ((xmx + relax) - (float)mc.x0) * (float)(1.0 / mc.dx);
-    const float gy = ((ymn - relax) - (float)mc.y0) * (float)(1.0 / mc.dy);
-    const float hy = ((ymx + relax) - (float)mc.y0) * (float)(1.0 / mc.dy);
+    const float gx = ((xmn - relax) - mc.fx0) * mc.fidx;
+    const float hx = ((xmx + relax) - mc.fx0) * mc.fidx;
+    const float gy = ((ymn - relax) - mc.fy0) * mc.fidy;
+    const float hy = ((ymx + relax) - mc.fy0) * mc.fidy;
     const float fi0 = fmaxf(ceilf(gx - (1e-3f + 1e-6f * fabsf(gx))), 0.0f);
-    const float fi1 = fminf(floorf(hx + (1e-3f + 1e-6f * fabsf(hx))), (float)(mc.nx - 1));
+    const float fi1 = fminf(floorf(hx + (1e-3f + 1e-6f * fabsf(hx))), mc.fnx1);
     const float fj0 = fmaxf(ceilf(gy - (1e-3f + 1e-6f * fabsf(gy))), 0.0f);
-    const float fj1 = fminf(floorf(hy + (1e-3f + 1e-6f * fabsf(hy))), (float)(mc.ny - 1));
+    const float fj1 = fminf(floorf(hy + (1e-3f + 1e-6f * fabsf(hy))), mc.fny1);
     if (!(fi0 <= fi1 && fj0 <= fj1)) return 0;
     if ((fi1 - fi0 + 1.0f) * (fj1 - fj0 + 1.0f) > (float)kBox3) return 2;
     i0 = (int)fi0; i1 = (int)fi1; j0 = (int)fj0; j1 = (int)fj1;
@@ -748,7 +745,7 @@ __device__ __forceinline__ int layer_fast(const VolStage &st, int l, const DevMi
 // microphones inside.  Same products, sums and decisions as mic_apply (for a microphone
 // inside, no plane test is negative, so only `near_any` decides ambiguity).
 __device__ __forceinline__ int mic_apply_staged(const VolStage &st, int l, const DevMics &mc, int i, int j, int k,
-                                                double delta, double air_m)
+                                                double d2, double air_m)
 {
     const V3 m = {mc.x0 + (double)i * mc.dx, mc.y0 + (double)j * mc.dy, mc.z + (double)k * mc.dz};
     const V3 A = {st.f[0][l], st.f[1][l], st.f[2][l]};
@@ -775,7 +772,6 @@ __device__ __forceinline__ int mic_apply_staged(const VolStage &st, int l, const
         sf = dot(Nf, m - V3{st.f[21][l], st.f[22][l], st.f[23][l]});
         if (!(sf >= 0.0)) return 0;
     }
-    const double d2 = delta * delta;
     bool near_any = false;
 #pragma unroll
     for (int e = 0; e < 3; ++e) near_any = near_any || sd[e] * sd[e] < d2 * dot(n[e], n[e]);
@@ -815,15 +811,23 @@ __global__ void __launch_bounds__(64, 4) k_mics3d(DevMesh M, DevQueue q, DevSegs
                 Frustum f{};  // caps the segment lacks are staged as zeros
                 load_frustum(M, q, segs, i, a.delta, f);
                 stage_frustum(st, lane, f);
-                int bits = (f.has_near ? 1 : 0) | (f.has_far ? 2 : 0) | (f.flag ? 4 : 0);
+                int pos = 0, neg = 0;
+                float sxlo = INFINITY, sxhi = -INFINITY, sylo = INFINITY, syhi = -INFINITY, smag = 0.0f;
 #pragma unroll
                 for (int e = 0; e < 3; ++e) {
-                    bits |= (d[e].z > 0.0 ? 256 : 0) << e;
-                    bits |= (d[e].z < 0.0 ? 65536 : 0) << e;
-                    st.sx[e][lane] = (float)(d[e].x / d[e].z);
-                    st.sy[e][lane] = (float)(d[e].y / d[e].z);
+                    pos += d[e].z > 0.0 ? 1 : 0;
+                    neg += d[e].z < 0.0 ? 1 : 0;
+                    const float sx = (float)(d[e].x / d[e].z), sy = (float)(d[e].y / d[e].z);
+                    sxlo = fminf(sxlo, sx); sxhi = fmaxf(sxhi, sx);
+                    sylo = fminf(sylo, sy); syhi = fmaxf(syhi, sy);
+                    smag = fmaxf(smag, fmaxf(fabsf(sx), fabsf(sy)));
                 }
-                st.bits[lane] = bits;
+                // the slopes are only read for layers every edge crosses (no dz = 0)
+                st.sxlo[lane] = sxlo; st.sxhi[lane] = sxhi;
+                st.sylo[lane] = sylo; st.syhi[lane] = syhi;
+                st.smag[lane] = smag;
+                st.bits[lane] = (f.has_near ? 1 : 0) | (f.has_far ? 2 : 0) | (f.flag ? 4 : 0) | (pos == 3 ? 8 : 0) |
+                                (neg == 3 ? 16 : 0) | (pos == 0 ? 32 : 0) | (neg == 0 ? 64 : 0);
                 st.K[lane] = f.K;
                 st.az[lane] = A.z;
                 st.ax[lane] = (float)A.x;
@@ -855,7 +859,9 @@ __global__ void __launch_bounds__(64, 4) k_mics3d(DevMesh M, DevQueue q, DevSegs
             if (lane == 0 && gm) gb = atomicAdd(&ctr->n_layers[a.gen], (unsigned long long)__popcll(gm));
             gb = __shfl(gb, 0, 64);
             if (gen_item) {
-                const unsigned long long e = gb + (unsigned long long)__popcll(gm & ((1ull << lane) - 1ull));
+                const unsigned below = __builtin_amdgcn_mbcnt_hi((unsigned)(gm >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((unsigned)gm, 0u));
+                const unsigned long long e = gb + (unsigned long long)below;
                 const long long seg = (long long)(s0 + base) + slot;
                 if (e < (unsigned long long)w.layers_cap) {
                     w.layers[e] = make_int2((int)seg, k);
@@ -882,7 +888,7 @@ __global__ void __launch_bounds__(64, 4) k_mics3d(DevMesh M, DevQueue q, DevSegs
                     const int row = o / bx.w;
                     tests++;
                     updates += mic_apply_staged(st, bx.x & 63, mc, bx.y + (o - row * bx.w), bx.z + row, bx.x >> 6,
-                                                a.delta, a.air_m);
+                                                a.delta2, a.air_m);
                 }
             }
             __syncthreads();
