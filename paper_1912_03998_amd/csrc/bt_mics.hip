@@ -623,8 +623,12 @@ struct VolStage {
     int bits[kVolSeg];          // 1 has near cap, 2 has far cap, 4 flagged; every edge dz > 0:
                                 // 8, every dz < 0: 16, no dz > 0: 32, no dz < 0: 64
     int k0[kVolSeg];
-    int prefix[kVolSeg + 1];    // exclusive scan of the batch's pair counts
-    int cprefix[65];            // exclusive scan of the pair chunk's candidate counts
+    alignas(16) int prefix[kVolSeg + 4];   // exclusive scan of the batch's pair counts
+    alignas(16) int psk1[4];    // its search skips: prefix[8 (q+1)] at q,
+    alignas(16) int psk2[16];   //   prefix[8q + 2 (t+1)] at 4q + t
+    alignas(16) int cprefix[68];  // exclusive scan of the pair chunk's candidate counts
+    alignas(16) int csk1[4];    // its search skips: cprefix[16 (q+1)] at q,
+    alignas(16) int csk2[16];   //   cprefix[16q + 4 (t+1)] at 4q + t
     int4 box[64];               // pair chunk: (slot | layer << 6, i0, j0, columns)
 };
 
@@ -641,18 +645,36 @@ __device__ __forceinline__ int wave_excl_scan(int v, int &total)
     return incl - v;
 }
 
-// Largest l in [0, 2^bits - 1] with pre[l] <= x (pre nondecreasing, pre[0] = 0 <= x).
-template <int kBits>
-__device__ __forceinline__ int owner_of(const int *pre, int x)
+// Largest l in [0, 4^3 s - 1] (s = 1: 64 entries, s = 1/2: 32) with pre[l] <= x, pre
+// nondecreasing with pre[0] = 0 <= x: a 4-ary search, three dependent LDS reads.
+// sk1[q] = pre[(q + 1) W], sk2[4q + t] = pre[qW + (t + 1) W/4] for W = 16 (64 entries)
+// or W = 8 (32 entries); the last level reads pre itself.
+__device__ __forceinline__ int owner64(const int *pre, const int *sk1, const int *sk2, int x)
 {
-    int lo = 0, hi = (1 << kBits) - 1;
-#pragma unroll
-    for (int it = 0; it < kBits; ++it) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (pre[mid] <= x) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
+    const int4 a = *reinterpret_cast<const int4 *>(sk1);
+    const int q = (a.x <= x) + (a.y <= x) + (a.z <= x);
+    const int4 b = *reinterpret_cast<const int4 *>(sk2 + 4 * q);
+    const int base = 16 * q + 4 * ((b.x <= x) + (b.y <= x) + (b.z <= x));
+    const int4 c = *reinterpret_cast<const int4 *>(pre + base);
+    return base + (c.y <= x) + (c.z <= x) + (c.w <= x);
+}
+__device__ __forceinline__ int owner32(const int *pre, const int *sk1, const int *sk2, int x)
+{
+    const int4 a = *reinterpret_cast<const int4 *>(sk1);
+    const int q = (a.x <= x) + (a.y <= x) + (a.z <= x);
+    const int4 b = *reinterpret_cast<const int4 *>(sk2 + 4 * q);
+    const int base = 8 * q + 2 * ((b.x <= x) + (b.y <= x) + (b.z <= x));
+    const int2 c = *reinterpret_cast<const int2 *>(pre + base);
+    return base + (c.y <= x);
+}
+
+// Writes lane l's prefix value into the search skips of owner64 (W = 16) or owner32 (W = 8).
+template <int W>
+__device__ __forceinline__ void write_skips(int *sk1, int *sk2, int l, int v)
+{
+    if (l > 0 && l % W == 0 && l / W <= 3) sk1[l / W - 1] = v;
+    const int r = l % W;
+    if (r > 0 && r % (W / 4) == 0) sk2[4 * (l / W) + r / (W / 4) - 1] = v;
 }
 
 __device__ __forceinline__ void stage_frustum(VolStage &st, int l, const Frustum &f)
@@ -840,6 +862,7 @@ __global__ void __launch_bounds__(64, 4) k_mics3d(DevMesh M, DevQueue q, DevSegs
         if (lane < kVolSeg) {
             st.prefix[lane] = pre;
             st.k0[lane] = k0;
+            write_skips<8>(st.psk1, st.psk2, lane, pre);
         }
         if (lane == 0) st.prefix[kVolSeg] = total;
         __syncthreads();
@@ -848,7 +871,7 @@ __global__ void __launch_bounds__(64, 4) k_mics3d(DevMesh M, DevQueue q, DevSegs
             const int p = pb + lane;
             int kind = 0, slot = 0, k = 0, i0 = 0, i1 = -1, j0 = 0, j1 = -1;
             if (p < total) {
-                slot = owner_of<5>(st.prefix, p);
+                slot = owner32(st.prefix, st.psk1, st.psk2, p);
                 k = st.k0[slot] + (p - st.prefix[slot]);
                 kind = layer_fast(st, slot, mc, k, i0, i1, j0, j1);
             }
@@ -876,13 +899,14 @@ __global__ void __launch_bounds__(64, 4) k_mics3d(DevMesh M, DevQueue q, DevSegs
             int ctotal;
             const int cpre = wave_excl_scan(nc, ctotal);
             st.cprefix[lane] = cpre;
+            write_skips<16>(st.csk1, st.csk2, lane, cpre);
             st.box[lane] = make_int4(slot | (k << 6), i0, j0, i1 - i0 + 1);
             if (lane == 0) st.cprefix[64] = ctotal;
             __syncthreads();
             for (int cb = 0; cb < ctotal; cb += 64) {
                 const int c = cb + lane;
                 if (c < ctotal) {
-                    const int pl = owner_of<6>(st.cprefix, c);
+                    const int pl = owner64(st.cprefix, st.csk1, st.csk2, c);
                     const int o = c - st.cprefix[pl];
                     const int4 bx = st.box[pl];
                     const int row = o / bx.w;
