@@ -115,7 +115,8 @@ bt_status bt_build_mesh(bt_ctx *ctx, const float *xyz, int64_t n_vert, const int
                         const float *absorption, int64_t n_tri, int32_t tiles_x, int32_t tiles_y,
                         bt_mesh **out);
 bt_status bt_mesh_free(bt_mesh *mesh);
-/* Hierarchy facts: nodes, max depth, triangle references after duplication. */
+/* Hierarchy facts: 4-wide nodes, depth of the binary SAH build they were collapsed
+ * from, triangle references after duplication. */
 bt_status bt_mesh_info(const bt_mesh *mesh, int64_t *n_nodes, int32_t *max_depth, int64_t *n_tri_refs);
 
 /* Microphones on a regular planar grid (paper Section 4: microphones regularly

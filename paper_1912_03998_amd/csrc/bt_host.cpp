@@ -346,6 +346,92 @@ struct Builder {
     }
 };
 
+// Collapse of a binary hierarchy (4 float4 per node) into a 4-wide one (8 float4 per
+// node: lo x, hi x, lo y, hi y, lo z, hi z of the four children, their references, and
+// padding).  A node takes its two children and keeps replacing the interior child with
+// the largest box area by that child's two children until it has four or only leaves.
+// Unused slots hold a box no ray window reaches and the empty reference.
+struct Collapse {
+    const std::vector<float4> &bin;
+    std::vector<float4> &out;
+    int max_push = 0;   // most entries the traversal stack can hold on any root-leaf path
+    struct Child {
+        float lo[3], hi[3];
+        int ref;
+    };
+    static double area(const Child &c)
+    {
+        const double x = (double)c.hi[0] - c.lo[0], y = (double)c.hi[1] - c.lo[1], z = (double)c.hi[2] - c.lo[2];
+        return x * y + y * z + z * x;
+    }
+    void children(int b, Child &l, Child &r) const
+    {
+        const float4 *nd = &bin[4 * (size_t)b];
+        l.lo[0] = nd[0].x; r.lo[0] = nd[0].y; l.hi[0] = nd[0].z; r.hi[0] = nd[0].w;
+        l.lo[1] = nd[1].x; r.lo[1] = nd[1].y; l.hi[1] = nd[1].z; r.hi[1] = nd[1].w;
+        l.lo[2] = nd[2].x; r.lo[2] = nd[2].y; l.hi[2] = nd[2].z; r.hi[2] = nd[2].w;
+        std::memcpy(&l.ref, &nd[3].x, 4);
+        std::memcpy(&r.ref, &nd[3].y, 4);
+    }
+    std::vector<int> height;   // binary height of each binary node's subtree (leaf = 0)
+    int height_of(int ref)
+    {
+        if (ref < 0) return 0;
+        if (height[ref] >= 0) return height[ref];
+        Child l, r;
+        children(ref, l, r);
+        return height[ref] = 1 + std::max(height_of(l.ref), height_of(r.ref));
+    }
+    // budget: stack entries still free on the way here; invariant: height_of(ref) <= budget
+    // (a binary walk of the subtree pushes at most its height)
+    int collapse(int ref, int pushed)
+    {
+        if (ref < 0) return ref;
+        if (height.empty()) height.assign(bin.size() / 4, -1);
+        const int budget = kStack - pushed;
+        Child c[4];
+        int n = 2;
+        children(ref, c[0], c[1]);
+        while (n < 4) {
+            int best = -1;
+            double ba = -1.0;
+            for (int k = 0; k < n; ++k)
+                if (c[k].ref >= 0 && area(c[k]) > ba) { ba = area(c[k]); best = k; }
+            if (best < 0) break;
+            Child a, b;
+            children(c[best].ref, a, b);
+            // one more child costs one more stack entry: take it only if every child's
+            // subtree still fits the entries left below this node
+            const int hmax = std::max({height_of(a.ref), height_of(b.ref), [&] {
+                int h = 0;
+                for (int k = 0; k < n; ++k) if (k != best) h = std::max(h, height_of(c[k].ref));
+                return h;
+            }()});
+            if (hmax > budget - n) break;
+            c[best] = a;
+            c[n++] = b;
+        }
+        const int idx = (int)(out.size() / 8);
+        out.resize(out.size() + 8);
+        max_push = std::max(max_push, pushed + n - 1);
+        int refs[4] = {kEmptyRoot, kEmptyRoot, kEmptyRoot, kEmptyRoot};
+        for (int k = 0; k < n; ++k) refs[k] = collapse(c[k].ref, pushed + n - 1);
+        float v[6][4];
+        for (int k = 0; k < 4; ++k)
+            for (int a = 0; a < 3; ++a) {
+                v[2 * a][k] = k < n ? c[k].lo[a] : 1e30f;
+                v[2 * a + 1][k] = k < n ? c[k].hi[a] : 1e30f;
+            }
+        float4 *nd = &out[8 * (size_t)idx];
+        for (int q = 0; q < 6; ++q) nd[q] = make_float4(v[q][0], v[q][1], v[q][2], v[q][3]);
+        float fr[4];
+        std::memcpy(fr, refs, sizeof fr);
+        nd[6] = make_float4(fr[0], fr[1], fr[2], fr[3]);
+        nd[7] = make_float4(0.f, 0.f, 0.f, 0.f);
+        return idx;
+    }
+};
+
 float round_down_f(double x)
 {
     float f = (float)x;
@@ -451,7 +537,8 @@ extern "C" bt_status bt_build_mesh(bt_ctx *ctx, const float *xyz, int64_t n_vert
     dm.tw = (dm.gx1 - dm.gx0) / tiles_x;
     dm.th = (dm.gy1 - dm.gy0) / tiles_y;
 
-    std::vector<float4> nodes, trefs;
+    std::vector<float4> nodes, trefs, nodes4;
+    int max_push = 0;
     std::vector<int> roots((size_t)tiles_x * tiles_y, kEmptyRoot);
     std::vector<float> tboxes((size_t)tiles_x * tiles_y * 6, 0.f);
     int max_depth = 0;
@@ -470,7 +557,12 @@ extern "C" bt_status bt_build_mesh(bt_ctx *ctx, const float *xyz, int64_t n_vert
             int tile = ty * tiles_x + tx;
             if (prims.empty()) continue;
             Builder b{prims, nodes, trefs, tri_rec};
-            roots[tile] = b.build(0, (int)prims.size(), 0);
+            {
+                const int root2 = b.build(0, (int)prims.size(), 0);
+                Collapse cl{nodes, nodes4};
+                roots[tile] = cl.collapse(root2, 0);
+                max_push = std::max(max_push, cl.max_push);
+            }
             max_depth = std::max(max_depth, b.max_depth);
             overflow = overflow || b.overflow;
             Box rb;
@@ -478,18 +570,19 @@ extern "C" bt_status bt_build_mesh(bt_ctx *ctx, const float *xyz, int64_t n_vert
             for (const Prim &p : prims) rb.grow(p.box);
             for (int c = 0; c < 3; ++c) { tboxes[6 * tile + c] = rb.lo[c]; tboxes[6 * tile + 3 + c] = rb.hi[c]; }
         }
-    if (overflow) return fail(ctx, BT_EOVERFLOW, "BVH deeper than the %d-entry traversal stack", kStack);
+    if (overflow || max_push > kStack)
+        return fail(ctx, BT_EOVERFLOW, "BVH deeper than the %d-entry traversal stack", kStack);
     if (trefs.size() / 3 >= (1u << 28)) return fail(ctx, BT_EOVERFLOW, "too many triangle references");
 
     bt_mesh *m = new bt_mesh();
     m->ctx = ctx;
-    m->n_nodes = (int64_t)(nodes.size() / 4);
+    m->n_nodes = (int64_t)(nodes4.size() / 8);
     m->n_refs = (int64_t)(trefs.size() / 3);
     m->max_depth = max_depth;
     m->delta_cap = delta_cap;
     m->r_eff = r_eff;
-    const void *src[6] = {nodes.data(), trefs.data(), tri_g.data(), absorption, roots.data(), tboxes.data()};
-    size_t sz[6] = {nodes.size() * sizeof(float4), trefs.size() * sizeof(float4), tri_g.size() * sizeof(float),
+    const void *src[6] = {nodes4.data(), trefs.data(), tri_g.data(), absorption, roots.data(), tboxes.data()};
+    size_t sz[6] = {nodes4.size() * sizeof(float4), trefs.size() * sizeof(float4), tri_g.size() * sizeof(float),
                     (size_t)n_tri * sizeof(float), roots.size() * sizeof(int), tboxes.size() * sizeof(float)};
     for (int i = 0; i < 6; ++i) {
         bt_status s = dev_alloc(ctx, &m->bufs[i], sz[i]);

@@ -28,11 +28,13 @@ namespace bt {
 // Global triangles (by id): float[9] vertices, float absorption.
 // ---------------------------------------------------------------------------------------
 
-constexpr int kStack = 32;          // traversal stack entries per lane (>= BVH depth)
-constexpr int kEmptyRoot = 0x7fffffff;
+constexpr int kStack = 32;          // traversal stack entries per lane (the builder bounds the
+                                    // pushes of any root-leaf walk by it)
+constexpr int kEmptyRoot = 0x7fffffff;  // empty tile, or unused child slot of a node
 
 struct DevMesh {
-    const float4 *nodes;
+    const float4 *nodes;      // 4-wide nodes, 8 float4 each: lo x, hi x, lo y, hi y, lo z,
+                              // hi z of the four children, their references, padding
     const float4 *tris;
     const float *tri_g;       // [n_tri][9]
     const float *alpha;       // [n_tri]

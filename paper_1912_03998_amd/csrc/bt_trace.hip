@@ -229,20 +229,42 @@ __device__ void traverse_tile(const DevMesh &M, int tile, RayState &r, RaySrc sr
     int ref = root;
     while (true) {
         while (ref >= 0) {
-            const float4 *nd = M.nodes + 4 * (long long)ref;
-            const float4 nx = nd[0], ny = nd[1], nz = nd[2], nr = nd[3];
+            const float4 *nd = M.nodes + 8 * (long long)ref;
+            const float4 lx = nd[0], hx = nd[1], ly = nd[2], hy = nd[3], lz = nd[4], hz = nd[5], rr = nd[6];
             r.node_visits++;
-            float t0, t1;
-            bool h0, h1;
-            box2(nx, ny, nz, r, flo, fhi, t0, t1, h0, h1);
-            const int c0 = __float_as_int(nr.x), c1 = __float_as_int(nr.y);
-            if (h0 && h1) {
-                const bool first0 = t0 <= t1;
-                stk[sp * bdim + tid] = first0 ? c1 : c0;
-                sp++;
-                ref = first0 ? c0 : c1;
-            } else if (h0 || h1) {
-                ref = h0 ? c0 : c1;
+            float t[4];
+            int c[4];
+            const float lxa[4] = {lx.x, lx.y, lx.z, lx.w}, hxa[4] = {hx.x, hx.y, hx.z, hx.w};
+            const float lya[4] = {ly.x, ly.y, ly.z, ly.w}, hya[4] = {hy.x, hy.y, hy.z, hy.w};
+            const float lza[4] = {lz.x, lz.y, lz.z, lz.w}, hza[4] = {hz.x, hz.y, hz.z, hz.w};
+            const int ca[4] = {__float_as_int(rr.x), __float_as_int(rr.y), __float_as_int(rr.z), __float_as_int(rr.w)};
+            int nh = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float ax = (lxa[k] - r.ox) * r.ix, bx = (hxa[k] - r.ox) * r.ix;
+                const float ay = (lya[k] - r.oy) * r.iy, by = (hya[k] - r.oy) * r.iy;
+                const float az = (lza[k] - r.oz) * r.iz, bz = (hza[k] - r.oz) * r.iz;
+                const float mn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), flo));
+                const float mx = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), fhi));
+                const bool h = mn <= mx && ca[k] != kEmptyRoot;
+                t[k] = h ? mn : INFINITY;
+                c[k] = ca[k];
+                nh += h ? 1 : 0;
+            }
+            // order the children by entry parameter (misses last)
+#define BT_CSWAP(i, j)                                              \
+    if (t[j] < t[i]) {                                              \
+        const float tt = t[i]; t[i] = t[j]; t[j] = tt;              \
+        const int cc = c[i]; c[i] = c[j]; c[j] = cc;                \
+    }
+            BT_CSWAP(0, 1) BT_CSWAP(2, 3) BT_CSWAP(0, 2) BT_CSWAP(1, 3) BT_CSWAP(1, 2)
+#undef BT_CSWAP
+            if (nh > 0) {
+                // the nearest next, the others pushed farthest first
+                if (nh > 3) stk[(sp++) * bdim + tid] = c[3];
+                if (nh > 2) stk[(sp++) * bdim + tid] = c[2];
+                if (nh > 1) stk[(sp++) * bdim + tid] = c[1];
+                ref = c[0];
             } else if (sp > 0) {
                 sp--;
                 ref = stk[sp * bdim + tid];
