@@ -677,7 +677,8 @@ __device__ __forceinline__ void write_skips(int *sk1, int *sk2, int l, int v)
     if (r > 0 && r % (W / 4) == 0) sk2[4 * (l / W) + r / (W / 4) - 1] = v;
 }
 
-__device__ __forceinline__ void stage_frustum(VolStage &st, int l, const Frustum &f)
+template <class Stage>
+__device__ __forceinline__ void stage_frustum(Stage &st, int l, const Frustum &f)
 {
     const double v[kVolF] = {f.A.x, f.A.y, f.A.z,
                              f.n[0].x, f.n[0].y, f.n[0].z, f.n[1].x, f.n[1].y, f.n[1].z, f.n[2].x, f.n[2].y, f.n[2].z,
@@ -766,7 +767,8 @@ __device__ __forceinline__ int layer_fast(const VolStage &st, int l, const DevMi
 // (most candidates fail one of them), then the caps; the ambiguity distances only for
 // microphones inside.  Same products, sums and decisions as mic_apply (for a microphone
 // inside, no plane test is negative, so only `near_any` decides ambiguity).
-__device__ __forceinline__ int mic_apply_staged(const VolStage &st, int l, const DevMics &mc, int i, int j, int k,
+template <class Stage>
+__device__ __forceinline__ int mic_apply_staged(const Stage &st, int l, const DevMics &mc, int i, int j, int k,
                                                 double d2, double air_m)
 {
     const V3 m = {mc.x0 + (double)i * mc.dx, mc.y0 + (double)j * mc.dy, mc.z + (double)k * mc.dz};
@@ -924,19 +926,120 @@ __global__ void __launch_bounds__(64, 4) k_mics3d(DevMesh M, DevQueue q, DevSegs
     if (lane == 0 && sv) atomicAdd(&ctr->mic_layer_visits, sv);
 }
 
-__global__ void __launch_bounds__(256, 3) k_mics3d_general(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
+// LDS staging of one wave of k_mics3d_general: kVolSeg (segment, layer) items with their
+// frustums and the five frustum half-planes on the item's layer.
+struct GenStage {
+    double f[kVolF][kVolSeg];     // frustum, as VolStage
+    double L[15][kVolSeg];        // half-planes 0..4 (a, b, k) on the item's layer
+    float K[kVolSeg];
+    int bits[kVolSeg];            // 1 near cap, 2 far cap, 4 flagged
+    int k[kVolSeg];               // the item's layer
+    int j0[kVolSeg];              // first row of its clipped footprint
+    alignas(16) int prefix[kVolSeg + 4];  // exclusive scan of the items' row counts
+    alignas(16) int psk1[4];
+    alignas(16) int psk2[16];
+    alignas(16) int cprefix[68];  // exclusive scan of the row chunk's column counts
+    alignas(16) int csk1[4];
+    alignas(16) int csk2[16];
+    int4 row[64];                 // row chunk: (slot, row, first column, -)
+};
+
+// row_cols on staged half-planes (the same arithmetic as row_cols).
+__device__ __forceinline__ bool row_cols_staged(const GenStage &st, int l, const DevMics &mc, int j, int &i0, int &i1)
+{
+    const double y = mc.y0 + (double)j * mc.dy;
+    double lo = -INFINITY, hi = INFINITY;
+#pragma unroll
+    for (int h = 0; h < 5; ++h) {
+        const double la = st.L[3 * h][l], lb = st.L[3 * h + 1][l], lk = st.L[3 * h + 2][l];
+        const double rest = lb * y + lk;
+        if (la > 0.0) lo = fmax(lo, -rest / la);
+        else if (la < 0.0) hi = fmin(hi, -rest / la);
+        else if (rest < 0.0) return false;
+    }
+    if (!(lo <= hi)) return false;
+    const double flo = (lo - mc.x0) / mc.dx, fhi = (hi - mc.x0) / mc.dx;
+    if (flo > (double)mc.nx || fhi < -1.0) return false;
+    const double a0 = fmax(ceil(flo) - 1.0, 0.0), a1 = fmin(floor(fhi) + 1.0, (double)(mc.nx - 1));
+    if (!(a0 <= a1)) return false;
+    i0 = (int)a0;
+    i1 = (int)a1;
+    return true;
+}
+
+// (segment, layer) items of the clipped-footprint path, kVolSeg per wave: each lane clips
+// its item's footprint (its row range), then the rows are spread evenly over the lanes
+// (each finds its column range), then the candidate microphones are spread evenly over
+// the lanes and tested against the staged frustums.  One wave per block, 3 per SIMD.
+__global__ void __launch_bounds__(64, 3) k_mics3d_general(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
                                                           DevMics mc, TraceArgs a, MicWork w)
 {
+    __shared__ GenStage st;
     unsigned long long n = ctr->n_layers[a.gen];
     if (n > (unsigned long long)w.layers_cap) n = (unsigned long long)w.layers_cap;
+    const int lane = lane_id();
     unsigned tests = 0, updates = 0;
-    for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
-        const unsigned long long r = base + (unsigned long long)lane_id();
-        if (r >= n) continue;
-        const int2 it = w.layers[r];
-        Frustum f;
-        load_frustum(M, q, segs, it.x, a.delta, f);
-        layer_general(f, mc, w, ctr, a, it.x, it.y, tests, updates);
+    for (unsigned long long base = (unsigned long long)blockIdx.x * kVolSeg; base < n;
+         base += (unsigned long long)gridDim.x * kVolSeg) {
+        int nrows = 0;
+        if (lane < kVolSeg && base + (unsigned long long)lane < n) {
+            const int2 it = w.layers[base + lane];
+            Frustum f{};
+            load_frustum(M, q, segs, it.x, a.delta, f);
+            HalfPlane L[9];
+            footprint_lines(f, mc, mc.z + (double)it.y * mc.dz, L);
+            int j0, j1;
+            if (footprint_rows(L, mc, j0, j1)) {
+                nrows = j1 - j0 + 1;
+                stage_frustum(st, lane, f);
+                st.bits[lane] = (f.has_near ? 1 : 0) | (f.has_far ? 2 : 0) | (f.flag ? 4 : 0);
+                st.K[lane] = f.K;
+                st.k[lane] = it.y;
+                st.j0[lane] = j0;
+#pragma unroll
+                for (int h = 0; h < 5; ++h) {
+                    st.L[3 * h][lane] = L[h].a;
+                    st.L[3 * h + 1][lane] = L[h].b;
+                    st.L[3 * h + 2][lane] = L[h].k;
+                }
+            }
+        }
+        int total;
+        const int pre = wave_excl_scan(nrows, total);
+        if (lane < kVolSeg) {
+            st.prefix[lane] = pre;
+            write_skips<8>(st.psk1, st.psk2, lane, pre);
+        }
+        __syncthreads();
+        // rows, 64 at a time
+        for (int rb = 0; rb < total; rb += 64) {
+            const int r = rb + lane;
+            int ncol = 0, slot = 0, j = 0, c0 = 0, c1 = -1;
+            if (r < total) {
+                slot = owner32(st.prefix, st.psk1, st.psk2, r);
+                j = st.j0[slot] + (r - st.prefix[slot]);
+                if (row_cols_staged(st, slot, mc, j, c0, c1)) ncol = c1 - c0 + 1;
+            }
+            int ctotal;
+            const int cpre = wave_excl_scan(ncol, ctotal);
+            st.cprefix[lane] = cpre;
+            write_skips<16>(st.csk1, st.csk2, lane, cpre);
+            st.row[lane] = make_int4(slot, j, c0, 0);
+            __syncthreads();
+            // candidate microphones, 64 at a time
+            for (int cb = 0; cb < ctotal; cb += 64) {
+                const int c = cb + lane;
+                if (c < ctotal) {
+                    const int rl = owner64(st.cprefix, st.csk1, st.csk2, c);
+                    const int4 rw = st.row[rl];
+                    tests++;
+                    updates += mic_apply_staged(st, rw.x, mc, rw.z + (c - st.cprefix[rl]), rw.y, st.k[rw.x],
+                                                a.delta2, a.air_m);
+                }
+            }
+            __syncthreads();
+        }
+        __syncthreads();
     }
     flush_mic_counters(ctr, tests, updates);
 }
@@ -971,7 +1074,7 @@ hipError_t launch_mics(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *
         k_mics3d<<<n_cu * 16, 64, 0, s>>>(m, q, segs, ctr, mics, a, w);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        k_mics3d_general<<<n_cu * kBlocksPerCU, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, mics, a, w);
+        k_mics3d_general<<<n_cu * 12, 64, 0, s>>>(m, q, segs, ctr, mics, a, w);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         k_mic_rows<false><<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
         if ((e = hipGetLastError()) != hipSuccess) return e;
