@@ -124,6 +124,25 @@ def test_batch_chunking_and_graph(torch_cuda, use_graph):
                 assert_same(a.flag, b.flag)
 
 
+@pytest.mark.parametrize("env,value", [("BT_MIC_ROW_CAPACITY", "40"), ("BT_MIC_SPAN_CAPACITY", "20")])
+def test_batch_mic_work_overflow(torch_cuda, monkeypatch, env, value):
+    """Scenario sets use the planar row, span and one-wave-per-segment kernels of the
+    microphone stage: tiny row and span buffers push wide footprints onto the one-wave path
+    and long rows onto in-place processing; every scenario keeps its result."""
+    from paper_1912_03998_amd import bt
+    say("batch mic work overflow", env, value)
+    ref = make_scenarios()
+    with session() as s:
+        bt.bt_batch_run(s.ctx, s.mesh, ref)
+    monkeypatch.setenv(env, value)
+    scs = make_scenarios()
+    with session() as s:
+        bt.bt_batch_run(s.ctx, s.mesh, scs)
+    for a, b in zip(scs, ref):
+        assert_same(a.energy, b.energy)
+        assert_same(a.flag, b.flag)
+
+
 def test_batch_rejects_bad_scenarios(torch_cuda):
     from paper_1912_03998_amd import bt
     say("batch validation")
