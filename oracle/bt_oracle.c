@@ -187,6 +187,10 @@ typedef struct {
        Microphone (i, j, k) has index (k mic_ny + j) mic_nx + i. */
     double mic_dz;
     int32_t mic_nz;
+    /* explicit microphone points (float [mic_n][3]); when set they replace the grid and
+       every point is tested against every segment */
+    const float *mic_xyz;
+    int64_t mic_n;
 } orc_scene;
 
 typedef struct {
@@ -775,6 +779,15 @@ static void accumulate_mics(const orc_scene *s, const orc_params *p, const obeam
     ofrustum f;
     make_frustum(s, bm, hit, bm->c, &f);
     const int64_t nz = s->mic_nz > 0 ? s->mic_nz : 1;
+    if (s->mic_xyz) {
+        for (int64_t mi = 0; mi < s->mic_n; ++mi) {
+            double m[3] = { (double)s->mic_xyz[3 * mi], (double)s->mic_xyz[3 * mi + 1], (double)s->mic_xyz[3 * mi + 2] };
+            int amb;
+            acc->counters[C_MIC_TESTS]++;
+            if (mic_inside(&f, bm->A, m, p->delta, &amb)) add_contribution(s, p, bm, mi, m, amb, acc);
+        }
+        return;
+    }
     if (p->mic_mode == 0) {
         /* every microphone of every layer */
         const int64_t nmic = (int64_t)s->mic_nx * s->mic_ny * nz;
@@ -911,7 +924,7 @@ int orc_trace(const orc_scene *s, const orc_params *p, orc_result *res)
     int64_t b0 = p->beam_begin < 0 ? 0 : p->beam_begin;
     int64_t b1 = p->beam_end > nb || p->beam_end < 0 ? nb : p->beam_end;
     int D = p->depth;
-    int64_t nmic = (int64_t)s->mic_nx * s->mic_ny * (s->mic_nz > 0 ? s->mic_nz : 1);
+    int64_t nmic = s->mic_xyz ? s->mic_n : (int64_t)s->mic_nx * s->mic_ny * (s->mic_nz > 0 ? s->mic_nz : 1);
     double *dirs = (double *)malloc(sizeof(double) * 9 * (size_t)nf);
     if (!dirs) return -2;
     if (orc_icosphere(p->level, dirs) != 0) { free(dirs); return -3; }

@@ -51,7 +51,8 @@ class _Scene(C.Structure):
                 ("alpha", C.c_void_p), ("src", C.c_void_p), ("power", C.c_void_p), ("n_src", C.c_int32),
                 ("mic_x0", C.c_double), ("mic_y0", C.c_double), ("mic_z", C.c_double),
                 ("mic_dx", C.c_double), ("mic_dy", C.c_double), ("mic_nx", C.c_int32), ("mic_ny", C.c_int32),
-                ("src_weight", C.c_void_p), ("mic_dz", C.c_double), ("mic_nz", C.c_int32)]
+                ("src_weight", C.c_void_p), ("mic_dz", C.c_double), ("mic_nz", C.c_int32),
+                ("mic_xyz", C.c_void_p), ("mic_n", C.c_int64)]
 
 
 class _Params(C.Structure):
@@ -96,7 +97,7 @@ def _ptr(a):
     return None if a is None else a.ctypes.data
 
 
-def _scene_struct(scene, keep, weights=None):
+def _scene_struct(scene, keep, weights=None, points=None):
     v = np.ascontiguousarray(scene.vertices, np.float32)
     t = np.ascontiguousarray(scene.triangles, np.int32)
     a = np.ascontiguousarray(scene.absorption, np.float32)
@@ -108,9 +109,14 @@ def _scene_struct(scene, keep, weights=None):
     if weights is not None:
         wt = np.ascontiguousarray(weights, np.float32)
         keep.append(wt)
+    pts = None
+    if points is not None:
+        pts = np.ascontiguousarray(points, np.float32).reshape(-1, 3)
+        keep.append(pts)
     return _Scene(_ptr(v), v.shape[0], _ptr(t), t.shape[0], _ptr(a), _ptr(s), _ptr(w), s.shape[0],
                   f32(scene.mic_x0), f32(scene.mic_y0), f32(scene.mic_z), f32(scene.mic_dx), f32(scene.mic_dy),
-                  scene.mic_nx, scene.mic_ny, _ptr(wt), f32(scene.mic_dz), scene.mic_nz)
+                  scene.mic_nx, scene.mic_ny, _ptr(wt), f32(scene.mic_dz), scene.mic_nz, _ptr(pts),
+                  0 if pts is None else pts.shape[0])
 
 
 def icosphere(level: int) -> np.ndarray:
@@ -148,10 +154,13 @@ class TraceResult:
 
 
 def trace(scene, *, level=None, depth=None, t_min=T_MIN, delta=DELTA, m_air=0.0, e_min=0.0, use_bvh=True,
-          mic_mode=1, n_threads=None, beam_begin=0, beam_end=-1, keep_paths=True, weights=None) -> TraceResult:
+          mic_mode=1, n_threads=None, beam_begin=0, beam_end=-1, keep_paths=True, weights=None,
+          points=None) -> TraceResult:
     """Trace the whole scene (or the initial beams [beam_begin, beam_end)) in FP64.
     weights: optional float32 [n_src][20 * 4**level] relative intensity of each source per
-    icosphere face (a directional source); None = omni."""
+    icosphere face (a directional source); None = omni.
+    points: optional float32 [n][3] explicit microphone points, replacing the grid (each is
+    tested against every segment); energies are then per point."""
     level = scene.level if level is None else level
     depth = scene.depth if depth is None else depth
     n_threads = n_threads or default_threads()
@@ -160,7 +169,7 @@ def trace(scene, *, level=None, depth=None, t_min=T_MIN, delta=DELTA, m_air=0.0,
         weights = np.asarray(weights, np.float32)
         assert weights.shape == (scene.n_src, 20 * 4 ** level), weights.shape
     keep = []
-    sc = _scene_struct(scene, keep, weights)
+    sc = _scene_struct(scene, keep, weights, points)
     pr = _Params(level, depth, t_min, delta, m_air, e_min, int(use_bvh), int(mic_mode), int(n_threads),
                  beam_begin, beam_end)
     hit = flag = th = None
@@ -171,8 +180,9 @@ def trace(scene, *, level=None, depth=None, t_min=T_MIN, delta=DELTA, m_air=0.0,
     count = np.zeros(depth + 1, np.int64)
     flagged = np.zeros(depth + 1, np.int64)
     power = np.zeros(depth + 1, np.float64)
-    es = np.zeros(scene.n_mic, np.float64)
-    ef = np.zeros(scene.n_mic, np.float64)
+    n_mic = scene.n_mic if points is None else int(np.asarray(points).reshape(-1, 3).shape[0])
+    es = np.zeros(n_mic, np.float64)
+    ef = np.zeros(n_mic, np.float64)
     res = _Result(_ptr(hit), _ptr(flag), _ptr(th), _ptr(count), _ptr(flagged), _ptr(power), _ptr(es), _ptr(ef))
     rc = lib().orc_trace(C.byref(sc), C.byref(pr), C.byref(res))
     if rc != 0:

@@ -265,6 +265,44 @@ def test_volumetric_layers_equal_planar_runs():
     assert (r.energy[per:] > 0).any()
 
 
+def test_explicit_points_free_field_and_ground():
+    """Explicit microphone points at random positions: W / (4 pi d^2) once each in free
+    field, and direct + image source above a ground plane (points below it get nothing)."""
+    rng = np.random.default_rng(5)
+    pts = rng.uniform([-9.0, -9.0, -6.0], [9.0, 9.0, 12.0], (300, 3)).astype(np.float32)
+    sc = empty_scene(level=3, src=(0.3, -0.2, 1.0))
+    r = O.trace(sc, points=pts)
+    m = pts.astype(np.float64)
+    ref = 1.0 / (FOUR_PI * ((m - sc.sources[0].astype(np.float64)) ** 2).sum(1))
+    assert np.abs(r.energy / ref - 1).max() < 1e-13
+    assert r.counters["mic_updates"] == len(pts)
+    alpha = 0.3
+    g = ground_scene(level=4, alpha=alpha)
+    r = O.trace(g, points=pts)
+    s0 = g.sources[0].astype(np.float64)
+    img = s0 * np.array([1, 1, -1.0])
+    a32 = float(np.float32(alpha))
+    ref = (1.0 / ((m - s0) ** 2).sum(1) + (1 - a32) / ((m - img) ** 2).sum(1)) / FOUR_PI
+    below = m[:, 2] < 0
+    assert below.sum() > 50 and (r.energy[below] == 0).all()
+    elev = np.degrees(np.arctan2(m[:, 2] + s0[2], np.hypot(m[:, 0] - s0[0], m[:, 1] - s0[1])))
+    ok = ~below & (elev > 15) & (r.e_flag == 0)
+    assert ok.sum() > 100
+    assert np.abs(r.energy[ok] / ref[ok] - 1).max() < 1e-13
+
+
+def test_explicit_points_equal_grid():
+    """Explicit points placed on the grid's positions (in a shuffled order) get the grid's
+    energies bit for bit, planar and volumetric."""
+    for sc in (tiny_scene(), tiny_scene().with_(mic_z=-2.5, mic_nz=5, mic_dz=4.0)):
+        grid = O.trace(sc, n_threads=1)
+        pos = sc.mic_positions()
+        perm = np.random.default_rng(1).permutation(len(pos))
+        r = O.trace(sc, n_threads=1, points=pos[perm].astype(np.float32))
+        assert np.array_equal(r.e_strict, grid.e_strict[perm])
+        assert np.array_equal(r.e_flag, grid.e_flag[perm])
+
+
 def test_directional_source_uniform_weights_is_omni():
     """Equal weights give the omni split (K = W / (4 pi)) up to the rounding of the solid
     angles' sum; any weights conserve the emitted power."""
