@@ -134,6 +134,20 @@ bt_status bt_mics_grid(bt_ctx *ctx, float x0, float y0, float z, float dx, float
  * planar grids. */
 bt_status bt_mics_grid3d(bt_ctx *ctx, float x0, float y0, float z0, float dx, float dy, float dz, int32_t nx,
                          int32_t ny, int32_t nz, bt_mics **out);
+/* Microphones at a chosen subset of a grid's points (paper Section 4's microphones are
+ * grid points; a query may want only some of them): idx host int32[n], grid indices in
+ * [0, nx ny nz), duplicates allowed; bt_levels returns the n points in idx order.  The set
+ * owns its energies (a grid-sized array; contributions to points outside the subset are
+ * skipped before accumulation) and copies idx.  `grid` must be a grid set (not a subset
+ * or a point set) and is not referenced afterwards.  BT_EINVAL on an empty or
+ * out-of-range idx. */
+bt_status bt_mics_subset(bt_ctx *ctx, const bt_mics *grid, const int32_t *idx, int64_t n, bt_mics **out);
+/* Microphones at explicit points (paper Section 2: every microphone inside a beam
+ * receives its contribution; the points need not lie on a grid): xyz host float[n][3],
+ * copied; 1 <= n < 2^31, finite coordinates (BT_EINVAL otherwise).  The library indexes
+ * them by uniform buckets in xy; bt_levels returns n values in input order.  Usable with
+ * bt_accumulate_mics and bt_run; the scenario and serving interfaces take grids. */
+bt_status bt_mics_points(bt_ctx *ctx, const float *xyz, int64_t n, bt_mics **out);
 bt_status bt_mics_reset(bt_ctx *ctx, bt_mics *mics);   /* zero the energies (kernel, no memset) */
 bt_status bt_mics_free(bt_mics *mics);
 

@@ -21,7 +21,7 @@ STATUS = {0: "BT_OK", 1: "BT_PENDING", -1: "BT_EINVAL", -2: "BT_ENOMEM", -3: "BT
           -4: "BT_EOVERFLOW", -5: "BT_ENOTFOUND", -6: "BT_ESTATE"}
 
 EXPORTED = ["bt_params_default", "bt_status_str", "bt_last_error", "bt_create", "bt_destroy", "bt_memory_used",
-            "bt_build_mesh", "bt_mesh_free", "bt_mesh_info", "bt_mics_grid", "bt_mics_grid3d", "bt_mics_reset", "bt_mics_free",
+            "bt_build_mesh", "bt_mesh_free", "bt_mesh_info", "bt_mics_grid", "bt_mics_grid3d", "bt_mics_subset", "bt_mics_points", "bt_mics_reset", "bt_mics_free",
             "bt_emit_beams", "bt_emit_beams_directional", "bt_beams_free", "bt_beams_stats", "bt_trace", "bt_accumulate_mics", "bt_levels",
             "bt_run", "bt_submit", "bt_poll", "bt_cancel", "bt_batch_run", "bt_batch_release", "bt_batch_autotune",
             "bt_server_create", "bt_server_submit", "bt_server_poll", "bt_server_destroy"]
@@ -82,6 +82,8 @@ def lib():
         "bt_mesh_info": (C.c_int, [P, P, P, P]),
         "bt_mics_grid": (C.c_int, [P, F32, F32, F32, F32, F32, I32, I32, P]),
         "bt_mics_grid3d": (C.c_int, [P, F32, F32, F32, F32, F32, F32, I32, I32, I32, P]),
+        "bt_mics_subset": (C.c_int, [P, P, P, I64, P]),
+        "bt_mics_points": (C.c_int, [P, P, I64, P]),
         "bt_mics_reset": (C.c_int, [P, P]),
         "bt_mics_free": (C.c_int, [P]),
         "bt_emit_beams": (C.c_int, [P, P, P, I32, I32, P]),
@@ -188,6 +190,20 @@ def bt_mics_grid(ctx, x0, y0, z, dx, dy, nx, ny):
 def bt_mics_grid3d(ctx, x0, y0, z0, dx, dy, dz, nx, ny, nz):
     out = C.c_void_p()
     _check(ctx, lib().bt_mics_grid3d(ctx, x0, y0, z0, dx, dy, dz, nx, ny, nz, C.byref(out)), "bt_mics_grid3d")
+    return out
+
+
+def bt_mics_subset(ctx, grid, idx):
+    idx = np.ascontiguousarray(idx, np.int32).ravel()
+    out = C.c_void_p()
+    _check(ctx, lib().bt_mics_subset(ctx, grid, _ptr(idx), idx.size, C.byref(out)), "bt_mics_subset")
+    return out
+
+
+def bt_mics_points(ctx, xyz):
+    xyz = np.ascontiguousarray(xyz, np.float32).reshape(-1, 3)
+    out = C.c_void_p()
+    _check(ctx, lib().bt_mics_points(ctx, _ptr(xyz), xyz.shape[0], C.byref(out)), "bt_mics_points")
     return out
 
 

@@ -273,4 +273,29 @@ hipError_t launch_levels(const double *es, const double *ef, double *level, long
     return hipGetLastError();
 }
 
+// A subset of a grid: its points' strict and flag energies and levels, in subset order.
+__global__ void k_select(const double *__restrict__ es, const double *__restrict__ ef,
+                         const long long *__restrict__ sel, long long n, double *__restrict__ out_s,
+                         double *__restrict__ out_f, double *__restrict__ out_level)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += stride) {
+        const long long i = sel[k];
+        const double a = es[i], b = ef[i], e = a + b;
+        out_s[k] = a;
+        out_f[k] = b;
+        out_level[k] = e > 0.0 ? 10.0 * log10(e / 1e-12) : -INFINITY;
+    }
+}
+
+hipError_t launch_select(const double *es, const double *ef, const long long *sel, long long n, double *out_s,
+                         double *out_f, double *out_level, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    k_select<<<(unsigned)blocks, 256, 0, s>>>(es, ef, sel, n, out_s, out_f, out_level);
+    return hipGetLastError();
+}
+
 }  // namespace bt

@@ -658,8 +658,140 @@ extern "C" bt_status bt_mics_grid3d(bt_ctx *ctx, float x0, float y0, float z0, f
     m->dev.e_strict = (double *)p;
     m->dev.e_flag = m->dev.e_strict + n;
     m->level = m->dev.e_flag + n;
+    m->n_out = n;
     s = bt_mics_reset(ctx, m);
     if (s != BT_OK) { bt_mics_free(m); return s; }
+    *out = m;
+    return BT_OK;
+}
+
+// Energies a set holds: a grid's (also for a subset of it) or one per explicit point.
+static long long mic_energies(const bt_mics *m)
+{
+    return m->points ? m->pts.n : (long long)m->dev.nx * m->dev.ny * m->dev.nz;
+}
+
+extern "C" bt_status bt_mics_subset(bt_ctx *ctx, const bt_mics *grid, const int32_t *idx, int64_t n, bt_mics **out)
+{
+    if (!ctx) return BT_EINVAL;
+    if (!out) return fail(ctx, BT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!grid || grid->points || grid->sel) return fail(ctx, BT_EINVAL, "a subset is taken of a grid set");
+    if (n < 1 || !idx) return fail(ctx, BT_EINVAL, "empty or NULL subset");
+    const long long N = mic_energies(grid);
+    for (int64_t k = 0; k < n; ++k)
+        if (idx[k] < 0 || idx[k] >= N) return fail(ctx, BT_EINVAL, "subset index %d not in [0, %lld)", idx[k], N);
+    (void)hipSetDevice(ctx->device);
+    bt_mics *m = new bt_mics();
+    m->ctx = ctx;
+    m->dev = grid->dev;
+    m->bytes = (size_t)N * sizeof(double) * 3;
+    m->mask_bytes = (size_t)((N + 31) / 32) * sizeof(unsigned);
+    void *p = nullptr, *q = nullptr, *r = nullptr, *t = nullptr;
+    bt_status s = dev_alloc(ctx, &p, m->bytes);
+    if (s == BT_OK) s = dev_alloc(ctx, &q, m->mask_bytes);
+    if (s == BT_OK) s = dev_alloc(ctx, &r, (size_t)n * sizeof(long long));
+    if (s == BT_OK) s = dev_alloc(ctx, &t, (size_t)n * 3 * sizeof(double));
+    m->dev.e_strict = (double *)p;
+    m->mask = (unsigned *)q;
+    m->sel = (long long *)r;
+    m->sel_buf = (double *)t;
+    m->n_out = n;
+    if (s != BT_OK) { bt_mics_free(m); return s; }
+    m->dev.e_flag = m->dev.e_strict + N;
+    m->level = m->dev.e_flag + N;
+    m->dev.mask = m->mask;
+    std::vector<unsigned> bits((size_t)((N + 31) / 32), 0u);
+    std::vector<long long> sel((size_t)n);
+    for (int64_t k = 0; k < n; ++k) {
+        bits[(size_t)(idx[k] >> 5)] |= 1u << (idx[k] & 31);
+        sel[(size_t)k] = idx[k];
+    }
+    if (hipMemcpy(m->mask, bits.data(), m->mask_bytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->sel, sel.data(), (size_t)n * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess) {
+        bt_mics_free(m);
+        return fail(ctx, BT_EDEVICE, "subset upload failed");
+    }
+    if ((s = bt_mics_reset(ctx, m)) != BT_OK) { bt_mics_free(m); return s; }
+    *out = m;
+    return BT_OK;
+}
+
+extern "C" bt_status bt_mics_points(bt_ctx *ctx, const float *xyz, int64_t n, bt_mics **out)
+{
+    if (!ctx) return BT_EINVAL;
+    if (!out) return fail(ctx, BT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !xyz || n >= (1ll << 31)) return fail(ctx, BT_EINVAL, "bad microphone point count %lld", (long long)n);
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t k = 0; k < n; ++k)
+        for (int c = 0; c < 3; ++c) {
+            const float v = xyz[3 * k + c];
+            if (!std::isfinite(v)) return fail(ctx, BT_EINVAL, "microphone point %lld is not finite", (long long)k);
+            lo[c] = std::min(lo[c], (double)v);
+            hi[c] = std::max(hi[c], (double)v);
+        }
+    // buckets in xy of about four points each; one spare column and row, so that no
+    // point's bucket is clamped
+    const double sx = hi[0] - lo[0], sy = hi[1] - lo[1];
+    double bh = std::sqrt(std::max(sx * sy, 0.0) / std::max((double)n / 4.0, 1.0));
+    bh = std::max(bh, std::max(std::max(sx, sy) / 4096.0, 1e-3));
+    const int nbx = (int)std::floor(sx / bh) + 2, nby = (int)std::floor(sy / bh) + 2;
+    const long long nb = (long long)nbx * nby;
+    std::vector<int> cell((size_t)nb + 1, 0), key((size_t)n);
+    for (int64_t k = 0; k < n; ++k) {
+        const int bi = (int)std::floor(((double)xyz[3 * k] - lo[0]) / bh);
+        const int bj = (int)std::floor(((double)xyz[3 * k + 1] - lo[1]) / bh);
+        key[(size_t)k] = bj * nbx + bi;
+        cell[(size_t)key[(size_t)k] + 1]++;
+    }
+    for (long long b = 0; b < nb; ++b) cell[(size_t)b + 1] += cell[(size_t)b];
+    std::vector<double> pos((size_t)n * 3);
+    std::vector<int> orig((size_t)n), fill(cell.begin(), cell.end() - 1);
+    for (int64_t k = 0; k < n; ++k) {
+        const int at = fill[(size_t)key[(size_t)k]]++;
+        pos[(size_t)at] = xyz[3 * k];
+        pos[(size_t)n + at] = xyz[3 * k + 1];
+        pos[2 * (size_t)n + at] = xyz[3 * k + 2];
+        orig[(size_t)at] = (int)k;
+    }
+    (void)hipSetDevice(ctx->device);
+    bt_mics *m = new bt_mics();
+    m->ctx = ctx;
+    m->points = true;
+    m->n_out = n;
+    m->bytes = (size_t)n * sizeof(double) * 3;
+    m->pts_bytes = (size_t)n * 3 * sizeof(double) + (size_t)n * sizeof(int) + (size_t)(nb + 1) * sizeof(int);
+    void *p = nullptr, *q = nullptr;
+    bt_status s = dev_alloc(ctx, &p, m->bytes);
+    if (s == BT_OK) s = dev_alloc(ctx, &q, m->pts_bytes);
+    m->dev.e_strict = (double *)p;
+    m->pts_buf = q;
+    if (s != BT_OK) { bt_mics_free(m); return s; }
+    m->dev.e_flag = m->dev.e_strict + n;
+    m->level = m->dev.e_flag + n;
+    char *b = (char *)q;
+    DevPoints &P = m->pts;
+    P.px = (const double *)b;
+    P.py = P.px + n;
+    P.pz = P.py + n;
+    P.orig = (const int *)(b + (size_t)n * 3 * sizeof(double));
+    P.cell = P.orig + n;
+    P.bx0 = lo[0];
+    P.by0 = lo[1];
+    P.bh = bh;
+    P.nbx = nbx;
+    P.nby = nby;
+    P.zlo = lo[2];
+    P.zhi = hi[2];
+    P.n = n;
+    if (hipMemcpy(b, pos.data(), (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy((void *)P.orig, orig.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy((void *)P.cell, cell.data(), (size_t)(nb + 1) * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+        bt_mics_free(m);
+        return fail(ctx, BT_EDEVICE, "microphone point upload failed");
+    }
+    if ((s = bt_mics_reset(ctx, m)) != BT_OK) { bt_mics_free(m); return s; }
     *out = m;
     return BT_OK;
 }
@@ -673,8 +805,7 @@ extern "C" bt_status bt_mics_grid(bt_ctx *ctx, float x0, float y0, float z, floa
 extern "C" bt_status bt_mics_reset(bt_ctx *ctx, bt_mics *m)
 {
     if (!ctx || !m) return BT_EINVAL;
-    long long n = (long long)m->dev.nx * m->dev.ny * m->dev.nz;
-    HIP_TRY(ctx, launch_fill(m->dev.e_strict, 2 * n, 0.0, ctx->stream));
+    HIP_TRY(ctx, launch_fill(m->dev.e_strict, 2 * mic_energies(m), 0.0, ctx->stream));
     return BT_OK;
 }
 
@@ -686,6 +817,7 @@ bt_status mics_fit(bt_ctx *ctx, bt_mics **m, float x0, float y0, float z, float 
         g->dev.x0 = x0; g->dev.y0 = y0; g->dev.z = z; g->dev.dx = dx; g->dev.dy = dy;
         g->dev.nx = nx; g->dev.ny = ny;
         g->dev.nz = 1; g->dev.dz = 0.0;
+        g->n_out = n;
         g->dev.e_flag = g->dev.e_strict + n;
         g->level = g->dev.e_flag + n;
         return bt_mics_reset(ctx, g);
@@ -701,6 +833,10 @@ extern "C" bt_status bt_mics_free(bt_mics *m)
 {
     if (!m) return BT_EINVAL;
     dev_free(m->ctx, m->dev.e_strict, m->bytes);
+    dev_free(m->ctx, m->mask, m->mask_bytes);
+    dev_free(m->ctx, m->sel, (size_t)m->n_out * sizeof(long long));
+    dev_free(m->ctx, m->sel_buf, (size_t)m->n_out * 3 * sizeof(double));
+    dev_free(m->ctx, m->pts_buf, m->pts_bytes);
     delete m;
     return BT_OK;
 }
@@ -1084,6 +1220,12 @@ extern "C" bt_status bt_accumulate_mics(bt_ctx *ctx, const bt_mesh *mesh, bt_bea
     // all generations traced since the previous call, in one pass
     TraceArgs a = make_args(p, b->acc_gen);
     a.gen_end = b->gen;
+    if (mics->points) {
+        HIP_TRY(ctx, launch_mics_points(mesh->dev, b->q, b->segs, b->ctr, mics->dev, mics->pts, a, ctx->n_cu,
+                                        ctx->stream));
+        b->acc_gen = b->gen;
+        return BT_OK;
+    }
     if (mics->dev.nz > 1 && (s = reserve_layers(ctx, b)) != BT_OK) return s;
     MicWork w{b->rows, b->rows_cap, b->spans, b->spans_cap, b->big_list + b->cap, b->big_list, b->layers,
               b->layers_cap};
@@ -1096,7 +1238,19 @@ extern "C" bt_status bt_levels(bt_ctx *ctx, const bt_mics *m, double *strict_out
 {
     if (!ctx || !m) return BT_EINVAL;
     (void)hipSetDevice(ctx->device);
-    long long n = (long long)m->dev.nx * m->dev.ny * m->dev.nz;
+    if (m->sel) {   // a subset: its points, in subset order
+        const long long n = m->n_out;
+        const size_t bytes = (size_t)n * sizeof(double);
+        HIP_TRY(ctx, launch_select(m->dev.e_strict, m->dev.e_flag, m->sel, n, m->sel_buf, m->sel_buf + n,
+                                   m->sel_buf + 2 * n, ctx->stream));
+        if (strict_out) HIP_TRY(ctx, hipMemcpyAsync(strict_out, m->sel_buf, bytes, hipMemcpyDefault, ctx->stream));
+        if (flag_out) HIP_TRY(ctx, hipMemcpyAsync(flag_out, m->sel_buf + n, bytes, hipMemcpyDefault, ctx->stream));
+        if (level_db_out)
+            HIP_TRY(ctx, hipMemcpyAsync(level_db_out, m->sel_buf + 2 * n, bytes, hipMemcpyDefault, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        return BT_OK;
+    }
+    long long n = mic_energies(m);
     size_t bytes = (size_t)n * sizeof(double);
     if (level_db_out) {
         HIP_TRY(ctx, launch_levels(m->dev.e_strict, m->dev.e_flag, m->level, n, ctx->stream));

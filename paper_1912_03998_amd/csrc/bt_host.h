@@ -46,6 +46,17 @@ struct bt_mics {
     DevMics dev{};
     double *level = nullptr;
     size_t bytes = 0;
+    long long n_out = 0;          // values bt_levels returns
+    // subset of a grid: the grid's energies, a membership bitmap and the output indices
+    unsigned *mask = nullptr;
+    size_t mask_bytes = 0;
+    long long *sel = nullptr;     // [n_out] grid indices of the outputs
+    double *sel_buf = nullptr;    // [3 n_out] strict, flag and level staging for bt_levels
+    // explicit points
+    bool points = false;
+    DevPoints pts{};
+    void *pts_buf = nullptr;
+    size_t pts_bytes = 0;
 };
 
 struct bt_beams {

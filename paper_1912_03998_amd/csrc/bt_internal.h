@@ -117,6 +117,19 @@ struct DevMics {
     float fnx1, fny1;
 };
 
+// Explicit microphone points with a uniform-bucket index in xy: the points sorted by
+// bucket (row-major: bucket (i, j) is j nbx + i), so that a row of buckets is one
+// contiguous index range.
+struct DevPoints {
+    const double *px, *py, *pz;   // sorted positions (float32 inputs, widened)
+    const int *orig;              // original index of each sorted point (energy index)
+    const int *cell;              // [nbx nby + 1] first sorted point of each bucket
+    double bx0, by0, bh;          // bucket grid origin and bucket size
+    int nbx, nby;
+    double zlo, zhi;              // z range of the points
+    long long n;
+};
+
 // Work buffers of the microphone stage: (segment, row) items of wide footprints,
 // (segment, row, first column, last column) spans of long rows, and the overflow list
 // of segments handled one wave each.
@@ -198,6 +211,10 @@ hipError_t launch_emit_table(const double *base20, const EmitTable &t, long long
 // Zero d->n_fill doubles at p; gather d->n_out outputs (e[i] + e[stride + i] and
 // e[stride + i] for i = idx[k]).  max_n bounds the sizes (grid size).
 hipError_t launch_fill_desc(double *p, const BatchDesc *d, long long max_n, hipStream_t s);
+hipError_t launch_mics_points(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mics,
+                              DevPoints pts, const TraceArgs &a, int n_cu, hipStream_t s);
+hipError_t launch_select(const double *es, const double *ef, const long long *sel, long long n, double *out_s,
+                         double *out_f, double *out_level, hipStream_t s);
 hipError_t launch_gather(const double *e, const long long *idx, const BatchDesc *d, long long max_n, double *out_e,
                          double *out_f, hipStream_t s);
 hipError_t launch_trace(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, const TraceArgs &a,

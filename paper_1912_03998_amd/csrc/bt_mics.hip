@@ -213,7 +213,7 @@ __device__ __forceinline__ int mic_apply(const Frustum &f, const DevMics &mc, in
     }
     if (!inside) return 0;
     const long long idx = ((long long)k * mc.ny + j) * mc.nx + i;
-    if (kSlots && mc.mask && !((mc.mask[idx >> 5] >> (idx & 31)) & 1u)) return 0;
+    if (mc.mask && !((mc.mask[idx >> 5] >> (idx & 31)) & 1u)) return 0;  // subsets
     const double d2 = dot(r, r);
     float e = f.K / (float)d2;
     if (air_m > 0.0) e *= expf(-(float)(air_m * sqrt(d2)));
@@ -768,10 +768,9 @@ __device__ __forceinline__ int layer_fast(const VolStage &st, int l, const DevMi
 // microphones inside.  Same products, sums and decisions as mic_apply (for a microphone
 // inside, no plane test is negative, so only `near_any` decides ambiguity).
 template <class Stage>
-__device__ __forceinline__ int mic_apply_staged(const Stage &st, int l, const DevMics &mc, int i, int j, int k,
-                                                double d2, double air_m)
+__device__ __forceinline__ int staged_contribute(const Stage &st, int l, V3 m, long long idx, double *e_strict,
+                                                 double *e_flag, const unsigned *mask, double d2, double air_m)
 {
-    const V3 m = {mc.x0 + (double)i * mc.dx, mc.y0 + (double)j * mc.dy, mc.z + (double)k * mc.dz};
     const V3 A = {st.f[0][l], st.f[1][l], st.f[2][l]};
     const V3 r = m - A;
     double sd[3];
@@ -801,12 +800,21 @@ __device__ __forceinline__ int mic_apply_staged(const Stage &st, int l, const De
     for (int e = 0; e < 3; ++e) near_any = near_any || sd[e] * sd[e] < d2 * dot(n[e], n[e]);
     if (bits & 1) near_any = near_any || sn * sn < d2 * dot(Nn, Nn);
     if (bits & 2) near_any = near_any || sf * sf < d2 * dot(Nf, Nf);
-    const long long idx = ((long long)k * mc.ny + j) * mc.nx + i;
+    if (mask && !((mask[idx >> 5] >> (idx & 31)) & 1u)) return 0;
     const double dd = dot(r, r);
     float e = st.K[l] / (float)dd;
     if (air_m > 0.0) e *= expf(-(float)(air_m * sqrt(dd)));
-    atomicAdd(((bits & 4) || near_any) ? &mc.e_flag[idx] : &mc.e_strict[idx], (double)e);
+    atomicAdd(((bits & 4) || near_any) ? &e_flag[idx] : &e_strict[idx], (double)e);
     return 1;
+}
+
+template <class Stage>
+__device__ __forceinline__ int mic_apply_staged(const Stage &st, int l, const DevMics &mc, int i, int j, int k,
+                                                double d2, double air_m)
+{
+    const V3 m = {mc.x0 + (double)i * mc.dx, mc.y0 + (double)j * mc.dy, mc.z + (double)k * mc.dz};
+    return staged_contribute(st, l, m, ((long long)k * mc.ny + j) * mc.nx + i, mc.e_strict, mc.e_flag, mc.mask, d2,
+                             air_m);
 }
 
 // One wave per block (the block's LDS is its staging), 4 waves per SIMD: at most 128 VGPRs.
@@ -1042,6 +1050,202 @@ __global__ void __launch_bounds__(64, 3) k_mics3d_general(DevMesh M, DevQueue q,
         __syncthreads();
     }
     flush_mic_counters(ctr, tests, updates);
+}
+
+// ---------------------------------------------------------------------------------------
+// Explicit microphone points
+//   k_mics_points: one wave per kVolSeg segments: each lane bounds its frustum within the
+//   points' z range in xy, the (segment, bucket row) pairs are spread evenly over the
+//   lanes (a bucket row is one contiguous range of sorted points), then the points of the
+//   ranges are spread evenly over the lanes and tested against the staged frustums.
+// ---------------------------------------------------------------------------------------
+
+// xy box of the part of a segment's frustum with z in [zlo, zhi], widened for rounding;
+// false when empty.  The frustum lies in the tetrahedron of the apex and the edge rays'
+// crossings of the hit plane (when all three cross it ahead of the apex), else in the cone
+// of the edge directions.  The tetrahedron (or, when every edge rises or every edge falls,
+// the cone) cut by the slab is the convex hull of its vertices inside the slab and its
+// edges' crossings of the slab's planes; any other cone is unbounded in the slab.
+__device__ bool seg_slab_box(const DevMesh &M, const DevQueue &q, long long i, int hit, V3 A, const V3 *d,
+                             double zlo, double zhi, double &x0, double &x1, double &y0, double &y1, bool &all)
+{
+    V3 P[3];
+    bool cut = hit >= 0;
+    if (cut) {
+        V3 v0, v1, v2;
+        tri_vertices(M.tri_g, hit, v0, v1, v2);
+        const V3 c = ld3(q.dbl + D_C * q.cap, q.cap, i);
+        V3 Nf = cross(v1 - v0, v2 - v0);
+        if (!(dot(c, Nf) > 0.0)) Nf = -1.0 * Nf;
+        const double c0 = dot(Nf, v0 - A);
+        cut = c0 > 0.0;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            const double g = dot(Nf, d[e]);
+            cut = cut && g > 0.0;
+            P[e] = A + (c0 / g) * d[e];
+        }
+    }
+    x0 = y0 = INFINITY;
+    x1 = y1 = -INFINITY;
+    double mag = fmax(fabs(A.x), fabs(A.y));
+    auto take = [&](V3 p) {
+        x0 = fmin(x0, p.x); x1 = fmax(x1, p.x);
+        y0 = fmin(y0, p.y); y1 = fmax(y1, p.y);
+        mag = fmax(mag, fmax(fabs(p.x), fabs(p.y)));
+    };
+    auto crossing = [&](V3 u, V3 v) {  // segment u-v against the two planes
+        const double zc[2] = {zlo, zhi};
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if ((u.z - zc[h]) * (v.z - zc[h]) < 0.0) take(u + ((zc[h] - u.z) / (v.z - u.z)) * (v - u));
+    };
+    auto inside = [&](V3 p) { return p.z >= zlo && p.z <= zhi; };
+    all = false;
+    if (inside(A)) take(A);
+    if (cut && isfinite(P[0].x + P[0].y + P[0].z + P[1].x + P[1].y + P[1].z + P[2].x + P[2].y + P[2].z)) {
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            if (inside(P[e])) take(P[e]);
+            crossing(A, P[e]);
+            crossing(P[e], P[(e + 1) % 3]);
+        }
+    } else {
+        const bool up = d[0].z > 0.0 && d[1].z > 0.0 && d[2].z > 0.0;
+        const bool down = d[0].z < 0.0 && d[1].z < 0.0 && d[2].z < 0.0;
+        if (!up && !down) {
+            all = true;   // horizontal directions in the cone: unbounded in the slab
+            return true;
+        }
+        // every edge crosses each plane at most once, ahead of the apex when it lies on
+        // its way: the crossings (t >= 0) and the apex bound the cut cone
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            const double zc[2] = {zlo, zhi};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const double t = (zc[h] - A.z) / d[e].z;
+                if (t >= 0.0) take(A + t * d[e]);
+            }
+        }
+    }
+    if (!(x0 <= x1 && y0 <= y1)) return false;
+    if (!isfinite(mag)) {
+        all = true;
+        return true;
+    }
+    const double slack = 1e-6 + 1e-9 * mag;
+    x0 -= slack; x1 += slack; y0 -= slack; y1 += slack;
+    return true;
+}
+
+struct PtsStage {
+    double f[kVolF][kVolSeg];     // frustum, as VolStage
+    float K[kVolSeg];
+    int bits[kVolSeg];            // 1 near cap, 2 far cap, 4 flagged
+    int bi0[kVolSeg], bi1[kVolSeg], bj0[kVolSeg];   // bucket columns and first bucket row
+    alignas(16) int prefix[kVolSeg + 4];  // exclusive scan of the segments' bucket rows
+    alignas(16) int psk1[4];
+    alignas(16) int psk2[16];
+    alignas(16) int cprefix[68];  // exclusive scan of the row chunk's point counts
+    alignas(16) int csk1[4];
+    alignas(16) int csk2[16];
+    int2 range[64];               // row chunk: (slot, first sorted point)
+};
+
+__global__ void __launch_bounds__(64, 3) k_mics_points(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
+                                                       DevMics mc, DevPoints pts, TraceArgs a)
+{
+    __shared__ PtsStage st;
+    const unsigned long long s0 = gen_start(ctr, a.gen);
+    const unsigned long long n = gen_start(ctr, a.gen_end) - s0;
+    const int lane = lane_id();
+    unsigned tests = 0, updates = 0;
+    for (unsigned long long base = (unsigned long long)blockIdx.x * kVolSeg; base < n;
+         base += (unsigned long long)gridDim.x * kVolSeg) {
+        int nrows = 0;
+        if (lane < kVolSeg && base + (unsigned long long)lane < n) {
+            const long long i = (long long)(s0 + base) + lane;
+            const V3 A = ld3(q.dbl + D_A * q.cap, q.cap, i);
+            V3 d[3];
+            d[0] = ld3(q.dbl + D_D0 * q.cap, q.cap, i);
+            d[1] = ld3(q.dbl + D_D1 * q.cap, q.cap, i);
+            d[2] = ld3(q.dbl + D_D2 * q.cap, q.cap, i);
+            double x0, x1, y0, y1;
+            bool all;
+            if (seg_slab_box(M, q, i, segs.hit[i], A, d, pts.zlo, pts.zhi, x0, x1, y0, y1, all)) {
+                int i0 = 0, i1 = pts.nbx - 1, j0 = 0, j1 = pts.nby - 1;
+                if (!all) {
+                    const double fi0 = fmax(floor((x0 - pts.bx0) / pts.bh), 0.0);
+                    const double fi1 = fmin(floor((x1 - pts.bx0) / pts.bh), (double)(pts.nbx - 1));
+                    const double fj0 = fmax(floor((y0 - pts.by0) / pts.bh), 0.0);
+                    const double fj1 = fmin(floor((y1 - pts.by0) / pts.bh), (double)(pts.nby - 1));
+                    if (fi0 <= fi1 && fj0 <= fj1) {
+                        i0 = (int)fi0; i1 = (int)fi1; j0 = (int)fj0; j1 = (int)fj1;
+                    } else {
+                        j1 = -1;
+                    }
+                }
+                if (j0 <= j1) {
+                    nrows = j1 - j0 + 1;
+                    Frustum f{};
+                    load_frustum(M, q, segs, i, a.delta, f);
+                    stage_frustum(st, lane, f);
+                    st.bits[lane] = (f.has_near ? 1 : 0) | (f.has_far ? 2 : 0) | (f.flag ? 4 : 0);
+                    st.K[lane] = f.K;
+                    st.bi0[lane] = i0;
+                    st.bi1[lane] = i1;
+                    st.bj0[lane] = j0;
+                }
+            }
+        }
+        int total;
+        const int pre = wave_excl_scan(nrows, total);
+        if (lane < kVolSeg) {
+            st.prefix[lane] = pre;
+            write_skips<8>(st.psk1, st.psk2, lane, pre);
+        }
+        __syncthreads();
+        for (int rb = 0; rb < total; rb += 64) {
+            const int r = rb + lane;
+            int cnt = 0, slot = 0, first = 0;
+            if (r < total) {
+                slot = owner32(st.prefix, st.psk1, st.psk2, r);
+                const int j = st.bj0[slot] + (r - st.prefix[slot]);
+                first = pts.cell[j * pts.nbx + st.bi0[slot]];
+                cnt = pts.cell[j * pts.nbx + st.bi1[slot] + 1] - first;
+            }
+            int ctotal;
+            const int cpre = wave_excl_scan(cnt, ctotal);
+            st.cprefix[lane] = cpre;
+            write_skips<16>(st.csk1, st.csk2, lane, cpre);
+            st.range[lane] = make_int2(slot, first);
+            __syncthreads();
+            for (int cb = 0; cb < ctotal; cb += 64) {
+                const int c = cb + lane;
+                if (c < ctotal) {
+                    const int rl = owner64(st.cprefix, st.csk1, st.csk2, c);
+                    const int2 rg = st.range[rl];
+                    const int k = rg.y + (c - st.cprefix[rl]);
+                    const V3 m = {pts.px[k], pts.py[k], pts.pz[k]};
+                    tests++;
+                    updates += staged_contribute(st, rg.x, m, (long long)pts.orig[k], mc.e_strict, mc.e_flag,
+                                                 (const unsigned *)nullptr, a.delta2, a.air_m);
+                }
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+    }
+    flush_mic_counters(ctr, tests, updates);
+}
+
+hipError_t launch_mics_points(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mics,
+                              DevPoints pts, const TraceArgs &a, int n_cu, hipStream_t s)
+{
+    if (a.scenarios || pts.n <= 0 || pts.nbx <= 0 || pts.nby <= 0) return hipErrorInvalidValue;
+    k_mics_points<<<n_cu * 12, 64, 0, s>>>(m, q, segs, ctr, mics, pts, a);
+    return hipGetLastError();
 }
 
 template <bool kSlots>
