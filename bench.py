@@ -170,6 +170,48 @@ def serve_bench(sess, rates, n_of_rate, warm_frac=0.1, seed=0, saturation=400):
     return res
 
 
+def points_bench(sess, scene, n_points=100_000, steps=3, seed=0):
+    """Explicit receivers on the district: n_points uniform over the 2 x 2 km at heights
+    U(1.5, 30) m, all sources, against the planar grid pass of the same step."""
+    import numpy as np
+    import torch
+    from paper_1912_03998_amd import bt
+
+    rng = np.random.default_rng(seed)
+    pts = rng.uniform([-1000.0, -1000.0, 1.5], [1000.0, 1000.0, 30.0], (n_points, 3)).astype(np.float32)
+    ctx, mesh, stream = sess.ctx, sess.mesh, sess.stream
+    params = sess.params(scene.depth)
+    t0 = time.perf_counter()
+    mics = bt.bt_mics_points(ctx, pts)
+    torch.cuda.synchronize()
+    index_s = time.perf_counter() - t0
+    src = np.ascontiguousarray(scene.sources, np.float32)
+    pw = np.ascontiguousarray(scene.power, np.float32)
+    mic_ms, upd = [], 0
+    for k in range(steps + 1):
+        sess.beams = bt.bt_emit_beams(ctx, src, pw, scene.level, sess.beams)
+        bt.bt_mics_reset(ctx, mics)
+        for _ in range(scene.depth + 1):
+            bt.bt_trace(ctx, mesh, sess.beams, params)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        bt.bt_accumulate_mics(ctx, mesh, sess.beams, params, mics)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        if k > 0:
+            mic_ms.append(ev[0].elapsed_time(ev[1]))
+        st = bt.bt_beams_stats(ctx, sess.beams)
+        upd = st["mic_updates"]
+    e = np.zeros(n_points)
+    bt.bt_levels(ctx, mics, e, None, None)
+    bt.bt_mics_free(mics)
+    ms = sorted(mic_ms)[len(mic_ms) // 2]
+    return {"workload": f"district, all sources, {n_points} receivers uniform over the district at 1.5-30 m",
+            "mic_stage_ms": round(ms, 3), "mic_updates_per_step": upd, "mic_tests_per_step": st["mic_tests"],
+            "mic_updates_per_s": upd / (ms * 1e-3), "receivers_reached": int((e > 0).sum()),
+            "index_build_s": round(index_s, 3)}
+
+
 def volumetric_bench(steps, warmup, chunk=7, level=8, oracle_sample=True):
     """The paper's experiment shape: the tall 2.5 x 1.5 km district (towers of 200 m and
     more), 49 street sources x 20 * 4**level beams, depth 8, microphones every 4 m filling
@@ -279,6 +321,7 @@ def main():
     ap.add_argument("--serve-full", action="store_true",
                     help="serving at the full stream lengths (200 warm-up + 2000 requests per rate)")
     ap.add_argument("--no-volumetric", action="store_true", help="skip the volumetric (tall district) measurement")
+    ap.add_argument("--no-points", action="store_true", help="skip the explicit-receiver measurement")
     ap.add_argument("--volumetric-only", action="store_true",
                     help="only the volumetric measurement (prints its JSON object; for profiling)")
     ap.add_argument("--vol-chunk", type=int, default=7, help="sources per beam set in the volumetric measurement")
@@ -414,6 +457,8 @@ def main():
         "end_to_end_segments_per_s": segs / (setup_s + ms_per_step * 1e-3),
         "kernel_sha256_16": kernel_hash(),
     }
+    if args.config == 2 and not args.no_points:
+        out["points"] = points_bench(sess, scene)
     if args.config == 2 and not args.no_batch:
         out["batched"] = batch_bench(sess)
     if args.config == 2 and not args.no_serve:

@@ -1139,11 +1139,60 @@ __device__ bool seg_slab_box(const DevMesh &M, const DevQueue &q, long long i, i
     return true;
 }
 
+// A convex polygon of at most kPolyMax vertices in xy.
+constexpr int kPolyMax = 8;
+struct Poly {
+    double x[kPolyMax], y[kPolyMax];
+    int n;
+};
+
+// Keeps the part of p with a x + b y + c >= 0 (Sutherland-Hodgman on a convex polygon).
+__device__ __forceinline__ void clip_poly(Poly &p, double a, double b, double c)
+{
+    Poly o;
+    o.n = 0;
+    for (int k = 0; k < p.n; ++k) {
+        const int l = k + 1 < p.n ? k + 1 : 0;
+        const double sk = a * p.x[k] + b * p.y[k] + c, sl = a * p.x[l] + b * p.y[l] + c;
+        if (sk >= 0.0 && o.n < kPolyMax) { o.x[o.n] = p.x[k]; o.y[o.n] = p.y[k]; o.n++; }
+        if ((sk >= 0.0) != (sl >= 0.0) && o.n < kPolyMax) {
+            const double t = sk / (sk - sl);
+            o.x[o.n] = p.x[k] + t * (p.x[l] - p.x[k]);
+            o.y[o.n] = p.y[k] + t * (p.y[l] - p.y[k]);
+            o.n++;
+        }
+    }
+    p = o;
+}
+
+// The wedge of xy directions a cone's edges span (their projections), as two half-planes
+// through the apex's projection: false when the projections span half the plane or more
+// (or nearly), the cone then being unbounded in every xy direction.
+__device__ __forceinline__ bool cone_wedge(const V3 *d, double &ua, double &ub, double &va, double &vb)
+{
+    // the pair (u, v) with the third direction between them, counter-clockwise u -> v
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int e = k >> 1, f = (e + 1 + (k & 1)) % 3, g = 3 - e - f;
+        const double uxv = d[e].x * d[f].y - d[e].y * d[f].x;
+        const double uxw = d[e].x * d[g].y - d[e].y * d[g].x, wxv = d[g].x * d[f].y - d[g].y * d[f].x;
+        const double lu = fabs(d[e].x) + fabs(d[e].y), lv = fabs(d[f].x) + fabs(d[f].y);
+        // clearly less than half a turn (sine above 1e-6 of the L1 lengths), w inside
+        if (uxv > 1e-6 * lu * lv && uxw >= 0.0 && wxv >= 0.0) {
+            ua = d[e].x; ub = d[e].y; va = d[f].x; vb = d[f].y;
+            return true;
+        }
+    }
+    return false;
+}
+
 struct PtsStage {
     double f[kVolF][kVolSeg];     // frustum, as VolStage
+    double px[kPolyMax][kVolSeg], py[kPolyMax][kVolSeg];   // its xy region in the points' slab
+    int pn[kVolSeg];
     float K[kVolSeg];
     int bits[kVolSeg];            // 1 near cap, 2 far cap, 4 flagged
-    int bi0[kVolSeg], bi1[kVolSeg], bj0[kVolSeg];   // bucket columns and first bucket row
+    int bj0[kVolSeg];             // first bucket row
     alignas(16) int prefix[kVolSeg + 4];  // exclusive scan of the segments' bucket rows
     alignas(16) int psk1[4];
     alignas(16) int psk2[16];
@@ -1151,6 +1200,7 @@ struct PtsStage {
     alignas(16) int csk1[4];
     alignas(16) int csk2[16];
     int2 range[64];               // row chunk: (slot, first sorted point)
+    double slack[kVolSeg];        // rounding allowance of the region
 };
 
 __global__ void __launch_bounds__(64, 3) k_mics_points(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
@@ -1174,28 +1224,51 @@ __global__ void __launch_bounds__(64, 3) k_mics_points(DevMesh M, DevQueue q, De
             double x0, x1, y0, y1;
             bool all;
             if (seg_slab_box(M, q, i, segs.hit[i], A, d, pts.zlo, pts.zhi, x0, x1, y0, y1, all)) {
-                int i0 = 0, i1 = pts.nbx - 1, j0 = 0, j1 = pts.nby - 1;
-                if (!all) {
-                    const double fi0 = fmax(floor((x0 - pts.bx0) / pts.bh), 0.0);
-                    const double fi1 = fmin(floor((x1 - pts.bx0) / pts.bh), (double)(pts.nbx - 1));
-                    const double fj0 = fmax(floor((y0 - pts.by0) / pts.bh), 0.0);
-                    const double fj1 = fmin(floor((y1 - pts.by0) / pts.bh), (double)(pts.nby - 1));
-                    if (fi0 <= fi1 && fj0 <= fj1) {
-                        i0 = (int)fi0; i1 = (int)fi1; j0 = (int)fj0; j1 = (int)fj1;
-                    } else {
-                        j1 = -1;
+                // the box (the points' extent when unbounded), cut by the cone's xy wedge
+                const double gx0 = pts.bx0, gx1 = pts.bx0 + pts.nbx * pts.bh;
+                const double gy0 = pts.by0, gy1 = pts.by0 + pts.nby * pts.bh;
+                if (all) { x0 = gx0; x1 = gx1; y0 = gy0; y1 = gy1; }
+                x0 = fmax(x0, gx0); x1 = fmin(x1, gx1); y0 = fmax(y0, gy0); y1 = fmin(y1, gy1);
+                Poly pg;
+                pg.n = 0;
+                if (x0 <= x1 && y0 <= y1) {
+                    pg.n = 4;
+                    pg.x[0] = x0; pg.y[0] = y0; pg.x[1] = x1; pg.y[1] = y0;
+                    pg.x[2] = x1; pg.y[2] = y1; pg.x[3] = x0; pg.y[3] = y1;
+                    double ua, ub, va, vb;
+                    if (cone_wedge(d, ua, ub, va, vb)) {
+                        // cross(u, p - a) >= 0 and cross(p - a, v) >= 0, each relaxed
+                        const double mg = fmax(fmax(fabs(A.x), fabs(A.y)), fmax(fmax(fabs(x0), fabs(x1)),
+                                                                                fmax(fabs(y0), fabs(y1))));
+                        const double lu = fabs(ua) + fabs(ub), lv = fabs(va) + fabs(vb);
+                        clip_poly(pg, -ub, ua, ub * A.x - ua * A.y + (1e-6 + 1e-9 * mg) * lu);
+                        clip_poly(pg, vb, -va, va * A.y - vb * A.x + (1e-6 + 1e-9 * mg) * lv);
                     }
                 }
-                if (j0 <= j1) {
-                    nrows = j1 - j0 + 1;
-                    Frustum f{};
-                    load_frustum(M, q, segs, i, a.delta, f);
-                    stage_frustum(st, lane, f);
-                    st.bits[lane] = (f.has_near ? 1 : 0) | (f.has_far ? 2 : 0) | (f.flag ? 4 : 0);
-                    st.K[lane] = f.K;
-                    st.bi0[lane] = i0;
-                    st.bi1[lane] = i1;
-                    st.bj0[lane] = j0;
+                double py0 = INFINITY, py1 = -INFINITY, mag = 1.0;
+                for (int v = 0; v < pg.n; ++v) {
+                    py0 = fmin(py0, pg.y[v]); py1 = fmax(py1, pg.y[v]);
+                    mag = fmax(mag, fmax(fabs(pg.x[v]), fabs(pg.y[v])));
+                }
+                const double sl = 1e-6 + 1e-9 * mag;
+                if (pg.n >= 3) {
+                    const double fj0 = fmax(floor((py0 - sl - pts.by0) / pts.bh), 0.0);
+                    const double fj1 = fmin(floor((py1 + sl - pts.by0) / pts.bh), (double)(pts.nby - 1));
+                    if (fj0 <= fj1) {
+                        nrows = (int)fj1 - (int)fj0 + 1;
+                        Frustum f{};
+                        load_frustum(M, q, segs, i, a.delta, f);
+                        stage_frustum(st, lane, f);
+                        st.bits[lane] = (f.has_near ? 1 : 0) | (f.has_far ? 2 : 0) | (f.flag ? 4 : 0);
+                        st.K[lane] = f.K;
+                        st.bj0[lane] = (int)fj0;
+                        st.pn[lane] = pg.n;
+                        st.slack[lane] = sl;
+                        for (int v = 0; v < pg.n; ++v) {
+                            st.px[v][lane] = pg.x[v];
+                            st.py[v][lane] = pg.y[v];
+                        }
+                    }
                 }
             }
         }
@@ -1212,8 +1285,32 @@ __global__ void __launch_bounds__(64, 3) k_mics_points(DevMesh M, DevQueue q, De
             if (r < total) {
                 slot = owner32(st.prefix, st.psk1, st.psk2, r);
                 const int j = st.bj0[slot] + (r - st.prefix[slot]);
-                first = pts.cell[j * pts.nbx + st.bi0[slot]];
-                cnt = pts.cell[j * pts.nbx + st.bi1[slot] + 1] - first;
+                // x extent of the region within the bucket row's strip (widened)
+                const double sl = st.slack[slot];
+                const double ya = pts.by0 + j * pts.bh - sl, yb = pts.by0 + (j + 1) * pts.bh + sl;
+                const int np = st.pn[slot];
+                double xa = INFINITY, xb = -INFINITY;
+                for (int v = 0; v < np; ++v) {
+                    const int w = v + 1 < np ? v + 1 : 0;
+                    const double x1 = st.px[v][slot], y1 = st.py[v][slot];
+                    const double x2 = st.px[w][slot], y2 = st.py[w][slot];
+                    if (y1 >= ya && y1 <= yb) { xa = fmin(xa, x1); xb = fmax(xb, x1); }
+                    const double yc[2] = {ya, yb};
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+                        if ((y1 - yc[h]) * (y2 - yc[h]) < 0.0) {
+                            const double x = x1 + (yc[h] - y1) / (y2 - y1) * (x2 - x1);
+                            xa = fmin(xa, x); xb = fmax(xb, x);
+                        }
+                }
+                if (xa <= xb) {
+                    const int bi0 = (int)fmax(floor((xa - sl - pts.bx0) / pts.bh), 0.0);
+                    const int bi1 = (int)fmin(floor((xb + sl - pts.bx0) / pts.bh), (double)(pts.nbx - 1));
+                    if (bi0 <= bi1) {
+                        first = pts.cell[j * pts.nbx + bi0];
+                        cnt = pts.cell[j * pts.nbx + bi1 + 1] - first;
+                    }
+                }
             }
             int ctotal;
             const int cpre = wave_excl_scan(cnt, ctotal);
