@@ -127,7 +127,7 @@ bt_status bt_mics_grid(bt_ctx *ctx, float x0, float y0, float z, float dx, float
 /* Microphones on a regular volumetric grid (paper Section 4: the experiment fills the
  * model's bounding box with microphones, one every 4 m in each direction):
  * positions (x0 + i dx, y0 + j dy, z0 + k dz), i < nx, j < ny, k < nz, index
- * (k ny + j) nx + i; nx ny nz <= 2^31; when nz > 1, dz > 0 and nx, ny < 2^24.  nz = 1
+ * (k ny + j) nx + i; nx ny nz <= 2^31; when nz > 1, dz > 0, nx, ny < 2^24 and nz < 2^25.  nz = 1
  * is bt_mics_grid.
  * Energies (bt_levels returns nx ny nz values) are owned by the set and start at zero.
  * Usable with bt_accumulate_mics and bt_run; the scenario and serving interfaces take

@@ -632,8 +632,9 @@ extern "C" bt_status bt_mics_grid3d(bt_ctx *ctx, float x0, float y0, float z0, f
     *out = nullptr;
     if (nx < 1 || ny < 1 || nz < 1 || (int64_t)nx * ny * nz > (1ll << 31))
         return fail(ctx, BT_EINVAL, "bad microphone grid %d x %d x %d", nx, ny, nz);
-    if (nz > 1 && (nx >= (1 << 24) || ny >= (1 << 24)))  // lattice indices stay exact in FP32
-        return fail(ctx, BT_EINVAL, "volumetric grid %d x %d x %d: nx and ny must be below 2^24", nx, ny, nz);
+    if (nz > 1 && (nx >= (1 << 24) || ny >= (1 << 24) || nz >= (1 << 25)))  // FP32-exact lattice indices;
+        return fail(ctx, BT_EINVAL, "volumetric grid %d x %d x %d: nx, ny must be below 2^24 and nz below 2^25",
+                    nx, ny, nz);  // layer numbers packed beside 6-bit slots
     if (!std::isfinite(x0) || !std::isfinite(y0) || !std::isfinite(z0) || !(dx > 0.f) || !(dy > 0.f) ||
         !std::isfinite(dx) || !std::isfinite(dy) || (nz > 1 && (!(dz > 0.f) || !std::isfinite(dz))))
         return fail(ctx, BT_EINVAL, "bad microphone grid geometry");
