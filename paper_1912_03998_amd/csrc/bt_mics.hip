@@ -817,6 +817,130 @@ __device__ __forceinline__ int mic_apply_staged(const Stage &st, int l, const De
                              air_m);
 }
 
+// LDS staging of one wave of k_mics_plane: up to kVolSeg segments with candidate boxes.
+struct PlaneStage {
+    double f[kVolF][kVolSeg];   // frustum, as VolStage
+    float K[kVolSeg];
+    int bits[kVolSeg];          // 1 near cap, 2 far cap, 4 flagged
+    alignas(16) int prefix[kVolSeg + 4];  // exclusive scan of the staged boxes' sizes
+    alignas(16) int psk1[4];              // its owner32 search skips
+    alignas(16) int psk2[16];
+    int4 box[kVolSeg];          // (first column, first row, columns, -)
+};
+
+// k_mics for a planar grid of one microphone set: the same dismissal, lattice boxes and
+// general-list regions (wave w of the grid is block w here), but the candidates of the
+// boxes are not tested by their segment's lane: the segments with candidates stage their
+// frustums (kVolSeg at a time) and the candidates are spread evenly over the lanes.
+__global__ void __launch_bounds__(64, 4) k_mics_plane(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
+                                                      DevMics mc, TraceArgs a, MicWork w, WaveScratch ws)
+{
+    __shared__ PlaneStage st;
+    const unsigned long long s0 = gen_start(ctr, a.gen);
+    const unsigned long long n = gen_start(ctr, a.gen_end) - s0;
+    const int lane = lane_id();
+    const unsigned long long wave = blockIdx.x;
+    const unsigned long long region = wave * general_region(n, ws.n_waves);
+    unsigned gcount = 0, tests = 0, updates = 0;
+    for (unsigned long long base = wave * 64; base < n; base += (unsigned long long)gridDim.x * 64) {
+        const long long i = (long long)(s0 + base) + lane;
+        bool general = false, boxed = false;
+        int i0 = 0, j0 = 0, ncol = 0, nc = 0;
+        if (base + (unsigned long long)lane < n) {
+            // the crossing-triangle bound of k_mics, in the same arithmetic
+            const long long cap = q.cap;
+            const V3 A = ld3(q.dbl + D_A * cap, cap, i);
+            const double zr = mc.z - A.z;
+            bool proper = zr != 0.0;
+            bool away = zr > 1e-6 || zr < -1e-6;
+            const float zrf = (float)zr, axf = (float)A.x, ayf = (float)A.y;
+            float xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
+            float mag = fmaxf(fabsf(axf), fabsf(ayf));
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const V3 d = ld3(q.dbl + (D_D0 + 3 * k) * cap, cap, i);
+                proper = proper && (zr > 0.0 ? d.z > 0.0 : d.z < 0.0);
+                away = away && (zr > 0.0 ? d.z <= 0.0 : d.z >= 0.0);
+                const float s = zrf / (float)d.z;
+                proper = proper && isfinite(s);
+                const float sx = s * (float)d.x, sy = s * (float)d.y;
+                const float px = axf + sx, py = ayf + sy;
+                xmn = fminf(xmn, px); xmx = fmaxf(xmx, px);
+                ymn = fminf(ymn, py); ymx = fmaxf(ymx, py);
+                mag = fmaxf(mag, fmaxf(fabsf(sx), fabsf(sy)));
+            }
+            general = !away;
+            if (proper) {
+                const double relax = 1e-6 + 1e-5 * (double)mag;
+                const double idx = 1.0 / mc.dx, idy = 1.0 / mc.dy;
+                const double fi0 = fmax(ceil(((double)xmn - relax - mc.x0) * idx - 1e-9), 0.0);
+                const double fi1 = fmin(floor(((double)xmx + relax - mc.x0) * idx + 1e-9), (double)(mc.nx - 1));
+                const double fj0 = fmax(ceil(((double)ymn - relax - mc.y0) * idy - 1e-9), 0.0);
+                const double fj1 = fmin(floor(((double)ymx + relax - mc.y0) * idy + 1e-9), (double)(mc.ny - 1));
+                if (!(fi0 <= fi1 && fj0 <= fj1)) {
+                    general = false;
+                } else if ((fi1 - fi0 + 1.0) * (fj1 - fj0 + 1.0) <= (double)kSpan) {
+                    general = false;
+                    boxed = true;
+                    i0 = (int)fi0;
+                    j0 = (int)fj0;
+                    ncol = (int)fi1 - i0 + 1;
+                    nc = ncol * ((int)fj1 - j0 + 1);
+                }
+            }
+        }
+        const unsigned long long gm = __ballot(general);
+        if (general) w.general[region + gcount + __popcll(gm & ((1ull << lane) - 1ull))] = (int)i;
+        gcount += (unsigned)__popcll(gm);
+        // boxed segments, kVolSeg per round
+        unsigned long long pend = __ballot(boxed);
+        while (pend) {
+            const unsigned below = __builtin_amdgcn_mbcnt_hi((unsigned)(pend >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((unsigned)pend, 0u));
+            const bool pending = (pend >> lane) & 1ull;
+            const bool mine = pending && below < (unsigned)kVolSeg;
+            const int nmine = min(__popcll(pend), kVolSeg);
+            if (mine) {
+                Frustum f{};  // caps the segment lacks are staged as zeros
+                load_frustum(M, q, segs, i, a.delta, f);
+                stage_frustum(st, (int)below, f);
+                st.bits[below] = (f.has_near ? 1 : 0) | (f.has_far ? 2 : 0) | (f.flag ? 4 : 0);
+                st.K[below] = f.K;
+                st.box[below] = make_int4(i0, j0, ncol, 0);
+            }
+            int total;
+            const int pre = wave_excl_scan(mine ? nc : 0, total);
+            if (mine) {
+                st.prefix[below] = pre;
+                write_skips<8>(st.psk1, st.psk2, (int)below, pre);
+            }
+            // slots past the staged ones hold the total, so that no candidate maps to them
+            // (lane l fills slot l, whether or not it staged a segment itself)
+            if (lane >= nmine && lane < kVolSeg) {
+                st.prefix[lane] = total;
+                write_skips<8>(st.psk1, st.psk2, lane, total);
+            }
+            __syncthreads();
+            for (int cb = 0; cb < total; cb += 64) {
+                const int c = cb + lane;
+                if (c < total) {
+                    const int sl = owner32(st.prefix, st.psk1, st.psk2, c);
+                    const int o = c - st.prefix[sl];
+                    const int4 bx = st.box[sl];
+                    const int row = o / bx.z;
+                    tests++;
+                    updates += mic_apply_staged(st, sl, mc, bx.x + (o - row * bx.z), bx.y + row, 0, a.delta2,
+                                                a.air_m);
+                }
+            }
+            __syncthreads();
+            pend = __ballot(pending && !mine);
+        }
+    }
+    if (lane == 0) ws.general[wave] = gcount;
+    flush_mic_counters(ctr, tests, updates);
+}
+
 // One wave per block (the block's LDS is its staging), 4 waves per SIMD: at most 128 VGPRs.
 __global__ void __launch_bounds__(64, 4) k_mics3d(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
                                                    DevMics mc, TraceArgs a, MicWork w)
@@ -1352,7 +1476,12 @@ static hipError_t launch_mics_t(const DevMesh &m, DevQueue q, DevSegs segs, DevC
     // k_mics and k_mics_general must use the same grid: wave w hands its region to wave w
     const int blocks = ws.n_waves / kWavesPerBlock;
     if (blocks <= 0 || blocks * kWavesPerBlock != ws.n_waves) return hipErrorInvalidValue;
-    k_mics<kSlots><<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, mics, a, w, ws);
+    if (kSlots) {
+        k_mics<kSlots><<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, mics, a, w, ws);
+    } else {
+        // one wave per block: block w is wave w of k_mics_general's grid
+        k_mics_plane<<<ws.n_waves, 64, 0, s>>>(m, q, segs, ctr, mics, a, w, ws);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_mics_general<kSlots><<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, mics, a, w, ws);
