@@ -1099,6 +1099,52 @@ __device__ __forceinline__ bool row_cols_staged(const GenStage &st, int l, const
     return true;
 }
 
+// The rows of the wave's staged footprints (slot l has nrows rows from st.j0[l] on layer
+// st.k[l]; lane l < kVolSeg passes its slot's count), spread evenly over the lanes, each
+// finding its row's column range; then the rows' candidate microphones spread evenly over
+// the lanes and tested against the staged frustums.  Every lane of the wave calls it.
+__device__ __forceinline__ void staged_rows(GenStage &st, const DevMics &mc, int nrows, const TraceArgs &a,
+                                            unsigned &tests, unsigned &updates)
+{
+    const int lane = lane_id();
+    int total;
+    const int pre = wave_excl_scan(nrows, total);
+    if (lane < kVolSeg) {
+        st.prefix[lane] = pre;
+        write_skips<8>(st.psk1, st.psk2, lane, pre);
+    }
+    __syncthreads();
+    // rows, 64 at a time
+    for (int rb = 0; rb < total; rb += 64) {
+        const int r = rb + lane;
+        int ncol = 0, slot = 0, j = 0, c0 = 0, c1 = -1;
+        if (r < total) {
+            slot = owner32(st.prefix, st.psk1, st.psk2, r);
+            j = st.j0[slot] + (r - st.prefix[slot]);
+            if (row_cols_staged(st, slot, mc, j, c0, c1)) ncol = c1 - c0 + 1;
+        }
+        int ctotal;
+        const int cpre = wave_excl_scan(ncol, ctotal);
+        st.cprefix[lane] = cpre;
+        write_skips<16>(st.csk1, st.csk2, lane, cpre);
+        st.row[lane] = make_int4(slot, j, c0, 0);
+        __syncthreads();
+        // candidate microphones, 64 at a time
+        for (int cb = 0; cb < ctotal; cb += 64) {
+            const int c = cb + lane;
+            if (c < ctotal) {
+                const int rl = owner64(st.cprefix, st.csk1, st.csk2, c);
+                const int4 rw = st.row[rl];
+                tests++;
+                updates += mic_apply_staged(st, rw.x, mc, rw.z + (c - st.cprefix[rl]), rw.y, st.k[rw.x], a.delta2,
+                                            a.air_m);
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+}
+
 // (segment, layer) items of the clipped-footprint path, kVolSeg per wave: each lane clips
 // its item's footprint (its row range), then the rows are spread evenly over the lanes
 // (each finds its column range), then the candidate microphones are spread evenly over
@@ -1136,42 +1182,7 @@ __global__ void __launch_bounds__(64, 3) k_mics3d_general(DevMesh M, DevQueue q,
                 }
             }
         }
-        int total;
-        const int pre = wave_excl_scan(nrows, total);
-        if (lane < kVolSeg) {
-            st.prefix[lane] = pre;
-            write_skips<8>(st.psk1, st.psk2, lane, pre);
-        }
-        __syncthreads();
-        // rows, 64 at a time
-        for (int rb = 0; rb < total; rb += 64) {
-            const int r = rb + lane;
-            int ncol = 0, slot = 0, j = 0, c0 = 0, c1 = -1;
-            if (r < total) {
-                slot = owner32(st.prefix, st.psk1, st.psk2, r);
-                j = st.j0[slot] + (r - st.prefix[slot]);
-                if (row_cols_staged(st, slot, mc, j, c0, c1)) ncol = c1 - c0 + 1;
-            }
-            int ctotal;
-            const int cpre = wave_excl_scan(ncol, ctotal);
-            st.cprefix[lane] = cpre;
-            write_skips<16>(st.csk1, st.csk2, lane, cpre);
-            st.row[lane] = make_int4(slot, j, c0, 0);
-            __syncthreads();
-            // candidate microphones, 64 at a time
-            for (int cb = 0; cb < ctotal; cb += 64) {
-                const int c = cb + lane;
-                if (c < ctotal) {
-                    const int rl = owner64(st.cprefix, st.csk1, st.csk2, c);
-                    const int4 rw = st.row[rl];
-                    tests++;
-                    updates += mic_apply_staged(st, rw.x, mc, rw.z + (c - st.cprefix[rl]), rw.y, st.k[rw.x],
-                                                a.delta2, a.air_m);
-                }
-            }
-            __syncthreads();
-        }
-        __syncthreads();
+        staged_rows(st, mc, nrows, a, tests, updates);
     }
     flush_mic_counters(ctr, tests, updates);
 }
