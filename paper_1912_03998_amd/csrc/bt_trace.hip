@@ -454,58 +454,108 @@ __global__ void __launch_bounds__(256, 4) k_trace(DevMesh M, DevQueue in, DevSeg
 // One block: exclusive scan of the per-wave child counts (the children's queue offsets,
 // in wave order, so the next generation's order is deterministic) and the generation's
 // totals, summed in a fixed order.
+constexpr int kScanLds = 8192;  // wave records whose child counts k_gen_scan keeps in LDS
 __global__ void __launch_bounds__(1024) k_gen_scan(DevCounters *ctr, TraceArgs a, WaveScratch ws)
 {
-    __shared__ unsigned long long part[1024];
-    __shared__ unsigned long long sred[3][1024];
-    __shared__ double pred[1024];
-    const int t = threadIdx.x;
+    // a wave's child count is at most 64 per batch it traced, far below 2^32
+    __shared__ unsigned s_child[kScanLds];
+    __shared__ unsigned long long wtot[16];
+    __shared__ unsigned long long wred[3][16];
+    __shared__ double wpow[16];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int W = ws.n_waves;
+    const bool in_lds = W <= kScanLds;
+    // coalesced pass over the records (thread t takes t, t + 1024, ...): the totals, and
+    // the child counts into LDS
+    unsigned long long f = 0, nv = 0, tt = 0;
+    double p = 0.0;
+    constexpr int kUnroll = 8;  // records per thread whose loads are issued together
+    for (int w0 = t; w0 < W; w0 += kUnroll * 1024) {
+        unsigned long long cv[kUnroll], fv[kUnroll], nvv[kUnroll], ttv[kUnroll];
+        double pv[kUnroll];
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) {
+            const int w = w0 + k * 1024;
+            const bool ok = w < W;
+            cv[k] = ok ? ws.children[w] : 0ull;
+            fv[k] = ok ? ws.stats[3 * w] : 0ull;
+            nvv[k] = ok ? ws.stats[3 * w + 1] : 0ull;
+            ttv[k] = ok ? ws.stats[3 * w + 2] : 0ull;
+            pv[k] = ok ? ws.power[w] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) {
+            const int w = w0 + k * 1024;
+            if (w < W) {
+                if (in_lds) s_child[w] = (unsigned)cv[k];
+                f += fv[k];
+                nv += nvv[k];
+                tt += ttv[k];
+                p += pv[k];
+            }
+        }
+    }
+    __syncthreads();
+    // thread t's contiguous records [t per, t per + per) for the scan
     const int per = (W + 1023) / 1024;
     const int b0 = t * per, b1 = min(b0 + per, W);
-    unsigned long long c = 0, f = 0, nv = 0, tt = 0;
-    double p = 0.0;
-    for (int w = b0; w < b1; ++w) {
-        c += ws.children[w];
-        f += ws.stats[3 * w];
-        nv += ws.stats[3 * w + 1];
-        tt += ws.stats[3 * w + 2];
-        p += ws.power[w];
+    unsigned long long c = 0;
+    for (int w = b0; w < b1; ++w) c += in_lds ? (unsigned long long)s_child[w] : ws.children[w];
+    // block-wide exclusive scan of the per-thread child counts: within the wave by
+    // shuffles, across the 16 waves through LDS
+    unsigned long long incl = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long u = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += u;
     }
-    part[t] = c;
-    sred[0][t] = f;
-    sred[1][t] = nv;
-    sred[2][t] = tt;
-    pred[t] = p;
+    const unsigned long long sf = wave_sum_u64(f), snv = wave_sum_u64(nv), stt = wave_sum_u64(tt);
+    const double sp = wave_sum_f64(p);
+    if (lane == 63) wtot[wv] = incl;
+    if (lane == 0) {
+        wred[0][wv] = sf;
+        wred[1][wv] = snv;
+        wred[2][wv] = stt;
+        wpow[wv] = sp;
+    }
     __syncthreads();
-    // inclusive scan of part[] (Hillis-Steele)
-    for (int off = 1; off < 1024; off <<= 1) {
-        const unsigned long long v = t >= off ? part[t - off] : 0ull;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    unsigned long long run = incl - c, total = 0;
+    for (int k = 0; k < 16; ++k) {
+        if (k < wv) run += wtot[k];
+        total += wtot[k];
     }
-    unsigned long long run = t > 0 ? part[t - 1] : 0ull;
-    for (int w = b0; w < b1; ++w) {
-        ws.offset[w] = run;
-        run += ws.children[w];
-    }
-    // tree reductions of the totals
-    for (int off = 512; off > 0; off >>= 1) {
-        if (t < off) {
-            sred[0][t] += sred[0][t + off];
-            sred[1][t] += sred[1][t + off];
-            sred[2][t] += sred[2][t + off];
-            pred[t] += pred[t + off];
+    if (in_lds && total < (1ull << 32)) {
+        // offsets through LDS (each thread turns its own records' counts into offsets),
+        // then stored coalesced
+        for (int w = b0; w < b1; ++w) {
+            const unsigned cw = s_child[w];
+            s_child[w] = (unsigned)run;
+            run += cw;
         }
         __syncthreads();
+        for (int w = t; w < W; w += 1024) ws.offset[w] = s_child[w];
+    } else {
+        for (int w = b0; w < b1; ++w) {
+            ws.offset[w] = run;
+            run += in_lds ? (unsigned long long)s_child[w] : ws.children[w];
+        }
     }
+    // the generation's totals, summed over the waves in order
     if (t == 0) {
-        ctr->count[a.gen + 1] = part[1023];
-        ctr->flagged[a.gen] = sred[0][0];
-        ctr->power[a.gen] = pred[0];
-        ctr->node_visits += sred[1][0];
-        ctr->tri_tests += sred[2][0];
+        unsigned long long tc = 0, tf = 0, tn = 0, ttt = 0;
+        double tp = 0.0;
+        for (int k = 0; k < 16; ++k) {
+            tc += wtot[k];
+            tf += wred[0][k];
+            tn += wred[1][k];
+            ttt += wred[2][k];
+            tp += wpow[k];
+        }
+        ctr->count[a.gen + 1] = tc;
+        ctr->flagged[a.gen] = tf;
+        ctr->power[a.gen] = tp;
+        ctr->node_visits += tn;
+        ctr->tri_tests += ttt;
     }
 }
 
