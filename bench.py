@@ -417,7 +417,7 @@ def main():
         # the microphone stage is the five kernels of one bt_accumulate_mics call
         trace_dominant = trace_ms >= mic_ms
         dominant = "k_trace+k_gen_scan+k_reflect" if trace_dominant else \
-            "k_mics+k_mics_general+k_mic_rows+k_mics_big+k_mic_spans"
+            "k_mics_plane+k_mics_general+k_mic_rows+k_mics_big+k_mic_spans"
         t_dom = trace_ms if trace_dominant else mic_ms
         b_dom = trace_bytes if trace_dominant else mic_bytes
         launches = 3 * (D + 1) if trace_dominant else 5
