@@ -69,6 +69,22 @@ def test_free_field_direct_path(torch_cuda, level):
     assert (g.hit[:, 0] == -1).all()
 
 
+def test_free_field_fine_grid_staged_boxes(torch_cuda):
+    """A 1 cm grid 1 m above the source, level 6: most upward beams hold a few lattice
+    points, so many 64-beam batches have more than 32 segments with candidate boxes
+    (several staging rounds), and others have such segments at scattered lanes (unused
+    staging slots among used ones).  Every microphone is reached once, with the closed-form
+    energy."""
+    sc = empty_scene(level=6, src=(0.003, -0.002, 0.0), n_mic=201, spacing=0.01, mic_z=1.0)
+    say("free field, 1 cm grid, level 6")
+    with session(sc) as s:
+        g = gpu_run(s, sc, parity=False)
+    m = sc.mic_positions()
+    ref = 1.0 / (FOUR_PI * ((m - sc.sources[0].astype(np.float64)) ** 2).sum(1))
+    assert g.stats["mic_updates"] == sc.n_mic
+    assert np.abs(g.energy / ref - 1).max() < 1e-6
+
+
 @pytest.mark.parametrize("level,alpha", [(3, 0.2), (5, 0.5)])
 def test_ground_reflection_image_source(torch_cuda, level, alpha):
     sc = ground_scene(level=level, alpha=alpha)
