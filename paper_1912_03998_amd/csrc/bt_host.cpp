@@ -414,7 +414,7 @@ struct Collapse {
         const int idx = (int)(out.size() / 8);
         out.resize(out.size() + 8);
         max_push = std::max(max_push, pushed + n - 1);
-        int refs[4] = {kEmptyRoot, kEmptyRoot, kEmptyRoot, kEmptyRoot};
+        int refs[4] = {kEmptyChild, kEmptyChild, kEmptyChild, kEmptyChild};
         for (int k = 0; k < n; ++k) refs[k] = collapse(c[k].ref, pushed + n - 1);
         float v[6][4];
         for (int k = 0; k < 4; ++k)

@@ -11,12 +11,12 @@ namespace bt {
 // ---------------------------------------------------------------------------------------
 // Mesh in HBM
 //
-// Nodes: binary BVH, one node = 64 B = 4 float4 holding BOTH children's boxes, so a node
-// fetch tests two boxes (x, y, z rows are [lo0, lo1, hi0, hi1]):
-//   n[0] = (lo0.x, lo1.x, hi0.x, hi1.x)
-//   n[1] = (lo0.y, lo1.y, hi0.y, hi1.y)
-//   n[2] = (lo0.z, lo1.z, hi0.z, hi1.z)
-//   n[3] = (ref0, ref1, -, -) as int bits
+// Nodes: 4-wide BVH, one node = 128 B = 8 float4 (one cache line) holding the boxes of
+// all four children, so a node fetch tests four boxes:
+//   n[0] = lo.x of children 0..3     n[1] = hi.x of children 0..3
+//   n[2] = lo.y                      n[3] = hi.y
+//   n[4] = lo.z                      n[5] = hi.z
+//   n[6] = (ref0, ref1, ref2, ref3) as int bits      n[7] = padding
 // A child reference >= 0 is an interior node; < 0 is a leaf: v = ~ref, first = v >> 3,
 // count = v & 7 (count <= 7), `first` indexing the triangle-reference array.
 // Boxes are grown by a margin covering FP32 rounding of the ray and the flag distance.
@@ -30,7 +30,11 @@ namespace bt {
 
 constexpr int kStack = 32;          // traversal stack entries per lane (the builder bounds the
                                     // pushes of any root-leaf walk by it)
-constexpr int kEmptyRoot = 0x7fffffff;  // empty tile, or unused child slot of a node
+constexpr int kEmptyRoot = 0x7fffffff;  // empty tile
+// Unused child slot of a node: an empty leaf (no triangle references) behind a box at
+// 1e30 that no ray enters (its slab entry or exit is beyond every window: |1/c| >= 1 on
+// each axis), so the traversal needs no test for it and an entry would be harmless.
+constexpr int kEmptyChild = -1;
 
 struct DevMesh {
     const float4 *nodes;      // 4-wide nodes, 8 float4 each: lo x, hi x, lo y, hi y, lo z,

@@ -210,6 +210,8 @@ __device__ __forceinline__ bool box1(const float *bx, const RayState &r, float t
 // once every lane is there.  Leaf tests are the long code path; taking them in one pass
 // keeps most lanes of the wave busy in it instead of a few lanes in every node step.
 constexpr int kDone = (int)0x80000000;  // no leaf reference can take this value (< 2^28 refs)
+constexpr int kTraceBlock = 64 * kWavesPerBlock;  // k_trace's block size (its launch uses it)
+static_assert(kTraceBlock == 256, "k_trace's LDS stacks are laid out for 256 lanes");
 
 // Traverse one tile's hierarchy over the ray window (t_lo, t_hi].
 __device__ void traverse_tile(const DevMesh &M, int tile, RayState &r, RaySrc src, double t_lo, double t_hi,
@@ -223,8 +225,8 @@ __device__ void traverse_tile(const DevMesh &M, int tile, RayState &r, RaySrc sr
     // FP32 upper end of the box window, refreshed after every leaf (which may lower best_t)
     float fhi = f32_up(fmin(t_hi, r.best_t + delta));
     if (!box1(M.tile_box + 6 * tile, r, flo, fhi)) return;
-    const int bdim = blockDim.x;
-    const int tid = threadIdx.x;
+    // the lane's stack: entry e at lane_stk[e * kTraceBlock] (a shift, not a multiply)
+    int *lane_stk = stk + threadIdx.x;
     int sp = 0;
     int ref = root;
     while (true) {
@@ -246,7 +248,7 @@ __device__ void traverse_tile(const DevMesh &M, int tile, RayState &r, RaySrc sr
                 const float az = (lza[k] - r.oz) * r.iz, bz = (hza[k] - r.oz) * r.iz;
                 const float mn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), flo));
                 const float mx = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), fhi));
-                const bool h = mn <= mx && ca[k] != kEmptyRoot;
+                const bool h = mn <= mx;  // unused slots never pass (kEmptyChild)
                 t[k] = h ? mn : INFINITY;
                 c[k] = ca[k];
                 nh += h ? 1 : 0;
@@ -261,13 +263,13 @@ __device__ void traverse_tile(const DevMesh &M, int tile, RayState &r, RaySrc sr
 #undef BT_CSWAP
             if (nh > 0) {
                 // the nearest next, the others pushed farthest first
-                if (nh > 3) stk[(sp++) * bdim + tid] = c[3];
-                if (nh > 2) stk[(sp++) * bdim + tid] = c[2];
-                if (nh > 1) stk[(sp++) * bdim + tid] = c[1];
+                if (nh > 3) lane_stk[(sp++) * kTraceBlock] = c[3];
+                if (nh > 2) lane_stk[(sp++) * kTraceBlock] = c[2];
+                if (nh > 1) lane_stk[(sp++) * kTraceBlock] = c[1];
                 ref = c[0];
             } else if (sp > 0) {
                 sp--;
-                ref = stk[sp * bdim + tid];
+                ref = lane_stk[sp * kTraceBlock];
             } else {
                 ref = kDone;
             }
@@ -278,7 +280,7 @@ __device__ void traverse_tile(const DevMesh &M, int tile, RayState &r, RaySrc sr
         fhi = f32_up(fmin(t_hi, r.best_t + delta));
         if (sp == 0) break;
         sp--;
-        ref = stk[sp * bdim + tid];
+        ref = lane_stk[sp * kTraceBlock];
     }
 }
 
@@ -358,10 +360,10 @@ __device__ __forceinline__ bool spawns_child(const DevMesh &M, const TraceArgs &
     return !(a.e_min > 0.0) || ((double)Kc * (double)om > a.e_min);
 }
 
-__global__ void __launch_bounds__(256, 4) k_trace(DevMesh M, DevQueue in, DevSegs segs, DevCounters *ctr, TraceArgs a,
+__global__ void __launch_bounds__(kTraceBlock, 4) k_trace(DevMesh M, DevQueue in, DevSegs segs, DevCounters *ctr, TraceArgs a,
                                                WaveScratch ws)
 {
-    __shared__ int stk[kStack * 256];
+    __shared__ int stk[kStack * kTraceBlock];
     // the tile table (roots and root boxes) staged in LDS for up to 256 tiles, so that a
     // tile change waits on no global load
     __shared__ int s_root[256];
@@ -638,7 +640,7 @@ hipError_t launch_trace(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters 
     (void)n_cu;
     const int blocks = ws.n_waves / kWavesPerBlock;
     if (blocks <= 0 || blocks * kWavesPerBlock != ws.n_waves) return hipErrorInvalidValue;
-    k_trace<<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, a, ws);
+    k_trace<<<blocks, kTraceBlock, 0, s>>>(m, q, segs, ctr, a, ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_gen_scan<<<1, 1024, 0, s>>>(ctr, a, ws);
