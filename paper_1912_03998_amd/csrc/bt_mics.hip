@@ -371,6 +371,8 @@ __global__ void __launch_bounds__(256, 4) k_mics(DevMesh M, DevQueue q, DevSegs 
     flush_mic_counters(ctr, tests, updates);
 }
 
+constexpr int kPoolWaves = 64;  // waves whose general-list regions k_mics_general pools
+
 // General path, one lane per listed segment: the footprint's row range from the clipped
 // polygon; up to kInlineRows rows are finished here, wider footprints become (segment,
 // row) work items.
@@ -378,17 +380,41 @@ template <bool kSlots>
 __global__ void __launch_bounds__(256, 3) k_mics_general(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
                                                       DevMics mc0, TraceArgs a, MicWork w, WaveScratch ws)
 {
-    // wave w takes the items k_mics wave w put in its region (same grid)
+    // The items the fast-path kernel's waves put in their regions (same wave numbering),
+    // pooled over kPoolWaves consecutive waves: the pool's waves take its concatenated
+    // list 64 items at a time, so that no wave is left with a short region or a mostly
+    // empty last batch of its own.
     const unsigned long long s0 = gen_start(ctr, a.gen);
     const unsigned long long n_seg = gen_start(ctr, a.gen_end) - s0;
     const int lane = lane_id();
     const unsigned long long wave = wave_first_batch() >> 6;
-    const unsigned long long region = wave * general_region(n_seg, ws.n_waves);
-    const unsigned long long n = ws.general[wave];
+    const unsigned long long rsize = general_region(n_seg, ws.n_waves);
+    const unsigned long long g0 = wave / kPoolWaves * kPoolWaves;  // the pool's first wave
+    const int gi = (int)(wave - g0);
+    const int pw = (int)min((unsigned long long)kPoolWaves, (unsigned long long)ws.n_waves - g0);
+    // lane l: items of the pool's waves before wave g0 + l (the total for l >= pw)
+    const int cnt = lane < pw ? (int)ws.general[g0 + lane] : 0;
+    int pre = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(pre, off, 64);
+        if (lane >= off) pre += u;
+    }
+    const int total = __shfl(pre, 63, 64);
+    pre -= cnt;
     unsigned tests = 0, updates = 0;
-    for (unsigned long long base = 0; base < n; base += 64) {
-        const bool active = base + lane < n;
-        const long long i = active ? w.general[region + base + lane] : 0;
+    for (int t0 = 64 * gi; t0 < total; t0 += 64 * pw) {
+        const int t = t0 + lane;
+        const bool active = t < total;
+        // the pool wave whose region holds item t: the largest l with pre[l] <= t
+        int r = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+            const int p = __shfl(pre, r + step < 64 ? r + step : 63, 64);
+            if (r + step < 64 && p <= t) r += step;
+        }
+        const int pr = __shfl(pre, r, 64);
+        const long long i = active ? w.general[(g0 + (unsigned long long)r) * rsize + (unsigned long long)(t - pr)] : 0;
         int nrows = 0, j0 = 0, j1 = -1;
         bool wide = false;
         if (active) {
