@@ -732,10 +732,11 @@ extern "C" bt_status bt_mics_points(bt_ctx *ctx, const float *xyz, int64_t n, bt
             lo[c] = std::min(lo[c], (double)v);
             hi[c] = std::max(hi[c], (double)v);
         }
-    // buckets in xy of about four points each; one spare column and row, so that no
-    // point's bucket is clamped
+    // buckets in xy of about two points each (smaller buckets fit thin beams' regions
+    // better, larger ones need fewer bucket rows per beam); one spare column and row, so
+    // that no point's bucket is clamped
     const double sx = hi[0] - lo[0], sy = hi[1] - lo[1];
-    double bh = std::sqrt(std::max(sx * sy, 0.0) / std::max((double)n / 4.0, 1.0));
+    double bh = std::sqrt(std::max(sx * sy, 0.0) / std::max((double)n / 2.0, 1.0));
     bh = std::max(bh, std::max(std::max(sx, sy) / 4096.0, 1e-3));
     const int nbx = (int)std::floor(sx / bh) + 2, nby = (int)std::floor(sy / bh) + 2;
     const long long nb = (long long)nbx * nby;
