@@ -1,4 +1,5 @@
-// Emission, counter initialisation, fills and levels.
+// Emission (single sets and scenario tables), counter initialisation, fills, levels and
+// output gathers (subsets, batch outputs).
 #include "bt_device.h"
 
 namespace bt {

@@ -13,14 +13,22 @@ namespace bt {
 // the hit plane (incoming side, closed).  The kernels first bound the polygon's rows,
 // then enumerate candidate microphones row by row (one column of slack on each side)
 // and decide membership with the exact plane tests.
-//   k_mics:      one lane per segment; footprints of <= kInlineRows rows are finished
-//                in place, wider ones are split into (segment, row) work items
-//   k_mic_rows:  one lane per (segment, row) work item
-//   k_mics_big:  one wave per segment, for segments whose rows did not fit the item
-//                buffer (overflow fallback)
+//   k_mics_plane:   one lane per segment (a set of its own): most segments are dismissed
+//                   from their edge rays' crossings of the plane; a small lattice box
+//                   of candidates is staged and its microphones spread over the lanes;
+//                   the rest go to the wave's region of the general list
+//   k_mics:         the same fast path for multi-scenario sets, candidates in place
+//   k_mics_general: one lane per listed segment (regions pooled over 64 waves): the
+//                   clipped footprint's rows; up to kInlineRows rows are finished in
+//                   place, wider footprints become (segment, row) work items
+//   k_mic_rows:     one lane per (segment, row) work item; rows longer than kSpan
+//                   columns become (segment, row, columns) span items for k_mic_spans
+//   k_mics_big:     one wave per segment, for segments whose rows did not fit the item
+//                   buffer (overflow fallback)
 // A volumetric grid (Section 4's experiment fills the model's bounding box with
 // microphones) is a stack of such planes: k_mics3d bounds the layers a segment's frustum
-// can reach and runs the same footprint logic on each of them.
+// can reach and runs the same footprint logic on each of them.  Explicit points
+// (k_mics_points) are found through a bucket index in xy.
 // ---------------------------------------------------------------------------------------
 struct Frustum {
     V3 A;
@@ -325,7 +333,8 @@ __device__ __forceinline__ int plane_fast(const DevQueue &q, long long i, const 
 // Fast path over all segments of generations [gen, gen_end) (contiguous in the queue):
 // footprints that are a proper triangle on the microphone plane with at most kSpan
 // lattice points in their bounding box are finished here (most have none); the others
-// are appended to the general list.
+// are appended to the general list.  k_mics_plane serves a set of its own; k_mics serves
+// multi-scenario sets, whose segments send their contributions to different sets.
 // Wave w's region of the general list: room for 64 items per batch it processes.
 __device__ __forceinline__ unsigned long long general_region(unsigned long long n, int n_waves)
 {
@@ -1489,8 +1498,8 @@ static hipError_t launch_mics_t(const DevMesh &m, DevQueue q, DevSegs segs, DevC
     // k_mics and k_mics_general must use the same grid: wave w hands its region to wave w
     const int blocks = ws.n_waves / kWavesPerBlock;
     if (blocks <= 0 || blocks * kWavesPerBlock != ws.n_waves) return hipErrorInvalidValue;
-    if (kSlots) {
-        k_mics<kSlots><<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, mics, a, w, ws);
+    if constexpr (kSlots) {
+        k_mics<true><<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, mics, a, w, ws);
     } else {
         // one wave per block: block w is wave w of k_mics_general's grid
         k_mics_plane<<<ws.n_waves, 64, 0, s>>>(m, q, segs, ctr, mics, a, w, ws);

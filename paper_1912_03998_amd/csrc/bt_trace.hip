@@ -1,6 +1,7 @@
 // Guiding-ray trace: closest hit through the per-tile hierarchies with hand-off along the
-// ray's tile path, edge/tie flags, and the fused specular reflection + compaction of the
-// children into the next generation's queue.
+// ray's tile path and edge/tie flags (k_trace, which also counts each wave's children);
+// the children's queue offsets (k_gen_scan); the specular reflection and compaction of
+// the children into the next generation's queue (k_reflect).
 //
 // Precision: boxes are tested in FP32 against boxes grown by a margin that covers the
 // rounding of the ray; every triangle first goes through a conservative FP32
