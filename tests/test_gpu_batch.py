@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
-from scenegen import block_scene
+from scenegen import batch_scenarios, block_scene, district_scene
 from tests.parity_check import check_mics
 
 pytestmark = pytest.mark.gpu
@@ -183,3 +183,29 @@ def test_batch_autotune(torch_cuda):
         bt.bt_batch_run(s.ctx, s.mesh, scs, opts=opts)
         for a, b in zip(scs, ref):
             assert_same(a.energy, b.energy)
+
+
+def test_full_batch_workload_sampled_against_oracle(torch_cuda):
+    """The batched workload at full size (256 district scenarios, 96.7 M generation-0
+    beams, several chunks): four scenarios, the three cheapest and the one with the
+    most sources, checked against the oracle over their microphone subsets."""
+    from paper_1912_03998_amd import bt
+    from paper_1912_03998_amd.tracer import Session
+    base = district_scene(0)
+    specs = batch_scenarios(0, 256)
+    say("full batch workload:", sum(q.n_beams0 for q in specs), "generation-0 beams")
+    with Session.from_scene(base) as s:
+        scs = [bt.Scenario(q.sources, q.power, q.level, q.depth, q.grid, q.subset) for q in specs]
+        st = bt.bt_batch_run(s.ctx, s.mesh, scs)
+    assert st["beams0"] == sum(q.n_beams0 for q in specs) and st["chunks"] > 1
+    cost = [q.n_beams0 * (q.depth + 1) for q in specs]
+    picks = sorted(range(len(specs)), key=lambda k: cost[k])[:3]
+    picks.append(max(range(len(specs)), key=lambda k: (len(specs[k].sources), -cost[k])))
+    for k in picks:
+        q = specs[k]
+        say("oracle for scenario", k, len(q.sources), "sources, level", q.level, "depth", q.depth)
+        x0, y0, z, dx, dy, nx, ny = q.grid
+        o = O.trace(base.with_(sources=q.sources, power=q.power, level=q.level, depth=q.depth, mic_x0=x0, mic_y0=y0,
+                               mic_z=z, mic_dx=dx, mic_dy=dy, mic_nx=nx, mic_ny=ny), keep_paths=False)
+        sc = scs[k]
+        check_mics(o.e_strict[q.subset], o.e_flag[q.subset], sc.energy - sc.flag, sc.flag)
