@@ -7,7 +7,9 @@ import time
 import numpy as np
 import pytest
 
-from scenegen import block_scene
+from oracle import oracle as O
+from scenegen import block_scene, district_scene, serving_requests
+from tests.parity_check import check_mics
 from tests.test_gpu_batch import alone, assert_same, make_scenarios
 
 pytestmark = pytest.mark.gpu
@@ -126,3 +128,35 @@ def test_server_errors(torch_cuda):
             assert e.value.status == -5
         with pytest.raises(bt.BTError):
             bt.Server(s.ctx, s.mesh, mode=7)
+
+
+def test_district_stream_sampled_against_oracle(torch_cuda):
+    """The serving workload on the district at 800 requests/s (300 requests submitted at
+    their Poisson arrival times, continuously batched): three requests (the cheapest, the
+    median and the costliest) checked against the oracle over their microphone rectangles."""
+    from paper_1912_03998_amd import bt
+    from paper_1912_03998_amd.tracer import Session
+    base = district_scene(0)
+    reqs = serving_requests(0, n=300, rate=800.0)
+    say("district stream: 300 requests at 800 req/s")
+    with Session.from_scene(base) as s:
+        scs = [bt.Scenario(q.sources, q.power, q.level, q.depth, q.grid) for q in reqs]
+        with bt.Server(s.ctx, s.mesh) as srv:
+            tickets = []
+            t0 = time.perf_counter()
+            for q, sc in zip(reqs, scs):
+                while time.perf_counter() - t0 < q.arrival:
+                    time.sleep(0.0001)
+                tickets.append(srv.submit(sc))
+            wait_all(srv, tickets, timeout=120.0)
+    cost = [q.n_beams0 * (q.depth + 1) for q in reqs]
+    order = sorted(range(len(reqs)), key=lambda k: cost[k])
+    for k in (order[0], order[len(order) // 2], order[-1]):
+        q = reqs[k]
+        say("oracle for request", k, len(q.sources), "sources, level", q.level, "depth", q.depth,
+            "mics", q.grid[5], "x", q.grid[6])
+        x0, y0, z, dx, dy, nx, ny = q.grid
+        o = O.trace(base.with_(sources=q.sources, power=q.power, level=q.level, depth=q.depth, mic_x0=x0, mic_y0=y0,
+                               mic_z=z, mic_dx=dx, mic_dy=dy, mic_nx=nx, mic_ny=ny), keep_paths=False)
+        sc = scs[k]
+        check_mics(o.e_strict, o.e_flag, sc.energy - sc.flag, sc.flag)
