@@ -40,8 +40,7 @@ def build(force: bool = True) -> str:
     if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
         return _LIB
     tmp = _LIB + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=gnu99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                           "-shared", "-pthread", "-Wall", "-Wno-unused-function", "-o", tmp, _SRC, "-lm"])
+    compile_to(_SRC, tmp)
     os.replace(tmp, _LIB)
     return _LIB
 
@@ -70,27 +69,41 @@ class _Result(C.Structure):
 _lib = None
 
 
+def load(path: str):
+    """Load a compiled oracle library from `path` and declare its entry points."""
+    L = C.CDLL(path)
+    L.orc_ico_nfaces.restype = C.c_int64
+    L.orc_ico_nfaces.argtypes = [C.c_int]
+    L.orc_icosphere.restype = C.c_int
+    L.orc_icosphere.argtypes = [C.c_int, C.c_void_p]
+    L.orc_solid_angle.restype = C.c_double
+    L.orc_solid_angle.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    L.orc_trace.restype = C.c_int
+    L.orc_trace.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(_Result)]
+    L.orc_closest_hits.restype = C.c_int
+    L.orc_closest_hits.argtypes = [C.POINTER(_Scene), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                   C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p]
+    L.orc_bvh_depth.restype = C.c_int
+    L.orc_bvh_depth.argtypes = [C.POINTER(_Scene), C.c_double]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         path = _LIB if os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC) else build()
-        L = C.CDLL(path)
-        L.orc_ico_nfaces.restype = C.c_int64
-        L.orc_ico_nfaces.argtypes = [C.c_int]
-        L.orc_icosphere.restype = C.c_int
-        L.orc_icosphere.argtypes = [C.c_int, C.c_void_p]
-        L.orc_solid_angle.restype = C.c_double
-        L.orc_solid_angle.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
-        L.orc_trace.restype = C.c_int
-        L.orc_trace.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(_Result)]
-        L.orc_closest_hits.restype = C.c_int
-        L.orc_closest_hits.argtypes = [C.POINTER(_Scene), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
-                                       C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                       C.c_void_p]
-        L.orc_bvh_depth.restype = C.c_int
-        L.orc_bvh_depth.argtypes = [C.POINTER(_Scene), C.c_double]
-        _lib = L
+        _lib = load(path)
     return _lib
+
+
+def compile_to(src: str, out: str, extra_flags=()) -> str:
+    """Compile an oracle source file (the oracle itself, or a modified copy of it in a
+    test) with the oracle's flags into the shared library `out`."""
+    subprocess.check_call(["gcc", "-O2", "-std=gnu99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                           "-shared", "-pthread", "-Wall", "-Wno-unused-function", *extra_flags, "-o", out, src,
+                           "-lm"])
+    return out
 
 
 def _ptr(a):

@@ -114,13 +114,13 @@ class _MeshBuilder:
         return v, t, a
 
 
-def _ground(mb: _MeshBuilder, x0, y0, x1, y1, alpha, cell=None):
-    """Ground at z = 0 over [x0,x1]x[y0,y1]; one quad (split along (x0,y0)-(x1,y1)) or a grid."""
+def _ground(mb: _MeshBuilder, x0, y0, x1, y1, alpha, cell=None, z=0.0):
+    """Ground at height z over [x0,x1]x[y0,y1]; one quad (split along (x0,y0)-(x1,y1)) or a grid."""
     if cell is None:
-        a = mb.vert(x0, y0, 0.0)
-        b = mb.vert(x1, y0, 0.0)
-        c = mb.vert(x1, y1, 0.0)
-        d = mb.vert(x0, y1, 0.0)
+        a = mb.vert(x0, y0, z)
+        b = mb.vert(x1, y0, z)
+        c = mb.vert(x1, y1, z)
+        d = mb.vert(x0, y1, z)
         mb.quad(a, b, c, d, alpha)
         return
     nx = int(round((x1 - x0) / cell))
@@ -364,15 +364,56 @@ def empty_scene(level=2, src=(0.3, -0.2, 1.0), n_mic=9, spacing=3.0, mic_z=2.5) 
 
 
 def ground_scene(level=3, alpha=0.2, half=1000.0, src=(0.25, -0.15, 2.0), n_mic=11, spacing=2.5,
-                 mic_z=1.5, depth=1) -> Scene:
-    """Single large ground quad at z = 0 (2 triangles)."""
+                 mic_z=1.5, depth=1, ground_z=0.0) -> Scene:
+    """Single large ground quad at z = ground_z (2 triangles)."""
     mb = _MeshBuilder()
-    _ground(mb, -half, -half, half, half, alpha)
+    _ground(mb, -half, -half, half, half, alpha, z=ground_z)
     v, t, a = mb.arrays()
     h = (n_mic - 1) / 2.0 * spacing
     return Scene("ground", v, t, a, np.array([src], np.float32), np.ones(1, np.float32),
                  mic_x0=-h, mic_y0=-h, mic_z=mic_z, mic_dx=spacing, mic_dy=spacing,
                  mic_nx=n_mic, mic_ny=n_mic, level=level, depth=depth)
+
+
+def wall_scene(level=4, alpha=0.3, wall_x=7.5, half=1000.0, src=(0.25, -0.15, 2.0), nx=9, ny=11, spacing=2.5,
+               mic_z=1.5, depth=1, behind=False) -> Scene:
+    """Single large vertical wall in the plane x = wall_x (2 triangles, y and z in
+    [-half, half]) and nothing else.  The microphone grid's columns lie in front of the wall
+    (x < wall_x, the source's side), or behind it when `behind` is set."""
+    mb = _MeshBuilder()
+    a0 = mb.vert(wall_x, -half, -half)
+    a1 = mb.vert(wall_x, half, -half)
+    a2 = mb.vert(wall_x, half, half)
+    a3 = mb.vert(wall_x, -half, half)
+    mb.quad(a0, a1, a2, a3, alpha)
+    v, t, a = mb.arrays()
+    x0 = wall_x + 1.0 if behind else wall_x - 1.0 - (nx - 1) * spacing
+    y0 = -(ny - 1) / 2.0 * spacing
+    return Scene("wall", v, t, a, np.array([src], np.float32), np.ones(1, np.float32),
+                 mic_x0=x0, mic_y0=y0, mic_z=mic_z, mic_dx=spacing, mic_dy=spacing,
+                 mic_nx=nx, mic_ny=ny, level=level, depth=depth)
+
+
+def corner_scene(level=5, alpha_ground=0.2, alpha_wall=0.35, wall_x=6.0, half=1000.0, src=(-3.0, 0.4, 2.5),
+                 nx=10, ny=13, spacing=2.0, mic_z=1.5, depth=3) -> Scene:
+    """A ground at z = 0 for x <= wall_x and a vertical wall in the plane x = wall_x above it
+    (z in [0, half]): a right-angle corner along the line x = wall_x, z = 0 (4 triangles,
+    ground first).  Microphones in front of the wall, above the ground."""
+    mb = _MeshBuilder()
+    g0 = mb.vert(-half, -half, 0.0)
+    g1 = mb.vert(wall_x, -half, 0.0)
+    g2 = mb.vert(wall_x, half, 0.0)
+    g3 = mb.vert(-half, half, 0.0)
+    mb.quad(g0, g1, g2, g3, alpha_ground)
+    w2 = mb.vert(wall_x, half, half)
+    w3 = mb.vert(wall_x, -half, half)
+    mb.quad(g1, g2, w2, w3, alpha_wall)
+    v, t, a = mb.arrays()
+    x0 = wall_x - 1.0 - (nx - 1) * spacing
+    y0 = -(ny - 1) / 2.0 * spacing
+    return Scene("corner", v, t, a, np.array([src], np.float32), np.ones(1, np.float32),
+                 mic_x0=x0, mic_y0=y0, mic_z=mic_z, mic_dx=spacing, mic_dy=spacing,
+                 mic_nx=nx, mic_ny=ny, level=level, depth=depth)
 
 
 def sealed_box_scene(level=2, alpha=0.25, depth=4, size=(10.0, 8.0, 6.0), src=(0.731, -0.412, 1.137)) -> Scene:

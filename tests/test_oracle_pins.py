@@ -12,8 +12,9 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
-from scenegen import (block_scene, district_scene, empty_scene, ground_scene, mirror_scene,
-                      sealed_box_scene, tiny_scene)
+from scenegen import (block_scene, corner_scene, district_scene, empty_scene, ground_scene, mirror_scene,
+                      sealed_box_scene, tiny_scene, wall_scene)
+from tests import closed_forms as CF
 
 FOUR_PI = 4.0 * math.pi
 
@@ -422,6 +423,97 @@ def test_energy_bookkeeping_block():
             assert (r.hit[:, g + 1] != -2).sum() == hit.sum()
             K = np.where(hit, K * (1 - alpha[np.maximum(r.hit[:, g], 0)]), K)
     assert (np.diff(r.count) <= 0).all()
+
+
+# ----------------------------------------------------------------------------
+# Reflectors off the origin, a second-order image and the energy threshold.
+# Each pin_* function raises AssertionError on a mismatch; the tests below run them
+# on the oracle, and tests/test_oracle_mutations.py runs them on deliberately broken
+# copies of it to show that each catches a plausible mistake.
+# ----------------------------------------------------------------------------
+
+# Microphone modes: 0 tests every microphone against every segment (the membership
+# rule alone decides), 1 rasterises the footprint first (a clipping mistake loses
+# microphones); a pin runs both.
+MODES = (0, 1)
+
+
+def pin_ground_off_origin(ground_z, level=4, alpha=0.3):
+    """Ground z = h: above it, the direct path plus the image at 2h - z_s (a mirror that
+    drops the plane's offset puts it at -z_s); below it, exactly nothing (a far or near
+    cap that drops the offset lets energy through)."""
+    src = (0.25, -0.15, ground_z + 2.0)
+    sc = ground_scene(level=level, alpha=alpha, src=src, mic_z=ground_z + 1.5, ground_z=ground_z)
+    ref, ok0 = CF.ground_offset(sc, ground_z, alpha)
+    for mode in MODES:
+        r = O.trace(sc, mic_mode=mode)
+        ok = ok0 & (r.e_flag == 0)
+        assert ok.sum() > 60, ok.sum()
+        err = np.abs(r.energy[ok] / ref[ok] - 1).max()
+        assert err < 1e-13, (mode, err)
+        below = O.trace(sc.with_(mic_z=ground_z - 1.5), mic_mode=mode)
+        assert (below.energy == 0.0).all(), (mode, below.energy.max())
+
+
+def pin_wall_off_origin(wall_x=7.5, level=4, alpha=0.3):
+    """Vertical wall x = c: in front, the direct path plus the image at 2c - x_s; behind
+    it, nothing."""
+    sc = wall_scene(level=level, alpha=alpha, wall_x=wall_x)
+    ref, ok0 = CF.wall_offset(sc, wall_x, alpha)
+    for mode in MODES:
+        r = O.trace(sc, mic_mode=mode)
+        ok = ok0 & (r.e_flag == 0)
+        assert ok.sum() > 60, ok.sum()
+        err = np.abs(r.energy[ok] / ref[ok] - 1).max()
+        assert err < 1e-13, (mode, err)
+        behind = O.trace(wall_scene(level=level, alpha=alpha, wall_x=wall_x, behind=True), mic_mode=mode)
+        assert (behind.energy == 0.0).all(), (mode, behind.energy.max())
+
+
+def pin_corner_second_order(level=5):
+    """Wall + ground corner: direct, two first-order and one second-order image with
+    weights 1, 1 - a_g, 1 - a_w, (1 - a_g)(1 - a_w), reached through either order."""
+    sc = corner_scene(level=level)
+    ref, ok0, last_on_wall = CF.corner(sc, 6.0, 0.2, 0.35)
+    for mode in MODES:
+        r = O.trace(sc, mic_mode=mode)
+        ok = ok0 & (r.e_flag == 0)
+        assert ok.sum() > 80, ok.sum()
+        assert last_on_wall[ok].sum() > 10 and (~last_on_wall[ok]).sum() > 10
+        err = np.abs(r.energy[ok] / ref[ok] - 1).max()
+        assert err < 1e-13, (mode, err)
+        assert r.count[3] == 0 and r.count[2] > 0   # no third reflection inside a right angle
+
+
+def pin_threshold_generation(eps, generation=3, alpha=0.1, depth=6):
+    """Level-0 sealed box with e_min at (1 - alpha)^G / 20 (1 +- 1e-9): generations end
+    exactly before or after G.  Comparing the power before absorption, or not at all,
+    moves the end by one generation."""
+    e_min, alive = CF.sealed_box_threshold(alpha, generation, eps)
+    r = O.trace(sealed_box_scene(level=0, alpha=alpha, depth=depth), e_min=e_min)
+    want = np.array([20 if g < alive else 0 for g in range(depth + 1)])
+    assert np.array_equal(r.count, want), (r.count.tolist(), want.tolist())
+    a = CF.f32(alpha)
+    pw = np.where(want > 0, (1 - a) ** np.arange(depth + 1), 0.0)
+    assert np.abs(r.power - pw).max() < 1e-14
+
+
+@pytest.mark.parametrize("ground_z", [3.7, -4.2])
+def test_ground_off_origin_is_image_source(ground_z):
+    pin_ground_off_origin(ground_z)
+
+
+def test_wall_off_origin_is_image_source():
+    pin_wall_off_origin()
+
+
+def test_wall_corner_second_order_image():
+    pin_corner_second_order()
+
+
+@pytest.mark.parametrize("eps", [1e-9, -1e-9])
+def test_energy_threshold_ends_at_exact_generation(eps):
+    pin_threshold_generation(eps)
 
 
 # ----------------------------------------------------------------------------
