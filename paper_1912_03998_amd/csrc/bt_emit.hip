@@ -46,7 +46,7 @@ hipError_t launch_fill(double *p, long long n, double v, hipStream_t s)
 // Face `f` of the level-`level` icosphere: its three edge directions, the guiding
 // direction and the solid angle.
 __device__ void face_of(const double *__restrict__ base20, int level, long long f, V3 &a, V3 &bb, V3 &c, V3 &cc,
-                        float &om)
+                        double &om)
 {
     int bf = (int)(f >> (2 * level));
     const double *bp = base20 + 9 * bf;
@@ -64,13 +64,13 @@ __device__ void face_of(const double *__restrict__ base20, int level, long long 
     cc = unit((a + bb) + c);
     double num = fabs(dot(a, cross(bb, c)));
     double den = 1.0 + dot(a, bb) + dot(bb, c) + dot(c, a);
-    om = (float)(2.0 * atan2(num, den));
+    om = 2.0 * atan2(num, den);
 }
 
 // A generation-0 beam record at queue index j: apex and origin at the source S, the face's
-// directions, intensity constant K.
-__device__ __forceinline__ void store_beam(DevQueue q, long long j, V3 S, V3 a, V3 bb, V3 c, V3 cc, float K, float om,
-                                           int meta, int id)
+// directions, intensity constant K (W/sr) and power P = K Omega (W).
+__device__ __forceinline__ void store_beam(DevQueue q, long long j, V3 S, V3 a, V3 bb, V3 c, V3 cc, double K,
+                                           double om, int meta, int id)
 {
     const long long cap = q.cap;
     st3(q.dbl + D_A * cap, cap, j, S);
@@ -79,8 +79,8 @@ __device__ __forceinline__ void store_beam(DevQueue q, long long j, V3 S, V3 a, 
     st3(q.dbl + D_D2 * cap, cap, j, c);
     st3(q.dbl + D_O * cap, cap, j, S);
     st3(q.dbl + D_C * cap, cap, j, cc);
-    q.flt[F_K * cap + j] = K;
-    q.flt[F_OMEGA * cap + j] = om;
+    q.flt[F_K * cap + j] = (float)K;
+    q.dbl[D_P * cap + j] = K * om;
     q.ints[I_ID * cap + j] = id;
     q.ints[I_START * cap + j] = -1;
     q.ints[I_META * cap + j] = meta;
@@ -92,14 +92,14 @@ __device__ void emit_one(const double *__restrict__ base20, int level, long long
                          DevQueue q, long long j)
 {
     V3 a, bb, c, cc;
-    float om;
+    double om;
     face_of(base20, level, f, a, bb, c, cc, om);
-    store_beam(q, j, S, a, bb, c, cc, (float)((double)W / (4.0 * M_PI)), om, meta, id);
+    store_beam(q, j, S, a, bb, c, cc, (double)W / (4.0 * M_PI), om, meta, id);
 }
 
 // The face table of one level, computed once: dirs[k * nf + f] for k = 0..11 (d0, d1, d2,
 // c) and om[f].
-__global__ void k_faces(const double *__restrict__ base20, int level, long long nf, double *dirs, float *om)
+__global__ void k_faces(const double *__restrict__ base20, int level, long long nf, double *dirs, double *om)
 {
     const long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (f >= nf) return;
@@ -111,7 +111,7 @@ __global__ void k_faces(const double *__restrict__ base20, int level, long long 
     st3(dirs + 9 * nf, nf, f, cc);
 }
 
-hipError_t launch_faces(const double *base20, int level, double *dirs, float *om, hipStream_t s)
+hipError_t launch_faces(const double *base20, int level, double *dirs, double *om, hipStream_t s)
 {
     const long long nf = 20ll << (2 * level);
     k_faces<<<(unsigned)((nf + 255) / 256), 256, 0, s>>>(base20, level, nf, dirs, om);
@@ -122,7 +122,7 @@ hipError_t launch_faces(const double *base20, int level, double *dirs, float *om
 // level's face table.  An omni source has K = W / (4 pi); a directional one (weights
 // w[s nf + f]) K = W w / norm[s], norm[s] = sum over faces of w Omega, so that its beams'
 // powers K Omega add up to W.
-__global__ void k_emit(const double *__restrict__ dirs, const float *__restrict__ fom, const float *__restrict__ src,
+__global__ void k_emit(const double *__restrict__ dirs, const double *__restrict__ fom, const float *__restrict__ src,
                        const float *__restrict__ power, const float *__restrict__ wt, const double *__restrict__ norm,
                        int n_src, long long nf, DevQueue q)
 {
@@ -131,22 +131,22 @@ __global__ void k_emit(const double *__restrict__ dirs, const float *__restrict_
     if (b >= total) return;
     long long s = b / nf, f = b - s * nf;
     const V3 S = {src[3 * s], src[3 * s + 1], src[3 * s + 2]};
-    float K;
-    if (wt) K = norm[s] > 0.0 ? (float)((double)power[s] * (double)wt[b] / norm[s]) : 0.0f;
-    else K = (float)((double)power[s] / (4.0 * M_PI));
+    double K;
+    if (wt) K = norm[s] > 0.0 ? (double)power[s] * (double)wt[b] / norm[s] : 0.0;
+    else K = (double)power[s] / (4.0 * M_PI);
     store_beam(q, b, S, ld3(dirs, nf, f), ld3(dirs + 3 * nf, nf, f), ld3(dirs + 6 * nf, nf, f),
                ld3(dirs + 9 * nf, nf, f), K, fom[f], 0, (int)b);
 }
 
 // norm[s] = sum over faces f of wt[s nf + f] Omega_f (FP64, one block per source, a fixed
 // reduction order).
-__global__ void __launch_bounds__(256) k_source_norms(const float *__restrict__ fom, const float *__restrict__ wt,
+__global__ void __launch_bounds__(256) k_source_norms(const double *__restrict__ fom, const float *__restrict__ wt,
                                                       long long nf, double *norm)
 {
     __shared__ double part[256];
     const long long s = blockIdx.x;
     double acc = 0.0;
-    for (long long f = threadIdx.x; f < nf; f += blockDim.x) acc += (double)wt[s * nf + f] * (double)fom[f];
+    for (long long f = threadIdx.x; f < nf; f += blockDim.x) acc += (double)wt[s * nf + f] * fom[f];
     part[threadIdx.x] = acc;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(256) k_source_norms(const float *__restrict__ 
     if (threadIdx.x == 0) norm[s] = part[0];
 }
 
-hipError_t launch_emit(const double *dirs, const float *om, const float *src, const float *power, const float *wt,
+hipError_t launch_emit(const double *dirs, const double *om, const float *src, const float *power, const float *wt,
                        double *norm, int n_src, int level, DevQueue q, hipStream_t s)
 {
     long long nf = 20ll << (2 * level);

@@ -185,7 +185,7 @@ extern "C" bt_status bt_destroy(bt_ctx *ctx)
     for (int l = 0; l <= BT_MAX_LEVEL; ++l) {
         const long long nf = 20ll << (2 * l);
         dev_free(ctx, ctx->face_dirs[l], (size_t)nf * 12 * sizeof(double));
-        dev_free(ctx, ctx->face_om[l], (size_t)nf * sizeof(float));
+        dev_free(ctx, ctx->face_om[l], (size_t)nf * sizeof(double));
     }
     dev_free(ctx, ctx->base20, 20 * 9 * sizeof(double));
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -1076,7 +1076,7 @@ static bt_status emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_
         // the level's face directions, computed once per context
         const long long nf = 20ll << (2 * level);
         if ((s = dev_alloc(ctx, (void **)&ctx->face_dirs[level], (size_t)nf * 12 * sizeof(double))) != BT_OK) return s;
-        if ((s = dev_alloc(ctx, (void **)&ctx->face_om[level], (size_t)nf * sizeof(float))) != BT_OK) return s;
+        if ((s = dev_alloc(ctx, (void **)&ctx->face_om[level], (size_t)nf * sizeof(double))) != BT_OK) return s;
         HIP_TRY(ctx, launch_faces(ctx->base20, level, ctx->face_dirs[level], ctx->face_om[level], ctx->stream));
     }
     HIP_TRY(ctx, launch_emit(ctx->face_dirs[level], ctx->face_om[level], b->src_dev, b->pow_dev,

@@ -27,7 +27,7 @@ struct bt_ctx {
     std::map<uint64_t, struct Request *> requests;
     struct BatchWork *batch = nullptr;  // bt_batch_run's workspace, kept between calls
     double *face_dirs[BT_MAX_LEVEL + 1] = {};  // per icosphere level, built on first use
-    float *face_om[BT_MAX_LEVEL + 1] = {};
+    double *face_om[BT_MAX_LEVEL + 1] = {};
 };
 
 struct bt_mesh {

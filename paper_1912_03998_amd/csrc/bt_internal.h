@@ -54,14 +54,17 @@ struct DevMesh {
 // Beam queue, structure of arrays with capacity `cap`.  All generations of a beam set
 // stay resident: generation g occupies [start_g, start_g + count_g) with
 // start_g = count_0 + ... + count_(g-1), so the capacity is n0 * (max_depth + 1) records.
-//   dbl[k * cap + i], k = 0..17: A.xyz, d0.xyz, d1.xyz, d2.xyz, o.xyz, c.xyz
-//   flt[k * cap + i], k = 0..1: K (W/sr), Omega (sr)
+//   dbl[k * cap + i], k = 0..18: A.xyz, d0.xyz, d1.xyz, d2.xyz, o.xyz, c.xyz, P
+//   flt[k * cap + i], k = 0: K (W/sr)
+// P is the beam's power K Omega in watts, kept in FP64 so that the energy-threshold
+// decision (P (1 - alpha) > e_min) is taken in the same precision as the oracle's; K,
+// which only scales the microphone contributions, is FP32.
 //   ints[k * cap + i], k = 0..2: initial beam id, start triangle, meta
 // meta: bits 0-7 depth, bit 8 near side is negative, bit 9 flagged (inherited); for beams
 // of a multi-scenario set (batches, served requests) also bits 10-14 the scenario's
 // max_depth and bits 16-31 its slot, inherited unchanged by children (zero otherwise)
-enum { D_A = 0, D_D0 = 3, D_D1 = 6, D_D2 = 9, D_O = 12, D_C = 15, D_N = 18 };
-enum { F_K = 0, F_OMEGA = 1, F_N = 2 };
+enum { D_A = 0, D_D0 = 3, D_D1 = 6, D_D2 = 9, D_O = 12, D_C = 15, D_P = 18, D_N = 19 };
+enum { F_K = 0, F_N = 1 };
 enum { I_ID = 0, I_START = 1, I_META = 2, I_N = 3 };
 constexpr int kMetaNegNear = 1 << 8;
 constexpr int kMetaFlag = 1 << 9;
@@ -201,12 +204,12 @@ struct BatchDesc {
 // Kernel launchers; all enqueue on `s` and return hipGetLastError().  The statically
 // partitioned kernels run ws.n_waves waves (blocks of kWavesPerBlock waves).
 hipError_t launch_init_counters(DevCounters *ctr, long long n0, hipStream_t s);
-// The face table of an icosphere level (dirs: 12 nf doubles, om: nf floats), and the
+// The face table of an icosphere level (dirs: 12 nf doubles, om: nf doubles), and the
 // emission of one beam set's generation 0 from it.
-hipError_t launch_faces(const double *base20, int level, double *dirs, float *om, hipStream_t s);
+hipError_t launch_faces(const double *base20, int level, double *dirs, double *om, hipStream_t s);
 // wt: NULL (omni) or [n_src][nf] face weights of directional sources, with norm a device
 // double[n_src] filled here.
-hipError_t launch_emit(const double *dirs, const float *om, const float *src, const float *power, const float *wt,
+hipError_t launch_emit(const double *dirs, const double *om, const float *src, const float *power, const float *wt,
                        double *norm, int n_src, int level, DevQueue q, hipStream_t s);
 // Appends the table's beams to generation `gen` (after its current beams) and adds their
 // number to count[gen].

@@ -351,14 +351,13 @@ __device__ void trace_ray(const DevMesh &M, RayState &r, RaySrc src, double t_mi
 }
 
 // A child is spawned by a hit with depth < max_depth whose power after absorption exceeds
-// e_min (when set).  k_trace counts children with this rule and k_reflect writes them.
-__device__ __forceinline__ bool spawns_child(const DevMesh &M, const TraceArgs &a, int hit, int meta, float K,
-                                             float om)
+// e_min (when set), decided in FP64 from the beam's FP64 power P.  k_trace counts
+// children with this rule and k_reflect writes them.
+__device__ __forceinline__ bool spawns_child(const DevMesh &M, const TraceArgs &a, int hit, int meta, double P)
 {
     const int max_depth = a.scenarios ? meta_max_depth(meta) : a.max_depth;
     if (hit < 0 || (meta & 0xff) >= max_depth) return false;
-    const float Kc = K * (1.0f - M.alpha[hit]);
-    return !(a.e_min > 0.0) || ((double)Kc * (double)om > a.e_min);
+    return !(a.e_min > 0.0) || (P * (1.0 - (double)M.alpha[hit]) > a.e_min);
 }
 
 __global__ void __launch_bounds__(kTraceBlock, 4) k_trace(DevMesh M, DevQueue in, DevSegs segs, DevCounters *ctr, TraceArgs a,
@@ -419,8 +418,7 @@ __global__ void __launch_bounds__(kTraceBlock, 4) k_trace(DevMesh M, DevQueue in
             trace_ray(Ml, r, src, a.t_min, a.delta, stk);
             const int meta = in.ints[I_META * icap + i];
             const int id = in.ints[I_ID * icap + i];
-            const float K = in.flt[F_K * icap + i];
-            const float om = in.flt[F_OMEGA * icap + i];
+            const double P = in.dbl[D_P * icap + i];
             const int hit = r.best_id;
             int own_flag;
             if (hit >= 0) own_flag = r.best_near || (r.c1_id != hit) || (r.c2_t < r.best_t + a.delta);
@@ -433,9 +431,9 @@ __global__ void __launch_bounds__(kTraceBlock, 4) k_trace(DevMesh M, DevQueue in
             if (a.hit_out) a.hit_out[oidx] = hit;
             if (a.flag_out) a.flag_out[oidx] = (uint8_t)flag_total;
             if (a.t_out) a.t_out[oidx] = r.best_t;
-            children += spawns_child(M, a, hit, meta, K, om);
+            children += spawns_child(M, a, hit, meta, P);
             flagged += flag_total;
-            power += (double)K * (double)om;
+            power += P;
             nv += r.node_visits;
             tt += r.tri_tests;
         }
@@ -582,19 +580,23 @@ __global__ void __launch_bounds__(256) k_reflect(DevMesh M, DevQueue q, DevSegs 
     for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
         const long long i = s0 + (long long)base + lane;
         int child = 0, hit = -1, meta = 0;
-        float K = 0.f, Kc = 0.f;
+        float Kc = 0.f;
+        double Pc = 0.0;
         if ((long long)base + lane < (long long)n) {
             hit = segs.hit[i];
             meta = in.ints[I_META * icap + i];
-            K = in.flt[F_K * icap + i];
-            child = spawns_child(M, a, hit, meta, K, in.flt[F_OMEGA * icap + i]);
-            if (child) Kc = K * (1.0f - M.alpha[hit]);
+            const double P = in.dbl[D_P * icap + i];
+            child = spawns_child(M, a, hit, meta, P);
+            if (child) {
+                const float al = M.alpha[hit];
+                Kc = in.flt[F_K * icap + i] * (1.0f - al);
+                Pc = P * (1.0 - (double)al);
+            }
         }
         const unsigned long long mask = __ballot(child);
         if (mask == 0) continue;
         V3 A2, o2, c2, m0, m1, m2;
         int meta2 = 0, id = 0;
-        float om = 0.f;
         if (child) {
             V3 v0, v1, v2;
             tri_vertices(M.tri_g, hit, v0, v1, v2);
@@ -612,7 +614,6 @@ __global__ void __launch_bounds__(256) k_reflect(DevMesh M, DevQueue q, DevSegs 
             // the child lives on the side the parent came from
             meta2 = (meta & kMetaInherited) | ((meta & 0xff) + 1) | (dot(c, N) > 0.0 ? kMetaNegNear : 0) |
                     (segs.flag[i] ? kMetaFlag : 0);
-            om = in.flt[F_OMEGA * icap + i];
             id = in.ints[I_ID * icap + i];
         }
         const unsigned long long my_base = obase;
@@ -626,7 +627,7 @@ __global__ void __launch_bounds__(256) k_reflect(DevMesh M, DevQueue q, DevSegs 
             st3(out.dbl + D_O * ocap, ocap, j, o2);
             st3(out.dbl + D_C * ocap, ocap, j, c2);
             out.flt[F_K * ocap + j] = Kc;
-            out.flt[F_OMEGA * ocap + j] = om;
+            out.dbl[D_P * ocap + j] = Pc;
             out.ints[I_ID * ocap + j] = id;
             out.ints[I_START * ocap + j] = hit;
             out.ints[I_META * ocap + j] = meta2;

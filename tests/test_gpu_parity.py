@@ -9,9 +9,11 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
-from scenegen import (block_scene, district_scene, empty_scene, ground_scene, mirror_scene, sealed_box_scene,
-                      tiny_scene)
-from tests.parity_check import check_counts, check_hits, check_mics
+from scenegen import (block_scene, corner_scene, district_scene, empty_scene, ground_scene, mirror_scene,
+                      sealed_box_scene, tiny_scene, wall_scene)
+from tests import closed_forms as CF
+from tests.parity_check import (check_counts, check_flags, check_hits, check_mics, paths_diverge,
+                                strict_share)
 
 pytestmark = pytest.mark.gpu
 FOUR_PI = 4.0 * math.pi
@@ -44,10 +46,17 @@ def gpu_run(s, scene, parity=True, sources=None, power=None, **kw):
     return s.run(src, pw, scene.level, scene.depth, grid(scene), parity=parity, **kw)
 
 
-def full_verdict(scene, g, o):
+def full_verdict(scene, g, o, min_strict_share=0.99):
+    """Hits, flags, counts and microphones against the oracle; at least min_strict_share of
+    the oracle's energised microphones must be strict (compared to 0.01 dB)."""
     n = check_hits(o.hit, o.flag, o.t_hit, g.hit, g.t_hit)
-    check_counts(o.count, o.flagged, g.stats["count"])
-    m = check_mics(o.e_strict, o.e_flag, g.e_strict, g.e_flag)
+    check_flags(o.hit, o.flag, g.flag)
+    div = paths_diverge(o.hit, g.hit)
+    check_counts(o.count, o.flagged, g.stats["count"], g.stats["flagged"], diverged=div)
+    m = check_mics(o.e_strict, o.e_flag, g.e_strict, g.e_flag, diverged=div)
+    say(f"verdict: {n} unflagged segments, {m['strict_energised']}/{m['energised']} energised microphones strict, "
+        f"max {m['max_db']:.2e} dB, paths diverge: {div}")
+    assert strict_share(m) >= min_strict_share, m
     return n, m
 
 
@@ -119,6 +128,66 @@ def test_sealed_box_counts_and_power(torch_cuda, level, alpha, depth):
     assert (g.hit >= 0).all()
 
 
+@pytest.mark.parametrize("ground_z", [3.7, -4.2])
+def test_ground_off_origin_image_source(torch_cuda, ground_z):
+    """Ground z = h != 0: direct path plus the image at 2h - z_s above it, nothing below."""
+    src = (0.25, -0.15, ground_z + 2.0)
+    sc = ground_scene(level=4, alpha=0.3, src=src, mic_z=ground_z + 1.5, ground_z=ground_z)
+    say("ground off the origin", ground_z)
+    ref, ok = CF.ground_offset(sc, ground_z, 0.3)
+    with session(sc) as s:
+        g = gpu_run(s, sc)
+        below = sc.with_(mic_z=ground_z - 1.5)
+        gb = gpu_run(s, below)
+    ok &= g.e_flag == 0
+    assert ok.sum() > 60
+    assert np.abs(g.energy[ok] / ref[ok] - 1).max() < 1e-6
+    assert (gb.energy == 0.0).all()
+
+
+def test_wall_off_origin_image_source(torch_cuda):
+    """Vertical wall x = c != 0: direct path plus the image at 2c - x_s in front, nothing
+    behind."""
+    sc = wall_scene(level=4, alpha=0.3, wall_x=7.5)
+    say("wall off the origin")
+    ref, ok = CF.wall_offset(sc, 7.5, 0.3)
+    with session(sc) as s:
+        g = gpu_run(s, sc)
+        gb = gpu_run(s, wall_scene(level=4, alpha=0.3, wall_x=7.5, behind=True))
+    ok &= g.e_flag == 0
+    assert ok.sum() > 60
+    assert np.abs(g.energy[ok] / ref[ok] - 1).max() < 1e-6
+    assert (gb.energy == 0.0).all()
+
+
+def test_wall_corner_second_order_image(torch_cuda):
+    """Wall + ground corner: four images with weights 1, 1 - a_g, 1 - a_w,
+    (1 - a_g)(1 - a_w); no third reflection."""
+    sc = corner_scene(level=5)
+    say("wall + ground corner")
+    ref, ok, last_on_wall = CF.corner(sc, 6.0, 0.2, 0.35)
+    with session(sc) as s:
+        g = gpu_run(s, sc)
+    ok &= g.e_flag == 0
+    assert ok.sum() > 80
+    assert last_on_wall[ok].sum() > 10 and (~last_on_wall[ok]).sum() > 10
+    assert np.abs(g.energy[ok] / ref[ok] - 1).max() < 1e-6
+    assert g.stats["count"][3] == 0 and g.stats["count"][2] > 0
+
+
+@pytest.mark.parametrize("eps", [1e-9, -1e-9])
+def test_energy_threshold_exact_generation(torch_cuda, eps):
+    """e_min within 1e-9 of a generation's beam power in a level-0 sealed box: the run ends
+    exactly before or after that generation (the decision is taken in FP64)."""
+    e_min, alive = CF.sealed_box_threshold(0.1, 3, eps)
+    sc = sealed_box_scene(level=0, alpha=0.1, depth=6)
+    say("energy threshold at an exact generation", eps)
+    with session(sc) as s:
+        g = gpu_run(s, sc, e_min=e_min)
+    want = np.array([20 if k < alive else 0 for k in range(7)])
+    assert np.array_equal(g.stats["count"], want), g.stats["count"]
+
+
 def test_sealed_box_maximum_depth(torch_cuda):
     """31 reflections (the maximum): after ~23 bounces a few beams graze a box corner
     within the 1 mm self-intersection guard and leave; both sides must agree."""
@@ -127,7 +196,9 @@ def test_sealed_box_maximum_depth(torch_cuda):
     o = O.trace(sc)
     with session(sc) as s:
         g = gpu_run(s, sc)
-    full_verdict(sc, g, o)
+    # after ~23 bounces some beams graze corners: 3 of the 56 energised microphones carry
+    # flagged energy on both sides
+    full_verdict(sc, g, o, min_strict_share=0.9)
     assert np.array_equal(g.stats["count"], o.count)
     assert np.abs(g.stats["power"] / o.power - 1).max() < 1e-5
 
@@ -155,7 +226,7 @@ def test_block_scene_parity(torch_cuda):
         g = gpu_run(s, sc)
     n, m = full_verdict(sc, g, o)
     assert n > 90_000
-    assert m["strict"] > 9000
+    assert m["energised"] > 1000
     # the GPU's own work counters agree with the oracle's segment and update counts
     assert g.stats["segments"] == o.counters["segments"]
     assert abs(g.stats["mic_updates"] - o.counters["mic_updates"]) <= o.flagged.sum() * 50
@@ -167,7 +238,9 @@ def test_mirror_scene_parity(torch_cuda):
     o = O.trace(sc)
     with session(sc) as s:
         g = gpu_run(s, sc)
-    full_verdict(sc, g, o)
+    # the source sits on the symmetry plane: its row of microphones lies on shared beam
+    # faces, so about 8 % of the energised microphones are ambiguous on both sides
+    full_verdict(sc, g, o, min_strict_share=0.9)
 
 
 @pytest.mark.parametrize("air_m,e_min", [(0.02, 0.0), (0.0, 2e-5)])
@@ -218,7 +291,7 @@ def test_district_sources_parity(torch_cuda, district):
         g1 = None
     n, m = full_verdict(sub, g, o)
     assert n > 300_000
-    assert m["strict"] > 20_000
+    assert m["energised"] > 30_000
     say("district partition invariance 1x1 vs 4x4")
     with session(sc, tiles=(1, 1)) as s:
         g1 = gpu_run(s, sub)
@@ -241,7 +314,7 @@ def test_district_full_size(torch_cuda, district):
         o = O.trace(sc)
         n, m = full_verdict(sc, g, o)
         assert n > 13_000_000
-        assert m["strict"] > 150_000
+        assert m["energised"] > 190_000
         assert st["segments"] == o.counters["segments"] or \
             abs(st["segments"] - o.counters["segments"]) <= o.flagged.sum()
         del o

@@ -12,7 +12,7 @@ import pytest
 
 from oracle import oracle as O
 from scenegen import block_scene, empty_scene, ground_scene, tiny_scene, volumetric_scene
-from tests.parity_check import check_counts, check_hits, check_mics
+from tests.parity_check import check_counts, check_flags, check_hits, check_mics, paths_diverge, strict_share
 
 pytestmark = pytest.mark.gpu
 FOUR_PI = 4.0 * math.pi
@@ -39,10 +39,15 @@ def gpu_run(s, scene, parity=True, **kw):
     return s.run(scene.sources, scene.power, scene.level, scene.depth, scene_grid(scene), parity=parity, **kw)
 
 
-def verdict(g, o):
+def verdict(g, o, min_strict_share=0.99):
     n = check_hits(o.hit, o.flag, o.t_hit, g.hit, g.t_hit)
-    check_counts(o.count, o.flagged, g.stats["count"])
-    return n, check_mics(o.e_strict, o.e_flag, g.e_strict, g.e_flag)
+    check_flags(o.hit, o.flag, g.flag)
+    div = paths_diverge(o.hit, g.hit)
+    check_counts(o.count, o.flagged, g.stats["count"], g.stats["flagged"], diverged=div)
+    m = check_mics(o.e_strict, o.e_flag, g.e_strict, g.e_flag, diverged=div)
+    say(f"verdict: {m['strict_energised']}/{m['energised']} energised microphones strict, paths diverge: {div}")
+    assert strict_share(m) >= min_strict_share, m
+    return n, m
 
 
 def crop(scene, src, nx, ny):
@@ -93,7 +98,9 @@ def test_tiny_scene_volumetric_parity(torch_cuda):
     o = O.trace(sc)
     with session(sc) as s:
         g = gpu_run(s, sc)
-    n, m = verdict(g, o)
+    # the source sits on the icosphere's vertex ray under the layers above it: 14 % of
+    # the energised microphones are ambiguous on both sides
+    n, m = verdict(g, o, min_strict_share=0.8)
     assert m["nonzero"] > 100
 
 
@@ -106,7 +113,7 @@ def test_block_scene_volumetric_parity(torch_cuda):
     with session(sc) as s:
         g = gpu_run(s, sc)
     n, m = verdict(g, o)
-    assert m["strict"] > 20_000
+    assert m["energised"] > 10_000
     assert g.stats["segments"] == o.counters["segments"]
     assert abs(g.stats["mic_updates"] - o.counters["mic_updates"]) <= o.flagged.sum() * 200
 
@@ -146,9 +153,9 @@ def test_tall_district_volumetric_parity(torch_cuda, tall):
     o = O.trace(sub)
     with session(sub) as s:
         g = gpu_run(s, sub)
-    n, m = verdict(g, o)
+    n, m = verdict(g, o, min_strict_share=0.98)
     assert n > 200_000
-    assert m["strict"] > 500_000
+    assert m["energised"] > 1_000_000
     assert g.stats["segments"] == o.counters["segments"] or \
         abs(g.stats["segments"] - o.counters["segments"]) <= o.flagged.sum()
 
@@ -164,7 +171,7 @@ def test_tall_district_full_grid_sample(torch_cuda, tall):
     with session(sc) as s:
         g = gpu_run(s, sc, parity=False)
         m = check_mics(o.e_strict, o.e_flag, g.e_strict, g.e_flag)
-        assert m["strict"] > 3_000_000
+        assert m["energised"] > 8_000_000 and strict_share(m) >= 0.99, m
         say("tall district planar layer 0")
         plane = sc.with_(mic_nz=1)
         p = s.run(plane.sources, plane.power, plane.level, plane.depth, scene_grid(plane), parity=False)
