@@ -193,6 +193,20 @@ bt_status bt_trace(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *beams, const bt_p
 bt_status bt_accumulate_mics(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *beams, const bt_params *params,
                              bt_mics *mics);
 
+/* bt_accumulate_mics for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments, kernels
+ * and results as bt_accumulate_mics; it calls no hipMalloc, hipFree or allocating library
+ * routine.  Its work lists live in a static device array of 64 MiB per GPU, which the
+ * library holds from its first bt_create on that GPU until the process ends.  Limit: the
+ * segments of the pass may number at most n_beams0 x (generations since the previous
+ * accumulation) <= about 5.4 M (e.g. one generation of 64 level-6 sources); a larger pass
+ * returns BT_EINVAL with nothing enqueued (accumulate after fewer generations).  Every call
+ * on a GPU shares that GPU's array: calls that overlap on one GPU (other contexts or
+ * streams) race and must be serialised by the caller.  Explicit point sets use no work
+ * lists. */
+bt_status bt_accumulate_mics_static(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *beams, const bt_params *params,
+                                    bt_mics *mics);
+
 /* Copy results to caller-owned host or device buffers (any may be NULL), then
  * synchronise: strict_out / flag_out double[n_mic] energies (W/m^2), level_db_out
  * double[n_mic] = 10 log10((strict + flag) / 1e-12), -inf where no energy arrived. */

@@ -22,7 +22,8 @@ STATUS = {0: "BT_OK", 1: "BT_PENDING", -1: "BT_EINVAL", -2: "BT_ENOMEM", -3: "BT
 
 EXPORTED = ["bt_params_default", "bt_status_str", "bt_last_error", "bt_create", "bt_destroy", "bt_memory_used",
             "bt_build_mesh", "bt_mesh_free", "bt_mesh_info", "bt_mics_grid", "bt_mics_grid3d", "bt_mics_subset", "bt_mics_points", "bt_mics_reset", "bt_mics_free",
-            "bt_emit_beams", "bt_emit_beams_directional", "bt_beams_free", "bt_beams_stats", "bt_trace", "bt_accumulate_mics", "bt_levels",
+            "bt_emit_beams", "bt_emit_beams_directional", "bt_beams_free", "bt_beams_stats", "bt_trace", "bt_accumulate_mics",
+            "bt_accumulate_mics_static", "bt_levels",
             "bt_run", "bt_submit", "bt_poll", "bt_cancel", "bt_batch_run", "bt_batch_release", "bt_batch_autotune",
             "bt_server_create", "bt_server_submit", "bt_server_poll", "bt_server_destroy"]
 
@@ -92,6 +93,7 @@ def lib():
         "bt_beams_stats": (C.c_int, [P, P, P]),
         "bt_trace": (C.c_int, [P, P, P, P, P]),
         "bt_accumulate_mics": (C.c_int, [P, P, P, P, P]),
+        "bt_accumulate_mics_static": (C.c_int, [P, P, P, P, P]),
         "bt_levels": (C.c_int, [P, P, P, P, P]),
         "bt_run": (C.c_int, [P, P, P, P, I32, I32, P, P, P]),
         "bt_submit": (C.c_int, [P, P, P, P]),
@@ -259,6 +261,10 @@ def bt_trace(ctx, mesh, beams, params, want_next=False):
 
 def bt_accumulate_mics(ctx, mesh, beams, params, mics):
     _check(ctx, lib().bt_accumulate_mics(ctx, mesh, beams, C.byref(params), mics), "bt_accumulate_mics")
+
+
+def bt_accumulate_mics_static(ctx, mesh, beams, params, mics):
+    _check(ctx, lib().bt_accumulate_mics_static(ctx, mesh, beams, C.byref(params), mics), "bt_accumulate_mics_static")
 
 
 def bt_levels(ctx, mics, strict_out=None, flag_out=None, level_db_out=None):

@@ -149,6 +149,12 @@ extern "C" bt_status bt_create(int device, size_t hbm_budget_bytes, void *hip_st
     ctx->budget = hbm_budget_bytes;
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess) { delete ctx; return BT_EDEVICE; }
+    // the device's static work area, looked up once per device with the device current
+    if (static_scratch(device, &ctx->scratch) != hipSuccess) {
+        (void)hipGetLastError();
+        delete ctx;
+        return BT_EDEVICE;
+    }
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
         ctx->n_cu = ncu;
@@ -1232,6 +1238,48 @@ extern "C" bt_status bt_accumulate_mics(bt_ctx *ctx, const bt_mesh *mesh, bt_bea
     MicWork w{b->rows, b->rows_cap, b->spans, b->spans_cap, b->big_list + b->cap, b->big_list, b->layers,
               b->layers_cap};
     HIP_TRY(ctx, launch_mics(mesh->dev, b->q, b->segs, b->ctr, mics->dev, a, w, b->ws, ctx->n_cu, ctx->stream));
+    b->acc_gen = b->gen;
+    return BT_OK;
+}
+
+// The allocation-free variant: the same kernels, with their work lists in the device's
+// static work area instead of the beam set's buffers.
+extern "C" bt_status bt_accumulate_mics_static(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *b, const bt_params *p,
+                                               bt_mics *mics)
+{
+    if (!ctx) return BT_EINVAL;
+    if (!mesh || !b || !mics) return fail(ctx, BT_EINVAL, "NULL mesh, beams or mics");
+    bt_status s = check_params(ctx, mesh, p);
+    if (s != BT_OK) return s;
+    if (b->gen == 0) return fail(ctx, BT_ESTATE, "no generation traced yet");
+    if (b->acc_gen == b->gen) return BT_OK;  // nothing traced since the last call
+    if (!ctx->scratch) return fail(ctx, BT_EDEVICE, "no static work area on device %d", ctx->device);
+    (void)hipSetDevice(ctx->device);
+    TraceArgs a = make_args(p, b->acc_gen);
+    a.gen_end = b->gen;
+    if (mics->points) {   // the point kernel uses no work lists
+        HIP_TRY(ctx, launch_mics_points(mesh->dev, b->q, b->segs, b->ctr, mics->dev, mics->pts, a, ctx->n_cu,
+                                        ctx->stream));
+        b->acc_gen = b->gen;
+        return BT_OK;
+    }
+    // segments of this pass: at most n0 per generation
+    const long long n_bound = std::max(b->n0, 1ll) * (long long)(b->gen - b->acc_gen);
+    const int W = b->ws.n_waves;
+    if (W > kStaticMaxWaves) return fail(ctx, BT_EINVAL, "%d waves exceed the static work area's %d", W, kStaticMaxWaves);
+    const long long n_max = (kStaticListInts - 64ll * (W + 1)) / 2;
+    if (n_bound > n_max)
+        return fail(ctx, BT_EINVAL,
+                    "this pass may hold %lld segments (%lld generation-0 beams x %d generations), more than the "
+                    "static work area's %lld; accumulate after fewer generations",
+                    n_bound, b->n0, b->gen - b->acc_gen, n_max);
+    char *base = (char *)ctx->scratch;
+    WaveScratch ws = b->ws;
+    ws.general = (unsigned *)base;
+    int *lists = (int *)(base + kStaticListsOffset);
+    MicWork w{(int2 *)(base + kStaticRowsOffset), kStaticRows, (int4 *)(base + kStaticSpansOffset), kStaticSpans,
+              lists + n_bound, lists, (int2 *)(base + kStaticLayersOffset), kStaticLayers};
+    HIP_TRY(ctx, launch_mics(mesh->dev, b->q, b->segs, b->ctr, mics->dev, a, w, ws, ctx->n_cu, ctx->stream));
     b->acc_gen = b->gen;
     return BT_OK;
 }

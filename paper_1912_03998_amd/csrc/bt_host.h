@@ -28,6 +28,7 @@ struct bt_ctx {
     struct BatchWork *batch = nullptr;  // bt_batch_run's workspace, kept between calls
     double *face_dirs[BT_MAX_LEVEL + 1] = {};  // per icosphere level, built on first use
     double *face_om[BT_MAX_LEVEL + 1] = {};
+    void *scratch = nullptr;   // this device's static work area (bt_accumulate_mics_static)
 };
 
 struct bt_mesh {

@@ -229,6 +229,30 @@ hipError_t launch_trace(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters 
 hipError_t launch_mics(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mics,
                        const TraceArgs &a, MicWork w, WaveScratch ws, int n_cu, hipStream_t s);
 hipError_t launch_fill(double *p, long long n, double v, hipStream_t s);
+
+// Static work area of the allocation-free microphone pass (bt_accumulate_mics_static): a
+// file-scope device array of kStaticScratchBytes per GPU, laid out as
+//   [0, kStaticCountBytes)                per-wave general-path counts (<= kStaticMaxWaves)
+//   rows:   kStaticRows int2              (segment, row) items (overflow: wave path)
+//   spans:  kStaticSpans int4             (segment, row, columns) items (full: in place)
+//   layers: kStaticLayers int2            volumetric (segment, layer) items (full: in place)
+//   lists:  the rest, as ints             wave-path list (n) then general list (n + 64 (W + 1))
+// Nothing in it needs to start at zero: every count lives in the beam set's counters.
+constexpr size_t kStaticScratchBytes = 64ull << 20;
+constexpr int kStaticMaxWaves = 16384;
+constexpr size_t kStaticCountBytes = (size_t)kStaticMaxWaves * sizeof(unsigned);
+constexpr long long kStaticRows = 1ll << 20;
+constexpr long long kStaticSpans = 1ll << 19;
+constexpr long long kStaticLayers = 1ll << 19;
+constexpr size_t kStaticRowsOffset = kStaticCountBytes;
+constexpr size_t kStaticSpansOffset = kStaticRowsOffset + (size_t)kStaticRows * 8;
+constexpr size_t kStaticLayersOffset = kStaticSpansOffset + (size_t)kStaticSpans * 16;
+constexpr size_t kStaticListsOffset = kStaticLayersOffset + (size_t)kStaticLayers * 8;
+constexpr long long kStaticListInts = (long long)((kStaticScratchBytes - kStaticListsOffset) / sizeof(int));
+static_assert(kStaticListsOffset % 256 == 0, "static work area sections stay aligned");
+// Device address of the calling thread's current device's static work area (looked up
+// once per device; `device` must be current).
+hipError_t static_scratch(int device, void **out);
 hipError_t launch_levels(const double *es, const double *ef, double *level, long long n, hipStream_t s);
 
 }  // namespace bt

@@ -1,6 +1,8 @@
 // Microphone accumulation: frustum footprints on the microphone plane, exact membership
 // and FP64 accumulation.  Built with -ffp-contract=off: the tie rule on shared beam faces
 // relies on exactly antisymmetric cross products.
+#include <mutex>
+
 #include "bt_device.h"
 
 namespace bt {
@@ -1538,6 +1540,35 @@ hipError_t launch_mics(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *
         return launch_mics_t<true>(m, q, segs, ctr, mics, a, w, ws, n_cu, s);
     }
     return launch_mics_t<false>(m, q, segs, ctr, mics, a, w, ws, n_cu, s);
+}
+
+// ---------------------------------------------------------------------------------------
+// The static work area of bt_accumulate_mics_static (callers that cannot allocate): one
+// array per GPU, held until the process ends.  Host code never names `scratch` in a kernel
+// argument or copy (its host-side symbol is not a device address); it uses the address
+// hipGetSymbolAddress returns, looked up once per device with that device current.
+// ---------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mtx;
+void *g_scratch_ptr[kScratchDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(int device, void **out)
+{
+    if (device < 0 || device >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mtx);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 }  // namespace bt
