@@ -316,6 +316,8 @@ def main():
     ap.add_argument("--config", type=int, default=2, help="0 tiny, 1 block, 2 district (default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tiles", type=int, default=0, help="override the tile partition (n x n)")
+    ap.add_argument("--queue-rounds", type=int, default=-1,
+                    help="per-tile queue rounds of the trace (0 = in-lane tile walk; default: the library's)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-scenario measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-full", action="store_true",
@@ -367,7 +369,8 @@ def main():
     ctx, mesh, stream = sess.ctx, sess.mesh, sess.stream
     grid = scene_grid(scene)
     mics = sess._mics(grid)
-    params = sess.params(scene.depth)
+    params = sess.params(scene.depth) if args.queue_rounds < 0 else \
+        sess.params(scene.depth, queue_rounds=args.queue_rounds)
     D = scene.depth
     with torch.cuda.stream(stream):
         level_out = torch.empty(scene.n_mic, dtype=torch.float64, device="cuda")

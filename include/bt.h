@@ -62,6 +62,14 @@ typedef struct {
                              ray near t*, is flagged; flags are inherited by children */
     double air_m;         /* air attenuation exp(-air_m * d); 0 = off */
     double e_min;         /* a child whose power K*Omega is <= e_min is dropped; 0 = off */
+    int32_t queue_rounds; /* sub-domain hand-off (paper Section 3: a beam leaving a sub-domain
+                             is passed to the one it enters): 0 = every guiding ray walks the
+                             tiles it crosses in its own lane; k in 1..8 = per-tile beam queues,
+                             each ray's first k tiles taken from the queue of the tile it is in
+                             (a ray leaving a tile unresolved is handed to the queue of the tile
+                             it enters) and any further tiles walked in its lane; partitions
+                             of more than 256 tiles always walk in-lane.  Results are
+                             identical either way. */
     /* optional per-(initial beam, generation) parity outputs, device pointers,
        row-major [n_beams0][max_depth + 1]; entries of untraced generations are
        left untouched (callers pre-fill them, e.g. with -2) */
@@ -86,7 +94,8 @@ typedef struct {
     int64_t mic_fallback;                /* volumetric grids: of which done in place (item buffer full) */
 } bt_stats;
 
-/* Defaults: max_depth 3, t_min 1e-3, edge_delta 1e-5, air_m 0, e_min 0, no outputs. */
+/* Defaults: max_depth 3, t_min 1e-3, edge_delta 1e-5, air_m 0, e_min 0, queue_rounds 0
+ * (measured faster), no outputs. */
 void bt_params_default(bt_params *p);
 
 const char *bt_status_str(bt_status s);

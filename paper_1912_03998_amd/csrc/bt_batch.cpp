@@ -138,6 +138,7 @@ struct BatchWork {
         if ((st = alloc_wave_scratch(ctx, beams, blocks_per_cu)) != BT_OK) return st;
         if ((st = reserve_queue(ctx, beams, r_, 0)) != BT_OK) return st;
         if ((st = reserve_work(ctx, beams, n0)) != BT_OK) return st;
+        if ((st = reserve_tiles(ctx, beams, n0)) != BT_OK) return st;
         cap_sources = s_;
         cap_slots = sl;
         cap_energy = e_;
@@ -172,7 +173,7 @@ bt_status enqueue_chunk(bt_ctx *ctx, const bt_mesh *mesh, BatchWork &w, const Tr
     for (int g = 0; g <= depth; ++g) {
         TraceArgs a = base;
         a.gen = g;
-        HIP_TRY(ctx, launch_trace(mesh->dev, b->q, b->segs, b->ctr, a, b->ws, ctx->n_cu, s));
+        HIP_TRY(ctx, launch_trace(mesh->dev, b->q, b->segs, b->ctr, a, b->ws, trace_tiles(b, mesh, a), ctx->n_cu, s));
     }
     TraceArgs a = base;
     a.gen = 0;

@@ -28,6 +28,21 @@ __global__ void k_fill(double *p, long long n, double v)
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
+__global__ void k_zero_ints(int *p, long long n)
+{
+    long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
+}
+
+hipError_t launch_zero_ints(int *p, long long n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    k_zero_ints<<<(unsigned)blocks, 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(double *p, long long n, double v, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;

@@ -75,6 +75,7 @@ extern "C" void bt_params_default(bt_params *p)
     p->edge_delta = 1e-5;
     p->air_m = 0.0;
     p->e_min = 0.0;
+    p->queue_rounds = 0;   // the in-lane walk measures faster on the district workload
 }
 
 extern "C" const char *bt_status_str(bt_status s)
@@ -908,6 +909,70 @@ void beams_release(bt_beams *b)
     b->layers = nullptr;
     b->layers_cap = 0;
     b->work_n0 = 0;
+    dev_free(ctx, b->tw_buf, b->tw_bytes);
+    b->tw_buf = nullptr;
+    b->tw_bytes = 0;
+    b->tw = TileWork{};
+}
+
+bt_status reserve_tiles(bt_ctx *ctx, bt_beams *b, long long n)
+{
+    n = std::max(n, 1ll);
+    const int W = b->ws.n_waves;
+    if (W <= 0) return fail(ctx, BT_EINVAL, "beam set without a wave grid");
+    if (b->tw_buf && b->tw.cap >= n && b->tw.n_waves == W) return BT_OK;
+    dev_free(ctx, b->tw_buf, b->tw_bytes);
+    b->tw_buf = nullptr;
+    b->tw_bytes = 0;
+    b->tw = TileWork{};
+    // a producer wave handles at most ceil(n / (64 W)) + 2 batches of 64 (static
+    // partition, or its XCD's share of the ordered list)
+    const long long region = 64 * ((n + 64ll * W - 1) / (64ll * W) + 2);
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t b_stage = up((size_t)W * region * sizeof(int2)), b_stage_n = up((size_t)W * sizeof(int));
+    const size_t b_cnt = up((size_t)kMaxQueueTiles * W * sizeof(int)), b_tot = up((kMaxQueueTiles + 1) * sizeof(int));
+    const size_t b_list = up((size_t)n * sizeof(int2)), b_dbl = up((size_t)n * sizeof(double));
+    const size_t b_int = up((size_t)n * sizeof(int));
+    const size_t bytes = b_stage + b_stage_n + 2 * b_cnt + b_tot + b_list + 3 * b_dbl + b_int;
+    bt_status s = dev_alloc(ctx, &b->tw_buf, bytes);
+    if (s != BT_OK) return s;
+    b->tw_bytes = bytes;
+    char *p = (char *)b->tw_buf;
+    b->tw.stage = (int2 *)p;
+    p += b_stage;
+    b->tw.stage_n = (int *)p;
+    p += b_stage_n;
+    b->tw.cnt = (int *)p;
+    p += b_cnt;
+    b->tw.off = (int *)p;
+    p += b_cnt;
+    b->tw.total = (int *)p;
+    b->tw.n_items = b->tw.total + kMaxQueueTiles;
+    p += b_tot;
+    b->tw.list = (int2 *)p;
+    p += b_list;
+    b->tw.lo = (double *)p;
+    p += b_dbl;
+    b->tw.c1t = (double *)p;
+    p += b_dbl;
+    b->tw.c2t = (double *)p;
+    p += b_dbl;
+    b->tw.c1id = (int *)p;
+    b->tw.cap = n;
+    b->tw.region = region;
+    b->tw.n_waves = W;
+    // the per-(tile, wave) counts start at zero; every scan clears them again
+    HIP_TRY(ctx, launch_zero_ints(b->tw.cnt, (long long)kMaxQueueTiles * W, ctx->stream));
+    return BT_OK;
+}
+
+const TileWork *trace_tiles(bt_beams *b, const bt_mesh *mesh, const TraceArgs &a)
+{
+    // partitions of more than kMaxQueueTiles tiles walk their tiles in-lane
+    if (a.queue_rounds <= 0 || !b->tw_buf || mesh->dev.tiles_x * mesh->dev.tiles_y > kMaxQueueTiles) return nullptr;
+    b->tw.n_tiles = mesh->dev.tiles_x * mesh->dev.tiles_y;
+    b->tw.rounds = a.queue_rounds;
+    return &b->tw;
 }
 
 // (segment, layer) item buffer of the volumetric microphone pass, sized from the
@@ -1163,6 +1228,8 @@ bt_status check_params(bt_ctx *ctx, const bt_mesh *mesh, const bt_params *p)
         return fail(ctx, BT_EINVAL, "edge_delta must be in [0, %g]", mesh->delta_cap);
     if (!(p->air_m >= 0.0) || !std::isfinite(p->air_m)) return fail(ctx, BT_EINVAL, "air_m invalid");
     if (!(p->e_min >= 0.0)) return fail(ctx, BT_EINVAL, "e_min invalid");
+    if (p->queue_rounds < 0 || p->queue_rounds > kMaxQueueRounds)
+        return fail(ctx, BT_EINVAL, "queue_rounds %d not in 0..%d", p->queue_rounds, kMaxQueueRounds);
     return BT_OK;
 }
 
@@ -1176,6 +1243,7 @@ TraceArgs make_args(const bt_params *p, int gen)
     a.delta2 = p->edge_delta * p->edge_delta;
     a.air_m = p->air_m;
     a.e_min = p->e_min;
+    a.queue_rounds = p->queue_rounds;
     a.hit_out = p->hit_out;
     a.flag_out = p->flag_out;
     a.t_out = p->t_out;
@@ -1204,7 +1272,9 @@ extern "C" bt_status bt_trace(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *b, con
     }
     b->max_depth = p->max_depth;
     TraceArgs a = make_args(p, g);
-    HIP_TRY(ctx, launch_trace(mesh->dev, b->q, b->segs, b->ctr, a, b->ws, ctx->n_cu, ctx->stream));
+    if (p->queue_rounds > 0 && (s = reserve_tiles(ctx, b, b->n0)) != BT_OK) return s;
+    HIP_TRY(ctx, launch_trace(mesh->dev, b->q, b->segs, b->ctr, a, b->ws, trace_tiles(b, mesh, a), ctx->n_cu,
+                              ctx->stream));
     b->gen = g + 1;
     if (n_next) {
         unsigned long long c = 0;

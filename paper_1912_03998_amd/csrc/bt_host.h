@@ -74,6 +74,9 @@ struct bt_beams {
     long long rows_cap = 0;
     int4 *spans = nullptr;
     long long spans_cap = 0;
+    TileWork tw{};            // per-tile beam queues of the trace (cap = largest generation)
+    void *tw_buf = nullptr;
+    size_t tw_bytes = 0;
     int2 *layers = nullptr;   // volumetric grids: (segment, layer) items, allocated on first use
     long long layers_cap = 0;
     long long work_n0 = 0;    // generation-0 size the work buffers were sized for
@@ -124,6 +127,11 @@ void queue_free(bt_ctx *ctx, DevQueue &q);
 void beams_release(bt_beams *b);
 bt_status reserve_queue(bt_ctx *ctx, bt_beams *b, long long n, long long keep);
 bt_status reserve_work(bt_ctx *ctx, bt_beams *b, long long n0);
+// Tile-queue capacity for generations of up to n rays (allocated on first use).
+bt_status reserve_tiles(bt_ctx *ctx, bt_beams *b, long long n);
+// The tile queues a trace of generation sizes up to the reserved capacity uses (NULL for the
+// in-lane walk).
+const TileWork *trace_tiles(bt_beams *b, const bt_mesh *mesh, const TraceArgs &a);
 
 bt_status check_params(bt_ctx *ctx, const bt_mesh *mesh, const bt_params *p);
 TraceArgs make_args(const bt_params *p, int gen);

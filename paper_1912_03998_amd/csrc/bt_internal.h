@@ -167,6 +167,34 @@ struct WaveScratch {
     int n_waves;                   // W
 };
 
+// Per-tile beam queues of one beam set (the trace's queued rounds).  Positions index the
+// generation being traced (0 .. its size - 1, at most cap).  A round's items are produced
+// by the waves of a W-wave grid, each into a region of its own (no shared cursor), counted
+// per (tile, wave), and then ordered by tile with those counts (a counting sort without
+// atomics: a scan over the waves of each tile, then a scatter).
+//   stage / stage_n: each producer wave's items and their number
+//   cnt:  [T][W] items per (tile, producer wave), cleared by the scan
+//   off:  [T][W] exclusive scan of cnt over the waves of each tile
+//   total, n_items: items per tile and in all of the round being sorted
+//   list: the round's items ordered by tile (then by producer wave, then lane order)
+//   lo, c1t, c2t, c1id: a handed-off ray's window start and flag candidates
+constexpr int kMaxQueueTiles = 256;   // partitions with more tiles walk their tiles in-lane
+constexpr int kMaxQueueRounds = 8;
+constexpr int kXcds = 8;              // MI355X: 8 accelerator complex dies, each with its own L2
+struct TileWork {
+    int2 *stage;
+    int *stage_n;
+    int *cnt, *off, *total, *n_items;
+    int2 *list;
+    double *lo, *c1t, *c2t;
+    int *c1id;
+    long long cap;       // positions: the largest generation
+    long long region;    // items per producer wave's region
+    int n_waves;         // W: the producers' (and consumers') grid in waves
+    int n_tiles;         // T of the mesh traced
+    int rounds;          // queued rounds (>= 1); the last one finishes its rays in-lane
+};
+
 struct TraceArgs {
     int gen;         // trace: the generation traced; microphones: first generation
     int gen_end;     // microphones: one past the last generation accumulated
@@ -175,6 +203,7 @@ struct TraceArgs {
     const DevMics *slot_mics;  // scenario sets: microphone set of each slot
     double t_min, delta, air_m, e_min;
     double delta2;   // delta^2, formed on the host (a kernel argument, so no register holds it)
+    int queue_rounds;  // trace: 0 = in-lane tile walk, k >= 1 = k rounds of per-tile queues
     int *hit_out;
     uint8_t *flag_out;
     double *t_out;
@@ -224,8 +253,10 @@ hipError_t launch_select(const double *es, const double *ef, const long long *se
                          double *out_f, double *out_level, hipStream_t s);
 hipError_t launch_gather(const double *e, const long long *idx, const BatchDesc *d, long long max_n, double *out_e,
                          double *out_f, hipStream_t s);
+// tw: NULL for the in-lane walk, else the beam set's tile queues (rounds from tw->rounds).
 hipError_t launch_trace(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, const TraceArgs &a,
-                        WaveScratch ws, int n_cu, hipStream_t s);
+                        WaveScratch ws, const TileWork *tw, int n_cu, hipStream_t s);
+hipError_t launch_zero_ints(int *p, long long n, hipStream_t s);
 hipError_t launch_mics(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mics,
                        const TraceArgs &a, MicWork w, WaveScratch ws, int n_cu, hipStream_t s);
 hipError_t launch_fill(double *p, long long n, double v, hipStream_t s);

@@ -171,6 +171,8 @@ bt_status alloc_session(bt_server *s, Session &q)
     if ((st = alloc_wave_scratch(ctx, q.b, s->opts.blocks_per_cu)) != BT_OK) return st;
     if ((st = reserve_queue(ctx, q.b, s->opts.max_records, 0)) != BT_OK) return st;
     if ((st = reserve_work(ctx, q.b, std::max<long long>(s->opts.max_records / 4, 1))) != BT_OK) return st;
+    // a generation holds at most every record of the session
+    if ((st = reserve_tiles(ctx, q.b, s->opts.max_records)) != BT_OK) return st;
     if ((st = s->dev(&q.slots, kSessionSlots)) != BT_OK || (st = s->host(&q.h_slots, kSessionSlots)) != BT_OK) return st;
     if ((st = alloc_table(s, q.dev, false)) != BT_OK || (st = alloc_table(s, q.host[0], true)) != BT_OK ||
         (st = alloc_table(s, q.host[1], true)) != BT_OK)
@@ -309,7 +311,8 @@ bt_status step_session(bt_server *s, Session &q, int parity, std::vector<Req *> 
     a.max_depth = kLastGen;
     a.scenarios = 1;
     a.slot_mics = q.slots;
-    HIP_TRY(ctx, launch_trace(s->mesh->dev, b->q, b->segs, b->ctr, a, b->ws, ctx->n_cu, st));
+    HIP_TRY(ctx, launch_trace(s->mesh->dev, b->q, b->segs, b->ctr, a, b->ws, trace_tiles(b, s->mesh, a), ctx->n_cu,
+                              st));
     q.dirty = true;
     // the microphone pass runs only in steps that finish a request, over every generation
     // traced since the previous pass (all stay resident in the session)

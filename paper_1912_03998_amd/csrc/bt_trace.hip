@@ -31,16 +31,19 @@ __device__ __forceinline__ float f32_up(double x)
 struct RaySrc {
     const double *o;   // queue + D_O * cap
     const double *c;   // queue + D_C * cap
-    long long cap, i;
+    long long cap;
+    int i;             // queue index (< 2^31): one register stays live, not a 64-bit pair
 };
 
 __device__ __forceinline__ void load_ray64(RaySrc src, V3 &o, V3 &c)
 {
     // launder the index so the loads are not hoisted out of the traversal loop
-    long long i = src.i;
+    int i = src.i;
     asm volatile("" : "+v"(i));
-    o = {src.o[i], src.o[src.cap + i], src.o[2 * src.cap + i]};
-    c = {src.c[i], src.c[src.cap + i], src.c[2 * src.cap + i]};
+    const double *ox = src.o, *oy = src.o + src.cap, *oz = src.o + 2 * src.cap;
+    const double *cx = src.c, *cy = src.c + src.cap, *cz = src.c + 2 * src.cap;
+    o = {ox[i], oy[i], oz[i]};
+    c = {cx[i], cy[i], cz[i]};
 }
 
 struct RayState {
@@ -285,74 +288,85 @@ __device__ void traverse_tile(const DevMesh &M, int tile, RayState &r, RaySrc sr
     }
 }
 
-// Walk the tiles crossed by the ray in order (half-open parameter windows (t_lo, t_hi]
-// shared by consecutive tiles) and traverse each over its window.
-__device__ void trace_ray(const DevMesh &M, RayState &r, RaySrc src, double t_min, double delta, int *stk)
+// ---------------------------------------------------------------------------------------
+// Tile windows.  A ray's parameter range inside the mesh's box, (t_start, tx], is cut by
+// the interior tile boundaries it crosses into consecutive half-open windows (t_lo, t_hi],
+// one per tile; t_hi is the nearer of the tile's x and y boundaries ahead (or tx), computed
+// from the tile index alone, so every path that reaches a tile computes the same window
+// end.  The first tile's window starts at t_start (a ray may start on a boundary).
+// ---------------------------------------------------------------------------------------
+// The ray's range in the mesh's box and the tile of its start point; false when the ray
+// misses the box.
+__device__ bool ray_box(const DevMesh &M, V3 o, V3 c, double t_min, double delta, double &t_start, double &tx,
+                        int &ix, int &iy)
 {
-    double te = -INFINITY, tx = INFINITY;
+    double te = -INFINITY;
+    tx = INFINITY;
     bool ok = true;
-    double tnx = INFINITY, tny = INFINITY, dtx = INFINITY, dty = INFINITY;
-    int ix, iy, sx, sy;
-    {
-        V3 o, c;
-        load_ray64(src, o, c);
-        const double o3[3] = {o.x, o.y, o.z}, c3[3] = {c.x, c.y, c.z};
-        const double lo3[3] = {M.gx0, M.gy0, M.zmin}, hi3[3] = {M.gx1, M.gy1, M.zmax};
+    const double o3[3] = {o.x, o.y, o.z}, c3[3] = {c.x, c.y, c.z};
+    const double lo3[3] = {M.gx0, M.gy0, M.zmin}, hi3[3] = {M.gx1, M.gy1, M.zmax};
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            if (c3[k] != 0.0) {
-                const double ta = (lo3[k] - o3[k]) / c3[k], tb = (hi3[k] - o3[k]) / c3[k];
-                te = fmax(te, fmin(ta, tb));
-                tx = fmin(tx, fmax(ta, tb));
-            } else if (o3[k] < lo3[k] || o3[k] > hi3[k]) {
-                ok = false;
-            }
-        }
-        const double t_start = fmax(te, t_min - delta);
-        if (!ok || !(t_start <= tx)) return;
-        te = t_start;
-        const double px = o.x + t_start * c.x, py = o.y + t_start * c.y;
-        ix = (int)floor((px - M.gx0) / M.tw);
-        iy = (int)floor((py - M.gy0) / M.th);
-        ix = ix < 0 ? 0 : (ix >= M.tiles_x ? M.tiles_x - 1 : ix);
-        iy = iy < 0 ? 0 : (iy >= M.tiles_y ? M.tiles_y - 1 : iy);
-        sx = c.x > 0.0 ? 1 : (c.x < 0.0 ? -1 : 0);
-        sy = c.y > 0.0 ? 1 : (c.y < 0.0 ? -1 : 0);
-        // parameter of the next interior tile boundary in x and y, and the step between
-        // boundaries; the outermost boundary is left to the exit parameter tx
-        if ((sx > 0 && ix < M.tiles_x - 1) || (sx < 0 && ix > 0)) {
-            tnx = (M.gx0 + (double)(sx > 0 ? ix + 1 : ix) * M.tw - o.x) / c.x;
-            dtx = M.tw / fabs(c.x);
-        }
-        if ((sy > 0 && iy < M.tiles_y - 1) || (sy < 0 && iy > 0)) {
-            tny = (M.gy0 + (double)(sy > 0 ? iy + 1 : iy) * M.th - o.y) / c.y;
-            dty = M.th / fabs(c.y);
+    for (int k = 0; k < 3; ++k) {
+        if (c3[k] != 0.0) {
+            const double ta = (lo3[k] - o3[k]) / c3[k], tb = (hi3[k] - o3[k]) / c3[k];
+            te = fmax(te, fmin(ta, tb));
+            tx = fmin(tx, fmax(ta, tb));
+        } else if (o3[k] < lo3[k] || o3[k] > hi3[k]) {
+            ok = false;
         }
     }
-    double t_lo = te;
-    for (int guard = 0; guard < 2 * (M.tiles_x + M.tiles_y) + 2; ++guard) {
-        const double t_hi = fmin(fmin(tnx, tny), tx);
+    t_start = fmax(te, t_min - delta);
+    if (!ok || !(t_start <= tx)) return false;
+    const double px = o.x + t_start * c.x, py = o.y + t_start * c.y;
+    ix = (int)floor((px - M.gx0) / M.tw);
+    iy = (int)floor((py - M.gy0) / M.th);
+    ix = ix < 0 ? 0 : (ix >= M.tiles_x ? M.tiles_x - 1 : ix);
+    iy = iy < 0 ? 0 : (iy >= M.tiles_y ? M.tiles_y - 1 : iy);
+    return true;
+}
+
+// End of tile (ix, iy)'s window and the tile entered there (both axes step when the
+// ray leaves through a corner).  Only interior boundaries count: the outer ones are the
+// box exit tx.
+__device__ __forceinline__ double tile_exit(const DevMesh &M, V3 o, V3 c, int ix, int iy, double tx, int &nix,
+                                            int &niy)
+{
+    double X = INFINITY, Y = INFINITY;
+    if (c.x > 0.0 && ix < M.tiles_x - 1) X = (M.gx0 + (double)(ix + 1) * M.tw - o.x) / c.x;
+    else if (c.x < 0.0 && ix > 0) X = (M.gx0 + (double)ix * M.tw - o.x) / c.x;
+    if (c.y > 0.0 && iy < M.tiles_y - 1) Y = (M.gy0 + (double)(iy + 1) * M.th - o.y) / c.y;
+    else if (c.y < 0.0 && iy > 0) Y = (M.gy0 + (double)iy * M.th - o.y) / c.y;
+    nix = ix + ((X <= Y && X < INFINITY) ? (c.x > 0.0 ? 1 : -1) : 0);
+    niy = iy + ((Y <= X && Y < INFINITY) ? (c.y > 0.0 ? 1 : -1) : 0);
+    return fmin(fmin(X, Y), tx);
+}
+
+// Traverse tiles in order from (ix, iy), whose window starts at t_lo, until the ray is
+// resolved (a hit with no other triangle within delta beyond the window, or the box
+// exit).  Only the tile index, t_lo and tx stay live across a tile's traversal; the FP64
+// ray is reloaded to find the next window.
+__device__ void walk_tiles(const DevMesh &M, RayState &r, RaySrc src, int ix, int iy, double t_lo, double tx,
+                           double t_min, double delta, int *stk)
+{
+    for (int guard = 0; guard < M.tiles_x + M.tiles_y; ++guard) {
+        int nix, niy;
+        double t_hi;
+        {
+            V3 o, c;
+            load_ray64(src, o, c);
+            t_hi = tile_exit(M, o, c, ix, iy, tx, nix, niy);
+        }
         if (t_hi > t_lo) traverse_tile(M, iy * M.tiles_x + ix, r, src, t_lo, t_hi, t_min, delta, stk);
         if (t_hi >= tx || t_hi >= r.best_t + delta) break;
-        const bool stepx = tnx <= tny, stepy = tny <= tnx;
-        if (stepx) {
-            ix += sx;
-            const bool more = (sx > 0 && ix < M.tiles_x - 1) || (sx < 0 && ix > 0);
-            tnx = more ? tnx + dtx : INFINITY;
-        }
-        if (stepy) {
-            iy += sy;
-            const bool more = (sy > 0 && iy < M.tiles_y - 1) || (sy < 0 && iy > 0);
-            tny = more ? tny + dty : INFINITY;
-        }
-        if (ix < 0 || ix >= M.tiles_x || iy < 0 || iy >= M.tiles_y) break;
+        ix = nix;
+        iy = niy;
         t_lo = t_hi;
     }
 }
 
 // A child is spawned by a hit with depth < max_depth whose power after absorption exceeds
-// e_min (when set), decided in FP64 from the beam's FP64 power P.  k_trace counts
-// children with this rule and k_reflect writes them.
+// e_min (when set), decided in FP64 from the beam's FP64 power P.  The child-counting
+// kernels and k_reflect apply this rule.
 __device__ __forceinline__ bool spawns_child(const DevMesh &M, const TraceArgs &a, int hit, int meta, double P)
 {
     const int max_depth = a.scenarios ? meta_max_depth(meta) : a.max_depth;
@@ -360,79 +374,113 @@ __device__ __forceinline__ bool spawns_child(const DevMesh &M, const TraceArgs &
     return !(a.e_min > 0.0) || (P * (1.0 - (double)M.alpha[hit]) > a.e_min);
 }
 
+// Ray state of queue record i, with nothing found yet.
+__device__ __forceinline__ void ray_init(RayState &r, RaySrc src, int start)
+{
+    V3 o, c;
+    load_ray64(src, o, c);
+    r.ox = (float)o.x;
+    r.oy = (float)o.y;
+    r.oz = (float)o.z;
+    r.cx = (float)c.x;
+    r.cy = (float)c.y;
+    r.cz = (float)c.z;
+    r.o_l1 = fabsf(r.ox) + fabsf(r.oy) + fabsf(r.oz);
+    const double tiny = 1e-20;
+    r.ix = (float)(1.0 / (fabs(c.x) < tiny ? copysign(tiny, c.x) : c.x));
+    r.iy = (float)(1.0 / (fabs(c.y) < tiny ? copysign(tiny, c.y) : c.y));
+    r.iz = (float)(1.0 / (fabs(c.z) < tiny ? copysign(tiny, c.z) : c.z));
+    r.start = start;
+    r.best_t = INFINITY;
+    r.best_id = -1;
+    r.best_near = 0;
+    r.c1_t = INFINITY;
+    r.c2_t = INFINITY;
+    r.c1_id = -1;
+    r.node_visits = 0;
+    r.tri_tests = 0;
+}
+
+// The resolved segment of record i: hit, parameter and flag (own or inherited), and the
+// optional per-(initial beam, generation) parity outputs.  Returns the flag.
+__device__ __forceinline__ int finish_ray(const RayState &r, const DevQueue &in, DevSegs segs, const TraceArgs &a,
+                                          long long i)
+{
+    const long long icap = in.cap;
+    const int meta = in.ints[I_META * icap + i];
+    const int hit = r.best_id;
+    int own_flag;
+    if (hit >= 0) own_flag = r.best_near || (r.c1_id != hit) || (r.c2_t < r.best_t + a.delta);
+    else own_flag = r.c1_t < INFINITY;
+    const int flag_total = ((meta & kMetaFlag) != 0) || own_flag;
+    segs.hit[i] = hit;
+    segs.t[i] = r.best_t;
+    segs.flag[i] = flag_total;
+    if (a.hit_out || a.flag_out || a.t_out) {
+        const long long oidx = (long long)in.ints[I_ID * icap + i] * (a.max_depth + 1) + a.gen;
+        if (a.hit_out) a.hit_out[oidx] = hit;
+        if (a.flag_out) a.flag_out[oidx] = (uint8_t)flag_total;
+        if (a.t_out) a.t_out[oidx] = r.best_t;
+    }
+    return flag_total;
+}
+
+// The tile table (roots and root boxes) staged in LDS for up to 256 tiles, so that a tile
+// change waits on no global load.
+struct TileTable {
+    int root[256];
+    float box[6 * 256];
+};
+__device__ __forceinline__ DevMesh stage_tiles(const DevMesh &M, TileTable &t)
+{
+    DevMesh Ml = M;
+    const int n_tiles = M.tiles_x * M.tiles_y;
+    if (n_tiles <= 256) {
+        for (int k = threadIdx.x; k < n_tiles; k += blockDim.x) t.root[k] = M.tile_root[k];
+        for (int k = threadIdx.x; k < 6 * n_tiles; k += blockDim.x) t.box[k] = M.tile_box[k];
+        __syncthreads();
+        Ml.tile_root = t.root;
+        Ml.tile_box = t.box;
+    }
+    return Ml;
+}
+
+// In-lane walk: each lane resolves its ray through every tile it crosses, then counts
+// the generation's children, flags and power per wave (static partition).
 __global__ void __launch_bounds__(kTraceBlock, 4) k_trace(DevMesh M, DevQueue in, DevSegs segs, DevCounters *ctr, TraceArgs a,
                                                WaveScratch ws)
 {
     __shared__ int stk[kStack * kTraceBlock];
-    // the tile table (roots and root boxes) staged in LDS for up to 256 tiles, so that a
-    // tile change waits on no global load
-    __shared__ int s_root[256];
-    __shared__ float s_box[6 * 256];
-    DevMesh Ml = M;
-    const int n_tiles = M.tiles_x * M.tiles_y;
-    if (n_tiles <= 256) {
-        for (int k = threadIdx.x; k < n_tiles; k += blockDim.x) s_root[k] = M.tile_root[k];
-        for (int k = threadIdx.x; k < 6 * n_tiles; k += blockDim.x) s_box[k] = M.tile_box[k];
-        __syncthreads();
-        Ml.tile_root = s_root;
-        Ml.tile_box = s_box;
-    }
+    __shared__ TileTable tt_lds;
+    const DevMesh Ml = stage_tiles(M, tt_lds);
     const unsigned long long n = ctr->count[a.gen];
     const long long s0 = (long long)gen_start(ctr, a.gen);
     const int lane = lane_id();
     const long long icap = in.cap;
-    const int D1 = a.max_depth + 1;
     // per-lane totals over all of this wave's batches, reduced once at the end
     unsigned children = 0, flagged = 0, nv = 0, tt = 0;
     double power = 0.0;
     for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
         const bool active = (long long)base + lane < (long long)n;
         const long long i = s0 + (long long)base + lane;
-        const RaySrc src{in.dbl + D_O * icap, in.dbl + D_C * icap, icap, active ? i : 0};
+        const RaySrc src{in.dbl + D_O * icap, in.dbl + D_C * icap, icap, active ? (int)i : 0};
         if (active) {
             RayState r;
+            ray_init(r, src, in.ints[I_START * icap + i]);
             {
-                V3 o, c;
-                load_ray64(src, o, c);
-                r.ox = (float)o.x;
-                r.oy = (float)o.y;
-                r.oz = (float)o.z;
-                r.cx = (float)c.x;
-                r.cy = (float)c.y;
-                r.cz = (float)c.z;
-                r.o_l1 = fabsf(r.ox) + fabsf(r.oy) + fabsf(r.oz);
-                const double tiny = 1e-20;
-                r.ix = (float)(1.0 / (fabs(c.x) < tiny ? copysign(tiny, c.x) : c.x));
-                r.iy = (float)(1.0 / (fabs(c.y) < tiny ? copysign(tiny, c.y) : c.y));
-                r.iz = (float)(1.0 / (fabs(c.z) < tiny ? copysign(tiny, c.z) : c.z));
+                double t_start, tx;
+                int ix, iy;
+                bool inside;
+                {
+                    V3 o, c;
+                    load_ray64(src, o, c);
+                    inside = ray_box(Ml, o, c, a.t_min, a.delta, t_start, tx, ix, iy);
+                }
+                if (inside) walk_tiles(Ml, r, src, ix, iy, t_start, tx, a.t_min, a.delta, stk);
             }
-            r.start = in.ints[I_START * icap + i];
-            r.best_t = INFINITY;
-            r.best_id = -1;
-            r.best_near = 0;
-            r.c1_t = INFINITY;
-            r.c2_t = INFINITY;
-            r.c1_id = -1;
-            r.node_visits = 0;
-            r.tri_tests = 0;
-            trace_ray(Ml, r, src, a.t_min, a.delta, stk);
-            const int meta = in.ints[I_META * icap + i];
-            const int id = in.ints[I_ID * icap + i];
+            flagged += finish_ray(r, in, segs, a, i);
             const double P = in.dbl[D_P * icap + i];
-            const int hit = r.best_id;
-            int own_flag;
-            if (hit >= 0) own_flag = r.best_near || (r.c1_id != hit) || (r.c2_t < r.best_t + a.delta);
-            else own_flag = r.c1_t < INFINITY;
-            const int flag_total = ((meta & kMetaFlag) != 0) || own_flag;
-            segs.hit[i] = hit;
-            segs.t[i] = r.best_t;
-            segs.flag[i] = flag_total;
-            const long long oidx = (long long)id * D1 + a.gen;
-            if (a.hit_out) a.hit_out[oidx] = hit;
-            if (a.flag_out) a.flag_out[oidx] = (uint8_t)flag_total;
-            if (a.t_out) a.t_out[oidx] = r.best_t;
-            children += spawns_child(M, a, hit, meta, P);
-            flagged += flag_total;
+            children += spawns_child(M, a, r.best_id, in.ints[I_META * icap + i], P);
             power += P;
             nv += r.node_visits;
             tt += r.tri_tests;
@@ -448,6 +496,295 @@ __global__ void __launch_bounds__(kTraceBlock, 4) k_trace(DevMesh M, DevQueue in
         ws.stats[3 * w] = sf;
         ws.stats[3 * w + 1] = snv;
         ws.stats[3 * w + 2] = stt;
+        ws.power[w] = sp;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Per-tile beam queues (the paper's sub-domain decomposition, Section 3, kept as an
+// on-GPU partition: each sub-domain owns a queue of the beams inside it, and a beam
+// leaving a sub-domain without a hit is handed to the queue of the sub-domain it enters).
+// A generation is traced in rounds:
+//   k_tbin:     every ray's entry tile; rays missing the mesh's box are resolved at once;
+//               the others become round-0 items of their tile
+//   k_tscan, k_tscatter: the round's items ordered by tile (counting sort, no atomics)
+//   k_ttrace:   the ordered items split into equal shares, one per XCD, so that each
+//               XCD's L2 holds the hierarchies of few tiles; a ray whose window ends
+//               unresolved becomes, with its partial result, an item of the next round
+//               queued for the tile it enters; in the last queued round it walks its
+//               remaining tiles in its own lane
+//   k_tcount:   children, flags and power per wave in the static partition k_reflect uses
+// Items are (position in the generation, tile | first-window bit << 16 | near bit << 17);
+// a handed-off ray's partial result lives in the segment record (best hit and parameter)
+// and in the per-position arrays of TileWork (flag candidates and the window start).
+// ---------------------------------------------------------------------------------------
+constexpr int kItemFirst = 1 << 16;
+constexpr int kItemNear = 1 << 17;
+
+__device__ __forceinline__ unsigned long long lanes_below() { return (1ull << lane_id()) - 1ull; }
+
+// Producer side: the lanes with `want` add their items to wave w's region and to its
+// per-tile counts (both owned by the wave, so no atomics).  `n_out` is the wave's item
+// count so far (uniform).
+__device__ __forceinline__ void wave_produce(const TileWork &tw, long long w, bool want, int tile, int2 item,
+                                             int &n_out)
+{
+    const unsigned long long m = __ballot(want);
+    if (m == 0) return;
+    if (want) {
+        const long long k = (long long)n_out + __popcll(m & lanes_below());
+        if (k < tw.region) tw.stage[w * tw.region + k] = item;
+    }
+    n_out += __popcll(m);
+    unsigned long long rem = m;
+    while (rem) {
+        const int leader = __ffsll((long long)rem) - 1;
+        const int t = __shfl(tile, leader, 64);
+        const unsigned long long same = __ballot(want && tile == t);
+        if (lane_id() == leader) tw.cnt[(long long)t * tw.n_waves + w] += __popcll(same);
+        rem &= ~same;
+    }
+}
+
+__device__ __forceinline__ long long global_wave() { return ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; }
+
+__global__ void __launch_bounds__(256) k_tbin(DevMesh M, DevQueue in, DevSegs segs, DevCounters *ctr, TraceArgs a,
+                                              WaveScratch ws, TileWork tw)
+{
+    const unsigned long long n0 = ctr->count[a.gen];
+    const unsigned long long n = (long long)n0 > tw.cap ? (unsigned long long)tw.cap : n0;
+    const long long s0 = (long long)gen_start(ctr, a.gen);
+    const int lane = lane_id();
+    const long long icap = in.cap;
+    const long long w = global_wave();
+    int n_out = 0;
+    for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
+        const bool active = (long long)base + lane < (long long)n;
+        const long long i = s0 + (long long)base + lane;
+        int tile = -1;
+        if (active) {
+            V3 o = ld3(in.dbl + D_O * icap, icap, i), c = ld3(in.dbl + D_C * icap, icap, i);
+            double t_start, tx;
+            int ix, iy;
+            if (ray_box(M, o, c, a.t_min, a.delta, t_start, tx, ix, iy)) {
+                tile = iy * M.tiles_x + ix;
+            } else {
+                // misses the mesh's box: resolved (escape, nothing near)
+                RayState r;
+                r.best_t = INFINITY;
+                r.best_id = -1;
+                r.best_near = 0;
+                r.c1_t = r.c2_t = INFINITY;
+                r.c1_id = -1;
+                finish_ray(r, in, segs, a, i);
+            }
+        }
+        wave_produce(tw, w, tile >= 0, tile, make_int2((int)(base + lane), tile | kItemFirst), n_out);
+    }
+    if (lane == 0) {
+        tw.stage_n[w] = n_out;
+        ws.stats[3 * w + 1] = 0;   // node visits and triangle tests, added to by the rounds
+        ws.stats[3 * w + 2] = 0;
+    }
+}
+
+// Block t: exclusive scan of tile t's counts over the producer waves, the tile's total;
+// the counts are cleared for the next round.
+constexpr int kScanBlock = 1024;
+__global__ void __launch_bounds__(kScanBlock) k_tscan(TileWork tw)
+{
+    __shared__ int s_wsum[kScanBlock / 64];
+    const int t = blockIdx.x;
+    const int W = tw.n_waves;
+    int *cnt = tw.cnt + (long long)t * W;
+    int *off = tw.off + (long long)t * W;
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    const int per = (W + kScanBlock - 1) / kScanBlock;
+    const int b0 = threadIdx.x * per, b1 = min(b0 + per, W);
+    int sum = 0;
+    for (int k = b0; k < b1; ++k) sum += cnt[k];
+    int incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) s_wsum[wv] = incl;
+    __syncthreads();
+    int run = incl - sum, tot = 0;
+    for (int k = 0; k < kScanBlock / 64; ++k) {
+        if (k < wv) run += s_wsum[k];
+        tot += s_wsum[k];
+    }
+    for (int k = b0; k < b1; ++k) {
+        const int c = cnt[k];
+        off[k] = run;
+        run += c;
+        cnt[k] = 0;
+    }
+    if (threadIdx.x == 0) tw.total[t] = tot;
+}
+
+// Wave w places the items of producer region w: tile start (scan of the totals) + the
+// wave's offset within the tile + the item's rank among the region's items of that tile.
+__global__ void __launch_bounds__(256) k_tscatter(TileWork tw)
+{
+    __shared__ int s_start[kMaxQueueTiles + 1];
+    __shared__ int s_run[4][kMaxQueueTiles];
+    const int T = tw.n_tiles, W = tw.n_waves;
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int t = 0; t < T; ++t) {
+            s_start[t] = run;
+            run += tw.total[t];
+        }
+        s_start[T] = run;
+        if (blockIdx.x == 0) *tw.n_items = run;
+    }
+    for (int k = lane; k < T; k += 64) s_run[wv][k] = 0;
+    __syncthreads();
+    const long long w = global_wave();
+    if (w >= W) return;
+    const int n = (int)min((long long)tw.stage_n[w], tw.region);
+    for (int base = 0; base < n; base += 64) {
+        const bool active = base + lane < n;
+        const int2 item = active ? tw.stage[w * tw.region + base + lane] : make_int2(0, 0);
+        const int tile = active ? (item.y & 0xffff) : -1;
+        unsigned long long rem = __ballot(active);
+        while (rem) {
+            const int leader = __ffsll((long long)rem) - 1;
+            const int t = __shfl(tile, leader, 64);
+            const unsigned long long same = __ballot(active && tile == t);
+            if (active && tile == t) {
+                const long long pos = (long long)s_start[t] + tw.off[(long long)t * W + w] + s_run[wv][t] +
+                                      __popcll(same & lanes_below());
+                if (pos < tw.cap) tw.list[pos] = item;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane == leader) s_run[wv][t] += __popcll(same);
+            __builtin_amdgcn_wave_barrier();
+            rem &= ~same;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kTraceBlock, 4) k_ttrace(DevMesh M, DevQueue in, DevSegs segs, DevCounters *ctr,
+                                                          TraceArgs a, WaveScratch ws, TileWork tw, int last)
+{
+    __shared__ int stk[kStack * kTraceBlock];
+    __shared__ TileTable tt_lds;
+    const DevMesh Ml = stage_tiles(M, tt_lds);
+    const long long n = min((long long)*tw.n_items, tw.cap);
+    const long long s0 = (long long)gen_start(ctr, a.gen);
+    const int lane = lane_id();
+    const long long icap = in.cap;
+    const long long w = global_wave();
+    // blocks are dispatched to the XCDs in turn: XCD x runs blocks x, x + 8, ... and
+    // takes the x-th share of the tile-ordered list
+    const int groups = (gridDim.x % kXcds) == 0 ? kXcds : 1;
+    const int xcd = (int)blockIdx.x % groups;
+    const long long wave_in_xcd = (long long)(blockIdx.x / groups) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const long long waves_per_xcd = (long long)(gridDim.x / groups) * (blockDim.x >> 6);
+    const long long share = ((n + groups - 1) / groups + 63) / 64 * 64;
+    const long long lo = (long long)xcd * share, hi = min(n, lo + share);
+    unsigned nv = 0, tt = 0;
+    int n_out = 0;
+    for (long long base = lo + 64 * wave_in_xcd; base < hi; base += 64 * waves_per_xcd) {
+        const bool active = base + lane < hi;
+        const int2 item = active ? tw.list[base + lane] : make_int2(0, 0);
+        const long long pos = item.x;
+        const long long i = s0 + pos;
+        const RaySrc src{in.dbl + D_O * icap, in.dbl + D_C * icap, icap, active ? (int)i : 0};
+        bool hand_off = false;
+        int next = 0;
+        if (active) {
+            RayState r;
+            ray_init(r, src, in.ints[I_START * icap + i]);
+            const int tile = item.y & 0xffff;
+            int ix = tile % Ml.tiles_x, iy = tile / Ml.tiles_x;
+            double t_lo, tx;
+            {
+                V3 o, c;
+                load_ray64(src, o, c);
+                double t_start;
+                int sx, sy;
+                ray_box(Ml, o, c, a.t_min, a.delta, t_start, tx, sx, sy);
+                t_lo = t_start;
+            }
+            if (!(item.y & kItemFirst)) {
+                // carried over from the previous round
+                r.best_t = segs.t[i];
+                r.best_id = segs.hit[i];
+                r.best_near = (item.y & kItemNear) ? 1 : 0;
+                r.c1_t = tw.c1t[pos];
+                r.c2_t = tw.c2t[pos];
+                r.c1_id = tw.c1id[pos];
+                t_lo = tw.lo[pos];
+            }
+            int nix, niy;
+            double t_hi;
+            {
+                V3 o, c;
+                load_ray64(src, o, c);
+                t_hi = tile_exit(Ml, o, c, ix, iy, tx, nix, niy);
+            }
+            if (t_hi > t_lo) traverse_tile(Ml, tile, r, src, t_lo, t_hi, a.t_min, a.delta, stk);
+            const bool done = t_hi >= tx || t_hi >= r.best_t + a.delta;
+            if (!done && !last) {
+                // hand off to the queue of the tile it enters, with its partial result
+                hand_off = true;
+                next = niy * Ml.tiles_x + nix;
+                segs.t[i] = r.best_t;
+                segs.hit[i] = r.best_id;
+                tw.c1t[pos] = r.c1_t;
+                tw.c2t[pos] = r.c2_t;
+                tw.c1id[pos] = r.c1_id;
+                tw.lo[pos] = t_hi;
+                next |= r.best_near ? kItemNear : 0;
+            } else {
+                if (!done) walk_tiles(Ml, r, src, nix, niy, t_hi, tx, a.t_min, a.delta, stk);
+                finish_ray(r, in, segs, a, i);
+            }
+            nv += r.node_visits;
+            tt += r.tri_tests;
+        }
+        if (!last) wave_produce(tw, w, hand_off, next & 0xffff, make_int2((int)pos, next), n_out);
+    }
+    const unsigned long long snv = wave_sum_u64(nv), stt = wave_sum_u64(tt);
+    if (lane == 0) {
+        if (!last) tw.stage_n[w] = n_out;
+        ws.stats[3 * w + 1] += snv;
+        ws.stats[3 * w + 2] += stt;
+    }
+}
+
+// Children, flags and power of the generation per wave, in the static partition that
+// k_reflect uses.
+__global__ void __launch_bounds__(256) k_tcount(DevMesh M, DevQueue in, DevSegs segs, DevCounters *ctr, TraceArgs a,
+                                                WaveScratch ws)
+{
+    const unsigned long long n = ctr->count[a.gen];
+    const long long s0 = (long long)gen_start(ctr, a.gen);
+    const int lane = lane_id();
+    const long long icap = in.cap;
+    unsigned children = 0, flagged = 0;
+    double power = 0.0;
+    for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
+        if ((long long)base + lane < (long long)n) {
+            const long long i = s0 + (long long)base + lane;
+            const double P = in.dbl[D_P * icap + i];
+            children += spawns_child(M, a, segs.hit[i], in.ints[I_META * icap + i], P);
+            flagged += segs.flag[i] != 0;
+            power += P;
+        }
+    }
+    const unsigned long long sc = wave_sum_u64(children), sf = wave_sum_u64(flagged);
+    const double sp = wave_sum_f64(power);
+    if (lane == 0) {
+        const unsigned long long w = wave_first_batch() >> 6;
+        ws.children[w] = sc;
+        ws.stats[3 * w] = sf;
         ws.power[w] = sp;
     }
 }
@@ -636,15 +973,35 @@ __global__ void __launch_bounds__(256) k_reflect(DevMesh M, DevQueue q, DevSegs 
 }
 
 hipError_t launch_trace(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *ctr, const TraceArgs &a,
-                        WaveScratch ws, int n_cu, hipStream_t s)
+                        WaveScratch ws, const TileWork *tw, int n_cu, hipStream_t s)
 {
-    // k_trace and k_reflect must use the same grid: wave w owns the same batches in both
+    // the statically partitioned kernels (k_trace / k_tbin / k_tcount and k_reflect) and
+    // the queued rounds must use the same grid: wave w owns the same batches, records and
+    // producer region in all of them
     (void)n_cu;
     const int blocks = ws.n_waves / kWavesPerBlock;
     if (blocks <= 0 || blocks * kWavesPerBlock != ws.n_waves) return hipErrorInvalidValue;
-    k_trace<<<blocks, kTraceBlock, 0, s>>>(m, q, segs, ctr, a, ws);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    hipError_t e;
+    if (tw) {
+        const int T = m.tiles_x * m.tiles_y;
+        if (tw->n_tiles != T || T > kMaxQueueTiles || tw->rounds < 1 || tw->rounds > kMaxQueueRounds ||
+            tw->n_waves != ws.n_waves)
+            return hipErrorInvalidValue;
+        k_tbin<<<blocks, 256, 0, s>>>(m, q, segs, ctr, a, ws, *tw);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        for (int r = 0; r < tw->rounds; ++r) {
+            k_tscan<<<T, kScanBlock, 0, s>>>(*tw);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            k_tscatter<<<blocks, 256, 0, s>>>(*tw);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            k_ttrace<<<blocks, kTraceBlock, 0, s>>>(m, q, segs, ctr, a, ws, *tw, r + 1 == tw->rounds);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        k_tcount<<<blocks, 256, 0, s>>>(m, q, segs, ctr, a, ws);
+    } else {
+        k_trace<<<blocks, kTraceBlock, 0, s>>>(m, q, segs, ctr, a, ws);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     k_gen_scan<<<1, 1024, 0, s>>>(ctr, a, ws);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_reflect<<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, a, ws);

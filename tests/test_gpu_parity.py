@@ -269,6 +269,24 @@ def test_partition_invariance_block(torch_cuda):
         assert np.abs(b.energy - e).max() <= 1e-12 * e.max()
 
 
+@pytest.mark.parametrize("tiles", [(3, 3), (7, 5)])
+def test_tile_queues_equal_in_lane_walk(torch_cuda, tiles):
+    """Per-tile beam queues with hand-off between them (1, 2 or 8 queued rounds) give the
+    in-lane tile walk's hits, flags, counts and energies exactly."""
+    sc = block_scene(0)
+    say("tile queues vs in-lane walk, block scene, tiles", tiles)
+    with session(sc, tiles=tiles) as s:
+        ref = gpu_run(s, sc, queue_rounds=0)
+        for rounds in (1, 2, 8):
+            g = gpu_run(s, sc, queue_rounds=rounds)
+            assert np.array_equal(g.hit, ref.hit) and np.array_equal(g.flag, ref.flag), rounds
+            assert np.array_equal(g.t_hit, ref.t_hit, equal_nan=True)
+            assert np.array_equal(g.stats["count"], ref.stats["count"])
+            assert np.array_equal(g.stats["flagged"], ref.stats["flagged"])
+            assert g.stats["mic_updates"] == ref.stats["mic_updates"]
+            assert np.abs(g.energy - ref.energy).max() <= 1e-12 * ref.energy.max()
+
+
 # ---------------------------------------------------------------------------------------
 # the district workload (full mesh, 4 x 4 tiles)
 # ---------------------------------------------------------------------------------------
@@ -297,6 +315,13 @@ def test_district_sources_parity(torch_cuda, district):
         g1 = gpu_run(s, sub)
     assert np.array_equal(g.hit, g1.hit) and np.array_equal(g.flag, g1.flag)
     assert np.abs(g.energy - g1.energy).max() <= 1e-12 * g.energy.max()
+    say("district tile queues: 2 and 8 queued rounds against the in-lane walk")
+    with session(sc) as s:
+        for rounds in (2, 8):
+            g2 = gpu_run(s, sub, queue_rounds=rounds)
+            assert np.array_equal(g.hit, g2.hit) and np.array_equal(g.flag, g2.flag), rounds
+            assert np.array_equal(g.stats["count"], g2.stats["count"])
+            assert np.abs(g.energy - g2.energy).max() <= 1e-12 * g.energy.max()
 
 
 def test_district_full_size(torch_cuda, district):
