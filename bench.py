@@ -55,17 +55,42 @@ def pmc_traffic(n_launch_units):
     return float(b.group(1)) / n_launch_units
 
 
-def cpu_baseline(scene):
-    """The FP64 oracle on the host cores over the whole workload (it finishes in seconds)."""
+def host_facts():
+    """The host's logical CPU count and CPU model (from /proc/cpuinfo)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"host_nproc": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline(scene, single_sources=16):
+    """The FP64 oracle as it stands on the host: every logical CPU (os.cpu_count(), one
+    thread each) over the whole workload, and one thread over a bounded sample (the first
+    `single_sources` sources, the paper's sequential reference point)."""
     from oracle import oracle as O
 
-    threads = O.default_threads()
+    threads = os.cpu_count() or 1
     t0 = time.perf_counter()
     r = O.trace(scene, keep_paths=False, n_threads=threads)
     dt = time.perf_counter() - t0
+    k = min(single_sources, scene.n_src)
+    one = scene.with_(sources=scene.sources[:k], power=scene.power[:k])
+    t0 = time.perf_counter()
+    r1 = O.trace(one, keep_paths=False, n_threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": r.counters["segments"] / dt, "unit": "beam-segments/s", "cores": threads, "kind": "oracle",
             "sample": f"whole workload ({r.counters['segments']} segments, {r.counters['mic_updates']} mic updates) "
-                      f"in {dt:.2f} s", "mic_updates_per_s": r.counters["mic_updates"] / dt}
+                      f"in {dt:.2f} s on {threads} threads", "mic_updates_per_s": r.counters["mic_updates"] / dt,
+            "single_thread": {"value": r1.counters["segments"] / dt1, "unit": "beam-segments/s", "cores": 1,
+                              "sample": f"sources 0-{k - 1} of the workload ({r1.counters['segments']} segments, "
+                                        f"{r1.counters['mic_updates']} mic updates) in {dt1:.2f} s",
+                              "mic_updates_per_s": r1.counters["mic_updates"] / dt1},
+            **host_facts()}
 
 
 def batch_bench(sess, seed=0, n=256):
@@ -296,7 +321,7 @@ def volumetric_bench(steps, warmup, chunk=7, level=8, oracle_sample=True):
         # the oracle on one whole source of the same workload (bounded CPU time)
         from oracle import oracle as O
         one = scene.with_(sources=scene.sources[20:21], power=scene.power[20:21])
-        threads = O.default_threads()
+        threads = os.cpu_count() or 1
         print("[bench] volumetric cpu baseline (oracle, one source) ...", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         r = O.trace(one, keep_paths=False, n_threads=threads)
@@ -316,12 +341,17 @@ def main():
     ap.add_argument("--config", type=int, default=2, help="0 tiny, 1 block, 2 district (default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tiles", type=int, default=0, help="override the tile partition (n x n)")
+    ap.add_argument("--run-call", action="store_true",
+                    help="time each step as one bt_run call (source chunks, two generation slots, a microphone "
+                         "pass per generation) instead of bt_emit_beams, bt_trace per generation and one "
+                         "bt_accumulate_mics")
     ap.add_argument("--queue-rounds", type=int, default=-1,
                     help="per-tile queue rounds of the trace (0 = in-lane tile walk; default: the library's)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-scenario measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
-    ap.add_argument("--serve-full", action="store_true",
-                    help="serving at the full stream lengths (200 warm-up + 2000 requests per rate)")
+    ap.add_argument("--serve-short", action="store_true",
+                    help="serving on short streams (300 / 800 / 2200 requests at 50 / 200 / 800 req/s) instead of "
+                         "the configured 200 warm-up + 2000 measured requests per rate")
     ap.add_argument("--no-volumetric", action="store_true", help="skip the volumetric (tall district) measurement")
     ap.add_argument("--no-points", action="store_true", help="skip the explicit-receiver measurement")
     ap.add_argument("--volumetric-only", action="store_true",
@@ -330,6 +360,9 @@ def main():
     ap.add_argument("--vol-level", type=int, default=8, help="icosphere level of the volumetric measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
+    ap.add_argument("--gather-calibration", action="store_true",
+                    help="only run a gather of one 8-byte value from each of 8 Mi distinct 128-byte lines "
+                         "(HBM counter calibration for scattered reads)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the tracer runs on one device)",
@@ -347,6 +380,18 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}), flush=True)
+        return
+    if args.gather_calibration:
+        # 8 Mi distinct 128-byte lines of a 1 GiB array, one FP64 value read from each, in a
+        # random order: 1 GiB of lines fetched, 64 MiB of values written
+        lines = 1 << 23
+        src = torch.ones(lines * 16, dtype=torch.float64, device="cuda")
+        idx = (torch.randperm(lines, device="cuda") * 16).contiguous()
+        for _ in range(3):
+            dst = torch.index_select(src, 0, idx)
+        torch.cuda.synchronize()
+        print(json.dumps({"gather_lines": lines, "line_bytes": 128, "values_written_bytes": lines * 8,
+                          "gathers": 3, "checksum": float(dst.sum().item())}), flush=True)
         return
 
     from paper_1912_03998_amd import bt
@@ -378,7 +423,19 @@ def main():
     pw = np.ascontiguousarray(scene.power, np.float32)
 
     def step(ev=None):
-        # the sequence of bt_run, with events between the stages
+        if args.run_call:
+            # one call: its stages are not separated (the whole step counts as the trace stage)
+            bt.bt_mics_reset(ctx, mics)
+            if ev is not None:
+                ev[0].record(stream)
+            sess.beams = bt.bt_run(ctx, mesh, src, pw, scene.level, params, mics, sess.beams)
+            if ev is not None:
+                ev[1].record(stream)
+                ev[2].record(stream)
+            bt.bt_levels(ctx, mics, None, None, level_out)
+            return
+        # emission, every generation's trace, one microphone pass over all of them, with
+        # events between the stages
         sess.beams = bt.bt_emit_beams(ctx, src, pw, scene.level, sess.beams)
         bt.bt_mics_reset(ctx, mics)
         if ev is not None:
@@ -416,19 +473,29 @@ def main():
         trace_bytes = (B_BEAM + B_HIT) * ref["segments"] + B_CHILD * ref["children"] + \
             B_NODE * ref["node_visits"] + B_TRI * ref["tri_tests"]
         mic_bytes = B_MIC * ref["mic_updates"]
-        # the trace stage is k_trace + k_gen_scan + k_reflect, launched by each bt_trace call;
-        # the microphone stage is the five kernels of one bt_accumulate_mics call
+        # the trace stage is what each bt_trace call launches: k_trace + k_gen_scan + k_reflect
+        # (in-lane tile walk), or with per-tile queues k_tbin, (k_tscan, k_tscatter, k_ttrace)
+        # per queued round, k_tcount, k_gen_scan, k_reflect; the microphone stage is the five
+        # kernels of one bt_accumulate_mics call
+        q = params.queue_rounds
         trace_dominant = trace_ms >= mic_ms
-        dominant = "k_trace+k_gen_scan+k_reflect" if trace_dominant else \
-            "k_mics_plane+k_mics_general+k_mic_rows+k_mics_big+k_mic_spans"
+        if trace_dominant:
+            dominant = "k_trace+k_gen_scan+k_reflect" if q == 0 else \
+                "k_tbin+k_tscan+k_tscatter+k_ttrace+k_tcount+k_gen_scan+k_reflect"
+        else:
+            dominant = "k_mics_plane+k_mics_general+k_mic_rows+k_mics_big+k_mic_spans"
         t_dom = trace_ms if trace_dominant else mic_ms
         b_dom = trace_bytes if trace_dominant else mic_bytes
-        launches = 3 * (D + 1) if trace_dominant else 5
+        launches = (3 if q == 0 else 4 + 3 * q) * (D + 1) if trace_dominant else 5
         achieved = b_dom / (t_dom * 1e-3) / 1e9
-        traffic = pmc_traffic(launches) if trace_ms >= mic_ms else None
+        traffic = pmc_traffic(launches) if trace_dominant and q == 0 else None
+        frac_alg = round(achieved / HBM_PEAK_GBS, 4)
+        # measured: the HBM bytes rocprofv3 counted for the stage (FETCH_SIZE + WRITE_SIZE,
+        # calibrated) over the stage's time, against the same peak
+        frac_meas = round(traffic * launches / (t_dom * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None
         roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "traffic_unit": "HBM bytes per launch (stage total / launches)",
+                    "unit": "GB/s", "frac": frac_alg, "frac_algorithmic": frac_alg, "frac_measured": frac_meas,
+                    "traffic": traffic, "traffic_unit": "HBM bytes per launch (stage total / launches)",
                     "algorithmic_bytes_per_step": b_dom, "launches_per_step": launches,
                     "kernel_ms_per_step": round(t_dom, 3)}
     gpu_bytes = (B_BEAM + B_HIT) * segs + B_NODE * st["node_visits"] + B_TRI * st["tri_tests"]
@@ -457,6 +524,9 @@ def main():
         "gpu_node_visits_per_segment": st["node_visits"] / max(segs, 1),
         "gpu_tri_tests_per_segment": st["tri_tests"] / max(segs, 1),
         "setup_s": round(setup_s, 3),
+        "step_call": "bt_run (source chunks, two generation slots)" if args.run_call else
+                     "bt_emit_beams, bt_trace per generation (every generation resident), bt_accumulate_mics",
+        "device_memory_bytes": bt.bt_memory_used(ctx),
         "end_to_end_segments_per_s": segs / (setup_s + ms_per_step * 1e-3),
         "kernel_sha256_16": kernel_hash(),
     }
@@ -465,10 +535,10 @@ def main():
     if args.config == 2 and not args.no_batch:
         out["batched"] = batch_bench(sess)
     if args.config == 2 and not args.no_serve:
-        if args.serve_full:
-            n_of_rate, warm = (lambda r: 2200), 200 / 2200
-        else:
+        if args.serve_short:
             n_of_rate, warm = (lambda r: int(min(2200, max(300, 4 * r)))), 0.1
+        else:
+            n_of_rate, warm = (lambda r: 2200), 200 / 2200
         out["served"] = serve_bench(sess, [50, 200, 800], n_of_rate, warm)
     sess.close()
     if args.config == 2 and not args.no_volumetric:

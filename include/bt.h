@@ -222,8 +222,16 @@ bt_status bt_accumulate_mics_static(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *
 bt_status bt_levels(bt_ctx *ctx, const bt_mics *mics, double *strict_out, double *flag_out,
                     double *level_db_out);
 
-/* Convenience: emit, then max_depth + 1 times (trace, accumulate).  Reuses *beams
- * when non-NULL (created otherwise; caller frees).  Does not synchronise. */
+/* Convenience: the whole method for a source set (paper Section 2), with memory bounded
+ * whatever the number of sources, level or depth.  The sources are taken in chunks of at
+ * most 16 Mi generation-0 beams (at least one source each); a chunk is emitted into a beam
+ * set that keeps two generation slots (not every generation), and each of its
+ * max_depth + 1 generations is traced and then accumulated at once.  So n_src x 20 4^level
+ * may exceed 2^31, and a run holds at most 2 x 16 Mi beam records.  Parity outputs in
+ * params keep their global rows [n_src 20 4^level][max_depth + 1].  bt_beams_stats on the
+ * set afterwards reports the whole run (it synchronises once per extra chunk).  Reuses
+ * *beams when non-NULL (created otherwise; caller frees).  Does not synchronise apart
+ * from those chunk boundaries. */
 bt_status bt_run(bt_ctx *ctx, const bt_mesh *mesh, const float *src_xyz, const float *src_power,
                  int32_t n_src, int32_t level, const bt_params *params, bt_mics *mics, bt_beams **beams);
 

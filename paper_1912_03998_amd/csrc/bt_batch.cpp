@@ -167,7 +167,7 @@ bt_status enqueue_chunk(bt_ctx *ctx, const bt_mesh *mesh, BatchWork &w, const Tr
     bt_beams *b = w.beams;
     hipStream_t s = ctx->stream;
     const EmitTable t{w.src, w.power, w.level, w.meta, w.id0, w.first, w.dims};
-    HIP_TRY(ctx, launch_init_counters(b->ctr, 0, s));
+    HIP_TRY(ctx, launch_init_counters(b->ctr, 0, 0, s));
     HIP_TRY(ctx, launch_emit_table(ctx->base20, t, w.cap_n0, b->q, b->ctr, 0, s));
     HIP_TRY(ctx, launch_fill_desc(w.energy, w.desc, 2 * w.cap_energy, s));
     for (int g = 0; g <= depth; ++g) {

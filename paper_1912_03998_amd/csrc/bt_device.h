@@ -78,11 +78,21 @@ __device__ __forceinline__ unsigned long long wave_batch_stride()
     return (unsigned long long)gridDim.x * blockDim.x;
 }
 
-// First queue index of generation g: the sizes of the generations before it.
+// First queue index of generation g: the sizes of the generations before it (resident
+// layout), or its slot (two-slot layout).
 __device__ __forceinline__ unsigned long long gen_start(const DevCounters *ctr, int g)
 {
+    if (ctr->ring) return (unsigned long long)(g & 1) * ctr->ring;
     unsigned long long s = 0;
     for (int k = 0; k < g; ++k) s += ctr->count[k];
+    return s;
+}
+// Segments of generations [g0, g1) (contiguous in the queue; one generation in the
+// two-slot layout).
+__device__ __forceinline__ unsigned long long gen_count(const DevCounters *ctr, int g0, int g1)
+{
+    unsigned long long s = 0;
+    for (int k = g0; k < g1; ++k) s += ctr->count[k];
     return s;
 }
 

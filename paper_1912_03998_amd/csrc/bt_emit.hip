@@ -7,18 +7,21 @@ namespace bt {
 // ---------------------------------------------------------------------------------------
 // counters
 // ---------------------------------------------------------------------------------------
-__global__ void k_init_counters(DevCounters *ctr, long long n0)
+__global__ void k_init_counters(DevCounters *ctr, long long n0, long long ring)
 {
     unsigned long long *w = reinterpret_cast<unsigned long long *>(ctr);
     const int nw = (int)(sizeof(DevCounters) / sizeof(unsigned long long));
     for (int i = threadIdx.x; i < nw; i += blockDim.x) w[i] = 0ull;  // doubles: +0.0 bits
     __syncthreads();
-    if (threadIdx.x == 0) ctr->count[0] = (unsigned long long)n0;
+    if (threadIdx.x == 0) {
+        ctr->count[0] = (unsigned long long)n0;
+        ctr->ring = (unsigned long long)ring;
+    }
 }
 
-hipError_t launch_init_counters(DevCounters *ctr, long long n0, hipStream_t s)
+hipError_t launch_init_counters(DevCounters *ctr, long long n0, long long ring, hipStream_t s)
 {
-    k_init_counters<<<1, 256, 0, s>>>(ctr, n0);
+    k_init_counters<<<1, 256, 0, s>>>(ctr, n0, ring);
     return hipGetLastError();
 }
 

@@ -1071,8 +1071,10 @@ bt_status reserve_work(bt_ctx *ctx, bt_beams *b, long long n0)
 }
 
 // Generation 0 of a beam set; src_weight NULL (omni sources) or host float[n_src][nf].
+// two_slot: the set keeps two generation slots of n0 records (each generation must be
+// accumulated before the next is traced) instead of every generation.
 static bt_status emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_power, const float *src_weight,
-                            int32_t n_src, int32_t level, bt_beams **inout)
+                            int32_t n_src, int32_t level, bt_beams **inout, bool two_slot = false)
 {
     if (!ctx) return BT_EINVAL;
     if (!inout) return fail(ctx, BT_EINVAL, "inout is NULL");
@@ -1108,8 +1110,12 @@ static bt_status emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_
         }
     }
     // room for every generation of the previous run's depth (grown at the first trace if
-    // the depth is larger)
-    const long long want = std::max(n0, 1ll) * (long long)(b->depth_hint + 1);
+    // the depth is larger), or for two generations
+    const long long want = std::max(n0, 1ll) * (two_slot ? 2ll : (long long)(b->depth_hint + 1));
+    if (two_slot && want > (1ll << 31) - 1) {
+        if (fresh) bt_beams_free(b);
+        return fail(ctx, BT_EINVAL, "two generations of %lld beams exceed 2^31 - 1 records", n0);
+    }
     bt_status s = reserve_queue(ctx, b, want <= (1ll << 31) - 1 ? want : std::max(n0, 1ll), 0);
     if (s == BT_OK) s = reserve_work(ctx, b, std::max(n0, 1ll));
     if (s == BT_OK && n_src > b->src_cap) {
@@ -1142,7 +1148,7 @@ static bt_status emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_
             HIP_TRY(ctx, hipMemcpyAsync(b->wt_dev, src_weight, (size_t)n0 * sizeof(float), hipMemcpyHostToDevice,
                                         ctx->stream));
     }
-    HIP_TRY(ctx, launch_init_counters(b->ctr, n0, ctx->stream));
+    HIP_TRY(ctx, launch_init_counters(b->ctr, n0, two_slot ? std::max(n0, 1ll) : 0, ctx->stream));
     if (!ctx->face_dirs[level]) {
         // the level's face directions, computed once per context
         const long long nf = 20ll << (2 * level);
@@ -1158,6 +1164,8 @@ static bt_status emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_
     b->acc_gen = 0;
     b->max_depth = -1;
     b->n0 = n0;
+    b->ring = two_slot ? std::max(n0, 1ll) : 0;
+    b->prior = bt_stats{};
     b->r_src = r_src;
     *inout = b;
     return BT_OK;
@@ -1216,6 +1224,22 @@ extern "C" bt_status bt_beams_stats(bt_ctx *ctx, const bt_beams *b, bt_stats *ou
         out->mic_general += (int64_t)h.n_layers[g];
         if ((long long)h.n_layers[g] > b->layers_cap) out->mic_fallback += (int64_t)h.n_layers[g] - b->layers_cap;
     }
+    // earlier source chunks of a bt_run
+    const bt_stats &q = b->prior;
+    out->generations = std::max(out->generations, q.generations);
+    for (int g = 0; g <= BT_MAX_DEPTH; ++g) {
+        out->count[g] += q.count[g];
+        out->flagged[g] += q.flagged[g];
+        out->power[g] += q.power[g];
+    }
+    out->segments += q.segments;
+    out->node_visits += q.node_visits;
+    out->tri_tests += q.tri_tests;
+    out->mic_tests += q.mic_tests;
+    out->mic_updates += q.mic_updates;
+    out->mic_layer_visits += q.mic_layer_visits;
+    out->mic_general += q.mic_general;
+    out->mic_fallback += q.mic_fallback;
     return BT_OK;
 }
 
@@ -1260,9 +1284,11 @@ extern "C" bt_status bt_trace(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *b, con
         return fail(ctx, BT_EINVAL, "max_depth changed between generations (%d -> %d)", b->max_depth, p->max_depth);
     if (b->gen > p->max_depth) return fail(ctx, BT_ESTATE, "all %d generations already traced", p->max_depth + 1);
     if (b->r_src > mesh->r_eff) return fail(ctx, BT_EINVAL, "a source lies outside the region the mesh margins cover (|x| <= %g)", mesh->r_eff);
+    if (b->ring && b->acc_gen < b->gen)
+        return fail(ctx, BT_ESTATE, "two-slot beam set: accumulate generation %d before tracing the next", b->gen - 1);
     (void)hipSetDevice(ctx->device);
     int g = b->gen;
-    if (g == 0) {
+    if (g == 0 && !b->ring) {
         // every generation stays resident: at most n0 records each
         const long long total = std::max(b->n0, 1ll) * (long long)(p->max_depth + 1);
         if (total > (1ll << 31) - 1)
@@ -1382,6 +1408,10 @@ extern "C" bt_status bt_levels(bt_ctx *ctx, const bt_mics *m, double *strict_out
     return BT_OK;
 }
 
+// Records a bt_run beam set holds at most (two generation slots); sources are taken in
+// chunks whose generation-0 beams fill at most half of it.
+constexpr long long kRunMaxRecords = 1ll << 25;
+
 extern "C" bt_status bt_run(bt_ctx *ctx, const bt_mesh *mesh, const float *src_xyz, const float *src_power,
                             int32_t n_src, int32_t level, const bt_params *p, bt_mics *mics, bt_beams **beams)
 {
@@ -1389,12 +1419,39 @@ extern "C" bt_status bt_run(bt_ctx *ctx, const bt_mesh *mesh, const float *src_x
     if (!mesh || !mics || !beams) return fail(ctx, BT_EINVAL, "NULL mesh, mics or beams");
     bt_status s = check_params(ctx, mesh, p);
     if (s != BT_OK) return s;
-    s = bt_emit_beams(ctx, src_xyz, src_power, n_src, level, beams);
-    if (s != BT_OK) return s;
-    for (int g = 0; g <= p->max_depth; ++g)
-        if ((s = bt_trace(ctx, mesh, *beams, p, nullptr)) != BT_OK) return s;
-    // one microphone pass over the segments of every generation (all stay resident)
-    return bt_accumulate_mics(ctx, mesh, *beams, p, mics);
+    if (level < 0 || level > BT_MAX_LEVEL) return fail(ctx, BT_EINVAL, "level %d not in 0..%d", level, BT_MAX_LEVEL);
+    if (n_src < 0 || (n_src > 0 && (!src_xyz || !src_power))) return fail(ctx, BT_EINVAL, "bad sources");
+    // Sources in chunks of at most kRunMaxRecords / 2 generation-0 beams (at least one
+    // source), each traced with two generation slots and every generation accumulated as
+    // soon as it is traced, so memory is bounded whatever the number of sources, depth or
+    // level.  The per-(initial beam, generation) parity outputs keep their global rows.
+    const long long nf = 20ll << (2 * level);
+    const long long per = std::max(1ll, (kRunMaxRecords / 2) / nf);
+    bt_stats total{};
+    for (long long c0 = 0; c0 < std::max<long long>(n_src, 1); c0 += per) {
+        const int32_t nc = (int32_t)std::min<long long>(per, (long long)n_src - c0);
+        if (c0 > 0) {
+            // the finished chunk's statistics carry over (one synchronisation per chunk)
+            bt_stats st;
+            if ((s = bt_beams_stats(ctx, *beams, &st)) != BT_OK) return s;
+            total = st;
+        }
+        s = emit_beams(ctx, nc > 0 ? src_xyz + 3 * c0 : src_xyz, nc > 0 ? src_power + c0 : src_power, nullptr,
+                       std::max(nc, 0), level, beams, true);
+        if (s != BT_OK) return s;
+        (*beams)->prior = total;
+        bt_params pc = *p;
+        const long long row0 = c0 * nf * (long long)(p->max_depth + 1);
+        if (p->hit_out) pc.hit_out = p->hit_out + row0;
+        if (p->flag_out) pc.flag_out = p->flag_out + row0;
+        if (p->t_out) pc.t_out = p->t_out + row0;
+        for (int g = 0; g <= p->max_depth; ++g) {
+            if ((s = bt_trace(ctx, mesh, *beams, &pc, nullptr)) != BT_OK) return s;
+            if ((s = bt_accumulate_mics(ctx, mesh, *beams, &pc, mics)) != BT_OK) return s;
+        }
+        if (nc <= 0) break;
+    }
+    return BT_OK;
 }
 
 // ---------------------------------------------------------------------------------------

@@ -91,6 +91,8 @@ struct bt_beams {
     int gen = 0;              // generations traced
     int max_depth = -1;       // fixed by the first trace
     long long n0 = 0;
+    long long ring = 0;       // two-slot layout's slot size (bt_run), 0 = every generation resident
+    bt_stats prior{};         // statistics of the earlier source chunks of a bt_run
     double r_src = 0.0;
 };
 

@@ -51,9 +51,12 @@ struct DevMesh {
     int n_tri;
 };
 
-// Beam queue, structure of arrays with capacity `cap`.  All generations of a beam set
-// stay resident: generation g occupies [start_g, start_g + count_g) with
+// Beam queue, structure of arrays with capacity `cap`.  Resident layout: all generations
+// of a beam set stay in the queue, generation g occupying [start_g, start_g + count_g) with
 // start_g = count_0 + ... + count_(g-1), so the capacity is n0 * (max_depth + 1) records.
+// Two-slot layout (DevCounters::ring = S > 0): generation g occupies [(g mod 2) S, + count_g)
+// and overwrites generation g - 2, so each generation must reach the microphones before the
+// one after it is traced; the capacity is 2 S records with S >= n0.
 //   dbl[k * cap + i], k = 0..18: A.xyz, d0.xyz, d1.xyz, d2.xyz, o.xyz, c.xyz, P
 //   flt[k * cap + i], k = 0: K (W/sr)
 // P is the beam's power K Omega in watts, kept in FP64 so that the energy-threshold
@@ -105,6 +108,7 @@ struct DevCounters {
     unsigned long long n_layers[BT_MAX_DEPTH + 2];   // volumetric: (segment, layer) items requested
     unsigned long long node_visits, tri_tests, mic_tests, mic_updates;
     unsigned long long mic_layer_visits;             // volumetric: (segment, layer) pairs examined
+    unsigned long long ring;                         // two-slot layout: slot size (0 = resident)
 };
 
 // Microphone (i, j, k) sits at (x0 + i dx, y0 + j dy, z + k dz) and has index
@@ -232,7 +236,8 @@ struct BatchDesc {
 
 // Kernel launchers; all enqueue on `s` and return hipGetLastError().  The statically
 // partitioned kernels run ws.n_waves waves (blocks of kWavesPerBlock waves).
-hipError_t launch_init_counters(DevCounters *ctr, long long n0, hipStream_t s);
+// ring: the two-slot layout's slot size, 0 for the resident layout.
+hipError_t launch_init_counters(DevCounters *ctr, long long n0, long long ring, hipStream_t s);
 // The face table of an icosphere level (dirs: 12 nf doubles, om: nf doubles), and the
 // emission of one beam set's generation 0 from it.
 hipError_t launch_faces(const double *base20, int level, double *dirs, double *om, hipStream_t s);

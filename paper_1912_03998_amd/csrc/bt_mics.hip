@@ -349,7 +349,7 @@ __global__ void __launch_bounds__(256, 4) k_mics(DevMesh M, DevQueue q, DevSegs 
                                               TraceArgs a, MicWork w, WaveScratch ws)
 {
     const unsigned long long s0 = gen_start(ctr, a.gen);
-    const unsigned long long n = gen_start(ctr, a.gen_end) - s0;
+    const unsigned long long n = gen_count(ctr, a.gen, a.gen_end);
     const int lane = lane_id();
     const unsigned long long wave = wave_first_batch() >> 6;
     const unsigned long long region = wave * general_region(n, ws.n_waves);
@@ -396,7 +396,7 @@ __global__ void __launch_bounds__(256, 3) k_mics_general(DevMesh M, DevQueue q, 
     // list 64 items at a time, so that no wave is left with a short region or a mostly
     // empty last batch of its own.
     const unsigned long long s0 = gen_start(ctr, a.gen);
-    const unsigned long long n_seg = gen_start(ctr, a.gen_end) - s0;
+    const unsigned long long n_seg = gen_count(ctr, a.gen, a.gen_end);
     const int lane = lane_id();
     const unsigned long long wave = wave_first_batch() >> 6;
     const unsigned long long rsize = general_region(n_seg, ws.n_waves);
@@ -883,7 +883,7 @@ __global__ void __launch_bounds__(64, 4) k_mics_plane(DevMesh M, DevQueue q, Dev
 {
     __shared__ PlaneStage st;
     const unsigned long long s0 = gen_start(ctr, a.gen);
-    const unsigned long long n = gen_start(ctr, a.gen_end) - s0;
+    const unsigned long long n = gen_count(ctr, a.gen, a.gen_end);
     const int lane = lane_id();
     const unsigned long long wave = blockIdx.x;
     const unsigned long long region = wave * general_region(n, ws.n_waves);
@@ -960,7 +960,7 @@ __global__ void __launch_bounds__(64, 4) k_mics3d(DevMesh M, DevQueue q, DevSegs
 {
     __shared__ VolStage st;
     const unsigned long long s0 = gen_start(ctr, a.gen);
-    const unsigned long long n = gen_start(ctr, a.gen_end) - s0;
+    const unsigned long long n = gen_count(ctr, a.gen, a.gen_end);
     const int lane = lane_id();
     unsigned tests = 0, updates = 0, visits = 0;
     for (unsigned long long base = (unsigned long long)blockIdx.x * kVolSeg; base < n;
@@ -1356,7 +1356,7 @@ __global__ void __launch_bounds__(64, 3) k_mics_points(DevMesh M, DevQueue q, De
 {
     __shared__ PtsStage st;
     const unsigned long long s0 = gen_start(ctr, a.gen);
-    const unsigned long long n = gen_start(ctr, a.gen_end) - s0;
+    const unsigned long long n = gen_count(ctr, a.gen, a.gen_end);
     const int lane = lane_id();
     unsigned tests = 0, updates = 0;
     for (unsigned long long base = (unsigned long long)blockIdx.x * kVolSeg; base < n;

@@ -185,7 +185,7 @@ bt_status alloc_session(bt_server *s, Session &q)
 // Empty the session for new requests: counters zeroed on the stream, arenas rewound.
 bt_status reset_session(bt_server *s, Session &q)
 {
-    if (q.dirty) HIP_TRY(s->ctx, launch_init_counters(q.b->ctr, 0, s->ctx->stream));
+    if (q.dirty) HIP_TRY(s->ctx, launch_init_counters(q.b->ctr, 0, 0, s->ctx->stream));
     q.dirty = false;
     q.arena_used = q.h_used = 0;
     q.records = 0;

@@ -446,7 +446,9 @@ __device__ __forceinline__ DevMesh stage_tiles(const DevMesh &M, TileTable &t)
 }
 
 // In-lane walk: each lane resolves its ray through every tile it crosses, then counts
-// the generation's children, flags and power per wave (static partition).
+// the generation's children, flags and power per wave (static partition).  The counts
+// are reduced over the wave after every batch, so that no per-lane total stays live
+// across the next batch's traversal (which needs every register it can get).
 __global__ void __launch_bounds__(kTraceBlock, 4) k_trace(DevMesh M, DevQueue in, DevSegs segs, DevCounters *ctr, TraceArgs a,
                                                WaveScratch ws)
 {
@@ -457,13 +459,14 @@ __global__ void __launch_bounds__(kTraceBlock, 4) k_trace(DevMesh M, DevQueue in
     const long long s0 = (long long)gen_start(ctr, a.gen);
     const int lane = lane_id();
     const long long icap = in.cap;
-    // per-lane totals over all of this wave's batches, reduced once at the end
-    unsigned children = 0, flagged = 0, nv = 0, tt = 0;
-    double power = 0.0;
+    unsigned long long sc = 0, sf = 0, snv = 0, stt = 0;
+    double sp = 0.0;
     for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
         const bool active = (long long)base + lane < (long long)n;
         const long long i = s0 + (long long)base + lane;
         const RaySrc src{in.dbl + D_O * icap, in.dbl + D_C * icap, icap, active ? (int)i : 0};
+        unsigned children = 0, flagged = 0, nv = 0, tt = 0;
+        double power = 0.0;
         if (active) {
             RayState r;
             ray_init(r, src, in.ints[I_START * icap + i]);
@@ -478,18 +481,20 @@ __global__ void __launch_bounds__(kTraceBlock, 4) k_trace(DevMesh M, DevQueue in
                 }
                 if (inside) walk_tiles(Ml, r, src, ix, iy, t_start, tx, a.t_min, a.delta, stk);
             }
-            flagged += finish_ray(r, in, segs, a, i);
+            flagged = finish_ray(r, in, segs, a, i);
             const double P = in.dbl[D_P * icap + i];
-            children += spawns_child(M, a, r.best_id, in.ints[I_META * icap + i], P);
-            power += P;
-            nv += r.node_visits;
-            tt += r.tri_tests;
+            children = spawns_child(M, a, r.best_id, in.ints[I_META * icap + i], P);
+            power = P;
+            nv = r.node_visits;
+            tt = r.tri_tests;
         }
+        sc += wave_sum_u64(children);
+        sf += wave_sum_u64(flagged);
+        snv += wave_sum_u64(nv);
+        stt += wave_sum_u64(tt);
+        sp += wave_sum_f64(power);
     }
     // one record per wave (no shared atomics); reduced by k_gen_scan
-    const unsigned long long sc = wave_sum_u64(children), sf = wave_sum_u64(flagged);
-    const unsigned long long snv = wave_sum_u64(nv), stt = wave_sum_u64(tt);
-    const double sp = wave_sum_f64(power);
     if (lane == 0) {
         const unsigned long long w = wave_first_batch() >> 6;
         ws.children[w] = sc;
@@ -907,7 +912,7 @@ __global__ void __launch_bounds__(256) k_reflect(DevMesh M, DevQueue q, DevSegs 
 {
     const unsigned long long n = ctr->count[a.gen];
     const long long s0 = (long long)gen_start(ctr, a.gen);
-    const long long s1 = s0 + (long long)n;  // the children's generation starts here
+    const long long s1 = (long long)gen_start(ctr, a.gen + 1);  // the children's generation starts here
     const int lane = lane_id();
     const DevQueue &in = q, &out = q;
     const long long icap = q.cap, ocap = q.cap;

@@ -340,6 +340,11 @@ def test_district_full_size(torch_cuda, district):
         n, m = full_verdict(sc, g, o)
         assert n > 13_000_000
         assert m["energised"] > 190_000
+        # bt_run keeps two generation slots, not all nine generations
+        from paper_1912_03998_amd import bt
+        used = bt.bt_memory_used(s.ctx)
+        say(f"district device memory through bt_run: {used / 1e9:.2f} GB")
+        assert used < 4e9
         assert st["segments"] == o.counters["segments"] or \
             abs(st["segments"] - o.counters["segments"]) <= o.flagged.sum()
         del o
@@ -353,6 +358,36 @@ def test_district_full_size(torch_cuda, district):
         e = g.energy
         assert np.abs(acc - e).max() <= 1e-9 * e.max()
         assert (e > 0).sum() > 100_000
+
+
+def test_run_chunks_sources_beyond_the_index_range(torch_cuda):
+    """49 sources at level 9 (256,901,120 generation-0 beams) with depth 8: n_beams0 (depth + 1)
+    exceeds 2^31 - 1, yet one bt_run call traces them (source chunks, two generation slots
+    each); the energies equal the sum of the 49 single-source runs to 1e-12, the statistics
+    add up, and the free-field closed form holds."""
+    from paper_1912_03998_amd import bt
+    sc = empty_scene(level=9, src=(0.0, 0.0, 1.0), n_mic=21, spacing=5.0, mic_z=6.0)
+    rng = np.random.default_rng(9)
+    src = rng.uniform([-8.0, -8.0, 0.5], [8.0, 8.0, 3.0], (49, 3)).astype(np.float32)
+    pw = rng.uniform(0.5, 2.0, 49).astype(np.float32)
+    depth, level = 8, 9
+    n0 = 49 * 20 * 4 ** level
+    assert n0 * (depth + 1) > 2 ** 31 - 1
+    say("bt_run over 49 level-9 sources, depth 8")
+    with session(sc) as s:
+        g = s.run(src, pw, level, depth, grid(sc), parity=False)
+        used = bt.bt_memory_used(s.ctx)
+        acc = np.zeros(sc.n_mic)
+        for k in range(49):
+            r = s.run(src[k:k + 1], pw[k:k + 1], level, depth, grid(sc), parity=False)
+            acc += r.energy
+    e = g.energy
+    assert np.abs(acc - e).max() <= 1e-12 * e.max()
+    assert g.stats["segments"] == n0 and g.stats["count"][0] == n0 and g.stats["mic_updates"] == 49 * sc.n_mic
+    m = sc.mic_positions()
+    ref = sum(float(w) / (FOUR_PI * ((m - p.astype(np.float64)) ** 2).sum(1)) for p, w in zip(src, pw))
+    assert np.abs(e / ref - 1).max() < 1e-6
+    assert used < 8e9, used
 
 
 # ---------------------------------------------------------------------------------------

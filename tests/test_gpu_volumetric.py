@@ -132,9 +132,9 @@ def test_volumetric_work_list_overflow(torch_cuda, monkeypatch, env, value):
         g = gpu_run(s, sc)
     verdict(g, o)
     assert g.stats["mic_layer_visits"] > 0 and g.stats["mic_general"] > 0
-    if env == "BT_MIC_LAYER_CAPACITY":   # the in-place path did run
+    if env == "BT_MIC_LAYER_CAPACITY":   # the in-place path did run (in every pass whose items overflowed)
         assert g.stats["mic_general"] > int(value)
-        assert g.stats["mic_fallback"] == g.stats["mic_general"] - int(value)
+        assert 0 < g.stats["mic_fallback"] <= g.stats["mic_general"] - int(value)
 
 
 @pytest.fixture(scope="module")
