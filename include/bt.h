@@ -101,6 +101,21 @@ void bt_params_default(bt_params *p);
 const char *bt_status_str(bt_status s);
 const char *bt_last_error(const bt_ctx *ctx);
 
+/* Host-only argument checks: the checks bt_build_mesh, bt_emit_beams(_directional),
+ * bt_mics_grid3d and the tracing calls make before they touch the device, callable without
+ * a context or a GPU (e.g. to validate inputs on a machine without one).  Return BT_OK,
+ * or BT_EINVAL with the reason written to msg (msg_len bytes, NUL-terminated; msg may be
+ * NULL).  Arguments as in the corresponding calls; src_weight may be NULL (omni sources);
+ * bt_validate_params checks edge_delta against the largest flag distance any mesh's box
+ * margins cover (1e-3 m). */
+bt_status bt_validate_mesh(const float *xyz, int64_t n_vert, const int32_t *tri, const float *absorption,
+                           int64_t n_tri, int32_t tiles_x, int32_t tiles_y, char *msg, size_t msg_len);
+bt_status bt_validate_sources(const float *src_xyz, const float *src_power, const float *src_weight, int32_t n_src,
+                              int32_t level, char *msg, size_t msg_len);
+bt_status bt_validate_grid(float x0, float y0, float z0, float dx, float dy, float dz, int32_t nx, int32_t ny,
+                           int32_t nz, char *msg, size_t msg_len);
+bt_status bt_validate_params(const bt_params *params, char *msg, size_t msg_len);
+
 /* Context on HIP device `device`.  hip_stream: a hipStream_t to enqueue on (e.g. a
  * torch stream's handle) or NULL for a library-owned stream.  hbm_budget_bytes caps
  * the device memory the context allocates (0 = unlimited). */

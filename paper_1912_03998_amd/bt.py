@@ -25,7 +25,8 @@ EXPORTED = ["bt_params_default", "bt_status_str", "bt_last_error", "bt_create", 
             "bt_emit_beams", "bt_emit_beams_directional", "bt_beams_free", "bt_beams_stats", "bt_trace", "bt_accumulate_mics",
             "bt_accumulate_mics_static", "bt_levels",
             "bt_run", "bt_submit", "bt_poll", "bt_cancel", "bt_batch_run", "bt_batch_release", "bt_batch_autotune",
-            "bt_server_create", "bt_server_submit", "bt_server_poll", "bt_server_destroy"]
+            "bt_server_create", "bt_server_submit", "bt_server_poll", "bt_server_destroy",
+            "bt_validate_mesh", "bt_validate_sources", "bt_validate_grid", "bt_validate_params"]
 
 
 class BTError(RuntimeError):
@@ -106,6 +107,11 @@ def lib():
         "bt_server_submit": (C.c_int, [P, P, P]),
         "bt_server_poll": (C.c_int, [P, C.c_uint64, P]),
         "bt_server_destroy": (C.c_int, [P]),
+        "bt_validate_mesh": (C.c_int, [P, C.c_int64, P, P, C.c_int64, I32, I32, P, C.c_size_t]),
+        "bt_validate_sources": (C.c_int, [P, P, P, I32, I32, P, C.c_size_t]),
+        "bt_validate_grid": (C.c_int, [C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, I32, I32,
+                                       I32, P, C.c_size_t]),
+        "bt_validate_params": (C.c_int, [P, P, C.c_size_t]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -142,6 +148,42 @@ def bt_params_default(**kw) -> bt_params:
             v = _ptr(v)
         setattr(p, k, v)
     return p
+
+
+def _validated(status, buf):
+    return status, buf.value.decode()
+
+
+def bt_validate_mesh(xyz, tri, absorption, tiles_x=1, tiles_y=1):
+    """Host-only check of bt_build_mesh's arguments: (status, reason)."""
+    xyz = np.ascontiguousarray(xyz, np.float32).reshape(-1, 3)
+    tri = np.ascontiguousarray(tri, np.int32).reshape(-1, 3)
+    absorption = np.ascontiguousarray(absorption, np.float32)
+    buf = C.create_string_buffer(512)
+    return _validated(lib().bt_validate_mesh(_ptr(xyz), xyz.shape[0], _ptr(tri), _ptr(absorption), tri.shape[0],
+                                             tiles_x, tiles_y, buf, len(buf)), buf)
+
+
+def bt_validate_sources(src_xyz, src_power, level, src_weight=None):
+    """Host-only check of bt_emit_beams(_directional)'s arguments: (status, reason)."""
+    src_xyz = np.ascontiguousarray(src_xyz, np.float32).reshape(-1, 3)
+    src_power = np.ascontiguousarray(src_power, np.float32)
+    w = None if src_weight is None else np.ascontiguousarray(src_weight, np.float32)
+    buf = C.create_string_buffer(512)
+    return _validated(lib().bt_validate_sources(_ptr(src_xyz), _ptr(src_power), _ptr(w), src_xyz.shape[0], level,
+                                                buf, len(buf)), buf)
+
+
+def bt_validate_grid(x0, y0, z0, dx, dy, dz, nx, ny, nz):
+    """Host-only check of bt_mics_grid3d's arguments: (status, reason)."""
+    buf = C.create_string_buffer(512)
+    return _validated(lib().bt_validate_grid(x0, y0, z0, dx, dy, dz, nx, ny, nz, buf, len(buf)), buf)
+
+
+def bt_validate_params(params):
+    """Host-only check of tracing parameters: (status, reason)."""
+    buf = C.create_string_buffer(512)
+    return _validated(lib().bt_validate_params(C.byref(params), buf, len(buf)), buf)
 
 
 def bt_create(device=0, hbm_budget_bytes=0, stream=None):

@@ -34,6 +34,132 @@ bt_status fail(bt_ctx *ctx, bt_status s, const char *fmt, ...)
     return s;
 }
 
+static bt_status why(std::string &msg, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    msg = buf;
+    return BT_EINVAL;
+}
+
+bt_status check_mesh_args(const float *xyz, int64_t n_vert, const int32_t *tri, const float *absorption, int64_t n_tri,
+                          int32_t tiles_x, int32_t tiles_y, std::string &msg)
+{
+    if (n_vert < 0 || n_tri < 0 || n_tri > (1ll << 27))
+        return why(msg, "bad sizes n_vert=%lld n_tri=%lld", (long long)n_vert, (long long)n_tri);
+    if (n_tri > 0 && (!xyz || !tri || !absorption)) return why(msg, "NULL mesh array");
+    if (tiles_x < 1 || tiles_y < 1 || tiles_x > 64 || tiles_y > 64)
+        return why(msg, "tiles must be in 1..64 (got %d x %d)", tiles_x, tiles_y);
+    for (int64_t t = 0; t < n_tri; ++t) {
+        double v[3][3];
+        for (int k = 0; k < 3; ++k) {
+            const int32_t id = tri[3 * t + k];
+            if (id < 0 || id >= n_vert) return why(msg, "triangle %lld has vertex index %d out of range", (long long)t, id);
+            for (int c = 0; c < 3; ++c) {
+                const float x = xyz[3 * (int64_t)id + c];
+                if (!std::isfinite(x)) return why(msg, "vertex %d is not finite", id);
+                v[k][c] = x;
+            }
+        }
+        const float a = absorption[t];
+        if (!(a >= 0.0f && a <= 1.0f)) return why(msg, "absorption of triangle %lld not in [0, 1]", (long long)t);
+        double e1[3], e2[3];
+        for (int c = 0; c < 3; ++c) { e1[c] = v[1][c] - v[0][c]; e2[c] = v[2][c] - v[0][c]; }
+        const double nx = e1[1] * e2[2] - e1[2] * e2[1], ny = e1[2] * e2[0] - e1[0] * e2[2];
+        const double nz = e1[0] * e2[1] - e1[1] * e2[0];
+        if (!(nx * nx + ny * ny + nz * nz > 0.0)) return why(msg, "triangle %lld has zero area", (long long)t);
+    }
+    return BT_OK;
+}
+
+bt_status check_source_args(const float *src_xyz, const float *src_power, const float *src_weight, int32_t n_src,
+                            int32_t level, bool two_slot, std::string &msg)
+{
+    if (n_src < 0 || (n_src > 0 && (!src_xyz || !src_power))) return why(msg, "bad sources");
+    if (level < 0 || level > BT_MAX_LEVEL) return why(msg, "level %d not in 0..%d", level, BT_MAX_LEVEL);
+    const long long nf = 20ll << (2 * level);
+    const long long n0 = nf * n_src;
+    if (n0 * (two_slot ? 2 : 1) > (1ll << 31) - 1) return why(msg, "too many beams (%lld)", n0);
+    if (src_weight)
+        for (long long k = 0; k < n0; ++k)
+            if (!(src_weight[k] >= 0.f) || !std::isfinite(src_weight[k]))
+                return why(msg, "weight %lld (source %lld, face %lld) invalid", k, k / nf, k % nf);
+    for (int i = 0; i < n_src; ++i) {
+        for (int c = 0; c < 3; ++c)
+            if (!std::isfinite(src_xyz[3 * i + c])) return why(msg, "source %d not finite", i);
+        if (!(src_power[i] >= 0.f) || !std::isfinite(src_power[i])) return why(msg, "source %d power invalid", i);
+    }
+    return BT_OK;
+}
+
+bt_status check_grid_args(float x0, float y0, float z0, float dx, float dy, float dz, int32_t nx, int32_t ny,
+                          int32_t nz, std::string &msg)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || (int64_t)nx * ny * nz > (1ll << 31))
+        return why(msg, "bad microphone grid %d x %d x %d", nx, ny, nz);
+    if (nz > 1 && (nx >= (1 << 24) || ny >= (1 << 24) || nz >= (1 << 25)))  // FP32-exact lattice indices;
+        return why(msg, "volumetric grid %d x %d x %d: nx, ny must be below 2^24 and nz below 2^25", nx, ny,
+                   nz);  // layer numbers packed beside 6-bit slots
+    if (!std::isfinite(x0) || !std::isfinite(y0) || !std::isfinite(z0) || !(dx > 0.f) || !(dy > 0.f) ||
+        !std::isfinite(dx) || !std::isfinite(dy) || (nz > 1 && (!(dz > 0.f) || !std::isfinite(dz))))
+        return why(msg, "bad microphone grid geometry");
+    return BT_OK;
+}
+
+bt_status check_param_args(const bt_params *p, double delta_cap, std::string &msg)
+{
+    if (!p) return why(msg, "params is NULL");
+    if (p->max_depth < 0 || p->max_depth > BT_MAX_DEPTH)
+        return why(msg, "max_depth %d not in 0..%d", p->max_depth, BT_MAX_DEPTH);
+    if (!(p->t_min >= 0.0) || !std::isfinite(p->t_min)) return why(msg, "t_min invalid");
+    if (!(p->edge_delta >= 0.0) || !(p->edge_delta <= delta_cap)) return why(msg, "edge_delta must be in [0, %g]", delta_cap);
+    if (!(p->air_m >= 0.0) || !std::isfinite(p->air_m)) return why(msg, "air_m invalid");
+    if (!(p->e_min >= 0.0)) return why(msg, "e_min invalid");
+    if (p->queue_rounds < 0 || p->queue_rounds > kMaxQueueRounds)
+        return why(msg, "queue_rounds %d not in 0..%d", p->queue_rounds, kMaxQueueRounds);
+    return BT_OK;
+}
+
+static bt_status to_caller(bt_status s, const std::string &msg, char *out, size_t out_len)
+{
+    if (out && out_len > 0) {
+        const size_t n = std::min(out_len - 1, msg.size());
+        std::memcpy(out, msg.data(), n);
+        out[n] = 0;
+    }
+    return s;
+}
+
+extern "C" bt_status bt_validate_mesh(const float *xyz, int64_t n_vert, const int32_t *tri, const float *absorption,
+                                      int64_t n_tri, int32_t tiles_x, int32_t tiles_y, char *msg, size_t msg_len)
+{
+    std::string m;
+    return to_caller(check_mesh_args(xyz, n_vert, tri, absorption, n_tri, tiles_x, tiles_y, m), m, msg, msg_len);
+}
+
+extern "C" bt_status bt_validate_sources(const float *src_xyz, const float *src_power, const float *src_weight,
+                                         int32_t n_src, int32_t level, char *msg, size_t msg_len)
+{
+    std::string m;
+    return to_caller(check_source_args(src_xyz, src_power, src_weight, n_src, level, false, m), m, msg, msg_len);
+}
+
+extern "C" bt_status bt_validate_grid(float x0, float y0, float z0, float dx, float dy, float dz, int32_t nx, int32_t ny,
+                                      int32_t nz, char *msg, size_t msg_len)
+{
+    std::string m;
+    return to_caller(check_grid_args(x0, y0, z0, dx, dy, dz, nx, ny, nz, m), m, msg, msg_len);
+}
+
+extern "C" bt_status bt_validate_params(const bt_params *p, char *msg, size_t msg_len)
+{
+    std::string m;
+    return to_caller(check_param_args(p, kDeltaCap, m), m, msg, msg_len);
+}
+
 bt_status hip_fail(bt_ctx *ctx, hipError_t e, const char *what)
 {
     return fail(ctx, BT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
@@ -461,15 +587,15 @@ extern "C" bt_status bt_build_mesh(bt_ctx *ctx, const float *xyz, int64_t n_vert
     if (!ctx) return BT_EINVAL;
     if (!out) return fail(ctx, BT_EINVAL, "out is NULL");
     *out = nullptr;
-    if (n_vert < 0 || n_tri < 0 || n_tri > (1ll << 27))
-        return fail(ctx, BT_EINVAL, "bad sizes n_vert=%lld n_tri=%lld", (long long)n_vert, (long long)n_tri);
-    if (n_tri > 0 && (!xyz || !tri || !absorption)) return fail(ctx, BT_EINVAL, "NULL mesh array");
-    if (tiles_x < 1 || tiles_y < 1 || tiles_x > 64 || tiles_y > 64)
-        return fail(ctx, BT_EINVAL, "tiles must be in 1..64 (got %d x %d)", tiles_x, tiles_y);
+    {
+        std::string msg;
+        bt_status s = check_mesh_args(xyz, n_vert, tri, absorption, n_tri, tiles_x, tiles_y, msg);
+        if (s != BT_OK) return fail(ctx, s, "%s", msg.c_str());
+    }
     (void)hipSetDevice(ctx->device);
 
-    // validation and per-triangle records
-    const double delta_cap = 1e-3;
+    // per-triangle records
+    const double delta_cap = kDeltaCap;
     double r_mesh = 0.0;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int64_t t = 0; t < n_tri; ++t) {
@@ -637,14 +763,11 @@ extern "C" bt_status bt_mics_grid3d(bt_ctx *ctx, float x0, float y0, float z0, f
     if (!ctx) return BT_EINVAL;
     if (!out) return fail(ctx, BT_EINVAL, "out is NULL");
     *out = nullptr;
-    if (nx < 1 || ny < 1 || nz < 1 || (int64_t)nx * ny * nz > (1ll << 31))
-        return fail(ctx, BT_EINVAL, "bad microphone grid %d x %d x %d", nx, ny, nz);
-    if (nz > 1 && (nx >= (1 << 24) || ny >= (1 << 24) || nz >= (1 << 25)))  // FP32-exact lattice indices;
-        return fail(ctx, BT_EINVAL, "volumetric grid %d x %d x %d: nx, ny must be below 2^24 and nz below 2^25",
-                    nx, ny, nz);  // layer numbers packed beside 6-bit slots
-    if (!std::isfinite(x0) || !std::isfinite(y0) || !std::isfinite(z0) || !(dx > 0.f) || !(dy > 0.f) ||
-        !std::isfinite(dx) || !std::isfinite(dy) || (nz > 1 && (!(dz > 0.f) || !std::isfinite(dz))))
-        return fail(ctx, BT_EINVAL, "bad microphone grid geometry");
+    {
+        std::string msg;
+        bt_status s = check_grid_args(x0, y0, z0, dx, dy, dz, nx, ny, nz, msg);
+        if (s != BT_OK) return fail(ctx, s, "%s", msg.c_str());
+    }
     (void)hipSetDevice(ctx->device);
     bt_mics *m = new bt_mics();
     m->ctx = ctx;
@@ -1078,23 +1201,16 @@ static bt_status emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_
 {
     if (!ctx) return BT_EINVAL;
     if (!inout) return fail(ctx, BT_EINVAL, "inout is NULL");
-    if (n_src < 0 || (n_src > 0 && (!src_xyz || !src_power))) return fail(ctx, BT_EINVAL, "bad sources");
-    if (level < 0 || level > BT_MAX_LEVEL) return fail(ctx, BT_EINVAL, "level %d not in 0..%d", level, BT_MAX_LEVEL);
-    long long nf = 20ll << (2 * level);
-    long long n0 = nf * n_src;
-    if (n0 > (1ll << 31) - 1) return fail(ctx, BT_EINVAL, "too many beams (%lld)", n0);
-    if (src_weight)
-        for (long long k = 0; k < n0; ++k)
-            if (!(src_weight[k] >= 0.f) || !std::isfinite(src_weight[k]))
-                return fail(ctx, BT_EINVAL, "weight %lld (source %lld, face %lld) invalid", k, k / nf, k % nf);
-    double r_src = 0.0;
-    for (int i = 0; i < n_src; ++i) {
-        for (int c = 0; c < 3; ++c) {
-            if (!std::isfinite(src_xyz[3 * i + c])) return fail(ctx, BT_EINVAL, "source %d not finite", i);
-            r_src = std::max(r_src, (double)std::fabs(src_xyz[3 * i + c]));
-        }
-        if (!(src_power[i] >= 0.f) || !std::isfinite(src_power[i])) return fail(ctx, BT_EINVAL, "source %d power invalid", i);
+    {
+        std::string msg;
+        bt_status s = check_source_args(src_xyz, src_power, src_weight, n_src, level, two_slot, msg);
+        if (s != BT_OK) return fail(ctx, s, "%s", msg.c_str());
     }
+    const long long nf = 20ll << (2 * level);
+    const long long n0 = nf * n_src;
+    double r_src = 0.0;
+    for (int i = 0; i < n_src; ++i)
+        for (int c = 0; c < 3; ++c) r_src = std::max(r_src, (double)std::fabs(src_xyz[3 * i + c]));
     (void)hipSetDevice(ctx->device);
     bt_beams *b = *inout;
     bool fresh = false;
@@ -1112,10 +1228,6 @@ static bt_status emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_
     // room for every generation of the previous run's depth (grown at the first trace if
     // the depth is larger), or for two generations
     const long long want = std::max(n0, 1ll) * (two_slot ? 2ll : (long long)(b->depth_hint + 1));
-    if (two_slot && want > (1ll << 31) - 1) {
-        if (fresh) bt_beams_free(b);
-        return fail(ctx, BT_EINVAL, "two generations of %lld beams exceed 2^31 - 1 records", n0);
-    }
     bt_status s = reserve_queue(ctx, b, want <= (1ll << 31) - 1 ? want : std::max(n0, 1ll), 0);
     if (s == BT_OK) s = reserve_work(ctx, b, std::max(n0, 1ll));
     if (s == BT_OK && n_src > b->src_cap) {
@@ -1245,15 +1357,9 @@ extern "C" bt_status bt_beams_stats(bt_ctx *ctx, const bt_beams *b, bt_stats *ou
 
 bt_status check_params(bt_ctx *ctx, const bt_mesh *mesh, const bt_params *p)
 {
-    if (!p) return fail(ctx, BT_EINVAL, "params is NULL");
-    if (p->max_depth < 0 || p->max_depth > BT_MAX_DEPTH) return fail(ctx, BT_EINVAL, "max_depth %d not in 0..%d", p->max_depth, BT_MAX_DEPTH);
-    if (!(p->t_min >= 0.0) || !std::isfinite(p->t_min)) return fail(ctx, BT_EINVAL, "t_min invalid");
-    if (!(p->edge_delta >= 0.0) || !(p->edge_delta <= mesh->delta_cap))
-        return fail(ctx, BT_EINVAL, "edge_delta must be in [0, %g]", mesh->delta_cap);
-    if (!(p->air_m >= 0.0) || !std::isfinite(p->air_m)) return fail(ctx, BT_EINVAL, "air_m invalid");
-    if (!(p->e_min >= 0.0)) return fail(ctx, BT_EINVAL, "e_min invalid");
-    if (p->queue_rounds < 0 || p->queue_rounds > kMaxQueueRounds)
-        return fail(ctx, BT_EINVAL, "queue_rounds %d not in 0..%d", p->queue_rounds, kMaxQueueRounds);
+    std::string msg;
+    bt_status s = check_param_args(p, mesh->delta_cap, msg);
+    if (s != BT_OK) return fail(ctx, s, "%s", msg.c_str());
     return BT_OK;
 }
 

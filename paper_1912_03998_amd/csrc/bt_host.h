@@ -136,6 +136,17 @@ bt_status reserve_tiles(bt_ctx *ctx, bt_beams *b, long long n);
 const TileWork *trace_tiles(bt_beams *b, const bt_mesh *mesh, const TraceArgs &a);
 
 bt_status check_params(bt_ctx *ctx, const bt_mesh *mesh, const bt_params *p);
+
+// Host-only argument checks, shared by the entry points and the bt_validate_* calls:
+// BT_OK, or BT_EINVAL with the reason in msg.  Nothing touches the device.
+constexpr double kDeltaCap = 1e-3;   // largest edge_delta a mesh's box margins cover
+bt_status check_mesh_args(const float *xyz, int64_t n_vert, const int32_t *tri, const float *absorption, int64_t n_tri,
+                          int32_t tiles_x, int32_t tiles_y, std::string &msg);
+bt_status check_source_args(const float *src_xyz, const float *src_power, const float *src_weight, int32_t n_src,
+                            int32_t level, bool two_slot, std::string &msg);
+bt_status check_grid_args(float x0, float y0, float z0, float dx, float dy, float dz, int32_t nx, int32_t ny,
+                          int32_t nz, std::string &msg);
+bt_status check_param_args(const bt_params *p, double delta_cap, std::string &msg);
 TraceArgs make_args(const bt_params *p, int gen);
 
 // Sizes of a scenario (a batch member or a served request), filled by validate_scenario,

@@ -6,6 +6,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1912_03998_amd import bt
@@ -66,3 +67,83 @@ def test_struct_layouts_match_header(name, tmp_path):
     got = _c_layout(name, fields, tmp_path)
     want = [C.sizeof(cls)] + [getattr(cls, f).offset for f in fields]
     assert got == want
+
+
+# ---------------------------------------------------------------------------------------
+# host-only argument checks (no context, no device): the checks the calls make before
+# they touch the GPU
+# ---------------------------------------------------------------------------------------
+
+def _lib_or_skip():
+    if not os.path.exists(bt.LIB_PATH):
+        pytest.skip("libbt.so not built")
+
+
+def test_validate_mesh_errors():
+    _lib_or_skip()
+    v = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [2, 2, 2]], np.float32)
+    t = np.array([[0, 1, 2]], np.int32)
+    a = np.array([0.1], np.float32)
+    assert bt.bt_validate_mesh(v, t, a) == (0, "")
+    assert bt.bt_validate_mesh(v, t, a, 4, 3)[0] == 0
+    cases = [
+        (v, np.array([[0, 1, 4]], np.int32), a, 1, 1, "out of range"),
+        (v, np.array([[0, -1, 2]], np.int32), a, 1, 1, "out of range"),
+        (np.where(np.arange(12).reshape(4, 3) == 4, np.nan, v).astype(np.float32), t, a, 1, 1, "not finite"),
+        (np.where(np.arange(12).reshape(4, 3) == 0, np.inf, v).astype(np.float32), t, a, 1, 1, "not finite"),
+        (v, t, np.array([1.5], np.float32), 1, 1, "absorption"),
+        (v, t, np.array([-0.1], np.float32), 1, 1, "absorption"),
+        (v, t, np.array([np.nan], np.float32), 1, 1, "absorption"),
+        (np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0]], np.float32), t, a, 1, 1, "zero area"),
+        (v, np.array([[0, 0, 2]], np.int32), a, 1, 1, "zero area"),
+        (v, t, a, 0, 1, "tiles"),
+        (v, t, a, 1, 65, "tiles"),
+    ]
+    for xyz, tri, alpha, tx, ty, why in cases:
+        st, msg = bt.bt_validate_mesh(xyz, tri, alpha, tx, ty)
+        assert st == -1 and why in msg, (why, st, msg)
+
+
+def test_validate_sources_errors():
+    _lib_or_skip()
+    s, w = np.array([[0, 0, 1]], np.float32), np.array([1.0], np.float32)
+    assert bt.bt_validate_sources(s, w, 3)[0] == 0
+    assert bt.bt_validate_sources(s, w, 9)[0] == 0
+    assert bt.bt_validate_sources(np.zeros((0, 3), np.float32), np.zeros(0, np.float32), 3)[0] == 0
+    for src, pw, level, why in [(s, w, 10, "level"), (s, w, -1, "level"),
+                                (np.array([[0, np.nan, 1]], np.float32), w, 3, "not finite"),
+                                (s, np.array([-1.0], np.float32), 3, "power"),
+                                (s, np.array([np.inf], np.float32), 3, "power"),
+                                (np.zeros((410, 3), np.float32), np.ones(410, np.float32), 9, "too many beams")]:
+        st, msg = bt.bt_validate_sources(src, pw, level)
+        assert st == -1 and why in msg, (why, st, msg)
+    wt = np.ones((1, 1280), np.float32)
+    assert bt.bt_validate_sources(s, w, 3, wt)[0] == 0
+    wt[0, 17] = -1.0
+    st, msg = bt.bt_validate_sources(s, w, 3, wt)
+    assert st == -1 and "weight 17" in msg
+
+
+def test_validate_grid_errors():
+    _lib_or_skip()
+    assert bt.bt_validate_grid(0, 0, 1.5, 4, 4, 0, 500, 500, 1)[0] == 0
+    assert bt.bt_validate_grid(0, 0, 2, 4, 4, 4, 625, 375, 58)[0] == 0
+    for args, why in [((0, 0, 1.5, 4, 4, 0, 0, 500, 1), "bad microphone grid"),
+                      ((0, 0, 1.5, 4, 4, 0, 65536, 65536, 1), "bad microphone grid"),
+                      ((0, 0, 1.5, 0, 4, 0, 5, 5, 1), "geometry"),
+                      ((float("nan"), 0, 1.5, 4, 4, 0, 5, 5, 1), "geometry"),
+                      ((0, 0, 1.5, 4, 4, 0, 5, 5, 3), "geometry"),
+                      ((0, 0, 1.5, 4, 4, 1, 1 << 24, 2, 2), "below 2^24")]:
+        st, msg = bt.bt_validate_grid(*args)
+        assert st == -1 and why in msg, (args, st, msg)
+
+
+def test_validate_params_errors():
+    _lib_or_skip()
+    assert bt.bt_validate_params(bt.bt_params_default()) == (0, "")
+    for kw, why in [({"max_depth": 32}, "max_depth"), ({"max_depth": -1}, "max_depth"),
+                    ({"t_min": -1.0}, "t_min"), ({"t_min": float("inf")}, "t_min"),
+                    ({"edge_delta": 2e-3}, "edge_delta"), ({"air_m": float("nan")}, "air_m"),
+                    ({"e_min": -1.0}, "e_min"), ({"queue_rounds": 9}, "queue_rounds")]:
+        st, msg = bt.bt_validate_params(bt.bt_params_default(**kw))
+        assert st == -1 and why in msg, (kw, st, msg)
