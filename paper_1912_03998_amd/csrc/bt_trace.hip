@@ -446,9 +446,7 @@ __device__ __forceinline__ DevMesh stage_tiles(const DevMesh &M, TileTable &t)
 }
 
 // In-lane walk: each lane resolves its ray through every tile it crosses, then counts
-// the generation's children, flags and power per wave (static partition).  The counts
-// are reduced over the wave after every batch, so that no per-lane total stays live
-// across the next batch's traversal (which needs every register it can get).
+// the generation's children, flags and power per wave (static partition).
 __global__ void __launch_bounds__(kTraceBlock, 4) k_trace(DevMesh M, DevQueue in, DevSegs segs, DevCounters *ctr, TraceArgs a,
                                                WaveScratch ws)
 {
@@ -459,14 +457,13 @@ __global__ void __launch_bounds__(kTraceBlock, 4) k_trace(DevMesh M, DevQueue in
     const long long s0 = (long long)gen_start(ctr, a.gen);
     const int lane = lane_id();
     const long long icap = in.cap;
-    unsigned long long sc = 0, sf = 0, snv = 0, stt = 0;
-    double sp = 0.0;
+    // per-lane totals over all of this wave's batches, reduced once at the end
+    unsigned children = 0, flagged = 0, nv = 0, tt = 0;
+    double power = 0.0;
     for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
         const bool active = (long long)base + lane < (long long)n;
         const long long i = s0 + (long long)base + lane;
         const RaySrc src{in.dbl + D_O * icap, in.dbl + D_C * icap, icap, active ? (int)i : 0};
-        unsigned children = 0, flagged = 0, nv = 0, tt = 0;
-        double power = 0.0;
         if (active) {
             RayState r;
             ray_init(r, src, in.ints[I_START * icap + i]);
@@ -481,20 +478,18 @@ __global__ void __launch_bounds__(kTraceBlock, 4) k_trace(DevMesh M, DevQueue in
                 }
                 if (inside) walk_tiles(Ml, r, src, ix, iy, t_start, tx, a.t_min, a.delta, stk);
             }
-            flagged = finish_ray(r, in, segs, a, i);
+            flagged += finish_ray(r, in, segs, a, i);
             const double P = in.dbl[D_P * icap + i];
-            children = spawns_child(M, a, r.best_id, in.ints[I_META * icap + i], P);
-            power = P;
-            nv = r.node_visits;
-            tt = r.tri_tests;
+            children += spawns_child(M, a, r.best_id, in.ints[I_META * icap + i], P);
+            power += P;
+            nv += r.node_visits;
+            tt += r.tri_tests;
         }
-        sc += wave_sum_u64(children);
-        sf += wave_sum_u64(flagged);
-        snv += wave_sum_u64(nv);
-        stt += wave_sum_u64(tt);
-        sp += wave_sum_f64(power);
     }
     // one record per wave (no shared atomics); reduced by k_gen_scan
+    const unsigned long long sc = wave_sum_u64(children), sf = wave_sum_u64(flagged);
+    const unsigned long long snv = wave_sum_u64(nv), stt = wave_sum_u64(tt);
+    const double sp = wave_sum_f64(power);
     if (lane == 0) {
         const unsigned long long w = wave_first_batch() >> 6;
         ws.children[w] = sc;

@@ -180,6 +180,22 @@ def test_tall_district_full_grid_sample(torch_cuda, tall):
     assert np.abs(p.energy - e0).max() <= 1e-9 * max(e0.max(), 1e-300)
 
 
+def test_tall_district_level8_full_lattice(torch_cuda, tall):
+    """The volumetric benchmark's own configuration for one source: level 8 (1,310,720 beams),
+    depth 8, every microphone of the 625 x 375 x 58 lattice; both sides complete."""
+    sc = tall.with_(level=8, sources=tall.sources[20:21], power=tall.power[20:21])
+    say("tall district full lattice, level 8, source 20")
+    o = O.trace(sc, keep_paths=False)
+    with session(sc) as s:
+        g = gpu_run(s, sc, parity=False)
+    m = check_mics(o.e_strict, o.e_flag, g.e_strict, g.e_flag)
+    say(f"level 8 lattice: {m['strict_energised']}/{m['energised']} energised microphones strict, "
+        f"max {m['max_db']:.2e} dB")
+    assert m["energised"] > 8_000_000 and strict_share(m) >= 0.99, m
+    assert g.stats["segments"] == o.counters["segments"] or \
+        abs(g.stats["segments"] - o.counters["segments"]) <= o.flagged.sum()
+
+
 def test_volumetric_grid_errors(torch_cuda):
     from paper_1912_03998_amd import bt
     say("volumetric grid errors")
