@@ -427,15 +427,16 @@ __device__ __forceinline__ int finish_ray(const RayState &r, const DevQueue &in,
 
 // The tile table (roots and root boxes) staged in LDS for up to 256 tiles, so that a tile
 // change waits on no global load.
+constexpr int kLdsTiles = 64;
 struct TileTable {
-    int root[256];
-    float box[6 * 256];
+    int root[kLdsTiles];
+    float box[6 * kLdsTiles];
 };
 __device__ __forceinline__ DevMesh stage_tiles(const DevMesh &M, TileTable &t)
 {
     DevMesh Ml = M;
     const int n_tiles = M.tiles_x * M.tiles_y;
-    if (n_tiles <= 256) {
+    if (n_tiles <= kLdsTiles) {
         for (int k = threadIdx.x; k < n_tiles; k += blockDim.x) t.root[k] = M.tile_root[k];
         for (int k = threadIdx.x; k < 6 * n_tiles; k += blockDim.x) t.box[k] = M.tile_box[k];
         __syncthreads();
@@ -445,21 +446,21 @@ __device__ __forceinline__ DevMesh stage_tiles(const DevMesh &M, TileTable &t)
     return Ml;
 }
 
-// In-lane walk: each lane resolves its ray through every tile it crosses, then counts
-// the generation's children, flags and power per wave (static partition).
+// In-lane walk: each lane resolves its ray through every tile it crosses and writes its
+// segment; the generation's children, flags and power are counted by k_tcount.
 __global__ void __launch_bounds__(kTraceBlock, 4) k_trace(DevMesh M, DevQueue in, DevSegs segs, DevCounters *ctr, TraceArgs a,
                                                WaveScratch ws)
 {
     __shared__ int stk[kStack * kTraceBlock];
     __shared__ TileTable tt_lds;
+    __shared__ unsigned s_nv[kTraceBlock], s_tt[kTraceBlock];  // per-lane totals (not in registers)
     const DevMesh Ml = stage_tiles(M, tt_lds);
     const unsigned long long n = ctr->count[a.gen];
     const long long s0 = (long long)gen_start(ctr, a.gen);
     const int lane = lane_id();
     const long long icap = in.cap;
-    // per-lane totals over all of this wave's batches, reduced once at the end
-    unsigned children = 0, flagged = 0, nv = 0, tt = 0;
-    double power = 0.0;
+    s_nv[threadIdx.x] = 0;
+    s_tt[threadIdx.x] = 0;
     for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
         const bool active = (long long)base + lane < (long long)n;
         const long long i = s0 + (long long)base + lane;
@@ -478,25 +479,16 @@ __global__ void __launch_bounds__(kTraceBlock, 4) k_trace(DevMesh M, DevQueue in
                 }
                 if (inside) walk_tiles(Ml, r, src, ix, iy, t_start, tx, a.t_min, a.delta, stk);
             }
-            flagged += finish_ray(r, in, segs, a, i);
-            const double P = in.dbl[D_P * icap + i];
-            children += spawns_child(M, a, r.best_id, in.ints[I_META * icap + i], P);
-            power += P;
-            nv += r.node_visits;
-            tt += r.tri_tests;
+            finish_ray(r, in, segs, a, i);
+            s_nv[threadIdx.x] += r.node_visits;
+            s_tt[threadIdx.x] += r.tri_tests;
         }
     }
-    // one record per wave (no shared atomics); reduced by k_gen_scan
-    const unsigned long long sc = wave_sum_u64(children), sf = wave_sum_u64(flagged);
-    const unsigned long long snv = wave_sum_u64(nv), stt = wave_sum_u64(tt);
-    const double sp = wave_sum_f64(power);
+    const unsigned long long snv = wave_sum_u64(s_nv[threadIdx.x]), stt = wave_sum_u64(s_tt[threadIdx.x]);
     if (lane == 0) {
         const unsigned long long w = wave_first_batch() >> 6;
-        ws.children[w] = sc;
-        ws.stats[3 * w] = sf;
         ws.stats[3 * w + 1] = snv;
         ws.stats[3 * w + 2] = stt;
-        ws.power[w] = sp;
     }
 }
 
@@ -1000,6 +992,8 @@ hipError_t launch_trace(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters 
         k_tcount<<<blocks, 256, 0, s>>>(m, q, segs, ctr, a, ws);
     } else {
         k_trace<<<blocks, kTraceBlock, 0, s>>>(m, q, segs, ctr, a, ws);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        k_tcount<<<blocks, 256, 0, s>>>(m, q, segs, ctr, a, ws);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_gen_scan<<<1, 1024, 0, s>>>(ctr, a, ws);
