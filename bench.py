@@ -195,6 +195,41 @@ def serve_bench(sess, rates, n_of_rate, warm_frac=0.1, seed=0, saturation=400):
     return res
 
 
+def two_slot_bench(scene, steps=5, warmup=2, run_records=1 << 24):
+    """The whole step as one bt_run call with a record budget below the workload's
+    n_beams0 (depth + 1): two generation slots and a microphone pass per generation, in a
+    session of its own (so its device memory is what this form needs)."""
+    import numpy as np
+    import torch
+    from paper_1912_03998_amd import bt
+    from paper_1912_03998_amd.tracer import Session, scene_grid
+
+    sess = Session.from_scene(scene)
+    ctx, mesh, stream = sess.ctx, sess.mesh, sess.stream
+    mics = sess._mics(scene_grid(scene))
+    params = sess.params(scene.depth, run_records=run_records)
+    src = np.ascontiguousarray(scene.sources, np.float32)
+    pw = np.ascontiguousarray(scene.power, np.float32)
+    e = np.zeros(scene.n_mic)
+
+    def step():
+        bt.bt_mics_reset(ctx, mics)
+        sess.beams = bt.bt_run(ctx, mesh, src, pw, scene.level, params, mics, sess.beams)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    bt.bt_levels(ctx, mics, e, None, None)
+    dt = (time.perf_counter() - t0) / steps
+    used = bt.bt_memory_used(ctx)
+    sess.close()
+    return {"step_call": f"bt_run with run_records = {run_records} (two generation slots)", "ms_per_step": round(dt * 1e3, 3),
+            "device_memory_bytes": used}
+
+
 def points_bench(sess, scene, n_points=100_000, steps=3, seed=0):
     """Explicit receivers on the district: n_points uniform over the 2 x 2 km at heights
     U(1.5, 30) m, all sources, against the planar grid pass of the same step."""
@@ -532,6 +567,8 @@ def main():
     }
     if args.config == 2 and not args.no_points:
         out["points"] = points_bench(sess, scene)
+    if args.config == 2 and not args.run_call:
+        out["two_slot_run"] = two_slot_bench(scene)
     if args.config == 2 and not args.no_batch:
         out["batched"] = batch_bench(sess)
     if args.config == 2 and not args.no_serve:

@@ -70,6 +70,10 @@ typedef struct {
                              it enters) and any further tiles walked in its lane; partitions
                              of more than 256 tiles always walk in-lane.  Results are
                              identical either way. */
+    int64_t run_records;  /* bt_run: beam records a source chunk may keep resident; a chunk whose
+                             n_beams0 (max_depth + 1) fits keeps every generation and makes one
+                             microphone pass, a larger one keeps two generation slots and
+                             accumulates each generation as it is traced; 0 = 64 Mi */
     /* optional per-(initial beam, generation) parity outputs, device pointers,
        row-major [n_beams0][max_depth + 1]; entries of untraced generations are
        left untouched (callers pre-fill them, e.g. with -2) */
@@ -95,7 +99,7 @@ typedef struct {
 } bt_stats;
 
 /* Defaults: max_depth 3, t_min 1e-3, edge_delta 1e-5, air_m 0, e_min 0, queue_rounds 0
- * (measured faster), no outputs. */
+ * (measured faster), run_records 0, no outputs. */
 void bt_params_default(bt_params *p);
 
 const char *bt_status_str(bt_status s);
@@ -239,10 +243,12 @@ bt_status bt_levels(bt_ctx *ctx, const bt_mics *mics, double *strict_out, double
 
 /* Convenience: the whole method for a source set (paper Section 2), with memory bounded
  * whatever the number of sources, level or depth.  The sources are taken in chunks of at
- * most 16 Mi generation-0 beams (at least one source each); a chunk is emitted into a beam
- * set that keeps two generation slots (not every generation), and each of its
- * max_depth + 1 generations is traced and then accumulated at once.  So n_src x 20 4^level
- * may exceed 2^31, and a run holds at most 2 x 16 Mi beam records.  Parity outputs in
+ * most 16 Mi generation-0 beams (at least one source each).  A chunk whose records,
+ * n_beams0 (max_depth + 1), fit params->run_records keeps every generation and makes one
+ * microphone pass at the end (the fast layout); a larger chunk keeps two generation slots
+ * and each of its generations is accumulated as soon as it is traced.  So n_src x 20
+ * 4^level may exceed 2^31, and a run holds at most max(run_records, 2 x 16 Mi) beam
+ * records.  Parity outputs in
  * params keep their global rows [n_src 20 4^level][max_depth + 1].  bt_beams_stats on the
  * set afterwards reports the whole run (it synchronises once per extra chunk).  Reuses
  * *beams when non-NULL (created otherwise; caller frees).  Does not synchronise apart

@@ -37,7 +37,8 @@ class BTError(RuntimeError):
 
 class bt_params(C.Structure):
     _fields_ = [("max_depth", C.c_int32), ("t_min", C.c_double), ("edge_delta", C.c_double),
-                ("air_m", C.c_double), ("e_min", C.c_double), ("queue_rounds", C.c_int32), ("hit_out", C.c_void_p),
+                ("air_m", C.c_double), ("e_min", C.c_double), ("queue_rounds", C.c_int32),
+                ("run_records", C.c_int64), ("hit_out", C.c_void_p),
                 ("flag_out", C.c_void_p), ("t_out", C.c_void_p)]
 
 

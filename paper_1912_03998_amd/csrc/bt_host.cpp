@@ -120,6 +120,8 @@ bt_status check_param_args(const bt_params *p, double delta_cap, std::string &ms
     if (!(p->e_min >= 0.0)) return why(msg, "e_min invalid");
     if (p->queue_rounds < 0 || p->queue_rounds > kMaxQueueRounds)
         return why(msg, "queue_rounds %d not in 0..%d", p->queue_rounds, kMaxQueueRounds);
+    if (p->run_records < 0 || p->run_records > (1ll << 31) - 1)
+        return why(msg, "run_records %lld not in 0..2^31 - 1", (long long)p->run_records);
     return BT_OK;
 }
 
@@ -1514,9 +1516,10 @@ extern "C" bt_status bt_levels(bt_ctx *ctx, const bt_mics *m, double *strict_out
     return BT_OK;
 }
 
-// Records a bt_run beam set holds at most (two generation slots); sources are taken in
-// chunks whose generation-0 beams fill at most half of it.
-constexpr long long kRunMaxRecords = 1ll << 25;
+// Generation-0 beams of a bt_run source chunk at most (a chunk in two generation slots
+// holds twice this), and the default record budget for keeping every generation.
+constexpr long long kRunChunkBeams = 1ll << 24;
+constexpr long long kRunResidentRecords = 1ll << 26;
 
 extern "C" bt_status bt_run(bt_ctx *ctx, const bt_mesh *mesh, const float *src_xyz, const float *src_power,
                             int32_t n_src, int32_t level, const bt_params *p, bt_mics *mics, bt_beams **beams)
@@ -1527,12 +1530,13 @@ extern "C" bt_status bt_run(bt_ctx *ctx, const bt_mesh *mesh, const float *src_x
     if (s != BT_OK) return s;
     if (level < 0 || level > BT_MAX_LEVEL) return fail(ctx, BT_EINVAL, "level %d not in 0..%d", level, BT_MAX_LEVEL);
     if (n_src < 0 || (n_src > 0 && (!src_xyz || !src_power))) return fail(ctx, BT_EINVAL, "bad sources");
-    // Sources in chunks of at most kRunMaxRecords / 2 generation-0 beams (at least one
-    // source), each traced with two generation slots and every generation accumulated as
-    // soon as it is traced, so memory is bounded whatever the number of sources, depth or
-    // level.  The per-(initial beam, generation) parity outputs keep their global rows.
+    // Sources in chunks of at most kRunChunkBeams generation-0 beams (at least one source);
+    // a chunk keeps every generation when they fit the record budget (one microphone pass),
+    // else two generation slots (a pass per generation), so memory is bounded whatever the
+    // number of sources, depth or level.  Parity outputs keep their global rows.
     const long long nf = 20ll << (2 * level);
-    const long long per = std::max(1ll, (kRunMaxRecords / 2) / nf);
+    const long long per = std::max(1ll, kRunChunkBeams / nf);
+    const long long budget = p->run_records > 0 ? p->run_records : kRunResidentRecords;
     bt_stats total{};
     for (long long c0 = 0; c0 < std::max<long long>(n_src, 1); c0 += per) {
         const int32_t nc = (int32_t)std::min<long long>(per, (long long)n_src - c0);
@@ -1542,8 +1546,10 @@ extern "C" bt_status bt_run(bt_ctx *ctx, const bt_mesh *mesh, const float *src_x
             if ((s = bt_beams_stats(ctx, *beams, &st)) != BT_OK) return s;
             total = st;
         }
+        const bool resident = std::max<long long>(nc, 1) * nf * (long long)(p->max_depth + 1) <= budget;
+        if (resident && *beams) (*beams)->depth_hint = p->max_depth;   // size the queue at emission
         s = emit_beams(ctx, nc > 0 ? src_xyz + 3 * c0 : src_xyz, nc > 0 ? src_power + c0 : src_power, nullptr,
-                       std::max(nc, 0), level, beams, true);
+                       std::max(nc, 0), level, beams, !resident);
         if (s != BT_OK) return s;
         (*beams)->prior = total;
         bt_params pc = *p;
@@ -1553,8 +1559,10 @@ extern "C" bt_status bt_run(bt_ctx *ctx, const bt_mesh *mesh, const float *src_x
         if (p->t_out) pc.t_out = p->t_out + row0;
         for (int g = 0; g <= p->max_depth; ++g) {
             if ((s = bt_trace(ctx, mesh, *beams, &pc, nullptr)) != BT_OK) return s;
-            if ((s = bt_accumulate_mics(ctx, mesh, *beams, &pc, mics)) != BT_OK) return s;
+            if (!resident && (s = bt_accumulate_mics(ctx, mesh, *beams, &pc, mics)) != BT_OK) return s;
         }
+        // resident: one pass over every generation
+        if (resident && (s = bt_accumulate_mics(ctx, mesh, *beams, &pc, mics)) != BT_OK) return s;
         if (nc <= 0) break;
     }
     return BT_OK;
