@@ -70,10 +70,11 @@ typedef struct {
                              it enters) and any further tiles walked in its lane; partitions
                              of more than 256 tiles always walk in-lane.  Results are
                              identical either way. */
-    int64_t run_records;  /* bt_run: beam records a source chunk may keep resident; a chunk whose
-                             n_beams0 (max_depth + 1) fits keeps every generation and makes one
-                             microphone pass, a larger one keeps two generation slots and
-                             accumulates each generation as it is traced; 0 = 64 Mi */
+    int64_t run_records;  /* bt_run: beam records a source chunk may keep resident; when the
+                             largest chunk's n_beams0 (max_depth + 1) fits, every chunk keeps
+                             every generation and makes one microphone pass, else every chunk
+                             keeps two generation slots and accumulates each generation as it
+                             is traced; 0 = 64 Mi */
     /* optional per-(initial beam, generation) parity outputs, device pointers,
        row-major [n_beams0][max_depth + 1]; entries of untraced generations are
        left untouched (callers pre-fill them, e.g. with -2) */
@@ -243,12 +244,12 @@ bt_status bt_levels(bt_ctx *ctx, const bt_mics *mics, double *strict_out, double
 
 /* Convenience: the whole method for a source set (paper Section 2), with memory bounded
  * whatever the number of sources, level or depth.  The sources are taken in chunks of at
- * most 16 Mi generation-0 beams (at least one source each).  A chunk whose records,
- * n_beams0 (max_depth + 1), fit params->run_records keeps every generation and makes one
- * microphone pass at the end (the fast layout); a larger chunk keeps two generation slots
- * and each of its generations is accumulated as soon as it is traced.  So n_src x 20
- * 4^level may exceed 2^31, and a run holds at most max(run_records, 2 x 16 Mi) beam
- * records.  Parity outputs in
+ * most 16 Mi generation-0 beams (at least one source each).  When the largest chunk's
+ * records, n_beams0 (max_depth + 1), fit params->run_records, every chunk keeps every
+ * generation and makes one microphone pass at its end (the fast layout); otherwise every
+ * chunk keeps two generation slots and each of its generations is accumulated as soon as
+ * it is traced.  So n_src x 20 4^level may exceed 2^31, and a run holds at most
+ * run_records (resident) or 2 x 16 Mi (two slots) beam records.  Parity outputs in
  * params keep their global rows [n_src 20 4^level][max_depth + 1].  bt_beams_stats on the
  * set afterwards reports the whole run (it synchronises once per extra chunk).  Reuses
  * *beams when non-NULL (created otherwise; caller frees).  Does not synchronise apart

@@ -1530,13 +1530,16 @@ extern "C" bt_status bt_run(bt_ctx *ctx, const bt_mesh *mesh, const float *src_x
     if (s != BT_OK) return s;
     if (level < 0 || level > BT_MAX_LEVEL) return fail(ctx, BT_EINVAL, "level %d not in 0..%d", level, BT_MAX_LEVEL);
     if (n_src < 0 || (n_src > 0 && (!src_xyz || !src_power))) return fail(ctx, BT_EINVAL, "bad sources");
-    // Sources in chunks of at most kRunChunkBeams generation-0 beams (at least one source);
-    // a chunk keeps every generation when they fit the record budget (one microphone pass),
-    // else two generation slots (a pass per generation), so memory is bounded whatever the
-    // number of sources, depth or level.  Parity outputs keep their global rows.
+    // Sources in chunks of at most kRunChunkBeams generation-0 beams (at least one source).
+    // The run keeps every generation when the largest chunk's records fit the record budget
+    // (one microphone pass per chunk), else two generation slots (a pass per generation),
+    // so memory is bounded whatever the number of sources, depth or level.  Parity outputs
+    // keep their global rows.
     const long long nf = 20ll << (2 * level);
     const long long per = std::max(1ll, kRunChunkBeams / nf);
     const long long budget = p->run_records > 0 ? p->run_records : kRunResidentRecords;
+    const long long largest = std::max(1ll, std::min<long long>(per, n_src));
+    const bool resident = largest * nf * (long long)(p->max_depth + 1) <= budget;
     bt_stats total{};
     for (long long c0 = 0; c0 < std::max<long long>(n_src, 1); c0 += per) {
         const int32_t nc = (int32_t)std::min<long long>(per, (long long)n_src - c0);
@@ -1546,7 +1549,6 @@ extern "C" bt_status bt_run(bt_ctx *ctx, const bt_mesh *mesh, const float *src_x
             if ((s = bt_beams_stats(ctx, *beams, &st)) != BT_OK) return s;
             total = st;
         }
-        const bool resident = std::max<long long>(nc, 1) * nf * (long long)(p->max_depth + 1) <= budget;
         if (resident && *beams) (*beams)->depth_hint = p->max_depth;   // size the queue at emission
         s = emit_beams(ctx, nc > 0 ? src_xyz + 3 * c0 : src_xyz, nc > 0 ? src_power + c0 : src_power, nullptr,
                        std::max(nc, 0), level, beams, !resident);
