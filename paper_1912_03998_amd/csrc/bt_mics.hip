@@ -395,7 +395,6 @@ __global__ void __launch_bounds__(256, 3) k_mics_general(DevMesh M, DevQueue q, 
     // pooled over kPoolWaves consecutive waves: the pool's waves take its concatenated
     // list 64 items at a time, so that no wave is left with a short region or a mostly
     // empty last batch of its own.
-    const unsigned long long s0 = gen_start(ctr, a.gen);
     const unsigned long long n_seg = gen_count(ctr, a.gen, a.gen_end);
     const int lane = lane_id();
     const unsigned long long wave = wave_first_batch() >> 6;
@@ -863,7 +862,9 @@ __device__ __forceinline__ int mic_apply_staged(const Stage &st, int l, const De
                              air_m);
 }
 
-// LDS staging of one wave of k_mics_plane: up to kVolSeg segments with candidate boxes.
+// LDS staging of one wave of k_mics_plane: up to kVolSeg segments with candidate boxes,
+// and a ring of boxed segments waiting for a staging round.
+constexpr int kPendRing = 128;   // > kVolSeg - 1 + 64: what one batch can leave waiting
 struct PlaneStage {
     double f[kVolF][kVolSeg];   // frustum, as VolStage
     float K[kVolSeg];
@@ -872,12 +873,61 @@ struct PlaneStage {
     alignas(16) int psk1[4];              // its owner32 search skips
     alignas(16) int psk2[16];
     int4 box[kVolSeg];          // (first column, first row, columns, -)
+    int pend_seg[kPendRing];    // waiting boxed segments (queue index) ...
+    int4 pend_box[kPendRing];   // ... and their boxes (first column, first row, columns, candidates)
 };
+
+// One staging round of k_mics_plane: the first nst (<= kVolSeg) waiting segments of the
+// ring, from position head, stage their frustums (lane l < nst takes entry head + l), and
+// their candidates are spread evenly over the lanes.  Every lane of the wave calls it.
+__device__ __forceinline__ void plane_round(PlaneStage &st, const DevMesh &M, const DevQueue &q, const DevSegs &segs,
+                                            const DevMics &mc, const TraceArgs &a, int head, int nst, unsigned &tests,
+                                            unsigned &updates)
+{
+    const int lane = lane_id();
+    const bool mine = lane < nst;
+    int nc = 0;
+    if (mine) {
+        const int e = (head + lane) & (kPendRing - 1);
+        const long long i = st.pend_seg[e];
+        const int4 bx = st.pend_box[e];
+        Frustum f{};  // caps the segment lacks are staged as zeros
+        load_frustum(M, q, segs, i, a.delta, f);
+        stage_frustum(st, lane, f);
+        st.bits[lane] = (f.has_near ? 1 : 0) | (f.has_far ? 2 : 0) | (f.flag ? 4 : 0);
+        st.K[lane] = f.K;
+        st.box[lane] = make_int4(bx.x, bx.y, bx.z, 0);
+        nc = bx.w;
+    }
+    int total;
+    const int pre = wave_excl_scan(nc, total);
+    // slots past the staged ones hold the total, so that no candidate maps to them
+    if (lane < kVolSeg) {
+        const int v = mine ? pre : total;
+        st.prefix[lane] = v;
+        write_skips<8>(st.psk1, st.psk2, lane, v);
+    }
+    __syncthreads();
+    for (int cb = 0; cb < total; cb += 64) {
+        const int c = cb + lane;
+        if (c < total) {
+            const int sl = owner32(st.prefix, st.psk1, st.psk2, c);
+            const int o = c - st.prefix[sl];
+            const int4 bx = st.box[sl];
+            const int row = o / bx.z;
+            tests++;
+            updates += mic_apply_staged(st, sl, mc, bx.x + (o - row * bx.z), bx.y + row, 0, a.delta2, a.air_m);
+        }
+    }
+    __syncthreads();
+}
 
 // k_mics for a planar grid of one microphone set: the same dismissal, lattice boxes and
 // general-list regions (wave w of the grid is block w here), but the candidates of the
-// boxes are not tested by their segment's lane: the segments with candidates stage their
-// frustums (kVolSeg at a time) and the candidates are spread evenly over the lanes.
+// boxes are not tested by their segment's lane.  Boxed segments wait in an LDS ring
+// across batches; whenever kVolSeg of them wait, they stage their frustums and their
+// candidates are spread evenly over the lanes, so that a staging round (dependent loads
+// and two barriers) serves full slots rather than the few boxed segments of one batch.
 __global__ void __launch_bounds__(64, 4) k_mics_plane(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr,
                                                       DevMics mc, TraceArgs a, MicWork w, WaveScratch ws)
 {
@@ -888,68 +938,35 @@ __global__ void __launch_bounds__(64, 4) k_mics_plane(DevMesh M, DevQueue q, Dev
     const unsigned long long wave = blockIdx.x;
     const unsigned long long region = wave * general_region(n, ws.n_waves);
     unsigned gcount = 0, tests = 0, updates = 0;
+    int head = 0, waiting = 0;   // the ring's first entry and its length (wave-uniform)
     for (unsigned long long base = wave * 64; base < n; base += (unsigned long long)gridDim.x * 64) {
         const long long i = (long long)(s0 + base) + lane;
         bool general = false, boxed = false;
-        int i0 = 0, j0 = 0, ncol = 0, nc = 0;
+        int i0 = 0, j0 = 0, i1 = -1, j1 = -1;
         if (base + (unsigned long long)lane < n) {
-            int i1 = -1, j1 = -1;
             const int kind = plane_fast(q, i, mc, i0, i1, j0, j1);
             general = kind == 2;
             boxed = kind == 1;
-            if (boxed) {
-                ncol = i1 - i0 + 1;
-                nc = ncol * (j1 - j0 + 1);
-            }
         }
         const unsigned long long gm = __ballot(general);
         if (general) w.general[region + gcount + __popcll(gm & ((1ull << lane) - 1ull))] = (int)i;
         gcount += (unsigned)__popcll(gm);
-        // boxed segments, kVolSeg per round
-        unsigned long long pend = __ballot(boxed);
-        while (pend) {
-            const unsigned below = __builtin_amdgcn_mbcnt_hi((unsigned)(pend >> 32),
-                                                             __builtin_amdgcn_mbcnt_lo((unsigned)pend, 0u));
-            const bool pending = (pend >> lane) & 1ull;
-            const bool mine = pending && below < (unsigned)kVolSeg;
-            const int nmine = min(__popcll(pend), kVolSeg);
-            if (mine) {
-                Frustum f{};  // caps the segment lacks are staged as zeros
-                load_frustum(M, q, segs, i, a.delta, f);
-                stage_frustum(st, (int)below, f);
-                st.bits[below] = (f.has_near ? 1 : 0) | (f.has_far ? 2 : 0) | (f.flag ? 4 : 0);
-                st.K[below] = f.K;
-                st.box[below] = make_int4(i0, j0, ncol, 0);
-            }
-            int total;
-            const int pre = wave_excl_scan(mine ? nc : 0, total);
-            if (mine) {
-                st.prefix[below] = pre;
-                write_skips<8>(st.psk1, st.psk2, (int)below, pre);
-            }
-            // slots past the staged ones hold the total, so that no candidate maps to them
-            // (lane l fills slot l, whether or not it staged a segment itself)
-            if (lane >= nmine && lane < kVolSeg) {
-                st.prefix[lane] = total;
-                write_skips<8>(st.psk1, st.psk2, lane, total);
-            }
-            __syncthreads();
-            for (int cb = 0; cb < total; cb += 64) {
-                const int c = cb + lane;
-                if (c < total) {
-                    const int sl = owner32(st.prefix, st.psk1, st.psk2, c);
-                    const int o = c - st.prefix[sl];
-                    const int4 bx = st.box[sl];
-                    const int row = o / bx.z;
-                    tests++;
-                    updates += mic_apply_staged(st, sl, mc, bx.x + (o - row * bx.z), bx.y + row, 0, a.delta2,
-                                                a.air_m);
-                }
-            }
-            __syncthreads();
-            pend = __ballot(pending && !mine);
+        const unsigned long long bm = __ballot(boxed);
+        if (boxed) {
+            const int e = (head + waiting + __popcll(bm & ((1ull << lane) - 1ull))) & (kPendRing - 1);
+            const int ncol = i1 - i0 + 1;
+            st.pend_seg[e] = (int)i;
+            st.pend_box[e] = make_int4(i0, j0, ncol, ncol * (j1 - j0 + 1));
+        }
+        waiting += __popcll(bm);
+        __syncthreads();
+        while (waiting >= kVolSeg) {
+            plane_round(st, M, q, segs, mc, a, head, kVolSeg, tests, updates);
+            head = (head + kVolSeg) & (kPendRing - 1);
+            waiting -= kVolSeg;
         }
     }
+    if (waiting > 0) plane_round(st, M, q, segs, mc, a, head, waiting, tests, updates);
     if (lane == 0) ws.general[wave] = gcount;
     flush_mic_counters(ctr, tests, updates);
 }

@@ -1,14 +1,18 @@
-// Guiding-ray trace: closest hit through the per-tile hierarchies with hand-off along the
-// ray's tile path and edge/tie flags (k_trace, which also counts each wave's children);
-// the children's queue offsets (k_gen_scan); the specular reflection and compaction of
-// the children into the next generation's queue (k_reflect).
+// Guiding-ray trace: closest hit through the per-tile hierarchies over the tiles a ray
+// crosses, with edge/tie flags (k_trace walks them in each lane; k_tbin, k_tscan,
+// k_tscatter and k_ttrace hand rays between per-tile queues instead); the generation's
+// children, flags and power per wave (k_tcount); the children's queue offsets
+// (k_gen_scan); the specular reflection and compaction of the children into the next
+// generation's queue (k_reflect).
 //
 // Precision: boxes are tested in FP32 against boxes grown by a margin that covers the
-// rounding of the ray; every triangle first goes through a conservative FP32
-// Moller-Trumbore filter, and only triangles that may be a hit or a flag candidate are
-// decided by the exact FP64 test (FP32 vertices widened exactly, FP64 ray).  The FP64 ray
-// is read from the queue where it is needed rather than held in registers, which keeps
-// the traversal loop small enough for more waves per SIMD.
+// rounding of the ray.  A slab parameter is one FMA, l (1/c) - fl(o (1/c)); in distance
+// along the ray it lies within about 8 x 2^-24 of the largest coordinate magnitude of its
+// exact value, inside the margin's 12 x 2^-24 of that magnitude.  Every triangle first
+// goes through a conservative FP32 Moller-Trumbore filter, and only triangles that may be
+// a hit or a flag candidate are decided by the exact FP64 test (FP32 vertices widened
+// exactly, FP64 ray).  The FP64 ray is read from the queue where it is needed rather than
+// held in registers, which keeps the traversal loop small enough for more waves per SIMD.
 #include "bt_device.h"
 
 namespace bt {
@@ -50,6 +54,7 @@ struct RayState {
     float ox, oy, oz;     // FP32 rounded origin
     float cx, cy, cz;     // FP32 rounded direction
     float ix, iy, iz;     // FP32 reciprocal direction (|c| clamped away from 0)
+    float oix, oiy, oiz;  // origin times reciprocal: a slab parameter is fma(l, i, -o i)
     float o_l1;           // |ox| + |oy| + |oz|, bounds the origin's rounding
     int start;
     double best_t;
@@ -247,9 +252,9 @@ __device__ void traverse_tile(const DevMesh &M, int tile, RayState &r, RaySrc sr
             int nh = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const float ax = (lxa[k] - r.ox) * r.ix, bx = (hxa[k] - r.ox) * r.ix;
-                const float ay = (lya[k] - r.oy) * r.iy, by = (hya[k] - r.oy) * r.iy;
-                const float az = (lza[k] - r.oz) * r.iz, bz = (hza[k] - r.oz) * r.iz;
+                const float ax = fmaf(lxa[k], r.ix, -r.oix), bx = fmaf(hxa[k], r.ix, -r.oix);
+                const float ay = fmaf(lya[k], r.iy, -r.oiy), by = fmaf(hya[k], r.iy, -r.oiy);
+                const float az = fmaf(lza[k], r.iz, -r.oiz), bz = fmaf(hza[k], r.iz, -r.oiz);
                 const float mn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), flo));
                 const float mx = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), fhi));
                 const bool h = mn <= mx;  // unused slots never pass (kEmptyChild)
@@ -390,6 +395,9 @@ __device__ __forceinline__ void ray_init(RayState &r, RaySrc src, int start)
     r.ix = (float)(1.0 / (fabs(c.x) < tiny ? copysign(tiny, c.x) : c.x));
     r.iy = (float)(1.0 / (fabs(c.y) < tiny ? copysign(tiny, c.y) : c.y));
     r.iz = (float)(1.0 / (fabs(c.z) < tiny ? copysign(tiny, c.z) : c.z));
+    r.oix = r.ox * r.ix;
+    r.oiy = r.oy * r.iy;
+    r.oiz = r.oz * r.iz;
     r.start = start;
     r.best_t = INFINITY;
     r.best_id = -1;
