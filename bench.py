@@ -376,6 +376,9 @@ def main():
     ap.add_argument("--config", type=int, default=2, help="0 tiny, 1 block, 2 district (default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tiles", type=int, default=0, help="override the tile partition (n x n)")
+    ap.add_argument("--no-classify", action="store_true",
+                    help="leave the beam set unbound (bt_beams_bind_mics not called): the microphone pass decides "
+                         "every segment's planar class from its frustum")
     ap.add_argument("--run-call", action="store_true",
                     help="time each step as one bt_run call (source chunks, two generation slots, a microphone "
                          "pass per generation) instead of bt_emit_beams, bt_trace per generation and one "
@@ -456,6 +459,9 @@ def main():
         level_out = torch.empty(scene.n_mic, dtype=torch.float64, device="cuda")
     src = np.ascontiguousarray(scene.sources, np.float32)
     pw = np.ascontiguousarray(scene.power, np.float32)
+    if not args.no_classify and not args.run_call:
+        # set-up, once: beams are classified for the grid as they are created
+        sess.beams = bt.bt_beams_bind_mics(ctx, sess.beams, mics)
 
     def step(ev=None):
         if args.run_call:
@@ -508,20 +514,20 @@ def main():
         trace_bytes = (B_BEAM + B_HIT) * ref["segments"] + B_CHILD * ref["children"] + \
             B_NODE * ref["node_visits"] + B_TRI * ref["tri_tests"]
         mic_bytes = B_MIC * ref["mic_updates"]
-        # the trace stage is what each bt_trace call launches: k_trace + k_gen_scan + k_reflect
-        # (in-lane tile walk), or with per-tile queues k_tbin, (k_tscan, k_tscatter, k_ttrace)
-        # per queued round, k_tcount, k_gen_scan, k_reflect; the microphone stage is the five
-        # kernels of one bt_accumulate_mics call
+        # the trace stage is what each bt_trace call launches: k_trace, k_tcount, k_gen_scan,
+        # k_reflect (in-lane tile walk), or with per-tile queues k_tbin, (k_tscan, k_tscatter,
+        # k_ttrace) per queued round, k_tcount, k_gen_scan, k_reflect; the microphone stage is
+        # the five kernels of one bt_accumulate_mics call
         q = params.queue_rounds
         trace_dominant = trace_ms >= mic_ms
         if trace_dominant:
-            dominant = "k_trace+k_gen_scan+k_reflect" if q == 0 else \
+            dominant = "k_trace+k_tcount+k_gen_scan+k_reflect" if q == 0 else \
                 "k_tbin+k_tscan+k_tscatter+k_ttrace+k_tcount+k_gen_scan+k_reflect"
         else:
             dominant = "k_mics_plane+k_mics_general+k_mic_rows+k_mics_big+k_mic_spans"
         t_dom = trace_ms if trace_dominant else mic_ms
         b_dom = trace_bytes if trace_dominant else mic_bytes
-        launches = (3 if q == 0 else 4 + 3 * q) * (D + 1) if trace_dominant else 5
+        launches = (4 if q == 0 else 4 + 3 * q) * (D + 1) if trace_dominant else 5
         achieved = b_dom / (t_dom * 1e-3) / 1e9
         traffic = pmc_traffic(launches) if trace_dominant and q == 0 else None
         frac_alg = round(achieved / HBM_PEAK_GBS, 4)
@@ -559,8 +565,12 @@ def main():
         "gpu_node_visits_per_segment": st["node_visits"] / max(segs, 1),
         "gpu_tri_tests_per_segment": st["tri_tests"] / max(segs, 1),
         "setup_s": round(setup_s, 3),
-        "step_call": "bt_run (source chunks, two generation slots)" if args.run_call else
-                     "bt_emit_beams, bt_trace per generation (every generation resident), bt_accumulate_mics",
+        "step_call": "bt_run (source chunks; every generation resident when the records fit run_records)"
+                     if args.run_call else
+                     ("bt_emit_beams, bt_trace per generation (every generation resident), bt_accumulate_mics" +
+                      ("" if args.no_classify else "; the beam set bound to the grid once at set-up "
+                       "(bt_beams_bind_mics: beams classified as they are created)")),
+        "mic_classified_per_step": st["mic_classified"],
         "device_memory_bytes": bt.bt_memory_used(ctx),
         "end_to_end_segments_per_s": segs / (setup_s + ms_per_step * 1e-3),
         "kernel_sha256_16": kernel_hash(),

@@ -97,6 +97,8 @@ typedef struct {
     int64_t mic_layer_visits;            /* volumetric grids: (segment, layer) pairs examined */
     int64_t mic_general;                 /* volumetric grids: of which on the clipped-footprint path */
     int64_t mic_fallback;                /* volumetric grids: of which done in place (item buffer full) */
+    int64_t mic_classified;              /* segments whose planar class was taken from their
+                                            creation (bt_beams_bind_mics) */
 } bt_stats;
 
 /* Defaults: max_depth 3, t_min 1e-3, edge_delta 1e-5, air_m 0, e_min 0, queue_rounds 0
@@ -221,6 +223,19 @@ bt_status bt_trace(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *beams, const bt_p
  * strict energy; both are FP64. */
 bt_status bt_accumulate_mics(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *beams, const bt_params *params,
                              bt_mics *mics);
+
+/* Classify a beam set's beams against a planar microphone grid as they are created
+ * (paper Section 2: a beam contributes to the microphones inside its frustum, and most
+ * beams hold none of a planar grid's microphones).  While bound, emission and every
+ * trace's reflection decide for each new beam, from its frustum alone, whether it can
+ * hold a microphone of the grid's plane, and which lattice box bounds the candidates; a
+ * later bt_accumulate_mics (or _static) with that grid, or a subset of it, then reads
+ * those decisions instead of every beam's frustum, for the generations created while
+ * bound.  Results are identical with or without it.  *beams may be NULL: an empty set is
+ * created (caller frees).  mics = NULL unbinds.  Costs 8 bytes of device memory per queue
+ * record.  BT_EINVAL for explicit points, volumetric grids and grids of 2^26 or more
+ * microphones per side.  bt_run binds its set to its microphones when they are planar. */
+bt_status bt_beams_bind_mics(bt_ctx *ctx, bt_beams **beams, const bt_mics *mics);
 
 /* bt_accumulate_mics for callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments, kernels

@@ -23,7 +23,7 @@ STATUS = {0: "BT_OK", 1: "BT_PENDING", -1: "BT_EINVAL", -2: "BT_ENOMEM", -3: "BT
 EXPORTED = ["bt_params_default", "bt_status_str", "bt_last_error", "bt_create", "bt_destroy", "bt_memory_used",
             "bt_build_mesh", "bt_mesh_free", "bt_mesh_info", "bt_mics_grid", "bt_mics_grid3d", "bt_mics_subset", "bt_mics_points", "bt_mics_reset", "bt_mics_free",
             "bt_emit_beams", "bt_emit_beams_directional", "bt_beams_free", "bt_beams_stats", "bt_trace", "bt_accumulate_mics",
-            "bt_accumulate_mics_static", "bt_levels",
+            "bt_accumulate_mics_static", "bt_beams_bind_mics", "bt_levels",
             "bt_run", "bt_submit", "bt_poll", "bt_cancel", "bt_batch_run", "bt_batch_release", "bt_batch_autotune",
             "bt_server_create", "bt_server_submit", "bt_server_poll", "bt_server_destroy",
             "bt_validate_mesh", "bt_validate_sources", "bt_validate_grid", "bt_validate_params"]
@@ -47,7 +47,7 @@ class bt_stats(C.Structure):
                 ("flagged", C.c_int64 * (BT_MAX_DEPTH + 1)), ("power", C.c_double * (BT_MAX_DEPTH + 1)),
                 ("segments", C.c_int64), ("node_visits", C.c_int64), ("tri_tests", C.c_int64),
                 ("mic_tests", C.c_int64), ("mic_updates", C.c_int64), ("mic_layer_visits", C.c_int64),
-                ("mic_general", C.c_int64), ("mic_fallback", C.c_int64)]
+                ("mic_general", C.c_int64), ("mic_fallback", C.c_int64), ("mic_classified", C.c_int64)]
 
 
 class bt_request(C.Structure):
@@ -96,6 +96,7 @@ def lib():
         "bt_trace": (C.c_int, [P, P, P, P, P]),
         "bt_accumulate_mics": (C.c_int, [P, P, P, P, P]),
         "bt_accumulate_mics_static": (C.c_int, [P, P, P, P, P]),
+        "bt_beams_bind_mics": (C.c_int, [P, P, P]),
         "bt_levels": (C.c_int, [P, P, P, P, P]),
         "bt_run": (C.c_int, [P, P, P, P, I32, I32, P, P, P]),
         "bt_submit": (C.c_int, [P, P, P, P]),
@@ -293,7 +294,8 @@ def bt_beams_stats(ctx, beams) -> dict:
     return {"generations": g, "count": np.array(s.count[:g], np.int64), "flagged": np.array(s.flagged[:g], np.int64),
             "power": np.array(s.power[:g], np.float64), "segments": s.segments, "node_visits": s.node_visits,
             "tri_tests": s.tri_tests, "mic_tests": s.mic_tests, "mic_updates": s.mic_updates,
-            "mic_layer_visits": s.mic_layer_visits, "mic_general": s.mic_general, "mic_fallback": s.mic_fallback}
+            "mic_layer_visits": s.mic_layer_visits, "mic_general": s.mic_general, "mic_fallback": s.mic_fallback,
+            "mic_classified": s.mic_classified}
 
 
 def bt_trace(ctx, mesh, beams, params, want_next=False):
@@ -308,6 +310,14 @@ def bt_accumulate_mics(ctx, mesh, beams, params, mics):
 
 def bt_accumulate_mics_static(ctx, mesh, beams, params, mics):
     _check(ctx, lib().bt_accumulate_mics_static(ctx, mesh, beams, C.byref(params), mics), "bt_accumulate_mics_static")
+
+
+def bt_beams_bind_mics(ctx, beams, mics):
+    """Classify the set's new beams against a planar grid (mics None: unbind); beams None
+    creates an empty set.  Returns the set."""
+    h = C.c_void_p(beams.value if beams is not None else None)
+    _check(ctx, lib().bt_beams_bind_mics(ctx, C.byref(h), mics), "bt_beams_bind_mics")
+    return h
 
 
 def bt_levels(ctx, mics, strict_out=None, flag_out=None, level_db_out=None):

@@ -142,7 +142,7 @@ hipError_t launch_faces(const double *base20, int level, double *dirs, double *o
 // powers K Omega add up to W.
 __global__ void k_emit(const double *__restrict__ dirs, const double *__restrict__ fom, const float *__restrict__ src,
                        const float *__restrict__ power, const float *__restrict__ wt, const double *__restrict__ norm,
-                       int n_src, long long nf, DevQueue q)
+                       int n_src, long long nf, DevQueue q, ClassGrid cg)
 {
     long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     long long total = nf * n_src;
@@ -152,8 +152,9 @@ __global__ void k_emit(const double *__restrict__ dirs, const double *__restrict
     double K;
     if (wt) K = norm[s] > 0.0 ? (double)power[s] * (double)wt[b] / norm[s] : 0.0;
     else K = (double)power[s] / (4.0 * M_PI);
-    store_beam(q, b, S, ld3(dirs, nf, f), ld3(dirs + 3 * nf, nf, f), ld3(dirs + 6 * nf, nf, f),
-               ld3(dirs + 9 * nf, nf, f), K, fom[f], 0, (int)b);
+    const V3 d0 = ld3(dirs, nf, f), d1 = ld3(dirs + 3 * nf, nf, f), d2 = ld3(dirs + 6 * nf, nf, f);
+    store_beam(q, b, S, d0, d1, d2, ld3(dirs + 9 * nf, nf, f), K, fom[f], 0, (int)b);
+    if (cg.cls) cg.cls[b] = plane_class(cg, S, d0, d1, d2);
 }
 
 // norm[s] = sum over faces f of wt[s nf + f] Omega_f (FP64, one block per source, a fixed
@@ -175,7 +176,7 @@ __global__ void __launch_bounds__(256) k_source_norms(const double *__restrict__
 }
 
 hipError_t launch_emit(const double *dirs, const double *om, const float *src, const float *power, const float *wt,
-                       double *norm, int n_src, int level, DevQueue q, hipStream_t s)
+                       double *norm, int n_src, int level, DevQueue q, ClassGrid cg, hipStream_t s)
 {
     long long nf = 20ll << (2 * level);
     long long total = nf * n_src;
@@ -185,7 +186,7 @@ hipError_t launch_emit(const double *dirs, const double *om, const float *src, c
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    k_emit<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(dirs, om, src, power, wt, norm, n_src, nf, q);
+    k_emit<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(dirs, om, src, power, wt, norm, n_src, nf, q, cg);
     return hipGetLastError();
 }
 

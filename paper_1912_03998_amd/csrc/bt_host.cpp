@@ -1038,6 +1038,11 @@ void beams_release(bt_beams *b)
     b->tw_buf = nullptr;
     b->tw_bytes = 0;
     b->tw = TileWork{};
+    dev_free(ctx, b->cgrid.cls, (size_t)b->cls_cap * sizeof(int2));
+    b->cgrid = ClassGrid{};
+    b->cls_cap = 0;
+    b->bound = false;
+    b->class_gens = 0;
 }
 
 bt_status reserve_tiles(bt_ctx *ctx, bt_beams *b, long long n)
@@ -1147,6 +1152,22 @@ bt_status reserve_queue(bt_ctx *ctx, bt_beams *b, long long n, long long keep)
                                         hipMemcpyDeviceToDevice, ctx->stream));
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the old arrays are freed next
     }
+    if (b->cgrid.cls) {
+        // the class array follows the queue (its kept records' classes too)
+        int2 *nc = nullptr;
+        if ((s = dev_alloc(ctx, (void **)&nc, (size_t)n * sizeof(int2))) != BT_OK) {
+            queue_free(ctx, nq);
+            return s;
+        }
+        if (keep > 0) {
+            HIP_TRY(ctx, hipMemcpyAsync(nc, b->cgrid.cls, (size_t)keep * sizeof(int2), hipMemcpyDeviceToDevice,
+                                        ctx->stream));
+            HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        }
+        dev_free(ctx, b->cgrid.cls, (size_t)b->cls_cap * sizeof(int2));
+        b->cgrid.cls = nc;
+        b->cls_cap = n;
+    }
     queue_free(ctx, b->q);
     b->q = nq;
     dev_free(ctx, b->segs.hit, (size_t)b->cap * sizeof(int));
@@ -1198,6 +1219,28 @@ bt_status reserve_work(bt_ctx *ctx, bt_beams *b, long long n0)
 // Generation 0 of a beam set; src_weight NULL (omni sources) or host float[n_src][nf].
 // two_slot: the set keeps two generation slots of n0 records (each generation must be
 // accumulated before the next is traced) instead of every generation.
+// An empty beam set of the context (counters and per-wave scratch only).
+static bt_status new_beams(bt_ctx *ctx, bt_beams **out)
+{
+    bt_beams *b = new bt_beams();
+    b->ctx = ctx;
+    bt_status s = dev_alloc(ctx, (void **)&b->ctr, sizeof(DevCounters));
+    if (s == BT_OK) s = alloc_wave_scratch(ctx, b, kBlocksPerCU);
+    if (s != BT_OK) {
+        bt_beams_free(b);
+        return s;
+    }
+    *out = b;
+    return BT_OK;
+}
+
+// The classification grid of the set's new records (none unless bound).
+static ClassGrid class_target(const bt_beams *b)
+{
+    if (!b->bound) return ClassGrid{};
+    return b->cgrid;
+}
+
 static bt_status emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_power, const float *src_weight,
                             int32_t n_src, int32_t level, bt_beams **inout, bool two_slot = false)
 {
@@ -1217,15 +1260,9 @@ static bt_status emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_
     bt_beams *b = *inout;
     bool fresh = false;
     if (!b) {
-        b = new bt_beams();
-        b->ctx = ctx;
+        bt_status s = new_beams(ctx, &b);
+        if (s != BT_OK) return s;
         fresh = true;
-        bt_status s = dev_alloc(ctx, (void **)&b->ctr, sizeof(DevCounters));
-        if (s == BT_OK) s = alloc_wave_scratch(ctx, b, kBlocksPerCU);
-        if (s != BT_OK) {
-            bt_beams_free(b);
-            return s;
-        }
     }
     // room for every generation of the previous run's depth (grown at the first trace if
     // the depth is larger), or for two generations
@@ -1271,7 +1308,9 @@ static bt_status emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_
         HIP_TRY(ctx, launch_faces(ctx->base20, level, ctx->face_dirs[level], ctx->face_om[level], ctx->stream));
     }
     HIP_TRY(ctx, launch_emit(ctx->face_dirs[level], ctx->face_om[level], b->src_dev, b->pow_dev,
-                             src_weight ? b->wt_dev : nullptr, b->norm_dev, n_src, level, b->q, ctx->stream));
+                             src_weight ? b->wt_dev : nullptr, b->norm_dev, n_src, level, b->q, class_target(b),
+                             ctx->stream));
+    b->class_gens = b->bound ? 1ull : 0ull;
     // host inputs are borrowed for the call only
     if (n_src > 0) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     b->gen = 0;
@@ -1334,6 +1373,7 @@ extern "C" bt_status bt_beams_stats(bt_ctx *ctx, const bt_beams *b, bt_stats *ou
     out->mic_tests = (int64_t)h.mic_tests;
     out->mic_updates = (int64_t)h.mic_updates;
     out->mic_layer_visits = (int64_t)h.mic_layer_visits;
+    out->mic_classified = (int64_t)h.mic_classified;
     for (int g = 0; g <= BT_MAX_DEPTH; ++g) {
         out->mic_general += (int64_t)h.n_layers[g];
         if ((long long)h.n_layers[g] > b->layers_cap) out->mic_fallback += (int64_t)h.n_layers[g] - b->layers_cap;
@@ -1351,6 +1391,7 @@ extern "C" bt_status bt_beams_stats(bt_ctx *ctx, const bt_beams *b, bt_stats *ou
     out->tri_tests += q.tri_tests;
     out->mic_tests += q.mic_tests;
     out->mic_updates += q.mic_updates;
+    out->mic_classified += q.mic_classified;
     out->mic_layer_visits += q.mic_layer_visits;
     out->mic_general += q.mic_general;
     out->mic_fallback += q.mic_fallback;
@@ -1406,16 +1447,78 @@ extern "C" bt_status bt_trace(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *b, con
     }
     b->max_depth = p->max_depth;
     TraceArgs a = make_args(p, g);
+    a.cg = class_target(b);
     if (p->queue_rounds > 0 && (s = reserve_tiles(ctx, b, b->n0)) != BT_OK) return s;
     HIP_TRY(ctx, launch_trace(mesh->dev, b->q, b->segs, b->ctr, a, b->ws, trace_tiles(b, mesh, a), ctx->n_cu,
                               ctx->stream));
     b->gen = g + 1;
+    if (g + 1 < 64) {
+        if (b->bound) b->class_gens |= 1ull << (g + 1);
+        else b->class_gens &= ~(1ull << (g + 1));
+    }
     if (n_next) {
         unsigned long long c = 0;
         HIP_TRY(ctx, hipMemcpyAsync(&c, &b->ctr->count[g + 1], sizeof c, hipMemcpyDeviceToHost, ctx->stream));
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
         *n_next = (int64_t)c;
     }
+    return BT_OK;
+}
+
+// The records' planar classes, when every generation of the pass [acc_gen, gen) was
+// classified against this microphone set's grid (a planar grid or a subset of one);
+// otherwise NULL and the pass decides from each frustum.  The decisions are the same.
+static const int2 *pass_classes(const bt_beams *b, const bt_mics *m)
+{
+    if (!b->cgrid.cls || m->points || m->dev.nz != 1 || b->gen > 63) return nullptr;
+    const ClassGrid &g = b->cgrid;
+    if (g.x0 != m->dev.x0 || g.y0 != m->dev.y0 || g.z != m->dev.z || g.dx != m->dev.dx || g.dy != m->dev.dy ||
+        g.nx != m->dev.nx || g.ny != m->dev.ny)
+        return nullptr;
+    for (int k = b->acc_gen; k < b->gen; ++k)
+        if (!((b->class_gens >> k) & 1ull)) return nullptr;
+    return g.cls;
+}
+
+extern "C" bt_status bt_beams_bind_mics(bt_ctx *ctx, bt_beams **beams, const bt_mics *mics)
+{
+    if (!ctx) return BT_EINVAL;
+    if (!beams) return fail(ctx, BT_EINVAL, "beams is NULL");
+    if (mics && (mics->points || mics->dev.nz != 1))
+        return fail(ctx, BT_EINVAL, "only a planar grid (or a subset of one) classifies beams");
+    if (mics && (mics->dev.nx >= kClassMaxDim || mics->dev.ny >= kClassMaxDim))
+        return fail(ctx, BT_EINVAL, "grid of %d x %d microphones: at most %d per side classify beams", mics->dev.nx,
+                    mics->dev.ny, kClassMaxDim - 1);
+    (void)hipSetDevice(ctx->device);
+    bt_status s;
+    if (!*beams && (s = new_beams(ctx, beams)) != BT_OK) return s;
+    bt_beams *b = *beams;
+    if (!mics) {
+        b->bound = false;
+        return BT_OK;
+    }
+    const DevMics &m = mics->dev;
+    const ClassGrid &g = b->cgrid;
+    const bool same = g.cls && g.x0 == m.x0 && g.y0 == m.y0 && g.z == m.z && g.dx == m.dx && g.dy == m.dy &&
+                      g.nx == m.nx && g.ny == m.ny;
+    if (!same) b->class_gens = 0;   // the records' classes refer to another grid
+    if (!b->cgrid.cls || b->cls_cap < b->cap) {
+        dev_free(ctx, b->cgrid.cls, (size_t)b->cls_cap * sizeof(int2));
+        b->cgrid.cls = nullptr;
+        b->cls_cap = 0;
+        b->class_gens = 0;
+        const long long n = std::max(b->cap, 1ll);
+        if ((s = dev_alloc(ctx, (void **)&b->cgrid.cls, (size_t)n * sizeof(int2))) != BT_OK) return s;
+        b->cls_cap = n;
+    }
+    b->cgrid.x0 = m.x0;
+    b->cgrid.y0 = m.y0;
+    b->cgrid.z = m.z;
+    b->cgrid.dx = m.dx;
+    b->cgrid.dy = m.dy;
+    b->cgrid.nx = m.nx;
+    b->cgrid.ny = m.ny;
+    b->bound = true;
     return BT_OK;
 }
 
@@ -1432,6 +1535,7 @@ extern "C" bt_status bt_accumulate_mics(bt_ctx *ctx, const bt_mesh *mesh, bt_bea
     // all generations traced since the previous call, in one pass
     TraceArgs a = make_args(p, b->acc_gen);
     a.gen_end = b->gen;
+    a.mic_cls = pass_classes(b, mics);
     if (mics->points) {
         HIP_TRY(ctx, launch_mics_points(mesh->dev, b->q, b->segs, b->ctr, mics->dev, mics->pts, a, ctx->n_cu,
                                         ctx->stream));
@@ -1461,6 +1565,7 @@ extern "C" bt_status bt_accumulate_mics_static(bt_ctx *ctx, const bt_mesh *mesh,
     (void)hipSetDevice(ctx->device);
     TraceArgs a = make_args(p, b->acc_gen);
     a.gen_end = b->gen;
+    a.mic_cls = pass_classes(b, mics);
     if (mics->points) {   // the point kernel uses no work lists
         HIP_TRY(ctx, launch_mics_points(mesh->dev, b->q, b->segs, b->ctr, mics->dev, mics->pts, a, ctx->n_cu,
                                         ctx->stream));
@@ -1540,6 +1645,11 @@ extern "C" bt_status bt_run(bt_ctx *ctx, const bt_mesh *mesh, const float *src_x
     const long long budget = p->run_records > 0 ? p->run_records : kRunResidentRecords;
     const long long largest = std::max(1ll, std::min<long long>(per, n_src));
     const bool resident = largest * nf * (long long)(p->max_depth + 1) <= budget;
+    // beams classified against a planar grid as they are created (the microphone pass
+    // then dismisses most of them without reading their frustums)
+    const bool planar = !mics->points && mics->dev.nz == 1 && mics->dev.nx < kClassMaxDim &&
+                        mics->dev.ny < kClassMaxDim;
+    if ((s = bt_beams_bind_mics(ctx, beams, planar ? mics : nullptr)) != BT_OK) return s;
     bt_stats total{};
     for (long long c0 = 0; c0 < std::max<long long>(n_src, 1); c0 += per) {
         const int32_t nc = (int32_t)std::min<long long>(per, (long long)n_src - c0);

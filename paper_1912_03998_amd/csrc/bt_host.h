@@ -92,6 +92,13 @@ struct bt_beams {
     int max_depth = -1;       // fixed by the first trace
     long long n0 = 0;
     long long ring = 0;       // two-slot layout's slot size (bt_run), 0 = every generation resident
+    // planar microphone classification (bt_beams_bind_mics): while bound, emission and
+    // reflection write each new record's fast-path class into cgrid.cls (cls_cap records);
+    // bit g of class_gens: generation g's records hold classes for cgrid
+    ClassGrid cgrid{};
+    long long cls_cap = 0;
+    bool bound = false;
+    unsigned long long class_gens = 0;
     bt_stats prior{};         // statistics of the earlier source chunks of a bt_run
     double r_src = 0.0;
 };

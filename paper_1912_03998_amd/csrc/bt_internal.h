@@ -108,6 +108,7 @@ struct DevCounters {
     unsigned long long n_layers[BT_MAX_DEPTH + 2];   // volumetric: (segment, layer) items requested
     unsigned long long node_visits, tri_tests, mic_tests, mic_updates;
     unsigned long long mic_layer_visits;             // volumetric: (segment, layer) pairs examined
+    unsigned long long mic_classified;               // planar: classes read from the records
     unsigned long long ring;                         // two-slot layout: slot size (0 = resident)
 };
 
@@ -199,6 +200,17 @@ struct TileWork {
     int rounds;          // queued rounds (>= 1); the last one finishes its rays in-lane
 };
 
+// A planar microphone grid that a beam set classifies its beams against as they are
+// created (emission, reflection): cls[j], parallel to the queue, holds the planar fast
+// path's decision for record j (plane_decide, encoded by plane_code), so that the
+// microphone pass dismisses a beam without reading its frustum.  cls = NULL: none.
+struct ClassGrid {
+    double x0, y0, z, dx, dy;   // the grid's plane and lattice (float32 values, widened)
+    int nx, ny;
+    int2 *cls;
+};
+constexpr int kClassMaxDim = 1 << 26;   // grids this wide or wider are not classified
+
 struct TraceArgs {
     int gen;         // trace: the generation traced; microphones: first generation
     int gen_end;     // microphones: one past the last generation accumulated
@@ -208,6 +220,9 @@ struct TraceArgs {
     double t_min, delta, air_m, e_min;
     double delta2;   // delta^2, formed on the host (a kernel argument, so no register holds it)
     int queue_rounds;  // trace: 0 = in-lane tile walk, k >= 1 = k rounds of per-tile queues
+    ClassGrid cg;      // trace: classify the children against this grid (cg.cls = NULL: not)
+    const int2 *mic_cls;  // microphones: the records' classes for this grid (NULL: decide
+                          // from each frustum)
     int *hit_out;
     uint8_t *flag_out;
     double *t_out;
@@ -242,9 +257,10 @@ hipError_t launch_init_counters(DevCounters *ctr, long long n0, long long ring, 
 // emission of one beam set's generation 0 from it.
 hipError_t launch_faces(const double *base20, int level, double *dirs, double *om, hipStream_t s);
 // wt: NULL (omni) or [n_src][nf] face weights of directional sources, with norm a device
-// double[n_src] filled here.
+// double[n_src] filled here; cg.cls non-NULL: each beam's planar fast-path class is
+// written there.
 hipError_t launch_emit(const double *dirs, const double *om, const float *src, const float *power, const float *wt,
-                       double *norm, int n_src, int level, DevQueue q, hipStream_t s);
+                       double *norm, int n_src, int level, DevQueue q, ClassGrid cg, hipStream_t s);
 // Appends the table's beams to generation `gen` (after its current beams) and adds their
 // number to count[gen].
 hipError_t launch_emit_table(const double *base20, const EmitTable &t, long long max_total, DevQueue q,

@@ -279,57 +279,16 @@ __device__ __forceinline__ void flush_mic_counters(DevCounters *ctr, unsigned te
     }
 }
 
-// Planar fast path of segment i: 0 = no microphone can be inside its frustum, 1 = the
-// candidates are the lattice box [i0, i1] x [j0, j1] (at most kSpan points), 2 = the
-// clipped footprint is needed.  When all three edge rays cross the microphone plane ahead
-// of the apex, the frustum meets the plane inside the triangle of the three crossing
-// points (the caps only cut it down), so the lattice points of that triangle's bounding
-// box are the only candidates.  Most segments have none, and are dismissed before the rest
-// of the frustum is loaded.
+// Planar fast path of segment i (plane_decide on its stored frustum): 0 = no microphone
+// can be inside, 1 = the lattice box [i0, i1] x [j0, j1], 2 = the clipped footprint.
+static_assert(kPlaneBox == kSpan, "a lattice box is at most one span of candidates");
 __device__ __forceinline__ int plane_fast(const DevQueue &q, long long i, const DevMics &mc, int &i0, int &i1,
                                           int &j0, int &j1)
 {
     const long long cap = q.cap;
-    const V3 A = ld3(q.dbl + D_A * cap, cap, i);
-    const double zr = mc.z - A.z;
-    bool proper = zr != 0.0;
-    // the frustum lies in the cone of its edge directions from the apex; when the apex is
-    // off the microphone plane (by far more than the plane tests' rounding) and no edge
-    // direction turns towards the plane, no microphone can be inside
-    bool away = zr > 1e-6 || zr < -1e-6;
-    // The crossing points are only used to bound the candidate lattice, so they are found
-    // in FP32: each coordinate is within 16 x 2^-24 of `mag` (the largest magnitude
-    // involved) of its exact value, and the box is widened by 1e-5 mag.  The exact FP64
-    // membership test decides every candidate.
-    const float zrf = (float)zr, axf = (float)A.x, ayf = (float)A.y;
-    float xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
-    float mag = fmaxf(fabsf(axf), fabsf(ayf));
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const V3 d = ld3(q.dbl + (D_D0 + 3 * k) * cap, cap, i);
-        proper = proper && (zr > 0.0 ? d.z > 0.0 : d.z < 0.0);
-        away = away && (zr > 0.0 ? d.z <= 0.0 : d.z >= 0.0);
-        const float s = zrf / (float)d.z;
-        proper = proper && isfinite(s);  // FP32 overflow: the general path decides
-        const float sx = s * (float)d.x, sy = s * (float)d.y;
-        const float px = axf + sx, py = ayf + sy;
-        xmn = fminf(xmn, px); xmx = fmaxf(xmx, px);
-        ymn = fminf(ymn, py); ymx = fmaxf(ymx, py);
-        mag = fmaxf(mag, fmaxf(fabsf(sx), fabsf(sy)));
-    }
-    if (away) return 0;
-    if (!proper) return 2;
-    // lattice range by a reciprocal multiply, widened by 1e-9 cells for its rounding
-    const double relax = 1e-6 + 1e-5 * (double)mag;
-    const double idx = 1.0 / mc.dx, idy = 1.0 / mc.dy;
-    const double fi0 = fmax(ceil(((double)xmn - relax - mc.x0) * idx - 1e-9), 0.0);
-    const double fi1 = fmin(floor(((double)xmx + relax - mc.x0) * idx + 1e-9), (double)(mc.nx - 1));
-    const double fj0 = fmax(ceil(((double)ymn - relax - mc.y0) * idy - 1e-9), 0.0);
-    const double fj1 = fmin(floor(((double)ymx + relax - mc.y0) * idy + 1e-9), (double)(mc.ny - 1));
-    if (!(fi0 <= fi1 && fj0 <= fj1)) return 0;  // no lattice point under the footprint
-    if ((fi1 - fi0 + 1.0) * (fj1 - fj0 + 1.0) > (double)kSpan) return 2;
-    i0 = (int)fi0; i1 = (int)fi1; j0 = (int)fj0; j1 = (int)fj1;
-    return 1;
+    return plane_decide(ld3(q.dbl + D_A * cap, cap, i), ld3(q.dbl + D_D0 * cap, cap, i),
+                        ld3(q.dbl + D_D1 * cap, cap, i), ld3(q.dbl + D_D2 * cap, cap, i), mc.x0, mc.y0, mc.z, mc.dx,
+                        mc.dy, mc.nx, mc.ny, i0, i1, j0, j1);
 }
 
 // Fast path over all segments of generations [gen, gen_end) (contiguous in the queue):
@@ -944,7 +903,9 @@ __global__ void __launch_bounds__(64, 4) k_mics_plane(DevMesh M, DevQueue q, Dev
         bool general = false, boxed = false;
         int i0 = 0, j0 = 0, i1 = -1, j1 = -1;
         if (base + (unsigned long long)lane < n) {
-            const int kind = plane_fast(q, i, mc, i0, i1, j0, j1);
+            // the decision taken when the beam was created, if the set classified it
+            const int kind = a.mic_cls ? plane_uncode(a.mic_cls[i], i0, i1, j0, j1)
+                                       : plane_fast(q, i, mc, i0, i1, j0, j1);
             general = kind == 2;
             boxed = kind == 1;
         }
@@ -969,6 +930,12 @@ __global__ void __launch_bounds__(64, 4) k_mics_plane(DevMesh M, DevQueue q, Dev
     if (waiting > 0) plane_round(st, M, q, segs, mc, a, head, waiting, tests, updates);
     if (lane == 0) ws.general[wave] = gcount;
     flush_mic_counters(ctr, tests, updates);
+    if (a.mic_cls && lane == 0 && wave * 64 < n) {
+        // segments of this wave's batches: 64 per full batch
+        const unsigned long long stride = (unsigned long long)gridDim.x * 64;
+        const unsigned long long full = (n - wave * 64) / stride, rest = (n - wave * 64) % stride;
+        atomicAdd(&ctr->mic_classified, 64 * full + (rest < 64 ? rest : 64));
+    }
 }
 
 // One wave per block (the block's LDS is its staging), 4 waves per SIMD: at most 128 VGPRs.

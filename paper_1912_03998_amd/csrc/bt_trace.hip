@@ -900,8 +900,9 @@ __global__ void __launch_bounds__(1024) k_gen_scan(DevCounters *ctr, TraceArgs a
 // Specular reflection without splitting: every hit with depth < max_depth (and, when set,
 // power above e_min) spawns one child mirrored in the hit triangle's plane (apex, edge and
 // guiding directions; d1 and d2 swapped to keep det > 0), starting at the hit point with
-// K (1 - alpha).  Children are compacted into the next queue with a wave ballot, a
-// popcount prefix and one atomic per wave.
+// K (1 - alpha).  Children are compacted into the next generation with a wave ballot and
+// a popcount prefix from the wave's offset (k_gen_scan).  When the set classifies its
+// beams, each child's planar microphone class is written while it is in registers.
 __global__ void __launch_bounds__(256) k_reflect(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, TraceArgs a,
                                                  WaveScratch ws)
 {
@@ -968,6 +969,7 @@ __global__ void __launch_bounds__(256) k_reflect(DevMesh M, DevQueue q, DevSegs 
             out.ints[I_ID * ocap + j] = id;
             out.ints[I_START * ocap + j] = hit;
             out.ints[I_META * ocap + j] = meta2;
+            if (a.cg.cls) a.cg.cls[j] = plane_class(a.cg, A2, m0, m1, m2);
         }
     }
 }
