@@ -358,7 +358,7 @@ bt_status run_batch(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *sc, int
             ooff += z[k].n_out;
         }
         for (int g = 0; g <= depth; ++g) segments += (long long)w.h_ctr->count[g];
-        updates += (long long)w.h_ctr->mic_updates;
+        updates += (long long)mic_stat_total(*w.h_ctr, MS_UPDATES);
         beams0 += ch.n0;
     }
     if (stats) {

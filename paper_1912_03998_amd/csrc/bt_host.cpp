@@ -991,7 +991,7 @@ size_t list_ints(long long n, int n_waves)
 bt_status alloc_wave_scratch(bt_ctx *ctx, bt_beams *b, int blocks_per_cu)
 {
     const int W = ctx->n_cu * blocks_per_cu * kWavesPerBlock;
-    const size_t bytes = (size_t)W * (6 * 8 + 4);
+    const size_t bytes = (size_t)W * (6 * 8 + 4 + 4);
     bt_status s = dev_alloc(ctx, &b->ws_buf, bytes);
     if (s != BT_OK) return s;
     b->ws_bytes = bytes;
@@ -1001,6 +1001,7 @@ bt_status alloc_wave_scratch(bt_ctx *ctx, bt_beams *b, int blocks_per_cu)
     b->ws.stats = b->ws.offset + W;
     b->ws.power = (double *)(b->ws.stats + 3 * (size_t)W);
     b->ws.general = (unsigned int *)(b->ws.power + W);
+    b->ws.rows_n = b->ws.general + W;
     b->ws.n_waves = W;
     return BT_OK;
 }
@@ -1195,9 +1196,11 @@ bt_status reserve_work(bt_ctx *ctx, bt_beams *b, long long n0)
     b->spans = nullptr;
     b->rows_cap = b->spans_cap = 0;
     bt_status s;
-    // row work items of wide footprints over all generations: 2 per initial beam covers the
-    // district workload (1.3 per beam) with room; overflow falls back to one wave per segment
-    long long rows_cap = std::max(2 * n0, 1ll << 20);
+    // row work items of wide footprints over all generations, in equal per-wave regions:
+    // 4 per initial beam gives every wave room for about three times the district
+    // workload's mean (1.2 per beam); a wave whose region is full sends its further wide
+    // segments to the one-wave-per-segment path
+    long long rows_cap = std::max(4 * n0, 1ll << 20);
     if (const char *env = std::getenv("BT_MIC_ROW_CAPACITY")) {  // testing the overflow path
         long long v = std::atoll(env);
         if (v > 0) rows_cap = v;
@@ -1370,10 +1373,10 @@ extern "C" bt_status bt_beams_stats(bt_ctx *ctx, const bt_beams *b, bt_stats *ou
     }
     out->node_visits = (int64_t)h.node_visits;
     out->tri_tests = (int64_t)h.tri_tests;
-    out->mic_tests = (int64_t)h.mic_tests;
-    out->mic_updates = (int64_t)h.mic_updates;
-    out->mic_layer_visits = (int64_t)h.mic_layer_visits;
-    out->mic_classified = (int64_t)h.mic_classified;
+    out->mic_tests = (int64_t)mic_stat_total(h, MS_TESTS);
+    out->mic_updates = (int64_t)mic_stat_total(h, MS_UPDATES);
+    out->mic_layer_visits = (int64_t)mic_stat_total(h, MS_LAYERS);
+    out->mic_classified = (int64_t)mic_stat_total(h, MS_CLASSIFIED);
     for (int g = 0; g <= BT_MAX_DEPTH; ++g) {
         out->mic_general += (int64_t)h.n_layers[g];
         if ((long long)h.n_layers[g] > b->layers_cap) out->mic_fallback += (int64_t)h.n_layers[g] - b->layers_cap;

@@ -97,20 +97,36 @@ struct DevSegs {
     int *flag;       // 1 = flagged (inherited or own)
 };
 
+// Microphone statistics are spread over kStatSlots cache lines: wave w of a kernel adds
+// its totals to line w mod kStatSlots, so that thousands of waves finishing together do
+// not serialise on one address (one device-scope atomic per wave on a single counter
+// cost a microphone pass about 0.15 ms).
+constexpr int kStatSlots = 256;
+constexpr int kStatStride = 16;   // 128 bytes per slot
+enum { MS_TESTS = 0, MS_UPDATES = 1, MS_LAYERS = 2, MS_CLASSIFIED = 3 };
+
 // Device-side counters of one beam set, zeroed at emission.
 struct DevCounters {
     unsigned long long count[BT_MAX_DEPTH + 2];      // beams per generation
     unsigned long long flagged[BT_MAX_DEPTH + 2];
     double power[BT_MAX_DEPTH + 2];
     unsigned long long n_big[BT_MAX_DEPTH + 2];      // segments for the wave-per-segment fallback
-    unsigned long long n_rows[BT_MAX_DEPTH + 2];     // (segment, row) work items requested
     unsigned long long n_spans[BT_MAX_DEPTH + 2];    // (segment, row, columns) work items
     unsigned long long n_layers[BT_MAX_DEPTH + 2];   // volumetric: (segment, layer) items requested
-    unsigned long long node_visits, tri_tests, mic_tests, mic_updates;
-    unsigned long long mic_layer_visits;             // volumetric: (segment, layer) pairs examined
-    unsigned long long mic_classified;               // planar: classes read from the records
+    unsigned long long node_visits, tri_tests;
     unsigned long long ring;                         // two-slot layout: slot size (0 = resident)
+    // microphone statistics per slot: MS_TESTS (segment, microphone) candidates tested,
+    // MS_UPDATES contributions, MS_LAYERS volumetric (segment, layer) pairs examined,
+    // MS_CLASSIFIED segments whose planar class was read from their record
+    alignas(128) unsigned long long mic_stat[kStatSlots][kStatStride];
 };
+// Sum of one microphone statistic over the slots (host).
+inline unsigned long long mic_stat_total(const DevCounters &h, int k)
+{
+    unsigned long long s = 0;
+    for (int i = 0; i < kStatSlots; ++i) s += h.mic_stat[i][k];
+    return s;
+}
 
 // Microphone (i, j, k) sits at (x0 + i dx, y0 + j dy, z + k dz) and has index
 // (k ny + j) nx + i; a planar grid has nz = 1.  Work items name a microphone row by its
@@ -169,6 +185,8 @@ struct WaveScratch {
     unsigned long long *stats;     // [W][3] flagged, node visits, triangle tests
     double *power;                 // [W]
     unsigned int *general;         // [W] general-path items per wave (microphones)
+    unsigned int *rows_n;          // [W] (segment, row) items per wave, in its region of the
+                                   // row buffer (rows_cap / W items each)
     int n_waves;                   // W
 };
 

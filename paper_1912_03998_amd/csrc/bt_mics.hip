@@ -16,17 +16,23 @@ namespace bt {
 // then enumerate candidate microphones row by row (one column of slack on each side)
 // and decide membership with the exact plane tests.
 //   k_mics_plane:   one lane per segment (a set of its own): most segments are dismissed
-//                   from their edge rays' crossings of the plane; a small lattice box
-//                   of candidates is staged and its microphones spread over the lanes;
-//                   the rest go to the wave's region of the general list
+//                   from their edge rays' crossings of the plane (or from the decision
+//                   stored when the beam was created); boxed segments wait in an LDS ring
+//                   until a round of them stages their frustums and their candidates
+//                   are spread over the lanes; the rest go to the wave's region of the
+//                   general list
 //   k_mics:         the same fast path for multi-scenario sets, candidates in place
 //   k_mics_general: one lane per listed segment (regions pooled over 64 waves): the
 //                   clipped footprint's rows; up to kInlineRows rows are finished in
-//                   place, wider footprints become (segment, row) work items
-//   k_mic_rows:     one lane per (segment, row) work item; rows longer than kSpan
-//                   columns become (segment, row, columns) span items for k_mic_spans
-//   k_mics_big:     one wave per segment, for segments whose rows did not fit the item
-//                   buffer (overflow fallback)
+//                   place, wider footprints become (segment, row) work items in the
+//                   wave's region of the row buffer
+//   k_mic_rows:     one lane per (segment, row) work item (regions pooled over 64
+//                   waves); rows longer than kSpan columns become (segment, row,
+//                   columns) span items for k_mic_spans
+//   k_mics_big:     one wave per segment, for segments whose rows did not fit the
+//                   wave's region (overflow fallback)
+// No kernel makes its waves meet on one shared counter: work lists live in per-wave
+// regions, and statistics are spread over slots.
 // A volumetric grid (Section 4's experiment fills the model's bounding box with
 // microphones) is a stack of such planes: k_mics3d bounds the layers a segment's frustum
 // can reach and runs the same footprint logic on each of them.  Explicit points
@@ -270,12 +276,18 @@ __device__ __forceinline__ DevMics seg_mics(const DevMics &mc, const TraceArgs &
     return a.slot_mics[meta_slot(q.ints[I_META * q.cap + i])];
 }
 
+__device__ __forceinline__ void add_mic_stat(DevCounters *ctr, int k, unsigned long long v)
+{
+    // this wave's slot (statistics only: no result depends on them)
+    const unsigned slot = (unsigned)(((unsigned long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6) % kStatSlots;
+    if (v) atomicAdd(&ctr->mic_stat[slot][k], v);
+}
 __device__ __forceinline__ void flush_mic_counters(DevCounters *ctr, unsigned tests, unsigned updates)
 {
     unsigned long long st = wave_sum_u64(tests), su = wave_sum_u64(updates);
     if (lane_id() == 0) {
-        if (st) atomicAdd(&ctr->mic_tests, st);
-        if (su) atomicAdd(&ctr->mic_updates, su);
+        add_mic_stat(ctr, MS_TESTS, st);
+        add_mic_stat(ctr, MS_UPDATES, su);
     }
 }
 
@@ -372,6 +384,10 @@ __global__ void __launch_bounds__(256, 3) k_mics_general(DevMesh M, DevQueue q, 
     const int total = __shfl(pre, 63, 64);
     pre -= cnt;
     unsigned tests = 0, updates = 0;
+    // this wave's region of the row buffer
+    const long long rcap = w.rows_cap / ws.n_waves;
+    const long long wave_row0 = (long long)wave * rcap;
+    long long rn = 0;
     for (int t0 = 64 * gi; t0 < total; t0 += 64 * pw) {
         const int t = t0 + lane;
         const bool active = t < total;
@@ -405,61 +421,80 @@ __global__ void __launch_bounds__(256, 3) k_mics_general(DevMesh M, DevQueue q, 
                 }
             }
         }
-        // wide footprints: reserve one work item per row (wave-aggregated)
+        // wide footprints: one work item per row, in this wave's region of the row buffer
+        // (no shared counter); the lanes whose rows no longer fit go to the wave path
         const int want = wide ? nrows : 0;
-        int incl = want;
+        long long incl = want;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
-            int v = __shfl_up(incl, off, 64);
+            const long long v = __shfl_up(incl, off, 64);
             if (lane >= off) incl += v;
         }
-        const int total = __shfl(incl, 63, 64);
-        unsigned long long rbase = 0;
-        if (lane == 0 && total > 0) rbase = atomicAdd(&ctr->n_rows[a.gen], (unsigned long long)total);
-        rbase = __shfl(rbase, 0, 64);
+        const bool fits = rn + incl <= rcap;   // a prefix of the lanes
         bool to_big = false;
         if (wide) {
-            const unsigned long long first = rbase + (unsigned long long)(incl - want);
-            if (first + (unsigned long long)want <= (unsigned long long)w.rows_cap) {
+            if (fits) {
+                const long long first = wave_row0 + rn + (incl - want);
                 for (int r = 0; r < want; ++r) w.rows[first + r] = make_int2((int)i, j0 + r);
             } else {
-                // does not fit: the whole segment goes to the wave path; slots of its
-                // reservation that lie inside the buffer are marked empty
-                for (unsigned long long r = first; r < (unsigned long long)w.rows_cap; ++r)
-                    w.rows[r] = make_int2(-1, 0);
                 to_big = true;
             }
         }
+        const unsigned long long fm = __ballot(fits);
+        if (fm) rn += __shfl(incl, 63 - __builtin_clzll(fm), 64);   // the last lane that fits
         const unsigned long long bm = __ballot(to_big);
         unsigned long long bbase = 0;
         if (lane == 0 && bm) bbase = atomicAdd(&ctr->n_big[a.gen], (unsigned long long)__popcll(bm));
         bbase = __shfl(bbase, 0, 64);
         if (to_big) w.big_list[bbase + __popcll(bm & ((1ull << lane) - 1ull))] = (int)i;
     }
+    if (lane == 0) ws.rows_n[wave] = (unsigned)rn;
     flush_mic_counters(ctr, tests, updates);
 }
 
+// One lane per (segment, row) item: the items the general kernel's waves put in their
+// regions of the row buffer, pooled over kPoolWaves consecutive waves as in
+// k_mics_general (this grid has the same waves).
 template <bool kSlots>
 __global__ void __launch_bounds__(256) k_mic_rows(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, DevMics mc0,
-                                                  TraceArgs a, MicWork w)
+                                                  TraceArgs a, MicWork w, WaveScratch ws)
 {
-    unsigned long long n = ctr->n_rows[a.gen];
-    if (n > (unsigned long long)w.rows_cap) n = (unsigned long long)w.rows_cap;
+    const int lane = lane_id();
+    const unsigned long long wave = wave_first_batch() >> 6;
+    const long long rcap = w.rows_cap / ws.n_waves;
+    const unsigned long long g0 = wave / kPoolWaves * kPoolWaves;
+    const int gi = (int)(wave - g0);
+    const int pw = (int)min((unsigned long long)kPoolWaves, (unsigned long long)ws.n_waves - g0);
+    const int cnt = lane < pw ? (int)ws.rows_n[g0 + lane] : 0;
+    int pre = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(pre, off, 64);
+        if (lane >= off) pre += u;
+    }
+    const int total = __shfl(pre, 63, 64);
+    pre -= cnt;
     unsigned tests = 0, updates = 0;
-    for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
-        const unsigned long long r = base + (unsigned long long)lane_id();
-        const int2 it = r < n ? w.rows[r] : make_int2(-1, 0);
-        if (it.x >= 0) {
+    for (int t0 = 64 * gi; t0 < total; t0 += 64 * pw) {
+        const int t = t0 + lane;
+        int r = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+            const int p = __shfl(pre, r + step < 64 ? r + step : 63, 64);
+            if (r + step < 64 && p <= t) r += step;
+        }
+        const int pr = __shfl(pre, r, 64);
+        if (t < total) {
+            const int2 it = w.rows[(long long)(g0 + (unsigned long long)r) * rcap + (t - pr)];
             const DevMics mc = seg_mics<kSlots>(mc0, a, q, it.x);
-            const int k = mc.nz > 1 ? it.y / mc.ny : 0;  // global row k ny + j
-            const int j = it.y - k * mc.ny;
+            const int j = it.y;
             Frustum f;
             load_frustum(M, q, segs, it.x, a.delta, f);
             HalfPlane L[9];
-            footprint_lines(f, mc, mc.z + (double)k * mc.dz, L);
+            footprint_lines(f, mc, mc.z, L);
             int c0, c1;
             if (row_cols(L, mc, j, c0, c1))
-                process_row<kSlots>(f, mc, w, ctr, a.gen, it.x, j, k, c0, c1, a.air_m, tests, updates);
+                process_row<kSlots>(f, mc, w, ctr, a.gen, it.x, j, 0, c0, c1, a.air_m, tests, updates);
         }
     }
     flush_mic_counters(ctr, tests, updates);
@@ -527,9 +562,8 @@ __global__ void __launch_bounds__(256) k_mics_big(DevMesh M, DevQueue q, DevSegs
 //                     its frustum from the wave's LDS staging.  Pairs that need the
 //                     clipped footprint become (segment, layer) items (done in place when
 //                     the item buffer is full).
-//   k_mics3d_general: one lane per (segment, layer) item: rows of the clipped footprint,
-//                     finished here when few, else (segment, global row) items for
-//                     k_mic_rows (done here when the row buffer is full)
+//   k_mics3d_general: kVolSeg (segment, layer) items per wave: rows of the clipped
+//                     footprints spread over the lanes, then their candidates
 // A segment spans from one to every layer and a layer box from none to kSpan candidates,
 // so a lane per segment would leave most lanes idle; the two even spreads keep them busy.
 // ---------------------------------------------------------------------------------------
@@ -582,8 +616,8 @@ __device__ __forceinline__ bool seg_layers(const DevMesh &M, const DevQueue &q, 
     return true;
 }
 
-// Rows of the clipped footprint of layer k: finished here when few (or when the row
-// buffer is full), else handed out as (segment, global row) items.
+// Rows of the clipped footprint of layer k, done here (k_mics3d's fallback when the
+// (segment, layer) item buffer is full).
 __device__ __forceinline__ void layer_general(const Frustum &f, const DevMics &mc, const MicWork &w, DevCounters *ctr,
                                               const TraceArgs &a, long long seg, int k, unsigned &tests,
                                               unsigned &updates)
@@ -592,17 +626,6 @@ __device__ __forceinline__ void layer_general(const Frustum &f, const DevMics &m
     footprint_lines(f, mc, mc.z + (double)k * mc.dz, L);
     int j0, j1;
     if (!footprint_rows(L, mc, j0, j1)) return;
-    const int nrows = j1 - j0 + 1;
-    if (nrows > kInlineRows) {
-        const unsigned long long b = atomicAdd(&ctr->n_rows[a.gen], (unsigned long long)nrows);
-        if (b + (unsigned long long)nrows <= (unsigned long long)w.rows_cap) {
-            for (int r = 0; r < nrows; ++r) w.rows[b + r] = make_int2((int)seg, k * mc.ny + j0 + r);
-            return;
-        }
-        // no room: slots of the reservation inside the buffer are marked empty and the
-        // rows are done here
-        for (unsigned long long r = b; r < (unsigned long long)w.rows_cap; ++r) w.rows[r] = make_int2(-1, 0);
-    }
     for (int j = j0; j <= j1; ++j) {
         int c0, c1;
         if (!row_cols(L, mc, j, c0, c1)) continue;
@@ -934,7 +957,7 @@ __global__ void __launch_bounds__(64, 4) k_mics_plane(DevMesh M, DevQueue q, Dev
         // segments of this wave's batches: 64 per full batch
         const unsigned long long stride = (unsigned long long)gridDim.x * 64;
         const unsigned long long full = (n - wave * 64) / stride, rest = (n - wave * 64) % stride;
-        atomicAdd(&ctr->mic_classified, 64 * full + (rest < 64 ? rest : 64));
+        add_mic_stat(ctr, MS_CLASSIFIED, 64 * full + (rest < 64 ? rest : 64));
     }
 }
 
@@ -1052,7 +1075,7 @@ __global__ void __launch_bounds__(64, 4) k_mics3d(DevMesh M, DevQueue q, DevSegs
     }
     flush_mic_counters(ctr, tests, updates);
     const unsigned long long sv = wave_sum_u64(visits);
-    if (lane == 0 && sv) atomicAdd(&ctr->mic_layer_visits, sv);
+    if (lane == 0) add_mic_stat(ctr, MS_LAYERS, sv);
 }
 
 // LDS staging of one wave of k_mics3d_general: kVolSeg (segment, layer) items with their
@@ -1494,7 +1517,7 @@ static hipError_t launch_mics_t(const DevMesh &m, DevQueue q, DevSegs segs, DevC
     if (e != hipSuccess) return e;
     k_mics_general<kSlots><<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, mics, a, w, ws);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_mic_rows<kSlots><<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
+    k_mic_rows<kSlots><<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, mics, a, w, ws);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_mics_big<kSlots><<<n_cu * 4, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1513,8 +1536,6 @@ hipError_t launch_mics(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         k_mics3d_general<<<n_cu * 12, 64, 0, s>>>(m, q, segs, ctr, mics, a, w);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        k_mic_rows<false><<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         k_mic_spans<false><<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
         return hipGetLastError();
