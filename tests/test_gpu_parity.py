@@ -528,14 +528,16 @@ def test_microphone_passes_between_generations(torch_cuda, every):
     check_mics(o.e_strict, o.e_flag, es, ef)
 
 
-@pytest.mark.parametrize("env", ["BT_MIC_ROW_CAPACITY", "BT_MIC_SPAN_CAPACITY"])
-def test_mic_work_buffer_overflow(torch_cuda, monkeypatch, env):
-    """Tiny work-item buffers force wide footprints onto the one-wave-per-segment path and
-    long rows onto in-place processing; results must not change."""
+@pytest.mark.parametrize("env,value", [("BT_MIC_ROW_CAPACITY", "1000"), ("BT_MIC_ROW_CAPACITY", "50000"),
+                                       ("BT_MIC_SPAN_CAPACITY", "1000")])
+def test_mic_work_buffer_overflow(torch_cuda, monkeypatch, env, value):
+    """Small work-item buffers force wide footprints onto the one-wave-per-segment path
+    (every one of them when the row buffer's per-wave regions hold nothing, some when they
+    hold a few rows each) and long rows onto in-place processing; results must not change."""
     sc = block_scene(0)
-    say("mic work buffer overflow", env)
+    say("mic work buffer overflow", env, value)
     o = O.trace(sc)
-    monkeypatch.setenv(env, "1000")
+    monkeypatch.setenv(env, value)
     with session(sc) as s:
         g = gpu_run(s, sc)
     full_verdict(sc, g, o)
