@@ -392,6 +392,8 @@ def main():
                          "the configured 200 warm-up + 2000 measured requests per rate")
     ap.add_argument("--no-volumetric", action="store_true", help="skip the volumetric (tall district) measurement")
     ap.add_argument("--no-points", action="store_true", help="skip the explicit-receiver measurement")
+    ap.add_argument("--no-two-slot", action="store_true",
+                    help="skip the two-generation-slot bt_run measurement (profiles of the default step)")
     ap.add_argument("--volumetric-only", action="store_true",
                     help="only the volumetric measurement (prints its JSON object; for profiling)")
     ap.add_argument("--vol-chunk", type=int, default=7, help="sources per beam set in the volumetric measurement")
@@ -577,7 +579,7 @@ def main():
     }
     if args.config == 2 and not args.no_points:
         out["points"] = points_bench(sess, scene)
-    if args.config == 2 and not args.run_call:
+    if args.config == 2 and not args.run_call and not args.no_two_slot:
         out["two_slot_run"] = two_slot_bench(scene)
     if args.config == 2 and not args.no_batch:
         out["batched"] = batch_bench(sess)
