@@ -187,8 +187,9 @@ def test_batch_autotune(torch_cuda):
 
 def test_full_batch_workload_sampled_against_oracle(torch_cuda):
     """The batched workload at full size (256 district scenarios, 96.7 M generation-0
-    beams, several chunks): four scenarios, the three cheapest and the one with the
-    most sources, checked against the oracle over their microphone subsets."""
+    beams, several chunks): 24 scenarios, the three cheapest, the one with the most
+    sources and 20 drawn at random over every chunk, checked against the oracle over
+    their microphone subsets."""
     from paper_1912_03998_amd import bt
     from paper_1912_03998_amd.tracer import Session
     base = district_scene(0)
@@ -201,6 +202,8 @@ def test_full_batch_workload_sampled_against_oracle(torch_cuda):
     cost = [q.n_beams0 * (q.depth + 1) for q in specs]
     picks = sorted(range(len(specs)), key=lambda k: cost[k])[:3]
     picks.append(max(range(len(specs)), key=lambda k: (len(specs[k].sources), -cost[k])))
+    rest = [k for k in range(len(specs)) if k not in picks]
+    picks += sorted(np.random.default_rng(5).choice(rest, 20, replace=False).tolist())
     for k in picks:
         q = specs[k]
         say("oracle for scenario", k, len(q.sources), "sources, level", q.level, "depth", q.depth)

@@ -132,8 +132,9 @@ def test_server_errors(torch_cuda):
 
 def test_district_stream_sampled_against_oracle(torch_cuda):
     """The serving workload on the district at 800 requests/s (300 requests submitted at
-    their Poisson arrival times, continuously batched): three requests (the cheapest, the
-    median and the costliest) checked against the oracle over their microphone rectangles."""
+    their Poisson arrival times, continuously batched): 20 requests (the cheapest, the
+    median, the costliest and 17 drawn at random) checked against the oracle over their
+    microphone rectangles."""
     from paper_1912_03998_amd import bt
     from paper_1912_03998_amd.tracer import Session
     base = district_scene(0)
@@ -151,7 +152,10 @@ def test_district_stream_sampled_against_oracle(torch_cuda):
             wait_all(srv, tickets, timeout=120.0)
     cost = [q.n_beams0 * (q.depth + 1) for q in reqs]
     order = sorted(range(len(reqs)), key=lambda k: cost[k])
-    for k in (order[0], order[len(order) // 2], order[-1]):
+    picks = [order[0], order[len(order) // 2], order[-1]]
+    rest = [k for k in range(len(reqs)) if k not in picks]
+    picks += sorted(np.random.default_rng(6).choice(rest, 17, replace=False).tolist())
+    for k in picks:
         q = reqs[k]
         say("oracle for request", k, len(q.sources), "sources, level", q.level, "depth", q.depth,
             "mics", q.grid[5], "x", q.grid[6])
