@@ -387,6 +387,9 @@ def main():
                     help="per-tile queue rounds of the trace (0 = in-lane tile walk; default: the library's)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-scenario measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-seeds", type=int, default=1,
+                    help="request streams per rate (seeds 0 .. N-1; the configured workload names seeds 0-2, "
+                         "each adding about two minutes)")
     ap.add_argument("--serve-short", action="store_true",
                     help="serving on short streams (300 / 800 / 2200 requests at 50 / 200 / 800 req/s) instead of "
                          "the configured 200 warm-up + 2000 measured requests per rate")
@@ -589,6 +592,10 @@ def main():
         else:
             n_of_rate, warm = (lambda r: 2200), 200 / 2200
         out["served"] = serve_bench(sess, [50, 200, 800], n_of_rate, warm)
+        for seed in range(1, max(args.serve_seeds, 1)):
+            # further request streams (another seed each), reported beside seed 0's
+            out.setdefault("served_other_seeds", {})[str(seed)] = \
+                serve_bench(sess, [50, 200, 800], n_of_rate, warm, seed=seed)
     sess.close()
     if args.config == 2 and not args.no_volumetric:
         out["volumetric"] = volumetric_bench(max(2, min(args.steps, 5)), max(1, min(args.warmup, 2)), args.vol_chunk,
