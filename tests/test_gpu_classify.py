@@ -129,3 +129,32 @@ def test_bt_run_classifies_district(torch_cuda):
             assert r.stats["mic_classified"] == r.stats["segments"] == st0["segments"]
             assert r.stats["mic_tests"] == st0["mic_tests"] and r.stats["mic_updates"] == st0["mic_updates"]
             assert same(es0, r.e_strict) and same(ef0, r.e_flag)
+
+
+def test_bind_rejects_non_planar_sets(torch_cuda):
+    """Explicit points and volumetric grids have no planar class: binding them is
+    refused (BT_EINVAL) and leaves the set as it was; unbinding always succeeds."""
+    from paper_1912_03998_amd import bt
+    from paper_1912_03998_amd.tracer import Session, scene_grid
+    sc = block_scene(0).with_(level=3, depth=2)
+    with Session.from_scene(sc) as s:
+        grid = bt.bt_mics_grid(s.ctx, *scene_grid(sc))
+        pts = bt.bt_mics_points(s.ctx, np.array([[1.0, 2.0, 1.5], [3.0, -4.0, 2.0]], np.float32))
+        vol = bt.bt_mics_grid3d(s.ctx, -98.0, -98.0, 1.5, 4.0, 4.0, 4.0, 50, 50, 4)
+        beams = bt.bt_beams_bind_mics(s.ctx, None, grid)
+        for m in (pts, vol):
+            with pytest.raises(bt.BTError) as e:
+                bt.bt_beams_bind_mics(s.ctx, beams, m)
+            assert e.value.status == -1
+        # still bound to the grid: a run classifies every segment
+        p = s.params(sc.depth)
+        beams = bt.bt_emit_beams(s.ctx, sc.sources, sc.power, sc.level, beams)
+        for _ in range(sc.depth + 1):
+            bt.bt_trace(s.ctx, s.mesh, beams, p)
+        bt.bt_accumulate_mics(s.ctx, s.mesh, beams, p, grid)
+        st = bt.bt_beams_stats(s.ctx, beams)
+        assert st["mic_classified"] == st["segments"] > 0
+        bt.bt_beams_bind_mics(s.ctx, beams, None)
+        bt.bt_beams_free(beams)
+        for m in (vol, pts, grid):
+            bt.bt_mics_free(m)
