@@ -195,7 +195,7 @@ def serve_bench(sess, rates, n_of_rate, warm_frac=0.1, seed=0, saturation=400):
     return res
 
 
-def two_slot_bench(scene, steps=5, warmup=2, run_records=1 << 24):
+def two_slot_bench(scene, steps=5, warmup=2, run_records=1 << 24, partitions=2):
     """The whole step as one bt_run call with a record budget below the workload's
     n_beams0 (depth + 1): two generation slots and a microphone pass per generation, in a
     session of its own (so its device memory is what this form needs)."""
@@ -206,6 +206,7 @@ def two_slot_bench(scene, steps=5, warmup=2, run_records=1 << 24):
 
     sess = Session.from_scene(scene)
     ctx, mesh, stream = sess.ctx, sess.mesh, sess.stream
+    bt.bt_set_partitions(ctx, partitions)
     mics = sess._mics(scene_grid(scene))
     params = sess.params(scene.depth, run_records=run_records)
     src = np.ascontiguousarray(scene.sources, np.float32)
@@ -220,10 +221,15 @@ def two_slot_bench(scene, steps=5, warmup=2, run_records=1 << 24):
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    each = []
     for _ in range(steps):
         step()
+        torch.cuda.synchronize()
+        each.append(time.perf_counter())
     bt.bt_levels(ctx, mics, e, None, None)
     dt = (time.perf_counter() - t0) / steps
+    print(f"[bench] two-slot steps (ms): {[round((b - a) * 1e3, 3) for a, b in zip([t0] + each, each)]}",
+          file=sys.stderr, flush=True)
     used = bt.bt_memory_used(ctx)
     sess.close()
     return {"step_call": f"bt_run with run_records = {run_records} (two generation slots)", "ms_per_step": round(dt * 1e3, 3),
@@ -383,6 +389,12 @@ def main():
                     help="time each step as one bt_run call (source chunks, two generation slots, a microphone "
                          "pass per generation) instead of bt_emit_beams, bt_trace per generation and one "
                          "bt_accumulate_mics")
+    ap.add_argument("--partitions", type=int, default=2,
+                    help="partitions of the beam set (bt_set_partitions): the sources split into this many groups, "
+                         "each traced and accumulated on a stream of its own (1 = one stream)")
+    ap.add_argument("--per-generation", action="store_true",
+                    help="trace with one bt_trace call per generation (the partitions' streams joined after each) "
+                         "instead of one bt_trace_all call")
     ap.add_argument("--queue-rounds", type=int, default=-1,
                     help="per-tile queue rounds of the trace (0 = in-lane tile walk; default: the library's)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-scenario measurement")
@@ -455,6 +467,8 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     ctx, mesh, stream = sess.ctx, sess.mesh, sess.stream
+    bt.bt_set_partitions(ctx, args.partitions)
+    parts = min(args.partitions, scene.n_src) if scene.n_src >= 2 else 1
     grid = scene_grid(scene)
     mics = sess._mics(grid)
     params = sess.params(scene.depth) if args.queue_rounds < 0 else \
@@ -486,8 +500,11 @@ def main():
         bt.bt_mics_reset(ctx, mics)
         if ev is not None:
             ev[0].record(stream)
-        for g in range(D + 1):
-            bt.bt_trace(ctx, mesh, sess.beams, params)
+        if args.per_generation:
+            for g in range(D + 1):
+                bt.bt_trace(ctx, mesh, sess.beams, params)
+        else:
+            bt.bt_trace_all(ctx, mesh, sess.beams, params)
         if ev is not None:
             ev[1].record(stream)
         bt.bt_accumulate_mics(ctx, mesh, sess.beams, params, mics)
@@ -532,7 +549,8 @@ def main():
             dominant = "k_mics_plane+k_mics_general+k_mic_rows+k_mics_big+k_mic_spans"
         t_dom = trace_ms if trace_dominant else mic_ms
         b_dom = trace_bytes if trace_dominant else mic_bytes
-        launches = (4 if q == 0 else 4 + 3 * q) * (D + 1) if trace_dominant else 5
+        # every partition launches the stage's kernels
+        launches = ((4 if q == 0 else 4 + 3 * q) * (D + 1) if trace_dominant else 5) * parts
         achieved = b_dom / (t_dom * 1e-3) / 1e9
         traffic = pmc_traffic(launches) if trace_dominant and q == 0 else None
         frac_alg = round(achieved / HBM_PEAK_GBS, 4)
@@ -572,9 +590,12 @@ def main():
         "setup_s": round(setup_s, 3),
         "step_call": "bt_run (source chunks; every generation resident when the records fit run_records)"
                      if args.run_call else
-                     ("bt_emit_beams, bt_trace per generation (every generation resident), bt_accumulate_mics" +
+                     (f"bt_emit_beams ({parts} partitions), " +
+                      ("bt_trace per generation" if args.per_generation else "bt_trace_all") +
+                      " (every generation resident), bt_accumulate_mics" +
                       ("" if args.no_classify else "; the beam set bound to the grid once at set-up "
                        "(bt_beams_bind_mics: beams classified as they are created)")),
+        "partitions": parts,
         "mic_classified_per_step": st["mic_classified"],
         "device_memory_bytes": bt.bt_memory_used(ctx),
         "end_to_end_segments_per_s": segs / (setup_s + ms_per_step * 1e-3),
@@ -583,7 +604,7 @@ def main():
     if args.config == 2 and not args.no_points:
         out["points"] = points_bench(sess, scene)
     if args.config == 2 and not args.run_call and not args.no_two_slot:
-        out["two_slot_run"] = two_slot_bench(scene)
+        out["two_slot_run"] = two_slot_bench(scene, partitions=args.partitions)
     if args.config == 2 and not args.no_batch:
         out["batched"] = batch_bench(sess)
     if args.config == 2 and not args.no_serve:

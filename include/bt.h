@@ -22,6 +22,9 @@
  *   - A bt_ctx is single-threaded except bt_submit / bt_poll / bt_cancel.
  *   - Work is enqueued on the context's stream; calls that return results to the
  *     host (bt_trace with n_next, bt_levels, bt_beams_stats, bt_poll) synchronise it.
+ *     A call on a partitioned beam set (bt_set_partitions) also runs work on the
+ *     library's own streams, forked from the context's stream at the call's start and
+ *     joined to it before the call returns, so the ordering above holds.
  */
 #ifndef BT_H
 #define BT_H
@@ -131,6 +134,21 @@ bt_status bt_destroy(bt_ctx *ctx);
 /* Device bytes currently allocated through the context. */
 bt_status bt_memory_used(const bt_ctx *ctx, size_t *bytes);
 
+/* Partitions of a beam set (paper Section 3 shares the beams out among processors; on
+ * one GPU the shares are streams).  A set emitted from n_src >= 2 sources is split by
+ * source into min(k, n_src) partitions of contiguous sources (near-equal counts), each
+ * with its own queue, counters and microphone work lists.  Every call on the set runs
+ * partition j's kernels on stream j of the context's partition streams (created together
+ * on first use, with default priority, so that the runtime gives them distinct hardware
+ * queues).  A generation's last rays leave most compute units idle; the other
+ * partitions' work fills them.  bt_trace joins the
+ * streams after each generation; bt_trace_all and bt_run run a partition's generations
+ * (and, in bt_run, its microphone passes) without waiting for the other partitions.
+ * Results do not depend on k: hit ids, parameters and flags are identical, and
+ * energies and power sums differ only in the order of FP64 additions.  k in
+ * 1..4 (BT_EINVAL otherwise); default 2.  It applies to sets emitted afterwards. */
+bt_status bt_set_partitions(bt_ctx *ctx, int32_t k);
+
 /* Triangulated model (paper Section 4: a detailed district model; Section 3: the
  * model is split once and reused for many simulations).
  *   xyz        host float[n_vert][3]
@@ -212,6 +230,13 @@ bt_status bt_beams_stats(bt_ctx *ctx, const bt_beams *beams, bt_stats *out);
 bt_status bt_trace(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *beams, const bt_params *params,
                    int64_t *n_next);
 
+/* Trace every remaining generation of the set, up to params->max_depth: the same work
+ * and results as that many bt_trace calls, enqueued at once without synchronisation.  On a
+ * partitioned set each partition's generations run on its own stream without waiting for
+ * the others' (joined to the context's stream before the call returns).  BT_ESTATE when
+ * every generation is already traced; otherwise as bt_trace. */
+bt_status bt_trace_all(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *beams, const bt_params *params);
+
 /* Add the contributions of every segment traced since the previous call (all of them
  * after a first call) to the microphones, in one pass (paper Section 2: microphones sum
  * the contributions reaching them); a call with nothing new traced does nothing.
@@ -220,7 +245,8 @@ bt_status bt_trace(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *beams, const bt_p
  * plane as far cap) receives K exp(-air_m d) / d^2, d = distance to the beam's
  * (image) apex.  Contributions of flagged segments, and memberships decided within
  * edge_delta of a frustum plane, go to the set's flag energy, the others to its
- * strict energy; both are FP64. */
+ * strict energy; both are FP64.  A partitioned set's partitions make their passes on
+ * their own streams at once (their contributions meet only in FP64 atomic additions). */
 bt_status bt_accumulate_mics(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *beams, const bt_params *params,
                              bt_mics *mics);
 
@@ -246,8 +272,9 @@ bt_status bt_beams_bind_mics(bt_ctx *ctx, bt_beams **beams, const bt_mics *mics)
  * accumulation) <= about 5.4 M (e.g. one generation of 64 level-6 sources); a larger pass
  * returns BT_EINVAL with nothing enqueued (accumulate after fewer generations).  Every call
  * on a GPU shares that GPU's array: calls that overlap on one GPU (other contexts or
- * streams) race and must be serialised by the caller.  Explicit point sets use no work
- * lists. */
+ * streams) race and must be serialised by the caller.  The partitions of a partitioned
+ * set are accumulated one after another on the context's stream, and the limit applies
+ * to each partition.  Explicit point sets use no work lists. */
 bt_status bt_accumulate_mics_static(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *beams, const bt_params *params,
                                     bt_mics *mics);
 
@@ -266,9 +293,11 @@ bt_status bt_levels(bt_ctx *ctx, const bt_mics *mics, double *strict_out, double
  * it is traced.  So n_src x 20 4^level may exceed 2^31, and a run holds at most
  * run_records (resident) or 2 x 16 Mi (two slots) beam records.  Parity outputs in
  * params keep their global rows [n_src 20 4^level][max_depth + 1].  bt_beams_stats on the
- * set afterwards reports the whole run (it synchronises once per extra chunk).  Reuses
- * *beams when non-NULL (created otherwise; caller frees).  Does not synchronise apart
- * from those chunk boundaries. */
+ * set afterwards reports the whole run (it synchronises once per extra chunk).  Each
+ * chunk is emitted in partitions (bt_set_partitions), and each partition traces all its
+ * generations and makes its microphone passes on its own stream, joined at the chunk's
+ * end.  Reuses *beams when non-NULL (created otherwise; caller frees).  Does not
+ * synchronise apart from those chunk boundaries. */
 bt_status bt_run(bt_ctx *ctx, const bt_mesh *mesh, const float *src_xyz, const float *src_power,
                  int32_t n_src, int32_t level, const bt_params *params, bt_mics *mics, bt_beams **beams);
 

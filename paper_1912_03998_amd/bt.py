@@ -22,7 +22,9 @@ STATUS = {0: "BT_OK", 1: "BT_PENDING", -1: "BT_EINVAL", -2: "BT_ENOMEM", -3: "BT
 
 EXPORTED = ["bt_params_default", "bt_status_str", "bt_last_error", "bt_create", "bt_destroy", "bt_memory_used",
             "bt_build_mesh", "bt_mesh_free", "bt_mesh_info", "bt_mics_grid", "bt_mics_grid3d", "bt_mics_subset", "bt_mics_points", "bt_mics_reset", "bt_mics_free",
-            "bt_emit_beams", "bt_emit_beams_directional", "bt_beams_free", "bt_beams_stats", "bt_trace", "bt_accumulate_mics",
+            "bt_set_partitions",
+            "bt_emit_beams", "bt_emit_beams_directional", "bt_beams_free", "bt_beams_stats", "bt_trace", "bt_trace_all",
+            "bt_accumulate_mics",
             "bt_accumulate_mics_static", "bt_beams_bind_mics", "bt_levels",
             "bt_run", "bt_submit", "bt_poll", "bt_cancel", "bt_batch_run", "bt_batch_release", "bt_batch_autotune",
             "bt_server_create", "bt_server_submit", "bt_server_poll", "bt_server_destroy",
@@ -94,6 +96,8 @@ def lib():
         "bt_beams_free": (C.c_int, [P]),
         "bt_beams_stats": (C.c_int, [P, P, P]),
         "bt_trace": (C.c_int, [P, P, P, P, P]),
+        "bt_trace_all": (C.c_int, [P, P, P, P]),
+        "bt_set_partitions": (C.c_int, [P, I32]),
         "bt_accumulate_mics": (C.c_int, [P, P, P, P, P]),
         "bt_accumulate_mics_static": (C.c_int, [P, P, P, P, P]),
         "bt_beams_bind_mics": (C.c_int, [P, P, P]),
@@ -302,6 +306,14 @@ def bt_trace(ctx, mesh, beams, params, want_next=False):
     n = C.c_int64(-1)
     _check(ctx, lib().bt_trace(ctx, mesh, beams, C.byref(params), C.byref(n) if want_next else None), "bt_trace")
     return n.value if want_next else None
+
+
+def bt_trace_all(ctx, mesh, beams, params):
+    _check(ctx, lib().bt_trace_all(ctx, mesh, beams, C.byref(params)), "bt_trace_all")
+
+
+def bt_set_partitions(ctx, k):
+    _check(ctx, lib().bt_set_partitions(ctx, k), "bt_set_partitions")
 
 
 def bt_accumulate_mics(ctx, mesh, beams, params, mics):

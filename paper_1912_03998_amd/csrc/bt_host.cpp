@@ -323,6 +323,14 @@ extern "C" bt_status bt_destroy(bt_ctx *ctx)
         dev_free(ctx, ctx->face_om[l], (size_t)nf * sizeof(double));
     }
     dev_free(ctx, ctx->base20, 20 * 9 * sizeof(double));
+    for (int k = 0; k < kMaxParts; ++k) {
+        if (ctx->part_stream[k]) {
+            (void)hipStreamSynchronize(ctx->part_stream[k]);
+            (void)hipStreamDestroy(ctx->part_stream[k]);
+        }
+        if (ctx->join_ev[k]) (void)hipEventDestroy(ctx->join_ev[k]);
+    }
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return BT_OK;
@@ -1244,29 +1252,47 @@ static ClassGrid class_target(const bt_beams *b)
     return b->cgrid;
 }
 
-static bt_status emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_power, const float *src_weight,
-                            int32_t n_src, int32_t level, bt_beams **inout, bool two_slot = false)
+// Bind set b to classification grid g (allocating its class array), or unbind it.
+static bt_status bind_set(bt_ctx *ctx, bt_beams *b, const ClassGrid *g)
 {
-    if (!ctx) return BT_EINVAL;
-    if (!inout) return fail(ctx, BT_EINVAL, "inout is NULL");
-    {
-        std::string msg;
-        bt_status s = check_source_args(src_xyz, src_power, src_weight, n_src, level, two_slot, msg);
-        if (s != BT_OK) return fail(ctx, s, "%s", msg.c_str());
+    if (!g) {
+        b->bound = false;
+        return BT_OK;
     }
+    const ClassGrid &c = b->cgrid;
+    const bool same = c.cls && c.x0 == g->x0 && c.y0 == g->y0 && c.z == g->z && c.dx == g->dx && c.dy == g->dy &&
+                      c.nx == g->nx && c.ny == g->ny;
+    if (!same) b->class_gens = 0;   // the records' classes refer to another grid
+    if (!b->cgrid.cls || b->cls_cap < b->cap) {
+        dev_free(ctx, b->cgrid.cls, (size_t)b->cls_cap * sizeof(int2));
+        b->cgrid.cls = nullptr;
+        b->cls_cap = 0;
+        b->class_gens = 0;
+        const long long n = std::max(b->cap, 1ll);
+        bt_status s = dev_alloc(ctx, (void **)&b->cgrid.cls, (size_t)n * sizeof(int2));
+        if (s != BT_OK) return s;
+        b->cls_cap = n;
+    }
+    int2 *cls = b->cgrid.cls;
+    b->cgrid = *g;
+    b->cgrid.cls = cls;
+    b->bound = true;
+    return BT_OK;
+}
+
+// Generation 0 of one set (a partition) from n_src sources, enqueued on the context's
+// stream; src_weight NULL (omni sources) or host float[n_src][nf].  two_slot: the set
+// keeps two generation slots of n0 records (each generation must be accumulated before
+// the next is traced) instead of every generation.  The caller synchronises before the
+// host inputs are released.
+static bt_status emit_set(bt_ctx *ctx, bt_beams *b, const float *src_xyz, const float *src_power,
+                          const float *src_weight, int32_t n_src, int32_t level, bool two_slot)
+{
     const long long nf = 20ll << (2 * level);
     const long long n0 = nf * n_src;
     double r_src = 0.0;
     for (int i = 0; i < n_src; ++i)
         for (int c = 0; c < 3; ++c) r_src = std::max(r_src, (double)std::fabs(src_xyz[3 * i + c]));
-    (void)hipSetDevice(ctx->device);
-    bt_beams *b = *inout;
-    bool fresh = false;
-    if (!b) {
-        bt_status s = new_beams(ctx, &b);
-        if (s != BT_OK) return s;
-        fresh = true;
-    }
     // room for every generation of the previous run's depth (grown at the first trace if
     // the depth is larger), or for two generations
     const long long want = std::max(n0, 1ll) * (two_slot ? 2ll : (long long)(b->depth_hint + 1));
@@ -1291,10 +1317,7 @@ static bt_status emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_
         s = dev_alloc(ctx, (void **)&b->wt_dev, (size_t)n0 * sizeof(float));
         if (s == BT_OK) b->wt_cap = n0;
     }
-    if (s != BT_OK) {
-        if (fresh) bt_beams_free(b);
-        return s;
-    }
+    if (s != BT_OK) return s;
     if (n_src > 0) {
         HIP_TRY(ctx, hipMemcpyAsync(b->src_dev, src_xyz, (size_t)n_src * 3 * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
         HIP_TRY(ctx, hipMemcpyAsync(b->pow_dev, src_power, (size_t)n_src * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
@@ -1305,7 +1328,6 @@ static bt_status emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_
     HIP_TRY(ctx, launch_init_counters(b->ctr, n0, two_slot ? std::max(n0, 1ll) : 0, ctx->stream));
     if (!ctx->face_dirs[level]) {
         // the level's face directions, computed once per context
-        const long long nf = 20ll << (2 * level);
         if ((s = dev_alloc(ctx, (void **)&ctx->face_dirs[level], (size_t)nf * 12 * sizeof(double))) != BT_OK) return s;
         if ((s = dev_alloc(ctx, (void **)&ctx->face_om[level], (size_t)nf * sizeof(double))) != BT_OK) return s;
         HIP_TRY(ctx, launch_faces(ctx->base20, level, ctx->face_dirs[level], ctx->face_om[level], ctx->stream));
@@ -1314,8 +1336,6 @@ static bt_status emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_
                              src_weight ? b->wt_dev : nullptr, b->norm_dev, n_src, level, b->q, class_target(b),
                              ctx->stream));
     b->class_gens = b->bound ? 1ull : 0ull;
-    // host inputs are borrowed for the call only
-    if (n_src > 0) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     b->gen = 0;
     b->acc_gen = 0;
     b->max_depth = -1;
@@ -1323,6 +1343,62 @@ static bt_status emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_
     b->ring = two_slot ? std::max(n0, 1ll) : 0;
     b->prior = bt_stats{};
     b->r_src = r_src;
+    return BT_OK;
+}
+
+// Partition k of a set (0: the set itself).
+static inline bt_beams *part_of(bt_beams *b, int k) { return k == 0 ? b : b->part[k - 1]; }
+static inline const bt_beams *part_of(const bt_beams *b, int k) { return k == 0 ? b : b->part[k - 1]; }
+
+// Generation 0 of a beam set.  With two or more sources and the context's partition count
+// above 1, the sources are split into min(parts, n_src) contiguous groups of near-equal
+// size, each emitted into a partition of its own (a set with its own queue, counters and
+// work lists; partition 0 is the set itself) that later calls trace on a stream of its
+// own.  A partition's beams keep their order and are numbered from 0; beam0 places them
+// in the emission (their parity-output rows).
+static bt_status emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_power, const float *src_weight,
+                            int32_t n_src, int32_t level, bt_beams **inout, bool two_slot = false)
+{
+    if (!ctx) return BT_EINVAL;
+    if (!inout) return fail(ctx, BT_EINVAL, "inout is NULL");
+    {
+        std::string msg;
+        bt_status s = check_source_args(src_xyz, src_power, src_weight, n_src, level, two_slot, msg);
+        if (s != BT_OK) return fail(ctx, s, "%s", msg.c_str());
+    }
+    (void)hipSetDevice(ctx->device);
+    bt_beams *b = *inout;
+    bool fresh = false;
+    if (!b) {
+        bt_status s = new_beams(ctx, &b);
+        if (s != BT_OK) return s;
+        fresh = true;
+    }
+    const long long nf = 20ll << (2 * level);
+    const int K = n_src >= 2 ? std::min(ctx->parts, (int)n_src) : 1;
+    bt_status s = BT_OK;
+    for (int k = 1; k < K && s == BT_OK; ++k) {
+        if (!b->part[k - 1]) s = new_beams(ctx, &b->part[k - 1]);
+        if (s == BT_OK) {
+            bt_beams *q = b->part[k - 1];
+            q->depth_hint = b->depth_hint;
+            s = bind_set(ctx, q, b->bound ? &b->cgrid : nullptr);
+        }
+    }
+    for (int k = 0; k < K && s == BT_OK; ++k) {
+        const long long s0 = (long long)n_src * k / K, s1 = (long long)n_src * (k + 1) / K;
+        bt_beams *q = part_of(b, k);
+        s = emit_set(ctx, q, src_xyz + 3 * s0, src_power + s0, src_weight ? src_weight + s0 * nf : nullptr,
+                     (int32_t)(s1 - s0), level, two_slot);
+        q->beam0 = s0 * nf;
+    }
+    if (s != BT_OK) {
+        if (fresh) bt_beams_free(b);
+        return s;
+    }
+    b->n_parts = K;
+    // host inputs are borrowed for the call only
+    if (n_src > 0) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     *inout = b;
     return BT_OK;
 }
@@ -1344,6 +1420,10 @@ extern "C" bt_status bt_emit_beams_directional(bt_ctx *ctx, const float *src_xyz
 extern "C" bt_status bt_beams_free(bt_beams *b)
 {
     if (!b) return BT_EINVAL;
+    for (bt_beams *&q : b->part) {
+        if (q) bt_beams_free(q);
+        q = nullptr;
+    }
     beams_release(b);
     dev_free(b->ctx, b->ctr, sizeof(DevCounters));
     dev_free(b->ctx, b->ws_buf, b->ws_bytes);
@@ -1358,28 +1438,36 @@ extern "C" bt_status bt_beams_free(bt_beams *b)
 extern "C" bt_status bt_beams_stats(bt_ctx *ctx, const bt_beams *b, bt_stats *out)
 {
     if (!ctx || !b || !out) return BT_EINVAL;
-    DevCounters h;
-    HIP_TRY(ctx, hipMemcpyAsync(&h, b->ctr, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+    // the counters of every partition (each partition's work is joined to the context's
+    // stream by the call that enqueued it)
+    const int K = b->n_parts;
+    std::vector<DevCounters> hv(K);
+    for (int k = 0; k < K; ++k)
+        HIP_TRY(ctx, hipMemcpyAsync(&hv[k], part_of(b, k)->ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     std::memset(out, 0, sizeof *out);
     out->generations = b->gen;
-    for (int g = 0; g <= BT_MAX_DEPTH; ++g) {
-        if (g < b->gen) {
-            out->count[g] = (int64_t)h.count[g];
-            out->flagged[g] = (int64_t)h.flagged[g];
-            out->power[g] = h.power[g];
-            out->segments += (int64_t)h.count[g];
+    for (int k = 0; k < K; ++k) {
+        const DevCounters &h = hv[k];
+        const bt_beams *q = part_of(b, k);
+        for (int g = 0; g <= BT_MAX_DEPTH; ++g) {
+            if (g < q->gen) {
+                out->count[g] += (int64_t)h.count[g];
+                out->flagged[g] += (int64_t)h.flagged[g];
+                out->power[g] += h.power[g];
+                out->segments += (int64_t)h.count[g];
+            }
         }
-    }
-    out->node_visits = (int64_t)h.node_visits;
-    out->tri_tests = (int64_t)h.tri_tests;
-    out->mic_tests = (int64_t)mic_stat_total(h, MS_TESTS);
-    out->mic_updates = (int64_t)mic_stat_total(h, MS_UPDATES);
-    out->mic_layer_visits = (int64_t)mic_stat_total(h, MS_LAYERS);
-    out->mic_classified = (int64_t)mic_stat_total(h, MS_CLASSIFIED);
-    for (int g = 0; g <= BT_MAX_DEPTH; ++g) {
-        out->mic_general += (int64_t)h.n_layers[g];
-        if ((long long)h.n_layers[g] > b->layers_cap) out->mic_fallback += (int64_t)h.n_layers[g] - b->layers_cap;
+        out->node_visits += (int64_t)h.node_visits;
+        out->tri_tests += (int64_t)h.tri_tests;
+        out->mic_tests += (int64_t)mic_stat_total(h, MS_TESTS);
+        out->mic_updates += (int64_t)mic_stat_total(h, MS_UPDATES);
+        out->mic_layer_visits += (int64_t)mic_stat_total(h, MS_LAYERS);
+        out->mic_classified += (int64_t)mic_stat_total(h, MS_CLASSIFIED);
+        for (int g = 0; g <= BT_MAX_DEPTH; ++g) {
+            out->mic_general += (int64_t)h.n_layers[g];
+            if ((long long)h.n_layers[g] > q->layers_cap) out->mic_fallback += (int64_t)h.n_layers[g] - q->layers_cap;
+        }
     }
     // earlier source chunks of a bt_run
     const bt_stats &q = b->prior;
@@ -1426,21 +1514,112 @@ TraceArgs make_args(const bt_params *p, int gen)
     return a;
 }
 
-extern "C" bt_status bt_trace(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *b, const bt_params *p, int64_t *n_next)
+// ---------------------------------------------------------------------------------------
+// Partition streams.  A call on a partitioned set forks the context's stream: each
+// partition stream first waits for the work enqueued on the context's stream so far,
+// partition k's work goes to partition stream k, and before the call returns the
+// context's stream waits for every partition stream, so the call's work is ordered on the
+// context's stream as the ABI states.  The partition streams are created together, one
+// after the other, so that the runtime spreads them over distinct hardware queues (two
+// busy streams on one in-order hardware queue would run one after the other, with every
+// small kernel's fixed cost paid twice); the context's own stream, idle while they run,
+// may share a queue with one of them.
+// ---------------------------------------------------------------------------------------
+static hipError_t ensure_streams(bt_ctx *ctx)
+{
+    if (ctx->fork_ev) return hipSuccess;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < kMaxParts && e == hipSuccess; ++k) {
+        // default priority, like the context's stream
+        e = hipStreamCreateWithFlags(&ctx->part_stream[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join_ev[k], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        for (int k = 0; k < kMaxParts; ++k) {
+            if (ctx->part_stream[k]) (void)hipStreamDestroy(ctx->part_stream[k]);
+            if (ctx->join_ev[k]) (void)hipEventDestroy(ctx->join_ev[k]);
+            ctx->part_stream[k] = nullptr;
+            ctx->join_ev[k] = nullptr;
+        }
+        ctx->fork_ev = nullptr;
+    }
+    return e;
+}
+
+class StreamFork {
+public:
+    StreamFork(bt_ctx *ctx, int n) : ctx_(ctx), n_(n) {}
+    StreamFork(const StreamFork &) = delete;
+    StreamFork &operator=(const StreamFork &) = delete;
+    ~StreamFork() { (void)join(); }
+    hipError_t begin()
+    {
+        if (n_ <= 1) return hipSuccess;
+        hipError_t e = ensure_streams(ctx_);
+        if (e != hipSuccess) return e;
+        if ((e = hipEventRecord(ctx_->fork_ev, ctx_->stream)) != hipSuccess) return e;
+        forked_ = true;   // from here on, join() orders the context's stream after every partition stream
+        for (int k = 0; k < n_; ++k)
+            if ((e = hipStreamWaitEvent(ctx_->part_stream[k], ctx_->fork_ev, 0)) != hipSuccess) return e;
+        return hipSuccess;
+    }
+    hipStream_t stream(int k) const { return forked_ ? ctx_->part_stream[k] : ctx_->stream; }
+    // The context's stream waits for every partition stream (on failure to order them by
+    // an event, the host waits for the partition stream instead).
+    hipError_t join()
+    {
+        if (!forked_) return hipSuccess;
+        forked_ = false;
+        hipError_t first = hipSuccess;
+        for (int k = 0; k < n_; ++k) {
+            hipError_t e = hipEventRecord(ctx_->join_ev[k], ctx_->part_stream[k]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(ctx_->stream, ctx_->join_ev[k], 0);
+            if (e != hipSuccess) {
+                (void)hipStreamSynchronize(ctx_->part_stream[k]);
+                if (first == hipSuccess) first = e;
+            }
+        }
+        return first;
+    }
+
+private:
+    bt_ctx *ctx_;
+    int n_;
+    bool forked_ = false;
+};
+
+extern "C" bt_status bt_set_partitions(bt_ctx *ctx, int32_t k)
 {
     if (!ctx) return BT_EINVAL;
-    if (!mesh || !b) return fail(ctx, BT_EINVAL, "NULL mesh or beams");
-    bt_status s = check_params(ctx, mesh, p);
-    if (s != BT_OK) return s;
+    if (k < 1 || k > kMaxParts) return fail(ctx, BT_EINVAL, "partitions %d not in 1..%d", k, kMaxParts);
+    ctx->parts = k;
+    return BT_OK;
+}
+
+// A partition's parameters: its parity-output rows start at its first beam's.
+static bt_params part_params(const bt_params *p, const bt_beams *b)
+{
+    bt_params q = *p;
+    const long long row0 = b->beam0 * (long long)(p->max_depth + 1);
+    if (q.hit_out) q.hit_out += row0;
+    if (q.flag_out) q.flag_out += row0;
+    if (q.t_out) q.t_out += row0;
+    return q;
+}
+
+// Checks and buffers before set (partition) b's next generation is traced; nothing is
+// enqueued but the queue's growth on the context's stream.
+static bt_status trace_prepare(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *b, const bt_params *p)
+{
     if (b->max_depth >= 0 && b->max_depth != p->max_depth)
         return fail(ctx, BT_EINVAL, "max_depth changed between generations (%d -> %d)", b->max_depth, p->max_depth);
     if (b->gen > p->max_depth) return fail(ctx, BT_ESTATE, "all %d generations already traced", p->max_depth + 1);
     if (b->r_src > mesh->r_eff) return fail(ctx, BT_EINVAL, "a source lies outside the region the mesh margins cover (|x| <= %g)", mesh->r_eff);
     if (b->ring && b->acc_gen < b->gen)
         return fail(ctx, BT_ESTATE, "two-slot beam set: accumulate generation %d before tracing the next", b->gen - 1);
-    (void)hipSetDevice(ctx->device);
-    int g = b->gen;
-    if (g == 0 && !b->ring) {
+    bt_status s;
+    if (b->gen == 0 && !b->ring) {
         // every generation stays resident: at most n0 records each
         const long long total = std::max(b->n0, 1ll) * (long long)(p->max_depth + 1);
         if (total > (1ll << 31) - 1)
@@ -1448,23 +1627,78 @@ extern "C" bt_status bt_trace(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *b, con
         if ((s = reserve_queue(ctx, b, total, b->n0)) != BT_OK) return s;
         b->depth_hint = p->max_depth;
     }
-    b->max_depth = p->max_depth;
-    TraceArgs a = make_args(p, g);
-    a.cg = class_target(b);
     if (p->queue_rounds > 0 && (s = reserve_tiles(ctx, b, b->n0)) != BT_OK) return s;
-    HIP_TRY(ctx, launch_trace(mesh->dev, b->q, b->segs, b->ctr, a, b->ws, trace_tiles(b, mesh, a), ctx->n_cu,
-                              ctx->stream));
+    return BT_OK;
+}
+
+// Enqueue the trace of set (partition) b's next generation on stream st.
+static bt_status trace_enqueue(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *b, const bt_params *p, hipStream_t st)
+{
+    const int g = b->gen;
+    b->max_depth = p->max_depth;
+    const bt_params q = part_params(p, b);
+    TraceArgs a = make_args(&q, g);
+    a.cg = class_target(b);
+    HIP_TRY(ctx, launch_trace(mesh->dev, b->q, b->segs, b->ctr, a, b->ws, trace_tiles(b, mesh, a), ctx->n_cu, st));
     b->gen = g + 1;
     if (g + 1 < 64) {
         if (b->bound) b->class_gens |= 1ull << (g + 1);
         else b->class_gens &= ~(1ull << (g + 1));
     }
-    if (n_next) {
-        unsigned long long c = 0;
-        HIP_TRY(ctx, hipMemcpyAsync(&c, &b->ctr->count[g + 1], sizeof c, hipMemcpyDeviceToHost, ctx->stream));
-        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-        *n_next = (int64_t)c;
+    return BT_OK;
+}
+
+extern "C" bt_status bt_trace(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *b, const bt_params *p, int64_t *n_next)
+{
+    if (!ctx) return BT_EINVAL;
+    if (!mesh || !b) return fail(ctx, BT_EINVAL, "NULL mesh or beams");
+    bt_status s = check_params(ctx, mesh, p);
+    if (s != BT_OK) return s;
+    (void)hipSetDevice(ctx->device);
+    const int K = b->n_parts;
+    for (int k = 0; k < K; ++k)
+        if ((s = trace_prepare(ctx, mesh, part_of(b, k), p)) != BT_OK) return s;
+    const int g = b->gen;
+    {
+        StreamFork f(ctx, K);
+        HIP_TRY(ctx, f.begin());
+        for (int k = 0; k < K; ++k)
+            if ((s = trace_enqueue(ctx, mesh, part_of(b, k), p, f.stream(k))) != BT_OK) return s;
+        HIP_TRY(ctx, f.join());
     }
+    if (n_next) {
+        unsigned long long c[kMaxParts] = {};
+        for (int k = 0; k < K; ++k)
+            HIP_TRY(ctx, hipMemcpyAsync(&c[k], &part_of(b, k)->ctr->count[g + 1], sizeof c[k], hipMemcpyDeviceToHost,
+                                        ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        unsigned long long t = 0;
+        for (int k = 0; k < K; ++k) t += c[k];
+        *n_next = (int64_t)t;
+    }
+    return BT_OK;
+}
+
+extern "C" bt_status bt_trace_all(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *b, const bt_params *p)
+{
+    if (!ctx) return BT_EINVAL;
+    if (!mesh || !b) return fail(ctx, BT_EINVAL, "NULL mesh or beams");
+    bt_status s = check_params(ctx, mesh, p);
+    if (s != BT_OK) return s;
+    if (b->ring) return fail(ctx, BT_ESTATE, "a two-slot beam set traces one generation per accumulation");
+    (void)hipSetDevice(ctx->device);
+    const int K = b->n_parts;
+    for (int k = 0; k < K; ++k)
+        if ((s = trace_prepare(ctx, mesh, part_of(b, k), p)) != BT_OK) return s;
+    const int n_gen = p->max_depth + 1 - b->gen;
+    StreamFork f(ctx, K);
+    HIP_TRY(ctx, f.begin());
+    // generation by generation, so that each stream is fed in turn; the streams do not
+    // wait for each other until the join
+    for (int i = 0; i < n_gen; ++i)
+        for (int k = 0; k < K; ++k)
+            if ((s = trace_enqueue(ctx, mesh, part_of(b, k), p, f.stream(k))) != BT_OK) return s;
+    HIP_TRY(ctx, f.join());
     return BT_OK;
 }
 
@@ -1496,32 +1730,49 @@ extern "C" bt_status bt_beams_bind_mics(bt_ctx *ctx, bt_beams **beams, const bt_
     bt_status s;
     if (!*beams && (s = new_beams(ctx, beams)) != BT_OK) return s;
     bt_beams *b = *beams;
-    if (!mics) {
-        b->bound = false;
-        return BT_OK;
+    ClassGrid g{};
+    if (mics) {
+        const DevMics &m = mics->dev;
+        g.x0 = m.x0;
+        g.y0 = m.y0;
+        g.z = m.z;
+        g.dx = m.dx;
+        g.dy = m.dy;
+        g.nx = m.nx;
+        g.ny = m.ny;
     }
-    const DevMics &m = mics->dev;
-    const ClassGrid &g = b->cgrid;
-    const bool same = g.cls && g.x0 == m.x0 && g.y0 == m.y0 && g.z == m.z && g.dx == m.dx && g.dy == m.dy &&
-                      g.nx == m.nx && g.ny == m.ny;
-    if (!same) b->class_gens = 0;   // the records' classes refer to another grid
-    if (!b->cgrid.cls || b->cls_cap < b->cap) {
-        dev_free(ctx, b->cgrid.cls, (size_t)b->cls_cap * sizeof(int2));
-        b->cgrid.cls = nullptr;
-        b->cls_cap = 0;
-        b->class_gens = 0;
-        const long long n = std::max(b->cap, 1ll);
-        if ((s = dev_alloc(ctx, (void **)&b->cgrid.cls, (size_t)n * sizeof(int2))) != BT_OK) return s;
-        b->cls_cap = n;
+    // the set and every partition it holds (later emissions bind new partitions alike)
+    for (int k = 0; k < kMaxParts; ++k) {
+        bt_beams *q = part_of(b, k);
+        if (q && (s = bind_set(ctx, q, mics ? &g : nullptr)) != BT_OK) return s;
     }
-    b->cgrid.x0 = m.x0;
-    b->cgrid.y0 = m.y0;
-    b->cgrid.z = m.z;
-    b->cgrid.dx = m.dx;
-    b->cgrid.dy = m.dy;
-    b->cgrid.nx = m.nx;
-    b->cgrid.ny = m.ny;
-    b->bound = true;
+    return BT_OK;
+}
+
+// Buffers of set (partition) b's microphone pass (allocation only).
+static bt_status accumulate_prepare(bt_ctx *ctx, bt_beams *b, const bt_mics *mics)
+{
+    if (!mics->points && mics->dev.nz > 1) return reserve_layers(ctx, b);
+    return BT_OK;
+}
+
+// Enqueue the microphone pass over set (partition) b's generations traced since its
+// previous pass, on stream st, with its own work lists.
+static bt_status accumulate_enqueue(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *b, const bt_params *p, bt_mics *mics,
+                                    hipStream_t st)
+{
+    if (b->acc_gen == b->gen) return BT_OK;
+    TraceArgs a = make_args(p, b->acc_gen);
+    a.gen_end = b->gen;
+    a.mic_cls = pass_classes(b, mics);
+    if (mics->points) {
+        HIP_TRY(ctx, launch_mics_points(mesh->dev, b->q, b->segs, b->ctr, mics->dev, mics->pts, a, ctx->n_cu, st));
+    } else {
+        MicWork w{b->rows, b->rows_cap, b->spans, b->spans_cap, b->big_list + b->cap, b->big_list, b->layers,
+                  b->layers_cap};
+        HIP_TRY(ctx, launch_mics(mesh->dev, b->q, b->segs, b->ctr, mics->dev, a, w, b->ws, ctx->n_cu, st));
+    }
+    b->acc_gen = b->gen;
     return BT_OK;
 }
 
@@ -1535,21 +1786,17 @@ extern "C" bt_status bt_accumulate_mics(bt_ctx *ctx, const bt_mesh *mesh, bt_bea
     if (b->gen == 0) return fail(ctx, BT_ESTATE, "no generation traced yet");
     if (b->acc_gen == b->gen) return BT_OK;  // nothing traced since the last call
     (void)hipSetDevice(ctx->device);
-    // all generations traced since the previous call, in one pass
-    TraceArgs a = make_args(p, b->acc_gen);
-    a.gen_end = b->gen;
-    a.mic_cls = pass_classes(b, mics);
-    if (mics->points) {
-        HIP_TRY(ctx, launch_mics_points(mesh->dev, b->q, b->segs, b->ctr, mics->dev, mics->pts, a, ctx->n_cu,
-                                        ctx->stream));
-        b->acc_gen = b->gen;
-        return BT_OK;
-    }
-    if (mics->dev.nz > 1 && (s = reserve_layers(ctx, b)) != BT_OK) return s;
-    MicWork w{b->rows, b->rows_cap, b->spans, b->spans_cap, b->big_list + b->cap, b->big_list, b->layers,
-              b->layers_cap};
-    HIP_TRY(ctx, launch_mics(mesh->dev, b->q, b->segs, b->ctr, mics->dev, a, w, b->ws, ctx->n_cu, ctx->stream));
-    b->acc_gen = b->gen;
+    // all generations traced since the previous call, in one pass per partition; the
+    // partitions' passes run on their own streams (their contributions meet only in the
+    // microphones' FP64 atomic additions)
+    const int K = b->n_parts;
+    for (int k = 0; k < K; ++k)
+        if ((s = accumulate_prepare(ctx, part_of(b, k), mics)) != BT_OK) return s;
+    StreamFork f(ctx, K);
+    HIP_TRY(ctx, f.begin());
+    for (int k = 0; k < K; ++k)
+        if ((s = accumulate_enqueue(ctx, mesh, part_of(b, k), p, mics, f.stream(k))) != BT_OK) return s;
+    HIP_TRY(ctx, f.join());
     return BT_OK;
 }
 
@@ -1566,33 +1813,42 @@ extern "C" bt_status bt_accumulate_mics_static(bt_ctx *ctx, const bt_mesh *mesh,
     if (b->acc_gen == b->gen) return BT_OK;  // nothing traced since the last call
     if (!ctx->scratch) return fail(ctx, BT_EDEVICE, "no static work area on device %d", ctx->device);
     (void)hipSetDevice(ctx->device);
-    TraceArgs a = make_args(p, b->acc_gen);
-    a.gen_end = b->gen;
-    a.mic_cls = pass_classes(b, mics);
-    if (mics->points) {   // the point kernel uses no work lists
-        HIP_TRY(ctx, launch_mics_points(mesh->dev, b->q, b->segs, b->ctr, mics->dev, mics->pts, a, ctx->n_cu,
-                                        ctx->stream));
-        b->acc_gen = b->gen;
-        return BT_OK;
-    }
-    // segments of this pass: at most n0 per generation
-    const long long n_bound = std::max(b->n0, 1ll) * (long long)(b->gen - b->acc_gen);
+    // the partitions share the device's static area, so their passes run one after the
+    // other on the context's stream; every partition is checked before any is enqueued
+    const int K = b->n_parts;
     const int W = b->ws.n_waves;
     if (W > kStaticMaxWaves) return fail(ctx, BT_EINVAL, "%d waves exceed the static work area's %d", W, kStaticMaxWaves);
     const long long n_max = (kStaticListInts - 64ll * (W + 1)) / 2;
-    if (n_bound > n_max)
-        return fail(ctx, BT_EINVAL,
-                    "this pass may hold %lld segments (%lld generation-0 beams x %d generations), more than the "
-                    "static work area's %lld; accumulate after fewer generations",
-                    n_bound, b->n0, b->gen - b->acc_gen, n_max);
-    char *base = (char *)ctx->scratch;
-    WaveScratch ws = b->ws;
-    ws.general = (unsigned *)base;
-    int *lists = (int *)(base + kStaticListsOffset);
-    MicWork w{(int2 *)(base + kStaticRowsOffset), kStaticRows, (int4 *)(base + kStaticSpansOffset), kStaticSpans,
-              lists + n_bound, lists, (int2 *)(base + kStaticLayersOffset), kStaticLayers};
-    HIP_TRY(ctx, launch_mics(mesh->dev, b->q, b->segs, b->ctr, mics->dev, a, w, ws, ctx->n_cu, ctx->stream));
-    b->acc_gen = b->gen;
+    for (int k = 0; k < K && !mics->points; ++k) {
+        // segments of this pass: at most n0 per generation
+        const bt_beams *q = part_of(b, k);
+        const long long n_bound = std::max(q->n0, 1ll) * (long long)(q->gen - q->acc_gen);
+        if (n_bound > n_max)
+            return fail(ctx, BT_EINVAL,
+                        "this pass may hold %lld segments (%lld generation-0 beams x %d generations), more than the "
+                        "static work area's %lld; accumulate after fewer generations",
+                        n_bound, q->n0, q->gen - q->acc_gen, n_max);
+    }
+    for (int k = 0; k < K; ++k) {
+        bt_beams *q = part_of(b, k);
+        TraceArgs a = make_args(p, q->acc_gen);
+        a.gen_end = q->gen;
+        a.mic_cls = pass_classes(q, mics);
+        if (mics->points) {   // the point kernel uses no work lists
+            HIP_TRY(ctx, launch_mics_points(mesh->dev, q->q, q->segs, q->ctr, mics->dev, mics->pts, a, ctx->n_cu,
+                                            ctx->stream));
+        } else {
+            const long long n_bound = std::max(q->n0, 1ll) * (long long)(q->gen - q->acc_gen);
+            char *base = (char *)ctx->scratch;
+            WaveScratch ws = q->ws;
+            ws.general = (unsigned *)base;
+            int *lists = (int *)(base + kStaticListsOffset);
+            MicWork w{(int2 *)(base + kStaticRowsOffset), kStaticRows, (int4 *)(base + kStaticSpansOffset),
+                      kStaticSpans, lists + n_bound, lists, (int2 *)(base + kStaticLayersOffset), kStaticLayers};
+            HIP_TRY(ctx, launch_mics(mesh->dev, q->q, q->segs, q->ctr, mics->dev, a, w, ws, ctx->n_cu, ctx->stream));
+        }
+        q->acc_gen = q->gen;
+    }
     return BT_OK;
 }
 
@@ -1666,18 +1922,35 @@ extern "C" bt_status bt_run(bt_ctx *ctx, const bt_mesh *mesh, const float *src_x
         s = emit_beams(ctx, nc > 0 ? src_xyz + 3 * c0 : src_xyz, nc > 0 ? src_power + c0 : src_power, nullptr,
                        std::max(nc, 0), level, beams, !resident);
         if (s != BT_OK) return s;
-        (*beams)->prior = total;
+        bt_beams *b = *beams;
+        b->prior = total;
         bt_params pc = *p;
         const long long row0 = c0 * nf * (long long)(p->max_depth + 1);
         if (p->hit_out) pc.hit_out = p->hit_out + row0;
         if (p->flag_out) pc.flag_out = p->flag_out + row0;
         if (p->t_out) pc.t_out = p->t_out + row0;
-        for (int g = 0; g <= p->max_depth; ++g) {
-            if ((s = bt_trace(ctx, mesh, *beams, &pc, nullptr)) != BT_OK) return s;
-            if (!resident && (s = bt_accumulate_mics(ctx, mesh, *beams, &pc, mics)) != BT_OK) return s;
+        // each partition of the chunk runs its whole method on its own stream: every
+        // generation's trace, and its microphone pass after each generation (two slots)
+        // or once after the last (resident); the streams meet again at the chunk's end
+        const int K = b->n_parts;
+        for (int k = 0; k < K; ++k) {
+            if ((s = trace_prepare(ctx, mesh, part_of(b, k), &pc)) != BT_OK) return s;
+            if ((s = accumulate_prepare(ctx, part_of(b, k), mics)) != BT_OK) return s;
         }
-        // resident: one pass over every generation
-        if (resident && (s = bt_accumulate_mics(ctx, mesh, *beams, &pc, mics)) != BT_OK) return s;
+        {
+            StreamFork f(ctx, K);
+            HIP_TRY(ctx, f.begin());
+            for (int g = 0; g <= p->max_depth; ++g)
+                for (int k = 0; k < K; ++k) {
+                    if ((s = trace_enqueue(ctx, mesh, part_of(b, k), &pc, f.stream(k))) != BT_OK) return s;
+                    if (!resident && (s = accumulate_enqueue(ctx, mesh, part_of(b, k), &pc, mics, f.stream(k))) != BT_OK)
+                        return s;
+                }
+            if (resident)
+                for (int k = 0; k < K; ++k)
+                    if ((s = accumulate_enqueue(ctx, mesh, part_of(b, k), &pc, mics, f.stream(k))) != BT_OK) return s;
+            HIP_TRY(ctx, f.join());
+        }
         if (nc <= 0) break;
     }
     return BT_OK;

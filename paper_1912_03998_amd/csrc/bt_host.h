@@ -13,10 +13,20 @@
 
 using namespace bt;
 
+// Partitions of one beam set at most: a set emitted from several sources is split by
+// source, and each partition is traced and accumulated on a stream of its own.
+constexpr int kMaxParts = 4;
+
 struct bt_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    int parts = 2;             // partitions of a beam set of two or more sources (bt_set_partitions)
+    // the partitions' streams and the events that fork them from `stream` and join them
+    // to it; all created together on first use
+    hipStream_t part_stream[kMaxParts] = {};
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[kMaxParts] = {};
     size_t budget = 0;
     size_t used = 0;
     int n_cu = 256;
@@ -101,6 +111,12 @@ struct bt_beams {
     unsigned long long class_gens = 0;
     bt_stats prior{};         // statistics of the earlier source chunks of a bt_run
     double r_src = 0.0;
+    // partitions of the last emission: partition 0 is this set, partition k >= 1 is
+    // part[k - 1], a set of its own (its sources follow partition k - 1's); beam0 is the
+    // partition's first beam in the emission, its first row of the parity outputs
+    int n_parts = 1;
+    bt_beams *part[kMaxParts - 1] = {};
+    long long beam0 = 0;
 };
 
 struct Request {

@@ -1,0 +1,257 @@
+"""Partitioned beam sets (bt_set_partitions): a set emitted from several sources is split
+by source into partitions, each traced and accumulated on a stream of its own.
+
+A beam's trace does not depend on any other beam, so hit ids, parameters and flags must be
+identical for every partition count, the per-generation counts and traversal counters
+identical, and energies and power sums equal up to the order of FP64 additions.
+bt_trace_all must equal the same number of bt_trace calls.  The oracle verdict for the
+partitioned path is taken here too (the default partition count already runs through the
+district parity tests).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from scenegen import district_scene
+from tests.parity_check import check_mics
+
+pytestmark = pytest.mark.gpu
+
+PICK = [3, 17, 29, 44, 58, 61]   # six of the district's 64 sources
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def scene():
+    sc = district_scene(0)
+    return sc.with_(sources=sc.sources[PICK], power=sc.power[PICK], level=4, depth=6)
+
+
+@pytest.fixture(scope="module")
+def sess(torch_cuda, scene):
+    from paper_1912_03998_amd.tracer import Session
+    s = Session.from_scene(scene)
+    yield s
+    s.close()
+
+
+def grid(scene):
+    from paper_1912_03998_amd.tracer import scene_grid
+    return scene_grid(scene)
+
+
+def same(a, b, rel=1e-12):
+    scale = max(np.abs(a).max(), 1e-300)
+    return np.abs(a - b).max() <= rel * scale
+
+
+EXACT_STATS = ("count", "flagged", "segments", "node_visits", "tri_tests", "mic_tests", "mic_updates",
+               "mic_classified", "generations")
+
+
+def assert_same_run(a, b, what):
+    assert np.array_equal(a.hit, b.hit), what
+    assert np.array_equal(a.flag, b.flag), what
+    assert np.array_equal(a.t_hit, b.t_hit, equal_nan=True), what
+    assert same(a.e_strict, b.e_strict) and same(a.e_flag, b.e_flag), what
+    for k in EXACT_STATS:
+        assert np.array_equal(np.asarray(a.stats[k]), np.asarray(b.stats[k])), (what, k)
+    assert same(np.asarray(a.stats["power"]), np.asarray(b.stats["power"])), what
+
+
+def test_partition_counts_give_identical_results(sess, scene):
+    """bt_run with 1, 2, 3 and 4 partitions (six sources): identical per-beam outputs and
+    counters, the same energies; the 4-partition energies against the oracle."""
+    from paper_1912_03998_amd import bt
+    runs = {}
+    for k in (1, 2, 3, 4):
+        say(f"district mesh, six sources, bt_run with {k} partitions")
+        bt.bt_set_partitions(sess.ctx, k)
+        runs[k] = sess.run(scene.sources, scene.power, scene.level, scene.depth, grid(scene), parity=True)
+    bt.bt_set_partitions(sess.ctx, 2)
+    base = runs[1]
+    assert base.stats["segments"] > 70_000 and base.stats["mic_updates"] > 300_000
+    for k in (2, 3, 4):
+        assert_same_run(base, runs[k], f"{k} partitions")
+    say("oracle verdict for 4 partitions")
+    o = O.trace(scene, keep_paths=False)
+    check_mics(o.e_strict, o.e_flag, runs[4].e_strict, runs[4].e_flag)
+
+
+def parity_outputs(torch, s, scene):
+    n0 = scene.n_beams0
+    dev = torch.device("cuda", s.device)
+    with torch.cuda.stream(s.stream):
+        return {"hit_out": torch.full((n0, scene.depth + 1), -2, dtype=torch.int32, device=dev),
+                "flag_out": torch.zeros((n0, scene.depth + 1), dtype=torch.uint8, device=dev),
+                "t_out": torch.full((n0, scene.depth + 1), float("nan"), dtype=torch.float64, device=dev)}
+
+
+def manual(torch, s, scene, mode, mics):
+    """Emit, trace (mode: 'each' = bt_trace per generation, 'all' = bt_trace_all, 'mixed'
+    = two bt_trace calls then bt_trace_all), one microphone pass; per-beam outputs,
+    energies and counters."""
+    from paper_1912_03998_amd import bt
+    outs = parity_outputs(torch, s, scene)
+    p = s.params(scene.depth, **outs)
+    beams = bt.bt_emit_beams(s.ctx, scene.sources, scene.power, scene.level, None)
+    if mode == "each":
+        for _ in range(scene.depth + 1):
+            bt.bt_trace(s.ctx, s.mesh, beams, p)
+    elif mode == "all":
+        bt.bt_trace_all(s.ctx, s.mesh, beams, p)
+    else:
+        bt.bt_trace(s.ctx, s.mesh, beams, p)
+        bt.bt_trace(s.ctx, s.mesh, beams, p)
+        bt.bt_trace_all(s.ctx, s.mesh, beams, p)
+    # every generation traced: a further trace is out of order either way
+    for call in (lambda: bt.bt_trace_all(s.ctx, s.mesh, beams, p), lambda: bt.bt_trace(s.ctx, s.mesh, beams, p)):
+        with pytest.raises(bt.BTError) as e:
+            call()
+        assert e.value.status == -6
+    bt.bt_mics_reset(s.ctx, mics)
+    bt.bt_accumulate_mics(s.ctx, s.mesh, beams, p, mics)
+    es, ef = np.zeros(scene.n_mic), np.zeros(scene.n_mic)
+    bt.bt_levels(s.ctx, mics, es, ef, None)
+    st = bt.bt_beams_stats(s.ctx, beams)
+    bt.bt_beams_free(beams)
+    s.stream.synchronize()
+
+    class R:
+        pass
+    r = R()
+    r.hit, r.flag, r.t_hit = (outs[k].cpu().numpy() for k in ("hit_out", "flag_out", "t_out"))
+    r.e_strict, r.e_flag, r.stats = es, ef, st
+    return r
+
+
+def test_trace_all_equals_generation_by_generation(sess, scene, torch_cuda):
+    """bt_trace_all (alone, or after two bt_trace calls) equals bt_trace per generation,
+    with one and with three partitions."""
+    from paper_1912_03998_amd import bt
+    mics = bt.bt_mics_grid(sess.ctx, *grid(scene))
+    try:
+        ref = None
+        for k in (1, 3):
+            bt.bt_set_partitions(sess.ctx, k)
+            for mode in ("each", "all", "mixed"):
+                say(f"district mesh, six sources, {k} partitions, trace mode {mode}")
+                r = manual(torch_cuda, sess, scene, mode, mics)
+                if ref is None:
+                    ref = r
+                    assert (r.hit[:, 0] >= -1).all() and r.stats["generations"] == scene.depth + 1
+                else:
+                    assert_same_run(ref, r, (k, mode))
+    finally:
+        bt.bt_set_partitions(sess.ctx, 2)
+        bt.bt_mics_free(mics)
+
+
+def test_partitioned_two_slot_run(sess, scene):
+    """bt_run with two generation slots (a microphone pass per generation on each
+    partition's stream): 1 against 3 partitions, and against the resident layout."""
+    from paper_1912_03998_amd import bt
+    runs = {}
+    for k in (1, 3):
+        say(f"district mesh, six sources, two-slot bt_run with {k} partitions")
+        bt.bt_set_partitions(sess.ctx, k)
+        runs[k] = sess.run(scene.sources, scene.power, scene.level, scene.depth, grid(scene), parity=True,
+                           run_records=scene.n_beams0)
+    bt.bt_set_partitions(sess.ctx, 2)
+    assert_same_run(runs[1], runs[3], "two slots")
+    resident = sess.run(scene.sources, scene.power, scene.level, scene.depth, grid(scene), parity=True)
+    assert_same_run(runs[1], resident, "two slots against resident")
+
+
+def test_partitioned_directional_sources(sess, scene, torch_cuda):
+    """Directional sources (per-face weights): each partition gets its own sources'
+    weights, so 1 and 3 partitions give the same beams."""
+    from paper_1912_03998_amd import bt
+    c = O.icosphere(scene.level).sum(1)
+    c /= np.linalg.norm(c, axis=1, keepdims=True)
+    axis = np.array([0.3, -1.0, 0.4]) / np.linalg.norm([0.3, -1.0, 0.4])
+    # a different pattern per source, so a weight row given to the wrong source shows
+    w = np.stack([(1.0 + 0.7 * (c @ np.roll(axis, j))) ** 2 for j in range(scene.n_src)]).astype(np.float32)
+    mics = bt.bt_mics_grid(sess.ctx, *grid(scene))
+    res = {}
+    try:
+        for k in (1, 3):
+            say(f"district mesh, six directional sources, {k} partitions")
+            bt.bt_set_partitions(sess.ctx, k)
+            outs = parity_outputs(torch_cuda, sess, scene)
+            p = sess.params(scene.depth, **outs)
+            beams = bt.bt_emit_beams_directional(sess.ctx, scene.sources, scene.power, w, scene.level, None)
+            bt.bt_trace_all(sess.ctx, sess.mesh, beams, p)
+            bt.bt_mics_reset(sess.ctx, mics)
+            bt.bt_accumulate_mics(sess.ctx, sess.mesh, beams, p, mics)
+            es, ef = np.zeros(scene.n_mic), np.zeros(scene.n_mic)
+            bt.bt_levels(sess.ctx, mics, es, ef, None)
+            st = bt.bt_beams_stats(sess.ctx, beams)
+            bt.bt_beams_free(beams)
+            sess.stream.synchronize()
+            res[k] = (outs["hit_out"].cpu().numpy(), es, ef, st)
+    finally:
+        bt.bt_set_partitions(sess.ctx, 2)
+        bt.bt_mics_free(mics)
+    assert np.array_equal(res[1][0], res[3][0])
+    assert same(res[1][1], res[3][1]) and same(res[1][2], res[3][2])
+    assert abs(res[3][3]["power"][0] - float(scene.power.sum())) < 1e-6 * float(scene.power.sum())
+    say("oracle verdict for the directional sources, 3 partitions")
+    o = O.trace(scene, weights=w, keep_paths=False)
+    check_mics(o.e_strict, o.e_flag, res[3][1], res[3][2])
+
+
+def test_partitioned_static_accumulation(sess, scene):
+    """bt_accumulate_mics_static on a set of three partitions (one after another through
+    the shared work area) equals bt_accumulate_mics."""
+    from paper_1912_03998_amd import bt
+    bt.bt_set_partitions(sess.ctx, 3)
+    mics = bt.bt_mics_grid(sess.ctx, *grid(scene))
+    out = []
+    try:
+        p = sess.params(scene.depth)
+        for fn in (bt.bt_accumulate_mics, bt.bt_accumulate_mics_static):
+            say(f"three partitions, {fn.__name__}")
+            beams = bt.bt_emit_beams(sess.ctx, scene.sources, scene.power, scene.level, None)
+            bt.bt_trace_all(sess.ctx, sess.mesh, beams, p)
+            bt.bt_mics_reset(sess.ctx, mics)
+            fn(sess.ctx, sess.mesh, beams, p, mics)
+            es, ef = np.zeros(scene.n_mic), np.zeros(scene.n_mic)
+            bt.bt_levels(sess.ctx, mics, es, ef, None)
+            bt.bt_beams_free(beams)
+            out.append((es, ef))
+    finally:
+        bt.bt_set_partitions(sess.ctx, 2)
+        bt.bt_mics_free(mics)
+    assert same(out[0][0], out[1][0]) and same(out[0][1], out[1][1])
+    assert out[0][0].sum() > 0
+
+
+def test_set_partitions_limits(sess, scene):
+    """Counts outside 1..4 are refused; a single source forms one partition whatever the
+    count, with the same results."""
+    from paper_1912_03998_amd import bt
+    for k in (0, 5, -1):
+        with pytest.raises(bt.BTError) as e:
+            bt.bt_set_partitions(sess.ctx, k)
+        assert e.value.status == -1
+    one = scene.with_(sources=scene.sources[:1], power=scene.power[:1])
+    res = []
+    for k in (1, 4):
+        say(f"one source, {k} partitions")
+        bt.bt_set_partitions(sess.ctx, k)
+        res.append(sess.run(one.sources, one.power, one.level, one.depth, grid(one), parity=True))
+    bt.bt_set_partitions(sess.ctx, 2)
+    assert_same_run(res[0], res[1], "one source")
