@@ -561,7 +561,11 @@ def main():
                     "unit": "GB/s", "frac": frac_alg, "frac_algorithmic": frac_alg, "frac_measured": frac_meas,
                     "traffic": traffic, "traffic_unit": "HBM bytes per launch (stage total / launches)",
                     "algorithmic_bytes_per_step": b_dom, "launches_per_step": launches,
-                    "kernel_ms_per_step": round(t_dom, 3)}
+                    "kernel_ms_per_step": round(t_dom, 3),
+                    "timing": "HIP events on the context's stream around the stage's call, whose partition "
+                              "streams fork from and join to it: the stage's wall-clock span per step (its kernels "
+                              "on the two streams overlap; the per-launch duration is that span over the "
+                              "launches, the figure the dispatch trace's span line in profiles/ gives)"}
     gpu_bytes = (B_BEAM + B_HIT) * segs + B_NODE * st["node_visits"] + B_TRI * st["tri_tests"]
 
     out = {
