@@ -536,21 +536,21 @@ def main():
         trace_bytes = (B_BEAM + B_HIT) * ref["segments"] + B_CHILD * ref["children"] + \
             B_NODE * ref["node_visits"] + B_TRI * ref["tri_tests"]
         mic_bytes = B_MIC * ref["mic_updates"]
-        # the trace stage is what each bt_trace call launches: k_trace, k_tcount, k_gen_scan,
-        # k_reflect (in-lane tile walk), or with per-tile queues k_tbin, (k_tscan, k_tscatter,
-        # k_ttrace) per queued round, k_tcount, k_gen_scan, k_reflect; the microphone stage is
-        # the five kernels of one bt_accumulate_mics call
+        # the trace stage is what the trace call launches per generation and partition:
+        # k_trace, k_tcount, k_reflect (in-lane tile walk), or with per-tile queues k_tbin,
+        # (k_tscan, k_tscatter, k_ttrace) per queued round, k_tcount, k_reflect; the
+        # microphone stage is the five kernels of one bt_accumulate_mics call per partition
         q = params.queue_rounds
         trace_dominant = trace_ms >= mic_ms
         if trace_dominant:
-            dominant = "k_trace+k_tcount+k_gen_scan+k_reflect" if q == 0 else \
-                "k_tbin+k_tscan+k_tscatter+k_ttrace+k_tcount+k_gen_scan+k_reflect"
+            dominant = "k_trace+k_tcount+k_reflect" if q == 0 else \
+                "k_tbin+k_tscan+k_tscatter+k_ttrace+k_tcount+k_reflect"
         else:
             dominant = "k_mics_plane+k_mics_general+k_mic_rows+k_mics_big+k_mic_spans"
         t_dom = trace_ms if trace_dominant else mic_ms
         b_dom = trace_bytes if trace_dominant else mic_bytes
         # every partition launches the stage's kernels
-        launches = ((4 if q == 0 else 4 + 3 * q) * (D + 1) if trace_dominant else 5) * parts
+        launches = ((3 if q == 0 else 3 + 3 * q) * (D + 1) if trace_dominant else 5) * parts
         achieved = b_dom / (t_dom * 1e-3) / 1e9
         traffic = pmc_traffic(launches) if trace_dominant and q == 0 else None
         frac_alg = round(achieved / HBM_PEAK_GBS, 4)

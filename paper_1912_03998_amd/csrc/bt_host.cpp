@@ -999,16 +999,17 @@ size_t list_ints(long long n, int n_waves)
 bt_status alloc_wave_scratch(bt_ctx *ctx, bt_beams *b, int blocks_per_cu)
 {
     const int W = ctx->n_cu * blocks_per_cu * kWavesPerBlock;
-    const size_t bytes = (size_t)W * (6 * 8 + 4 + 4);
+    const size_t bytes = (size_t)W * (7 * 8 + 4 + 4);
     bt_status s = dev_alloc(ctx, &b->ws_buf, bytes);
     if (s != BT_OK) return s;
     b->ws_bytes = bytes;
     char *p = (char *)b->ws_buf;
     b->ws.children = (unsigned long long *)p;
-    b->ws.offset = b->ws.children + W;
-    b->ws.stats = b->ws.offset + W;
+    b->ws.block_rec = b->ws.children + W;                      // [W / kWavesPerBlock][4]
+    b->ws.stats = b->ws.block_rec + W;
     b->ws.power = (double *)(b->ws.stats + 3 * (size_t)W);
-    b->ws.general = (unsigned int *)(b->ws.power + W);
+    b->ws.block_power = b->ws.power + W;                       // [W / kWavesPerBlock], W reserved
+    b->ws.general = (unsigned int *)(b->ws.block_power + W);
     b->ws.rows_n = b->ws.general + W;
     b->ws.n_waves = W;
     return BT_OK;

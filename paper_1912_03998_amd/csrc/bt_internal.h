@@ -181,7 +181,10 @@ constexpr int kBlocksPerCU = 8;
 constexpr int kWavesPerBlock = 4;
 struct WaveScratch {
     unsigned long long *children;  // [W]
-    unsigned long long *offset;    // [W] exclusive scan of children
+    // per block of kWavesPerBlock waves (k_tcount): children, flagged segments, node visits
+    // and triangle tests ([W / kWavesPerBlock][4]), and power ([W / kWavesPerBlock])
+    unsigned long long *block_rec;
+    double *block_power;
     unsigned long long *stats;     // [W][3] flagged, node visits, triangle tests
     double *power;                 // [W]
     unsigned int *general;         // [W] general-path items per wave (microphones)

@@ -1,9 +1,10 @@
 // Guiding-ray trace: closest hit through the per-tile hierarchies over the tiles a ray
 // crosses, with edge/tie flags (k_trace walks them in each lane; k_tbin, k_tscan,
 // k_tscatter and k_ttrace hand rays between per-tile queues instead); the generation's
-// children, flags and power per wave (k_tcount); the children's queue offsets
-// (k_gen_scan); the specular reflection and compaction of the children into the next
-// generation's queue (k_reflect).
+// children, flags and power per wave and children per block (k_tcount); the specular
+// reflection and compaction of the children into the next generation's queue, each block
+// finding its queue offset from the counts of the blocks before it, and the generation's
+// totals (k_reflect).
 //
 // Precision: boxes are tested in FP32 against boxes grown by a margin that covers the
 // rounding of the ray.  A slab parameter is one FMA, l (1/c) - fl(o (1/c)); in distance
@@ -759,9 +760,9 @@ __global__ void __launch_bounds__(kTraceBlock, 4) k_ttrace(DevMesh M, DevQueue i
     }
 }
 
-// Children, flags and power of the generation per wave, in the static partition that
-// k_reflect uses.
-__global__ void __launch_bounds__(256) k_tcount(DevMesh M, DevQueue in, DevSegs segs, DevCounters *ctr, TraceArgs a,
+// Children, flags and power of the generation per wave, and children per block, in the
+// static partition that k_reflect uses.
+__global__ void __launch_bounds__(64 * kWavesPerBlock) k_tcount(DevMesh M, DevQueue in, DevSegs segs, DevCounters *ctr, TraceArgs a,
                                                 WaveScratch ws)
 {
     const unsigned long long n = ctr->count[a.gen];
@@ -781,130 +782,112 @@ __global__ void __launch_bounds__(256) k_tcount(DevMesh M, DevQueue in, DevSegs 
     }
     const unsigned long long sc = wave_sum_u64(children), sf = wave_sum_u64(flagged);
     const double sp = wave_sum_f64(power);
+    __shared__ unsigned long long s_rec[kWavesPerBlock][4];
+    __shared__ double s_pow[kWavesPerBlock];
     if (lane == 0) {
         const unsigned long long w = wave_first_batch() >> 6;
         ws.children[w] = sc;
         ws.stats[3 * w] = sf;
         ws.power[w] = sp;
+        const int wv = (int)threadIdx.x >> 6;
+        s_rec[wv][0] = sc;
+        s_rec[wv][1] = sf;
+        s_rec[wv][2] = ws.stats[3 * w + 1];   // the trace's node visits and triangle tests
+        s_rec[wv][3] = ws.stats[3 * w + 2];
+        s_pow[wv] = sp;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        unsigned long long b = 0;
+        for (int k = 0; k < kWavesPerBlock; ++k) b += s_rec[k][threadIdx.x];
+        ws.block_rec[4 * (long long)blockIdx.x + threadIdx.x] = b;
+    } else if (threadIdx.x == 4) {
+        double b = 0.0;
+        for (int k = 0; k < kWavesPerBlock; ++k) b += s_pow[k];
+        ws.block_power[blockIdx.x] = b;
     }
 }
 
-// One block: exclusive scan of the per-wave child counts (the children's queue offsets,
-// in wave order, so the next generation's order is deterministic) and the generation's
-// totals, summed in a fixed order.
-constexpr int kScanLds = 8192;  // wave records whose child counts k_gen_scan keeps in LDS
-__global__ void __launch_bounds__(1024) k_gen_scan(DevCounters *ctr, TraceArgs a, WaveScratch ws)
+// The generation's totals, summed by one block over k_tcount's block records in a fixed
+// order (so they are the same on every run): children (the next generation's size),
+// flagged segments, power, and the traversal counters.
+__device__ void generation_totals(DevCounters *ctr, const TraceArgs &a, const WaveScratch &ws)
 {
-    // a wave's child count is at most 64 per batch it traced, far below 2^32
-    __shared__ unsigned s_child[kScanLds];
-    __shared__ unsigned long long wtot[16];
-    __shared__ unsigned long long wred[3][16];
-    __shared__ double wpow[16];
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int W = ws.n_waves;
-    const bool in_lds = W <= kScanLds;
-    // coalesced pass over the records (thread t takes t, t + 1024, ...): the totals, and
-    // the child counts into LDS
-    unsigned long long f = 0, nv = 0, tt = 0;
+    constexpr int kThreads = 64 * kWavesPerBlock;
+    __shared__ unsigned long long s_tot[4][kWavesPerBlock];
+    __shared__ double s_pow[kWavesPerBlock];
+    const int nb = ws.n_waves / kWavesPerBlock, lane = lane_id(), wv = (int)threadIdx.x >> 6;
+    unsigned long long t[4] = {0, 0, 0, 0};
     double p = 0.0;
-    constexpr int kUnroll = 8;  // records per thread whose loads are issued together
-    for (int w0 = t; w0 < W; w0 += kUnroll * 1024) {
-        unsigned long long cv[kUnroll], fv[kUnroll], nvv[kUnroll], ttv[kUnroll];
-        double pv[kUnroll];
+    for (int b = threadIdx.x; b < nb; b += kThreads) {
 #pragma unroll
-        for (int k = 0; k < kUnroll; ++k) {
-            const int w = w0 + k * 1024;
-            const bool ok = w < W;
-            cv[k] = ok ? ws.children[w] : 0ull;
-            fv[k] = ok ? ws.stats[3 * w] : 0ull;
-            nvv[k] = ok ? ws.stats[3 * w + 1] : 0ull;
-            ttv[k] = ok ? ws.stats[3 * w + 2] : 0ull;
-            pv[k] = ok ? ws.power[w] : 0.0;
-        }
-#pragma unroll
-        for (int k = 0; k < kUnroll; ++k) {
-            const int w = w0 + k * 1024;
-            if (w < W) {
-                if (in_lds) s_child[w] = (unsigned)cv[k];
-                f += fv[k];
-                nv += nvv[k];
-                tt += ttv[k];
-                p += pv[k];
-            }
-        }
+        for (int k = 0; k < 4; ++k) t[k] += ws.block_rec[4 * (long long)b + k];
+        p += ws.block_power[b];
     }
-    __syncthreads();
-    // thread t's contiguous records [t per, t per + per) for the scan
-    const int per = (W + 1023) / 1024;
-    const int b0 = t * per, b1 = min(b0 + per, W);
-    unsigned long long c = 0;
-    for (int w = b0; w < b1; ++w) c += in_lds ? (unsigned long long)s_child[w] : ws.children[w];
-    // block-wide exclusive scan of the per-thread child counts: within the wave by
-    // shuffles, across the 16 waves through LDS
-    unsigned long long incl = c;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const unsigned long long u = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += u;
-    }
-    const unsigned long long sf = wave_sum_u64(f), snv = wave_sum_u64(nv), stt = wave_sum_u64(tt);
-    const double sp = wave_sum_f64(p);
-    if (lane == 63) wtot[wv] = incl;
+    for (int k = 0; k < 4; ++k) t[k] = wave_sum_u64(t[k]);
+    p = wave_sum_f64(p);
     if (lane == 0) {
-        wred[0][wv] = sf;
-        wred[1][wv] = snv;
-        wred[2][wv] = stt;
-        wpow[wv] = sp;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s_tot[k][wv] = t[k];
+        s_pow[wv] = p;
     }
     __syncthreads();
-    unsigned long long run = incl - c, total = 0;
-    for (int k = 0; k < 16; ++k) {
-        if (k < wv) run += wtot[k];
-        total += wtot[k];
-    }
-    if (in_lds && total < (1ull << 32)) {
-        // offsets through LDS (each thread turns its own records' counts into offsets),
-        // then stored coalesced
-        for (int w = b0; w < b1; ++w) {
-            const unsigned cw = s_child[w];
-            s_child[w] = (unsigned)run;
-            run += cw;
-        }
-        __syncthreads();
-        for (int w = t; w < W; w += 1024) ws.offset[w] = s_child[w];
-    } else {
-        for (int w = b0; w < b1; ++w) {
-            ws.offset[w] = run;
-            run += in_lds ? (unsigned long long)s_child[w] : ws.children[w];
-        }
-    }
-    // the generation's totals, summed over the waves in order
-    if (t == 0) {
-        unsigned long long tc = 0, tf = 0, tn = 0, ttt = 0;
+    if (threadIdx.x == 0) {
+        unsigned long long tt[4] = {0, 0, 0, 0};
         double tp = 0.0;
-        for (int k = 0; k < 16; ++k) {
-            tc += wtot[k];
-            tf += wred[0][k];
-            tn += wred[1][k];
-            ttt += wred[2][k];
-            tp += wpow[k];
+        for (int w = 0; w < kWavesPerBlock; ++w) {
+            for (int k = 0; k < 4; ++k) tt[k] += s_tot[k][w];
+            tp += s_pow[w];
         }
-        ctr->count[a.gen + 1] = tc;
-        ctr->flagged[a.gen] = tf;
+        ctr->count[a.gen + 1] = tt[0];
+        ctr->flagged[a.gen] = tt[1];
         ctr->power[a.gen] = tp;
-        ctr->node_visits += tn;
-        ctr->tri_tests += ttt;
+        ctr->node_visits += tt[2];
+        ctr->tri_tests += tt[3];
     }
+}
+
+// First queue position, in the next generation, of this wave's children: the children of
+// the blocks before this one (k_tcount's block records, summed by the whole block, their
+// loads issued together) and of this block's earlier waves.  Children keep the order of
+// the waves, so the next generation's order is deterministic.
+__device__ unsigned long long child_offset(const WaveScratch &ws)
+{
+    constexpr int kThreads = 64 * kWavesPerBlock;
+    constexpr int kUnroll = 4;
+    __shared__ unsigned long long s_part[kWavesPerBlock], s_wc[kWavesPerBlock];
+    const int lane = lane_id(), wv = (int)threadIdx.x >> 6;
+    const int nb = (int)blockIdx.x;
+    unsigned long long part = 0;
+    for (int b0 = threadIdx.x; b0 < nb; b0 += kUnroll * kThreads) {
+        unsigned long long v[kUnroll];
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k)
+            v[k] = b0 + k * kThreads < nb ? ws.block_rec[4 * (long long)(b0 + k * kThreads)] : 0ull;
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) part += v[k];
+    }
+    part = wave_sum_u64(part);
+    if (lane == 0) {
+        s_part[wv] = part;
+        s_wc[wv] = ws.children[(long long)nb * kWavesPerBlock + wv];
+    }
+    __syncthreads();
+    unsigned long long off = 0;
+    for (int k = 0; k < kWavesPerBlock; ++k) off += s_part[k] + (k < wv ? s_wc[k] : 0ull);
+    return off;
 }
 
 // Specular reflection without splitting: every hit with depth < max_depth (and, when set,
 // power above e_min) spawns one child mirrored in the hit triangle's plane (apex, edge and
 // guiding directions; d1 and d2 swapped to keep det > 0), starting at the hit point with
 // K (1 - alpha).  Children are compacted into the next generation with a wave ballot and
-// a popcount prefix from the wave's offset (k_gen_scan).  When the set classifies its
-// beams, each child's planar microphone class is written while it is in registers.
-__global__ void __launch_bounds__(256) k_reflect(DevMesh M, DevQueue q, DevSegs segs, DevCounters *ctr, TraceArgs a,
-                                                 WaveScratch ws)
+// a popcount prefix from the wave's offset.  When the set classifies its beams, each
+// child's planar microphone class is written while it is in registers.  Block 0 also
+// writes the generation's totals (the next generation's size among them).
+__global__ void __launch_bounds__(64 * kWavesPerBlock) k_reflect(DevMesh M, DevQueue q, DevSegs segs,
+                                                                 DevCounters *ctr, TraceArgs a, WaveScratch ws)
 {
     const unsigned long long n = ctr->count[a.gen];
     const long long s0 = (long long)gen_start(ctr, a.gen);
@@ -912,9 +895,10 @@ __global__ void __launch_bounds__(256) k_reflect(DevMesh M, DevQueue q, DevSegs 
     const int lane = lane_id();
     const DevQueue &in = q, &out = q;
     const long long icap = q.cap, ocap = q.cap;
+    if (blockIdx.x == 0) generation_totals(ctr, a, ws);
     // this wave's children go to [offset, offset + children) of the next generation, in
     // batch order (the same static partition as k_trace, which counted them)
-    unsigned long long obase = ws.offset[wave_first_batch() >> 6];
+    unsigned long long obase = child_offset(ws);
     for (unsigned long long base = wave_first_batch(); base < n; base += wave_batch_stride()) {
         const long long i = s0 + (long long)base + lane;
         int child = 0, hit = -1, meta = 0;
@@ -999,14 +983,12 @@ hipError_t launch_trace(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters 
             k_ttrace<<<blocks, kTraceBlock, 0, s>>>(m, q, segs, ctr, a, ws, *tw, r + 1 == tw->rounds);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
-        k_tcount<<<blocks, 256, 0, s>>>(m, q, segs, ctr, a, ws);
+        k_tcount<<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, a, ws);
     } else {
         k_trace<<<blocks, kTraceBlock, 0, s>>>(m, q, segs, ctr, a, ws);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        k_tcount<<<blocks, 256, 0, s>>>(m, q, segs, ctr, a, ws);
+        k_tcount<<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, a, ws);
     }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_gen_scan<<<1, 1024, 0, s>>>(ctr, a, ws);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_reflect<<<blocks, 64 * kWavesPerBlock, 0, s>>>(m, q, segs, ctr, a, ws);
     return hipGetLastError();
