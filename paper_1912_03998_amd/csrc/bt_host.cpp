@@ -1043,6 +1043,8 @@ void beams_release(bt_beams *b)
     dev_free(ctx, b->layers, (size_t)b->layers_cap * sizeof(int2));
     b->layers = nullptr;
     b->layers_cap = 0;
+    dev_free(ctx, b->layer_cnt, (size_t)kLayerRegions * kLayerCntStride * sizeof(unsigned));
+    b->layer_cnt = nullptr;
     b->work_n0 = 0;
     dev_free(ctx, b->tw_buf, b->tw_bytes);
     b->tw_buf = nullptr;
@@ -1129,6 +1131,9 @@ static bt_status reserve_layers(bt_ctx *ctx, bt_beams *b)
     dev_free(ctx, b->layers, (size_t)b->layers_cap * sizeof(int2));
     b->layers = nullptr;
     b->layers_cap = 0;
+    if (!b->layer_cnt &&
+        dev_alloc(ctx, (void **)&b->layer_cnt, (size_t)kLayerRegions * kLayerCntStride * sizeof(unsigned)) != BT_OK)
+        return BT_ENOMEM;
     bt_status s = dev_alloc(ctx, (void **)&b->layers, (size_t)want * sizeof(int2));
     if (s != BT_OK) return s;
     b->layers_cap = want;
@@ -1465,10 +1470,8 @@ extern "C" bt_status bt_beams_stats(bt_ctx *ctx, const bt_beams *b, bt_stats *ou
         out->mic_updates += (int64_t)mic_stat_total(h, MS_UPDATES);
         out->mic_layer_visits += (int64_t)mic_stat_total(h, MS_LAYERS);
         out->mic_classified += (int64_t)mic_stat_total(h, MS_CLASSIFIED);
-        for (int g = 0; g <= BT_MAX_DEPTH; ++g) {
-            out->mic_general += (int64_t)h.n_layers[g];
-            if ((long long)h.n_layers[g] > q->layers_cap) out->mic_fallback += (int64_t)h.n_layers[g] - q->layers_cap;
-        }
+        for (int g = 0; g <= BT_MAX_DEPTH; ++g) out->mic_general += (int64_t)h.n_layers[g];
+        out->mic_fallback += (int64_t)mic_stat_total(h, MS_LAYER_FALLBACK);
     }
     // earlier source chunks of a bt_run
     const bt_stats &q = b->prior;
@@ -1770,7 +1773,7 @@ static bt_status accumulate_enqueue(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *
         HIP_TRY(ctx, launch_mics_points(mesh->dev, b->q, b->segs, b->ctr, mics->dev, mics->pts, a, ctx->n_cu, st));
     } else {
         MicWork w{b->rows, b->rows_cap, b->spans, b->spans_cap, b->big_list + b->cap, b->big_list, b->layers,
-                  b->layers_cap};
+                  b->layers_cap, b->layer_cnt};
         HIP_TRY(ctx, launch_mics(mesh->dev, b->q, b->segs, b->ctr, mics->dev, a, w, b->ws, ctx->n_cu, st));
     }
     b->acc_gen = b->gen;
@@ -1845,7 +1848,8 @@ extern "C" bt_status bt_accumulate_mics_static(bt_ctx *ctx, const bt_mesh *mesh,
             ws.general = (unsigned *)base;
             int *lists = (int *)(base + kStaticListsOffset);
             MicWork w{(int2 *)(base + kStaticRowsOffset), kStaticRows, (int4 *)(base + kStaticSpansOffset),
-                      kStaticSpans, lists + n_bound, lists, (int2 *)(base + kStaticLayersOffset), kStaticLayers};
+                      kStaticSpans, lists + n_bound, lists, (int2 *)(base + kStaticLayersOffset), kStaticLayers,
+                      (unsigned *)(base + kStaticLayerCntOffset)};
             HIP_TRY(ctx, launch_mics(mesh->dev, q->q, q->segs, q->ctr, mics->dev, a, w, ws, ctx->n_cu, ctx->stream));
         }
         q->acc_gen = q->gen;

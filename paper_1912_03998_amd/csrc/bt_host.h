@@ -89,6 +89,7 @@ struct bt_beams {
     size_t tw_bytes = 0;
     int2 *layers = nullptr;   // volumetric grids: (segment, layer) items, allocated on first use
     long long layers_cap = 0;
+    unsigned *layer_cnt = nullptr;  // their regions' reservation counters
     long long work_n0 = 0;    // generation-0 size the work buffers were sized for
     int acc_gen = 0;          // first generation not yet accumulated at the microphones
     int depth_hint = 0;       // max_depth of the previous run, to size the queue at emission

@@ -103,7 +103,7 @@ struct DevSegs {
 // cost a microphone pass about 0.15 ms).
 constexpr int kStatSlots = 256;
 constexpr int kStatStride = 16;   // 128 bytes per slot
-enum { MS_TESTS = 0, MS_UPDATES = 1, MS_LAYERS = 2, MS_CLASSIFIED = 3 };
+enum { MS_TESTS = 0, MS_UPDATES = 1, MS_LAYERS = 2, MS_CLASSIFIED = 3, MS_LAYER_FALLBACK = 4 };
 
 // Device-side counters of one beam set, zeroed at emission.
 struct DevCounters {
@@ -113,11 +113,13 @@ struct DevCounters {
     unsigned long long n_big[BT_MAX_DEPTH + 2];      // segments for the wave-per-segment fallback
     unsigned long long n_spans[BT_MAX_DEPTH + 2];    // (segment, row, columns) work items
     unsigned long long n_layers[BT_MAX_DEPTH + 2];   // volumetric: (segment, layer) items requested
+                                                     // by the pass starting at this generation
     unsigned long long node_visits, tri_tests;
     unsigned long long ring;                         // two-slot layout: slot size (0 = resident)
     // microphone statistics per slot: MS_TESTS (segment, microphone) candidates tested,
     // MS_UPDATES contributions, MS_LAYERS volumetric (segment, layer) pairs examined,
-    // MS_CLASSIFIED segments whose planar class was read from their record
+    // MS_CLASSIFIED segments whose planar class was read from their record,
+    // MS_LAYER_FALLBACK volumetric items done in place (their region of the buffer full)
     alignas(128) unsigned long long mic_stat[kStatSlots][kStatStride];
 };
 // Sum of one microphone statistic over the slots (host).
@@ -168,9 +170,17 @@ struct MicWork {
     long long spans_cap;
     int *general;      // segments for the general footprint path; capacity: the queue's
     int *big_list;     // capacity: the queue capacity
-    int2 *layers;      // volumetric grids: (segment, layer) items of the general path
-    long long layers_cap;
+    int2 *layers;      // volumetric grids: (segment, layer) items of the general path, in
+    long long layers_cap;  // kLayerRegions regions of layers_cap / kLayerRegions items
+    unsigned *layer_cnt;   // [kLayerRegions][kLayerCntStride]: items requested per region in
+                           // this pass (element 0 of each 128-byte line), zeroed per pass
 };
+// The volumetric pass's (segment, layer) items go to one of kLayerRegions regions of the
+// item buffer, chosen by the producing wave's block, each with a reservation counter on a
+// cache line of its own: thousands of waves reserving on one shared counter serialise on
+// its address.
+constexpr int kLayerRegions = 256;
+constexpr int kLayerCntStride = 32;
 
 // Per-wave records of the statically partitioned kernels (wave w of a grid of W waves
 // takes the batches w, w + W, ...), so that counts and offsets need no shared atomic:
@@ -309,6 +319,7 @@ hipError_t launch_fill(double *p, long long n, double v, hipStream_t s);
 //   rows:   kStaticRows int2              (segment, row) items (overflow: wave path)
 //   spans:  kStaticSpans int4             (segment, row, columns) items (full: in place)
 //   layers: kStaticLayers int2            volumetric (segment, layer) items (full: in place)
+//   layer counters: kLayerRegions x kLayerCntStride unsigned
 //   lists:  the rest, as ints             wave-path list (n) then general list (n + 64 (W + 1))
 // Nothing in it needs to start at zero: every count lives in the beam set's counters.
 constexpr size_t kStaticScratchBytes = 64ull << 20;
@@ -320,7 +331,8 @@ constexpr long long kStaticLayers = 1ll << 19;
 constexpr size_t kStaticRowsOffset = kStaticCountBytes;
 constexpr size_t kStaticSpansOffset = kStaticRowsOffset + (size_t)kStaticRows * 8;
 constexpr size_t kStaticLayersOffset = kStaticSpansOffset + (size_t)kStaticSpans * 16;
-constexpr size_t kStaticListsOffset = kStaticLayersOffset + (size_t)kStaticLayers * 8;
+constexpr size_t kStaticLayerCntOffset = kStaticLayersOffset + (size_t)kStaticLayers * 8;
+constexpr size_t kStaticListsOffset = kStaticLayerCntOffset + (size_t)kLayerRegions * kLayerCntStride * 4;
 constexpr long long kStaticListInts = (long long)((kStaticScratchBytes - kStaticListsOffset) / sizeof(int));
 static_assert(kStaticListsOffset % 256 == 0, "static work area sections stay aligned");
 // Device address of the calling thread's current device's static work area (looked up

@@ -969,7 +969,12 @@ __global__ void __launch_bounds__(64, 4) k_mics3d(DevMesh M, DevQueue q, DevSegs
     const unsigned long long s0 = gen_start(ctr, a.gen);
     const unsigned long long n = gen_count(ctr, a.gen, a.gen_end);
     const int lane = lane_id();
-    unsigned tests = 0, updates = 0, visits = 0;
+    // this wave's region of the item buffer and its reservation counter
+    const int region = (int)(blockIdx.x % kLayerRegions);
+    const long long rcap = w.layers_cap / kLayerRegions;
+    int2 *const items = w.layers + (long long)region * rcap;
+    unsigned *const rcnt = w.layer_cnt + region * kLayerCntStride;
+    unsigned tests = 0, updates = 0, visits = 0, in_place = 0;
     for (unsigned long long base = (unsigned long long)blockIdx.x * kVolSeg; base < n;
          base += (unsigned long long)gridDim.x * kVolSeg) {
         // stage the batch's segments (lanes 0..kVolSeg-1) and count their layers
@@ -1029,23 +1034,25 @@ __global__ void __launch_bounds__(64, 4) k_mics3d(DevMesh M, DevQueue q, DevSegs
                 k = st.k0[slot] + (p - st.prefix[slot]);
                 kind = layer_fast(st, slot, mc, k, i0, i1, j0, j1);
             }
-            // clipped-footprint pairs become items (wave-aggregated reservation)
+            // clipped-footprint pairs become items of the wave's region (wave-aggregated
+            // reservation on the region's counter)
             const bool gen_item = kind == 2;
             const unsigned long long gm = __ballot(gen_item);
-            unsigned long long gb = 0;
-            if (lane == 0 && gm) gb = atomicAdd(&ctr->n_layers[a.gen], (unsigned long long)__popcll(gm));
+            unsigned gb = 0;
+            if (lane == 0 && gm) gb = atomicAdd(rcnt, (unsigned)__popcll(gm));
             gb = __shfl(gb, 0, 64);
             if (gen_item) {
                 const unsigned below = __builtin_amdgcn_mbcnt_hi((unsigned)(gm >> 32),
                                                                  __builtin_amdgcn_mbcnt_lo((unsigned)gm, 0u));
-                const unsigned long long e = gb + (unsigned long long)below;
+                const long long e = (long long)gb + (long long)below;
                 const long long seg = (long long)(s0 + base) + slot;
-                if (e < (unsigned long long)w.layers_cap) {
-                    w.layers[e] = make_int2((int)seg, k);
+                if (e < rcap) {
+                    items[e] = make_int2((int)seg, k);
                 } else {
-                    Frustum f;  // the item buffer is full: done here
+                    Frustum f;  // the region is full: done here
                     unstage_frustum(st, slot, a.delta, f);
                     layer_general(f, mc, w, ctr, a, seg, k, tests, updates);
+                    in_place++;
                 }
             }
             // candidates of the lattice boxes, 64 at a time
@@ -1074,8 +1081,11 @@ __global__ void __launch_bounds__(64, 4) k_mics3d(DevMesh M, DevQueue q, DevSegs
         __syncthreads();
     }
     flush_mic_counters(ctr, tests, updates);
-    const unsigned long long sv = wave_sum_u64(visits);
-    if (lane == 0) add_mic_stat(ctr, MS_LAYERS, sv);
+    const unsigned long long sv = wave_sum_u64(visits), sp = wave_sum_u64(in_place);
+    if (lane == 0) {
+        add_mic_stat(ctr, MS_LAYERS, sv);
+        if (sp) add_mic_stat(ctr, MS_LAYER_FALLBACK, sp);
+    }
 }
 
 // LDS staging of one wave of k_mics3d_general: kVolSeg (segment, layer) items with their
@@ -1173,15 +1183,23 @@ __global__ void __launch_bounds__(64, 3) k_mics3d_general(DevMesh M, DevQueue q,
                                                           DevMics mc, TraceArgs a, MicWork w)
 {
     __shared__ GenStage st;
-    unsigned long long n = ctr->n_layers[a.gen];
-    if (n > (unsigned long long)w.layers_cap) n = (unsigned long long)w.layers_cap;
+    // wave b takes region b mod kLayerRegions, with the other waves of that region (the
+    // grid has at least kLayerRegions waves, one per block)
+    const int region = (int)(blockIdx.x % kLayerRegions);
+    const unsigned sub = blockIdx.x / kLayerRegions;
+    const unsigned nsub = (gridDim.x - (unsigned)region + kLayerRegions - 1) / kLayerRegions;
+    const long long rcap = w.layers_cap / kLayerRegions;
+    const unsigned requested = w.layer_cnt[region * kLayerCntStride];
+    const unsigned long long n = (long long)requested < rcap ? requested : (unsigned long long)rcap;
+    const int2 *const items = w.layers + (long long)region * rcap;
     const int lane = lane_id();
+    if (sub == 0 && lane == 0 && requested) atomicAdd(&ctr->n_layers[a.gen], (unsigned long long)requested);
     unsigned tests = 0, updates = 0;
-    for (unsigned long long base = (unsigned long long)blockIdx.x * kVolSeg; base < n;
-         base += (unsigned long long)gridDim.x * kVolSeg) {
+    for (unsigned long long base = (unsigned long long)sub * kVolSeg; base < n;
+         base += (unsigned long long)nsub * kVolSeg) {
         int nrows = 0;
         if (lane < kVolSeg && base + (unsigned long long)lane < n) {
-            const int2 it = w.layers[base + lane];
+            const int2 it = items[base + lane];
             Frustum f{};
             load_frustum(M, q, segs, it.x, a.delta, f);
             HalfPlane L[9];
@@ -1530,12 +1548,14 @@ hipError_t launch_mics(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *
 {
     if (!a.scenarios && mics.nz > 1) {
         if (!(mics.dz > 0.0)) return hipErrorInvalidValue;
-        if (!w.layers || w.layers_cap <= 0) return hipErrorInvalidValue;
+        if (!w.layers || w.layers_cap <= 0 || !w.layer_cnt) return hipErrorInvalidValue;
+        // the regions' reservation counters start at zero in every pass
+        hipError_t e = launch_zero_ints((int *)w.layer_cnt, (long long)kLayerRegions * kLayerCntStride, s);
+        if (e != hipSuccess) return e;
         // one wave per block: a block's LDS is its wave's staging area
         k_mics3d<<<n_cu * 16, 64, 0, s>>>(m, q, segs, ctr, mics, a, w);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        k_mics3d_general<<<n_cu * 12, 64, 0, s>>>(m, q, segs, ctr, mics, a, w);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        k_mics3d_general<<<std::max(n_cu * 12, kLayerRegions), 64, 0, s>>>(m, q, segs, ctr, mics, a, w);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         k_mic_spans<false><<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
         return hipGetLastError();

@@ -132,9 +132,11 @@ def test_volumetric_work_list_overflow(torch_cuda, monkeypatch, env, value):
         g = gpu_run(s, sc)
     verdict(g, o)
     assert g.stats["mic_layer_visits"] > 0 and g.stats["mic_general"] > 0
-    if env == "BT_MIC_LAYER_CAPACITY":   # the in-place path did run (in every pass whose items overflowed)
+    if env == "BT_MIC_LAYER_CAPACITY":
+        # the in-place path did run: the buffer holds at most `value` items (its regions
+        # of value // 256 items each), the rest were done where they were found
         assert g.stats["mic_general"] > int(value)
-        assert 0 < g.stats["mic_fallback"] <= g.stats["mic_general"] - int(value)
+        assert g.stats["mic_general"] - int(value) <= g.stats["mic_fallback"] < g.stats["mic_general"]
 
 
 @pytest.fixture(scope="module")
