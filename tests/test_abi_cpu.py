@@ -44,6 +44,18 @@ def test_host_only_helpers():
     assert bt.lib().bt_last_error(None) == b"null context"
 
 
+def test_null_context_calls_are_refused():
+    """Entry points given no context return BT_EINVAL before touching any device."""
+    if not os.path.exists(bt.LIB_PATH):
+        pytest.skip("libbt.so not built")
+    L = bt.lib()
+    p = bt.bt_params_default()
+    assert L.bt_set_partitions(None, 2) == -1
+    assert L.bt_trace_all(None, None, None, C.byref(p)) == -1
+    assert L.bt_trace(None, None, None, C.byref(p), None) == -1
+    assert L.bt_accumulate_mics(None, None, None, C.byref(p), None) == -1
+
+
 def _c_layout(struct, fields, tmp_path):
     """sizeof and offsetof of a bt.h struct, from a gcc-compiled probe."""
     src = tmp_path / "probe.c"
