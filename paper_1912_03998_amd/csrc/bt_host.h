@@ -79,6 +79,8 @@ struct bt_beams {
     WaveScratch ws{};         // per-wave records of the statically partitioned kernels
     void *ws_buf = nullptr;
     size_t ws_bytes = 0;
+    int ws_cap_waves = 0;     // waves the per-wave arrays (and the lists sized per wave) hold;
+                              // the grid in use, ws.n_waves, may be smaller
     int *big_list = nullptr;  // 2 * cap: wave-path overflow list, then the general-path list
     int2 *rows = nullptr;
     long long rows_cap = 0;
