@@ -1514,7 +1514,9 @@ hipError_t launch_mics_points(const DevMesh &m, DevQueue q, DevSegs segs, DevCou
                               DevPoints pts, const TraceArgs &a, int n_cu, hipStream_t s)
 {
     if (a.scenarios || pts.n <= 0 || pts.nbx <= 0 || pts.nby <= 0) return hipErrorInvalidValue;
-    k_mics_points<<<n_cu * 12, 64, 0, s>>>(m, q, segs, ctr, mics, pts, a);
+    // eight times the resident waves, as the volumetric pass (100,000 district receivers:
+    // 9.5 ms per pass at n_cu x 12 one-wave blocks, 8.0 at x 96)
+    k_mics_points<<<n_cu * 96, 64, 0, s>>>(m, q, segs, ctr, mics, pts, a);
     return hipGetLastError();
 }
 
@@ -1552,10 +1554,14 @@ hipError_t launch_mics(const DevMesh &m, DevQueue q, DevSegs segs, DevCounters *
         // the regions' reservation counters start at zero in every pass
         hipError_t e = launch_zero_ints((int *)w.layer_cnt, (long long)kLayerRegions * kLayerCntStride, s);
         if (e != hipSuccess) return e;
-        // one wave per block: a block's LDS is its wave's staging area
-        k_mics3d<<<n_cu * 16, 64, 0, s>>>(m, q, segs, ctr, mics, a, w);
+        // one wave per block: a block's LDS is its wave's staging area.  A wave's batches
+        // differ widely in work (layers per segment, candidates per layer), so the grid is
+        // eight times what is resident at once: waves that finish early leave room for the
+        // rest (tall district: 129 ms per step at n_cu x 16 one-wave blocks, 110 at x 128,
+        // 111 at x 512)
+        k_mics3d<<<n_cu * 128, 64, 0, s>>>(m, q, segs, ctr, mics, a, w);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        k_mics3d_general<<<std::max(n_cu * 12, kLayerRegions), 64, 0, s>>>(m, q, segs, ctr, mics, a, w);
+        k_mics3d_general<<<std::max(n_cu * 96, kLayerRegions), 64, 0, s>>>(m, q, segs, ctr, mics, a, w);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         k_mic_spans<false><<<n_cu * 8, 256, 0, s>>>(m, q, segs, ctr, mics, a, w);
         return hipGetLastError();
