@@ -278,7 +278,7 @@ def points_bench(sess, scene, n_points=100_000, steps=3, seed=0):
             "index_build_s": round(index_s, 3)}
 
 
-def volumetric_bench(steps, warmup, chunk=7, level=8, oracle_sample=True):
+def volumetric_bench(steps, warmup, chunk=7, level=8, oracle_sample=True, partitions=2):
     """The paper's experiment shape: the tall 2.5 x 1.5 km district (towers of 200 m and
     more), 49 street sources x 20 * 4**level beams, depth 8, microphones every 4 m filling
     the bounding box.  A step traces all sources, `chunk` sources per beam set (the queue
@@ -298,6 +298,7 @@ def volumetric_bench(steps, warmup, chunk=7, level=8, oracle_sample=True):
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     ctx, mesh, stream = sess.ctx, sess.mesh, sess.stream
+    bt.bt_set_partitions(ctx, partitions)
     mics = sess._mics(scene_grid(scene))
     params = sess.params(scene.depth)
     with torch.cuda.stream(stream):
@@ -314,8 +315,7 @@ def volumetric_bench(steps, warmup, chunk=7, level=8, oracle_sample=True):
             sess.beams = bt.bt_emit_beams(ctx, src[g], pw[g], scene.level, sess.beams)
             if ev is not None:
                 ev[gi][0].record(stream)
-            for _ in range(scene.depth + 1):
-                bt.bt_trace(ctx, mesh, sess.beams, params)
+            bt.bt_trace_all(ctx, mesh, sess.beams, params)
             if ev is not None:
                 ev[gi][1].record(stream)
             bt.bt_accumulate_mics(ctx, mesh, sess.beams, params, mics)
@@ -345,6 +345,7 @@ def volumetric_bench(steps, warmup, chunk=7, level=8, oracle_sample=True):
                     f"(icosphere level {level}), depth {scene.depth}, {scene.mic_nx} x {scene.mic_ny} x "
                     f"{scene.mic_nz} = {scene.n_mic} microphones (4 m lattice filling the bounding box), "
                     f"{len(groups)} beam sets of <= {chunk} sources",
+        "step_call": f"per beam set: bt_emit_beams ({partitions} partitions), bt_trace_all, bt_accumulate_mics",
         "ms_per_step": round(elapsed * 1000.0 / steps, 2),
         "beam_segments_per_s": totals["segments"] * steps / elapsed,
         "mic_updates_per_s": totals["mic_updates"] * steps / elapsed,
@@ -387,8 +388,7 @@ def main():
                          "every segment's planar class from its frustum")
     ap.add_argument("--run-call", action="store_true",
                     help="time each step as one bt_run call (source chunks, two generation slots, a microphone "
-                         "pass per generation) instead of bt_emit_beams, bt_trace per generation and one "
-                         "bt_accumulate_mics")
+                         "pass per generation) instead of bt_emit_beams, bt_trace_all and one bt_accumulate_mics")
     ap.add_argument("--partitions", type=int, default=2,
                     help="partitions of the beam set (bt_set_partitions): the sources split into this many groups, "
                          "each traced and accumulated on a stream of its own (1 = one stream)")
@@ -455,7 +455,8 @@ def main():
 
     if args.volumetric_only:
         print(json.dumps(volumetric_bench(args.steps, args.warmup, args.vol_chunk, args.vol_level,
-                                          oracle_sample=not args.no_cpu_baseline)), flush=True)
+                                          oracle_sample=not args.no_cpu_baseline, partitions=args.partitions)),
+              flush=True)
         return
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -624,7 +625,8 @@ def main():
     sess.close()
     if args.config == 2 and not args.no_volumetric:
         out["volumetric"] = volumetric_bench(max(2, min(args.steps, 5)), max(1, min(args.warmup, 2)), args.vol_chunk,
-                                             args.vol_level, oracle_sample=not args.no_cpu_baseline)
+                                             args.vol_level, oracle_sample=not args.no_cpu_baseline,
+                                             partitions=args.partitions)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scene)
