@@ -6,6 +6,9 @@
 // launches, one microphone pass sends each segment's contributions to its own scenario's
 // grid arrays, and a gather kernel collects each scenario's outputs.  All sizes a chunk's
 // kernels need are read from device memory, so one captured hipGraph serves every chunk.
+// Two workspaces take the chunks in turn on two of the context's partition streams: while
+// one chunk's last, sparse generations drain, the next chunk's tables are filled on the
+// host and its launches run beside them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -64,6 +67,9 @@ struct BatchWork {
     hipGraphExec_t exec = nullptr;
     int graph_depth = -1;
     bt_params graph_params{};
+    hipStream_t stream = nullptr;   // the stream of the chunk in flight (if any)
+    hipEvent_t done = nullptr;      // recorded after the chunk's output copies
+    int pending = -1;               // the chunk in flight, its outputs not yet unpacked
 
     void drop_graph()
     {
@@ -76,6 +82,8 @@ struct BatchWork {
     void release()
     {
         if (ctx && ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+        if (stream) (void)hipStreamSynchronize(stream);
+        pending = -1;
         drop_graph();
         if (beams) bt_beams_free(beams);
         beams = nullptr;
@@ -86,7 +94,11 @@ struct BatchWork {
         cap_sources = cap_slots = cap_energy = cap_mask = cap_out = cap_n0 = cap_records = 0;
         bpc = 0;
     }
-    ~BatchWork() { release(); }
+    ~BatchWork()
+    {
+        release();
+        if (done) (void)hipEventDestroy(done);
+    }
     template <class T> bt_status dev(T **p, long long n)
     {
         const size_t bytes = (size_t)std::max(n, 1ll) * sizeof(T);
@@ -153,7 +165,7 @@ struct BatchWork {
 
 void batch_work_free(bt_ctx *ctx)
 {
-    delete ctx->batch;
+    delete[] ctx->batch;
     ctx->batch = nullptr;
 }
 
@@ -162,10 +174,10 @@ namespace {
 // The chunk's launches: counters, emission, zeroed energies, every generation's trace,
 // one microphone pass over all of them, the gather.  Grid sizes follow the capacities;
 // the kernels read the chunk's own sizes from device memory.
-bt_status enqueue_chunk(bt_ctx *ctx, const bt_mesh *mesh, BatchWork &w, const TraceArgs &base, int depth)
+bt_status enqueue_chunk(bt_ctx *ctx, const bt_mesh *mesh, BatchWork &w, const TraceArgs &base, int depth,
+                        hipStream_t s)
 {
     bt_beams *b = w.beams;
-    hipStream_t s = ctx->stream;
     const EmitTable t{w.src, w.power, w.level, w.meta, w.id0, w.first, w.dims};
     HIP_TRY(ctx, launch_init_counters(b->ctr, 0, 0, s));
     HIP_TRY(ctx, launch_emit_table(ctx->base20, t, w.cap_n0, b->q, b->ctr, 0, s));
@@ -240,23 +252,78 @@ bt_status run_batch(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *sc, int
         records = std::max(records, ch.records);
     }
     if (!ctx->batch) {
-        ctx->batch = new BatchWork();
-        ctx->batch->ctx = ctx;
+        ctx->batch = new BatchWork[2];
+        ctx->batch[0].ctx = ctx->batch[1].ctx = ctx;
     }
-    BatchWork &w = *ctx->batch;
-    if ((st = w.ensure(need, records, o.blocks_per_cu)) != BT_OK) {
-        w.release();
+    BatchWork *W = ctx->batch;
+    // two workspaces when there are two chunks or more (one if the second does not fit)
+    int n_slots = chunks.size() > 1 ? 2 : 1;
+    if ((st = W[0].ensure(need, records, o.blocks_per_cu)) != BT_OK) {
+        W[0].release();
         return st;
+    }
+    if (n_slots == 2 && W[1].ensure(need, records, o.blocks_per_cu) != BT_OK) {
+        W[1].release();
+        n_slots = 1;
+        ctx->err.clear();
+    }
+    hipStream_t streams[2] = {ctx->stream, ctx->stream};
+    if (n_slots == 2) {
+        HIP_TRY(ctx, partition_streams(ctx));
+        // the slots' streams start after everything enqueued on the context's stream so far
+        HIP_TRY(ctx, hipEventRecord(ctx->fork_ev, ctx->stream));
+        for (int k = 0; k < 2; ++k) {
+            streams[k] = ctx->part_stream[k];
+            HIP_TRY(ctx, hipStreamWaitEvent(streams[k], ctx->fork_ev, 0));
+        }
+    }
+    for (int k = 0; k < n_slots; ++k) {
+        if (!W[k].done) HIP_TRY(ctx, hipEventCreateWithFlags(&W[k].done, hipEventDisableTiming));
+        W[k].stream = streams[k];
+        W[k].pending = -1;
     }
     TraceArgs base = make_args(&p, 0);
     base.max_depth = depth;
     base.scenarios = 1;
-    base.slot_mics = w.slots;
-    hipStream_t s = ctx->stream;
-    if (w.exec && (w.graph_depth != depth || !same_physics(w.graph_params, p))) w.drop_graph();
     const auto t0 = std::chrono::steady_clock::now();
     long long segments = 0, updates = 0, beams0 = 0;
-    for (const Chunk &ch : chunks) {
+    // a finished chunk's outputs to the scenarios' buffers, and its counts
+    auto unpack = [&](BatchWork &w) -> bt_status {
+        if (w.pending < 0) return BT_OK;
+        HIP_TRY(ctx, hipEventSynchronize(w.done));
+        const Chunk &ch = chunks[(size_t)w.pending];
+        long long off = 0;
+        for (int k = ch.first; k < ch.end; ++k) {
+            std::memcpy(sc[k].energy_out, w.h_out + off, (size_t)z[k].n_out * sizeof(double));
+            if (sc[k].flag_out)
+                std::memcpy(sc[k].flag_out, w.h_out + w.cap_out + off, (size_t)z[k].n_out * sizeof(double));
+            off += z[k].n_out;
+        }
+        for (int g = 0; g <= depth; ++g) segments += (long long)w.h_ctr->count[g];
+        updates += (long long)mic_stat_total(*w.h_ctr, MS_UPDATES);
+        beams0 += ch.n0;
+        w.pending = -1;
+        return BT_OK;
+    };
+    // on any early return, the slots' streams are drained (their host buffers stay valid)
+    struct Drain {
+        BatchWork *w;
+        int n;
+        ~Drain()
+        {
+            for (int k = 0; k < n; ++k)
+                if (w[k].stream) (void)hipStreamSynchronize(w[k].stream);
+        }
+    } drain{W, n_slots};
+    for (size_t ci = 0; ci < chunks.size(); ++ci) {
+        const Chunk &ch = chunks[ci];
+        BatchWork &w = W[ci % (size_t)n_slots];
+        const hipStream_t s = w.stream;
+        // the slot's previous chunk must be finished before its pinned tables are refilled
+        if ((st = unpack(w)) != BT_OK) return st;
+        if (w.exec && (w.graph_depth != depth || !same_physics(w.graph_params, p))) w.drop_graph();
+        TraceArgs bw = base;
+        bw.slot_mics = w.slots;
         // emission table, slot microphone sets, subset masks and gather indices; the flag
         // energies follow the chunk's E strict ones
         long long E = 0;
@@ -326,7 +393,7 @@ bt_status run_batch(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *sc, int
         if (o.use_graph) {
             if (!w.exec) {
                 HIP_TRY(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                bt_status cs = enqueue_chunk(ctx, mesh, w, base, depth);
+                bt_status cs = enqueue_chunk(ctx, mesh, w, bw, depth, s);
                 hipGraph_t g = nullptr;
                 const hipError_t ce = hipStreamEndCapture(s, &g);
                 if (cs != BT_OK) {
@@ -340,7 +407,7 @@ bt_status run_batch(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *sc, int
                 w.graph_params = p;
             }
             HIP_TRY(ctx, hipGraphLaunch(w.exec, s));
-        } else if ((st = enqueue_chunk(ctx, mesh, w, base, depth)) != BT_OK) {
+        } else if ((st = enqueue_chunk(ctx, mesh, w, bw, depth, s)) != BT_OK) {
             return st;
         }
         if (ooff > 0) {
@@ -349,18 +416,11 @@ bt_status run_batch(bt_ctx *ctx, const bt_mesh *mesh, const bt_scenario *sc, int
                                         hipMemcpyDeviceToHost, s));
         }
         HIP_TRY(ctx, hipMemcpyAsync(w.h_ctr, w.beams->ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
-        HIP_TRY(ctx, hipStreamSynchronize(s));
-        ooff = 0;
-        for (int k = ch.first; k < ch.end; ++k) {
-            std::memcpy(sc[k].energy_out, w.h_out + ooff, (size_t)z[k].n_out * sizeof(double));
-            if (sc[k].flag_out)
-                std::memcpy(sc[k].flag_out, w.h_out + w.cap_out + ooff, (size_t)z[k].n_out * sizeof(double));
-            ooff += z[k].n_out;
-        }
-        for (int g = 0; g <= depth; ++g) segments += (long long)w.h_ctr->count[g];
-        updates += (long long)mic_stat_total(*w.h_ctr, MS_UPDATES);
-        beams0 += ch.n0;
+        HIP_TRY(ctx, hipEventRecord(w.done, s));
+        w.pending = (int)ci;
     }
+    for (int k = 0; k < n_slots; ++k)
+        if ((st = unpack(W[k])) != BT_OK) return st;
     if (stats) {
         stats->chunks = (int32_t)chunks.size();
         stats->beams0 = beams0;

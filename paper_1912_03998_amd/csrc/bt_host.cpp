@@ -1543,7 +1543,7 @@ TraceArgs make_args(const bt_params *p, int gen)
 // small kernel's fixed cost paid twice); the context's own stream, idle while they run,
 // may share a queue with one of them.
 // ---------------------------------------------------------------------------------------
-static hipError_t ensure_streams(bt_ctx *ctx)
+hipError_t partition_streams(bt_ctx *ctx)
 {
     if (ctx->fork_ev) return hipSuccess;
     hipError_t e = hipSuccess;
@@ -1574,7 +1574,7 @@ public:
     hipError_t begin()
     {
         if (n_ <= 1) return hipSuccess;
-        hipError_t e = ensure_streams(ctx_);
+        hipError_t e = partition_streams(ctx_);
         if (e != hipSuccess) return e;
         if ((e = hipEventRecord(ctx_->fork_ev, ctx_->stream)) != hipSuccess) return e;
         forked_ = true;   // from here on, join() orders the context's stream after every partition stream

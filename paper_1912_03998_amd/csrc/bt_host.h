@@ -35,7 +35,7 @@ struct bt_ctx {
     std::mutex mtx;            // submit / poll / cancel
     uint64_t next_ticket = 1;
     std::map<uint64_t, struct Request *> requests;
-    struct BatchWork *batch = nullptr;  // bt_batch_run's workspace, kept between calls
+    struct BatchWork *batch = nullptr;  // bt_batch_run's two workspaces ([2]), kept between calls
     double *face_dirs[BT_MAX_LEVEL + 1] = {};  // per icosphere level, built on first use
     double *face_om[BT_MAX_LEVEL + 1] = {};
     void *scratch = nullptr;   // this device's static work area (bt_accumulate_mics_static)
@@ -192,3 +192,6 @@ bt_status mics_fit(bt_ctx *ctx, bt_mics **m, float x0, float y0, float z, float 
 
 // Free bt_batch_run's cached workspace (bt_destroy, bt_batch_release).
 void batch_work_free(bt_ctx *ctx);
+
+// The context's partition streams (created together on first use, default priority).
+hipError_t partition_streams(bt_ctx *ctx);
