@@ -32,13 +32,19 @@ REF_WORK = os.path.join(ROOT, "oracle", "reference_work.json")
 B_BEAM, B_CHILD, B_HIT, B_NODE, B_TRI, B_MIC = 80, 80, 8, 64, 36, 16
 
 
+DEVICE_HEADERS = ("bt_device.h", "bt_internal.h")   # what the .hip files include besides include/bt.h
+
+
 def kernel_hash() -> str:
-    """Hash of the device sources (kernels and the headers they include)."""
+    """Hash of the device code: the kernel sources, the library headers they include and
+    the public header (host-only sources such as bt_host.h do not change it)."""
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".h")):
+        if name.endswith(".hip") or name in DEVICE_HEADERS:
             h.update(name.encode())
             h.update(open(os.path.join(CSRC, name), "rb").read())
+    h.update(b"bt.h")
+    h.update(open(os.path.join(ROOT, "include", "bt.h"), "rb").read())
     return h.hexdigest()[:16]
 
 
