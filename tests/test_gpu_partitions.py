@@ -255,3 +255,46 @@ def test_set_partitions_limits(sess, scene):
         res.append(sess.run(one.sources, one.power, one.level, one.depth, grid(one), parity=True))
     bt.bt_set_partitions(sess.ctx, 2)
     assert_same_run(res[0], res[1], "one source")
+
+
+@pytest.mark.parametrize("kind", ["volumetric", "points", "subset"])
+def test_partitions_with_other_microphone_sets(sess, scene, kind):
+    """A volumetric grid, explicit points and a grid subset: the partitions' microphone
+    passes run side by side on their streams (the volumetric pass with its item regions,
+    the point pass with its bucket index); 1 and 3 partitions give the same energies and
+    counters."""
+    from paper_1912_03998_amd import bt
+    res = {}
+    for k in (1, 3):
+        say(f"district mesh, six sources, {kind} microphones, {k} partitions")
+        bt.bt_set_partitions(sess.ctx, k)
+        if kind == "volumetric":
+            mics = bt.bt_mics_grid3d(sess.ctx, -200.0, -200.0, 1.5, 8.0, 8.0, 6.0, 50, 50, 6)
+            n_out = 50 * 50 * 6
+        elif kind == "points":
+            pts = np.random.default_rng(11).uniform([-300.0, -300.0, 1.5], [300.0, 300.0, 40.0],
+                                                   (5000, 3)).astype(np.float32)
+            mics = bt.bt_mics_points(sess.ctx, pts)
+            n_out = len(pts)
+        else:
+            grid_set = bt.bt_mics_grid(sess.ctx, *grid(scene))
+            idx = np.random.default_rng(11).choice(scene.n_mic, 2000, replace=False).astype(np.int32)
+            mics = bt.bt_mics_subset(sess.ctx, grid_set, idx)
+            bt.bt_mics_free(grid_set)
+            n_out = len(idx)
+        try:
+            p = sess.params(scene.depth)
+            beams = bt.bt_run(sess.ctx, sess.mesh, scene.sources, scene.power, scene.level, p, mics, None)
+            es, ef = np.zeros(n_out), np.zeros(n_out)
+            bt.bt_levels(sess.ctx, mics, es, ef, None)
+            st = bt.bt_beams_stats(sess.ctx, beams)
+            bt.bt_beams_free(beams)
+        finally:
+            bt.bt_mics_free(mics)
+        res[k] = (es, ef, st)
+    bt.bt_set_partitions(sess.ctx, 2)
+    (a_s, a_f, a_st), (b_s, b_f, b_st) = res[1], res[3]
+    assert (a_s + a_f).sum() > 0
+    assert same(a_s, b_s) and same(a_f, b_f)
+    for key in ("segments", "mic_tests", "mic_updates", "mic_layer_visits", "mic_general"):
+        assert a_st[key] == b_st[key], key
