@@ -226,7 +226,9 @@ bt_status bt_beams_stats(bt_ctx *ctx, const bt_beams *beams, bt_stats *out);
  * stay resident in device memory (n_beams0 * (max_depth + 1) records at most) until the
  * next emission.  n_next: NULL (no synchronisation) or host int64 receiving the next
  * generation's size (syncs).  Returns BT_ESTATE once max_depth + 1 generations have been
- * traced, BT_EINVAL if n_beams0 * (max_depth + 1) exceeds 2^31 - 1. */
+ * traced, or for a set that holds no emission (created by bt_beams_bind_mics and never
+ * emitted, or whose last emission failed after its arguments were accepted, e.g. out of
+ * memory: emit again); BT_EINVAL if n_beams0 * (max_depth + 1) exceeds 2^31 - 1. */
 bt_status bt_trace(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *beams, const bt_params *params,
                    int64_t *n_next);
 

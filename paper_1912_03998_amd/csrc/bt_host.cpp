@@ -1252,6 +1252,9 @@ static bt_status new_beams(bt_ctx *ctx, bt_beams **out)
     b->ctx = ctx;
     bt_status s = dev_alloc(ctx, (void **)&b->ctr, sizeof(DevCounters));
     if (s == BT_OK) s = alloc_wave_scratch(ctx, b, kBlocksPerCU);
+    // counters start at zero (no beams), so statistics of a set never emitted are zeros
+    if (s == BT_OK && launch_init_counters(b->ctr, 0, 0, ctx->stream) != hipSuccess)
+        s = hip_fail(ctx, hipGetLastError(), "launch_init_counters");
     if (s != BT_OK) {
         bt_beams_free(b);
         return s;
@@ -1358,6 +1361,7 @@ static bt_status emit_set(bt_ctx *ctx, bt_beams *b, const float *src_xyz, const 
     b->ring = two_slot ? std::max(n0, 1ll) : 0;
     b->prior = bt_stats{};
     b->r_src = r_src;
+    b->emitted = true;
     return BT_OK;
 }
 
@@ -1395,6 +1399,10 @@ static bt_status emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_
     // (measured on the district with two partitions: 4 workgroups per CU each 5.58 ms per
     // step, 8 each 5.80, 2 each 6.58)
     const int bpc = std::max(1, kBlocksPerCU / K);
+    // until every partition is emitted, the set holds no emission (a failed call leaves it
+    // so: it must be emitted again before it is traced)
+    b->emitted = false;
+    b->n_parts = 1;
     bt_status s = BT_OK;
     for (int k = 1; k < K && s == BT_OK; ++k) {
         if (!b->part[k - 1]) s = new_beams(ctx, &b->part[k - 1]);
@@ -1413,6 +1421,7 @@ static bt_status emit_beams(bt_ctx *ctx, const float *src_xyz, const float *src_
         q->beam0 = s0 * nf;
     }
     if (s != BT_OK) {
+        b->emitted = false;
         if (fresh) bt_beams_free(b);
         return s;
     }
@@ -1630,6 +1639,7 @@ static bt_params part_params(const bt_params *p, const bt_beams *b)
 // enqueued but the queue's growth on the context's stream.
 static bt_status trace_prepare(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *b, const bt_params *p)
 {
+    if (!b->emitted) return fail(ctx, BT_ESTATE, "the beam set holds no emission (emit beams first)");
     if (b->max_depth >= 0 && b->max_depth != p->max_depth)
         return fail(ctx, BT_EINVAL, "max_depth changed between generations (%d -> %d)", b->max_depth, p->max_depth);
     if (b->gen > p->max_depth) return fail(ctx, BT_ESTATE, "all %d generations already traced", p->max_depth + 1);
@@ -1801,6 +1811,7 @@ extern "C" bt_status bt_accumulate_mics(bt_ctx *ctx, const bt_mesh *mesh, bt_bea
     if (!mesh || !b || !mics) return fail(ctx, BT_EINVAL, "NULL mesh, beams or mics");
     bt_status s = check_params(ctx, mesh, p);
     if (s != BT_OK) return s;
+    if (!b->emitted) return fail(ctx, BT_ESTATE, "the beam set holds no emission (emit beams first)");
     if (b->gen == 0) return fail(ctx, BT_ESTATE, "no generation traced yet");
     if (b->acc_gen == b->gen) return BT_OK;  // nothing traced since the last call
     (void)hipSetDevice(ctx->device);
@@ -1827,6 +1838,7 @@ extern "C" bt_status bt_accumulate_mics_static(bt_ctx *ctx, const bt_mesh *mesh,
     if (!mesh || !b || !mics) return fail(ctx, BT_EINVAL, "NULL mesh, beams or mics");
     bt_status s = check_params(ctx, mesh, p);
     if (s != BT_OK) return s;
+    if (!b->emitted) return fail(ctx, BT_ESTATE, "the beam set holds no emission (emit beams first)");
     if (b->gen == 0) return fail(ctx, BT_ESTATE, "no generation traced yet");
     if (b->acc_gen == b->gen) return BT_OK;  // nothing traced since the last call
     if (!ctx->scratch) return fail(ctx, BT_EDEVICE, "no static work area on device %d", ctx->device);

@@ -120,6 +120,7 @@ struct bt_beams {
     int n_parts = 1;
     bt_beams *part[kMaxParts - 1] = {};
     long long beam0 = 0;
+    bool emitted = false;     // holds an emission (false when created, or after a failed one)
 };
 
 struct Request {

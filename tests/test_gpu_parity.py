@@ -428,6 +428,17 @@ def test_error_paths(torch_cuda):
         beams = bt.bt_emit_beams(ctx, [[0.2, 0.2, 1]], [1.0], 1)
         mics = bt.bt_mics_grid(ctx, 0, 0, 0.5, 0.25, 0.25, 4, 4)
         p = bt.bt_params_default(max_depth=1)
+        # a set created by binding and never emitted: nothing to trace or accumulate, and
+        # its statistics are zeros
+        unemitted = bt.bt_beams_bind_mics(ctx, None, mics)
+        for call in (lambda: bt.bt_trace(ctx, mesh, unemitted, p), lambda: bt.bt_trace_all(ctx, mesh, unemitted, p),
+                     lambda: bt.bt_accumulate_mics(ctx, mesh, unemitted, p, mics)):
+            with pytest.raises(bt.BTError) as e:
+                call()
+            assert e.value.status == -6
+        st0 = bt.bt_beams_stats(ctx, unemitted)
+        assert st0["segments"] == 0 and st0["generations"] == 0 and st0["node_visits"] == 0
+        bt.bt_beams_free(unemitted)
         with pytest.raises(bt.BTError) as e:
             bt.bt_accumulate_mics(ctx, mesh, beams, p, mics)
         assert e.value.status == -6
