@@ -228,7 +228,9 @@ bt_status bt_beams_stats(bt_ctx *ctx, const bt_beams *beams, bt_stats *out);
  * generation's size (syncs).  Returns BT_ESTATE once max_depth + 1 generations have been
  * traced, or for a set that holds no emission (created by bt_beams_bind_mics and never
  * emitted, or whose last emission failed after its arguments were accepted, e.g. out of
- * memory: emit again); BT_EINVAL if n_beams0 * (max_depth + 1) exceeds 2^31 - 1. */
+ * memory: emit again); BT_EINVAL if n_beams0 * (max_depth + 1) exceeds 2^31 - 1, or if
+ * the set's earlier generations were traced with another mesh (an emission's generations
+ * and their accumulation all use one mesh). */
 bt_status bt_trace(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *beams, const bt_params *params,
                    int64_t *n_next);
 

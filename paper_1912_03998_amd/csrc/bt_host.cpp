@@ -1362,6 +1362,7 @@ static bt_status emit_set(bt_ctx *ctx, bt_beams *b, const float *src_xyz, const 
     b->prior = bt_stats{};
     b->r_src = r_src;
     b->emitted = true;
+    b->mesh = nullptr;
     return BT_OK;
 }
 
@@ -1640,6 +1641,8 @@ static bt_params part_params(const bt_params *p, const bt_beams *b)
 static bt_status trace_prepare(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *b, const bt_params *p)
 {
     if (!b->emitted) return fail(ctx, BT_ESTATE, "the beam set holds no emission (emit beams first)");
+    if (b->mesh && b->mesh != mesh)
+        return fail(ctx, BT_EINVAL, "the beam set's generations were traced with another mesh");
     if (b->max_depth >= 0 && b->max_depth != p->max_depth)
         return fail(ctx, BT_EINVAL, "max_depth changed between generations (%d -> %d)", b->max_depth, p->max_depth);
     if (b->gen > p->max_depth) return fail(ctx, BT_ESTATE, "all %d generations already traced", p->max_depth + 1);
@@ -1664,6 +1667,7 @@ static bt_status trace_enqueue(bt_ctx *ctx, const bt_mesh *mesh, bt_beams *b, co
 {
     const int g = b->gen;
     b->max_depth = p->max_depth;
+    b->mesh = mesh;
     const bt_params q = part_params(p, b);
     TraceArgs a = make_args(&q, g);
     a.cg = class_target(b);
@@ -1813,6 +1817,7 @@ extern "C" bt_status bt_accumulate_mics(bt_ctx *ctx, const bt_mesh *mesh, bt_bea
     if (s != BT_OK) return s;
     if (!b->emitted) return fail(ctx, BT_ESTATE, "the beam set holds no emission (emit beams first)");
     if (b->gen == 0) return fail(ctx, BT_ESTATE, "no generation traced yet");
+    if (b->mesh != mesh) return fail(ctx, BT_EINVAL, "the beam set was traced with another mesh");
     if (b->acc_gen == b->gen) return BT_OK;  // nothing traced since the last call
     (void)hipSetDevice(ctx->device);
     // all generations traced since the previous call, in one pass per partition; the
@@ -1840,6 +1845,7 @@ extern "C" bt_status bt_accumulate_mics_static(bt_ctx *ctx, const bt_mesh *mesh,
     if (s != BT_OK) return s;
     if (!b->emitted) return fail(ctx, BT_ESTATE, "the beam set holds no emission (emit beams first)");
     if (b->gen == 0) return fail(ctx, BT_ESTATE, "no generation traced yet");
+    if (b->mesh != mesh) return fail(ctx, BT_EINVAL, "the beam set was traced with another mesh");
     if (b->acc_gen == b->gen) return BT_OK;  // nothing traced since the last call
     if (!ctx->scratch) return fail(ctx, BT_EDEVICE, "no static work area on device %d", ctx->device);
     (void)hipSetDevice(ctx->device);

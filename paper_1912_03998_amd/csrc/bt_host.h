@@ -121,6 +121,7 @@ struct bt_beams {
     bt_beams *part[kMaxParts - 1] = {};
     long long beam0 = 0;
     bool emitted = false;     // holds an emission (false when created, or after a failed one)
+    const bt_mesh *mesh = nullptr;  // the mesh its emission is traced with (its hit ids index it)
 };
 
 struct Request {

@@ -445,6 +445,15 @@ def test_error_paths(torch_cuda):
         with pytest.raises(bt.BTError):
             bt.bt_trace(ctx, mesh, beams, bt.bt_params_default(max_depth=40))
         assert bt.bt_trace(ctx, mesh, beams, p, want_next=True) >= 0
+        # the emission's generations belong to the mesh they were traced with
+        other = bt.bt_build_mesh(ctx, v * 2.0, t, a)
+        with pytest.raises(bt.BTError) as e:
+            bt.bt_trace(ctx, other, beams, p)
+        assert e.value.status == -1
+        with pytest.raises(bt.BTError) as e:
+            bt.bt_accumulate_mics(ctx, other, beams, p, mics)
+        assert e.value.status == -1
+        bt.bt_mesh_free(other)
         bt.bt_accumulate_mics(ctx, mesh, beams, p, mics)
         with pytest.raises(bt.BTError):
             bt.bt_trace(ctx, mesh, beams, bt.bt_params_default(max_depth=2))
