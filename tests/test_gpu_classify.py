@@ -111,6 +111,36 @@ def test_classes_used_only_when_they_cover_the_pass(torch_cuda):
     assert same(es0[idx], es3) and same(ef0[idx], ef3)
 
 
+def test_sealed_box_every_beam_reflects(torch_cuda):
+    """A sealed box around the source: every beam reflects at every generation (depth 7,
+    so the queue holds 8 n0 segments), and the microphone plane inside is crossed from
+    both sides.  Classified at creation or in the pass, resident or with two generation
+    slots: the same tests, updates and energies, which meet the oracle."""
+    from paper_1912_03998_amd import bt
+    from paper_1912_03998_amd.tracer import Session, scene_grid
+    from scenegen import sealed_box_scene
+    sc = sealed_box_scene(level=3, depth=7)
+    with Session.from_scene(sc) as s:
+        mics = bt.bt_mics_grid(s.ctx, *scene_grid(sc))
+        say("sealed box level 3 depth 7: unbound, then bound before emission")
+        es0, ef0, st0 = manual_run(s, sc, mics)
+        es1, ef1, st1 = manual_run(s, sc, mics, bind=mics)
+        bt.bt_mics_free(mics)
+        n0 = 20 * 4 ** sc.level
+        assert list(st1["count"]) == [n0] * (sc.depth + 1)   # every beam reflects
+        assert st1["mic_classified"] == st1["segments"] == (sc.depth + 1) * n0
+        assert st0["mic_tests"] == st1["mic_tests"] > 0 and st0["mic_updates"] == st1["mic_updates"] > 0
+        assert same(es0, es1) and same(ef0, ef1)
+        for records in (0, 1):
+            say("sealed box through bt_run, run_records", records)
+            r = s.run(sc.sources, sc.power, sc.level, sc.depth, scene_grid(sc), run_records=records)
+            assert r.stats["mic_classified"] == r.stats["segments"] == st0["segments"]
+            assert r.stats["mic_tests"] == st0["mic_tests"] and r.stats["mic_updates"] == st0["mic_updates"]
+            assert same(es0, r.e_strict) and same(ef0, r.e_flag)
+    o = O.trace(sc, keep_paths=False)
+    check_mics(o.e_strict, o.e_flag, es1, ef1)
+
+
 def test_bt_run_classifies_district(torch_cuda):
     """bt_run binds its set to a planar grid: on the full district (64 sources, depth 8)
     every segment's class comes from its creation, in the resident layout and with two
