@@ -364,6 +364,35 @@ def volumetric_bench(steps, warmup, chunk=7, level=8, oracle_sample=True, partit
         "mics_reached": int(np.isfinite(e).sum()),
         "setup_s": round(setup_s, 2),
     }
+    # the same step as one bt_run call over all sources: the library takes them in chunks
+    # (every generation of a chunk resident) and runs each partition's trace and
+    # microphone pass back to back on the partition's stream
+    run_params = sess.params(scene.depth, run_records=1 << 28)
+    run_beams = [None]
+
+    def run_step():
+        bt.bt_mics_reset(ctx, mics)
+        run_beams[0] = bt.bt_run(ctx, mesh, src, pw, scene.level, run_params, mics, run_beams[0])
+        bt.bt_levels(ctx, mics, None, None, level_out)
+
+    for _ in range(max(warmup, 1)):
+        run_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run_step()
+    torch.cuda.synchronize()
+    run_elapsed = time.perf_counter() - t0
+    st = bt.bt_beams_stats(ctx, run_beams[0])
+    bt.bt_beams_free(run_beams[0])
+    out["one_call"] = {
+        "step_call": f"bt_run over all {scene.n_src} sources (run_records = 2^28: the library's source chunks, "
+                     "every generation of a chunk resident), then bt_levels",
+        "ms_per_step": round(run_elapsed * 1000.0 / steps, 2),
+        "segments_per_step": st["segments"], "mic_updates_per_step": st["mic_updates"],
+        "same_counts_as_beam_sets": st["segments"] == totals["segments"] and
+                                    st["mic_updates"] == totals["mic_updates"],
+    }
     sess.close()
     if oracle_sample:
         # the oracle on one whole source of the same workload (bounded CPU time)
