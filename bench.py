@@ -519,6 +519,9 @@ def main():
         sess.beams = bt.bt_beams_bind_mics(ctx, sess.beams, mics)
 
     def step(ev=None):
+        # ev: [trace start, trace end, microphones end, step start, step end]
+        if ev is not None:
+            ev[3].record(stream)
         if args.run_call:
             # one call: its stages are not separated (the whole step counts as the trace stage)
             bt.bt_mics_reset(ctx, mics)
@@ -529,6 +532,8 @@ def main():
                 ev[1].record(stream)
                 ev[2].record(stream)
             bt.bt_levels(ctx, mics, None, None, level_out)
+            if ev is not None:
+                ev[4].record(stream)
             return
         # emission, every generation's trace, one microphone pass over all of them, with
         # events between the stages
@@ -547,10 +552,12 @@ def main():
         if ev is not None:
             ev[2].record(stream)
         bt.bt_levels(ctx, mics, None, None, level_out)
+        if ev is not None:
+            ev[4].record(stream)
 
     for _ in range(args.warmup):
         step()
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -563,6 +570,7 @@ def main():
     trace_ms /= args.steps
     mic_ms /= args.steps
     ms_per_step = elapsed * 1000.0 / args.steps
+    each_ms = sorted(events[k][3].elapsed_time(events[k][4]) for k in range(args.steps))
     segs, upd = st["segments"], st["mic_updates"]
 
     # algorithmic bytes of the trace kernel, fixed by the oracle's reference traversal
@@ -624,6 +632,9 @@ def main():
                    "flagged_per_generation": st["flagged"].tolist()},
         "roofline": roofline,
         "kernel_ms_per_step": {"trace": round(trace_ms, 3), "mics": round(mic_ms, 3)},
+        "step_ms_events": {"median": round(float(np.median(each_ms)), 3), "min": round(each_ms[0], 3),
+                           "max": round(each_ms[-1], 3),
+                           "note": "HIP events on the context's stream around each timed step (emission to levels)"},
         "gpu_hierarchy_bytes_per_s": gpu_bytes / (trace_ms * 1e-3) if trace_ms > 0 else None,
         "gpu_node_visits_per_segment": st["node_visits"] / max(segs, 1),
         "gpu_tri_tests_per_segment": st["tri_tests"] / max(segs, 1),
